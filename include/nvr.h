@@ -1,0 +1,374 @@
+/*
+ * nvr.h -- C ABI of the MI355X (gfx950) hot path of Instant-NVR's on-the-fly
+ * radiance-field back-end: march rays with occupancy skipping, warp live human
+ * samples into the canonical space, encode with a multiresolution hash grid,
+ * evaluate the density and colour networks, alpha-composite, back-propagate the
+ * colour / depth loss and update the parameters with Adam.
+ *
+ * Paper: "Instant-NVR: Instant Neural Volumetric Rendering for Human-object
+ * Interactions from Monocular RGBD Stream" (CVPR 2023).  Each entry point
+ * below names the passage that defines what it computes.
+ *
+ * Conventions (every entry point):
+ *   - Array pointers are DEVICE pointers owned by the caller unless a comment
+ *     says "host".  Descriptors (structs) are host memory, read during the call.
+ *   - Arrays are dense, row-major, naturally aligned; float32 unless stated.
+ *     "(acc)" outputs are ACCUMULATED into (the caller zeroes them); others are
+ *     overwritten.  "nullable" arguments may be NULL to skip that output/input.
+ *   - All work is enqueued on `stream` (0 = the null stream); nothing
+ *     synchronises implicitly unless a comment says so.
+ *   - Shapes and descriptors are validated on the host BEFORE anything is
+ *     launched; on failure the call returns a negative nvr_status, launches
+ *     nothing and sets a thread-local message readable by nvr_last_error().
+ *     No entry point aborts or exits.
+ *   - Sample counts that are only known on the device (after marching) are
+ *     passed as `const int32_t *n_dev`: kernels read the count there and are
+ *     launched for `capacity` samples, so no host synchronisation is needed.
+ */
+#ifndef NVR_H
+#define NVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *nvr_stream;   /* hipStream_t */
+
+typedef enum {
+    NVR_OK = 0,
+    NVR_EINVAL = -1,        /* bad descriptor, size, pointer or alignment */
+    NVR_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. F != 2) */
+    NVR_EHIP = -3,          /* a HIP runtime call failed */
+    NVR_ENOMEM = -4,        /* device allocation failed (context workspace) */
+    NVR_ENONFINITE = -5,    /* non-finite gradients: step skipped (informational) */
+    NVR_EOVERFLOW = -6      /* more samples than the given capacity */
+} nvr_status;
+
+typedef enum { NVR_F32 = 0, NVR_F16 = 1, NVR_BF16 = 2 } nvr_dtype;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *nvr_last_error(void);
+/* Library version string. */
+const char *nvr_version(void);
+
+/* ------------------------------------------------------------------------
+ * Multiresolution hash grid.  The paper extracts per-point features from a
+ * hash table for each field (Sec. 4.2, "Separated instant neural
+ * representation"), delegating the encoding to Instant-NGP: level l has
+ * resolution N_l = floor(N_min * b^l), b = exp((ln N_max - ln N_min)/(L-1))
+ * (float64 on the host); x_hat = clamp((x - aabb_min)/(aabb_max - aabb_min),
+ * 0, 1); x_l = x_hat * N_l; cell c = min(floor(x_l), N_l - 1); trilinear
+ * weights over the 8 corners; a level with (N_l+1)^3 <= T vertices is
+ * indexed densely (cx + (N_l+1)(cy + (N_l+1) cz)), else by
+ * (cx*1 ^ cy*2654435761 ^ cz*805459861) mod 2^32 & (T-1).
+ * Table layout: [n_entries][F] with level l at entries offset[l]..offset[l+1).
+ * ---------------------------------------------------------------------- */
+#define NVR_MAX_LEVELS 32
+typedef struct {
+    int32_t n_levels;            /* L, 1..32 */
+    int32_t n_features;          /* F, must be 2 */
+    int32_t log2_table;          /* log2 T, 4..24 */
+    int32_t res[NVR_MAX_LEVELS];     /* N_l */
+    int32_t dense[NVR_MAX_LEVELS];   /* 1 if level l is dense */
+    int64_t offset[NVR_MAX_LEVELS + 1];  /* entry offsets; offset[L] = n_entries */
+    float aabb_min[3], aabb_max[3];
+} nvr_grid_desc;
+
+/* Fill `g` (host) from the level ladder parameters.  aabb_* are host arrays. */
+nvr_status nvr_grid_init(nvr_grid_desc *g, int32_t n_levels, int32_t n_features,
+                         int32_t log2_table, int32_t res_min, int32_t res_max,
+                         const float *aabb_min, const float *aabb_max);
+
+/* feat[n][L*F] = encoding of x[n][3] (world positions).  table_dtype is
+ * NVR_F32 or NVR_F16; feat_dtype NVR_F32, NVR_F16 or NVR_BF16.  The fp16-table
+ * path is the level-split kernel (each XCD serves a fixed subset of levels). */
+nvr_status nvr_encode_fwd(const nvr_grid_desc *g, int64_t n, const float *x,
+                          const void *table, nvr_dtype table_dtype,
+                          void *feat, nvr_dtype feat_dtype, nvr_stream stream);
+
+/* Backward: dtable[e][f] += sum over samples/corners of w * dfeat (acc, f32);
+ * dx[n][3] += d/dx of sum(feat * dfeat) (acc, nullable; 0 where x_hat was
+ * clamped).  dfeat is [n][L*F] float32. */
+nvr_status nvr_encode_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
+                          const void *table, nvr_dtype table_dtype,
+                          const float *dfeat, float *dtable, float *dx,
+                          nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Ray marching with occupancy skipping (the back-end is built on Instant-NGP,
+ * Sec. 4.3; its marcher is not described in the paper).  Per ray: clip
+ * o + t d to the box (slab method) intersected with [near, far]; samples at
+ * t_i = t_n + (i + 1/2) * step while t_i < t_f, at most max_steps; keep a
+ * sample iff its occupancy voxel's bit is set (voxel v = clamp(floor((x -
+ * aabb_min) * (occ_res/side)), 0, occ_res-1), index vx + R(vy + R vz), bit
+ * idx&31 of word idx>>5).  These integer decisions are taken in IEEE float32,
+ * one rounding per operation, no fused multiply-add.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    float aabb_min[3], aabb_max[3];
+    float near_t, far_t;
+    float step;                  /* <= 0: float(sqrt(3) * max side / max_steps) */
+    int32_t max_steps;           /* 1..1024 */
+    int32_t occ_res;             /* 0: keep every sample */
+} nvr_march_desc;
+
+/* Bytes of scratch nvr_march needs for n_rays rays. */
+size_t nvr_march_workspace(int64_t n_rays);
+
+/* Marches rays [ray_begin, ray_end) of o[n_rays][3], d[n_rays][3]; rays outside
+ * the range get no samples.  Writes off[n_rays+1] (ray r owns samples
+ * off[r]..off[r+1]-1, ray-major, increasing t), and for each sample ray_id, t,
+ * dt and its position x[3]; n_dev[0] = total kept samples (may exceed
+ * capacity: samples past capacity are not written, and the caller must treat
+ * n_dev[0] > capacity as NVR_EOVERFLOW).  occ is the bitfield (nullable iff
+ * occ_res == 0).  workspace: nvr_march_workspace(n_rays) bytes. */
+nvr_status nvr_march(const nvr_march_desc *m, int64_t n_rays, int64_t ray_begin,
+                     int64_t ray_end, const float *o, const float *d,
+                     const uint32_t *occ, int64_t capacity, int32_t *off,
+                     int32_t *ray_id, float *t, float *dt, float *x, int32_t *n_dev,
+                     void *workspace, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Hybrid warp live -> canonical (Sec. 4.2, Eq. 4, with the node weight of
+ * Sec. 4.1 after Eq. 1, r = 0.1, and the voxel look-up of neighbour nodes of
+ * "On-the-fly Radiance Fields").  Per sample x (live): inverse skinning over
+ * the k_joints nearest joints (Gaussian weights, sigma_skin, normalised;
+ * y = sum_j w_j (R_j x + t_j) with bones given as live->canonical [R|t]), then
+ * the inverse node blend over the k_nodes ids listed for x's live voxel:
+ * b = sum_i s_i w_i conj(dq_i), w_i = exp(-(|y-g_i|^2 - min_k|y-g_k|^2)/r^2),
+ * s_i = sign <q_r,i, q_r,first>, c = b/|b_r|, z = R(c_r) y + 2 vec(c_d c_r*).
+ * Voxel choice, joint choice and sign are float32 decisions (see nvr_march).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_joints;            /* <= 64 */
+    int32_t k_joints;            /* 1..8 */
+    float sigma_skin;            /* skinning Gaussian width (0.1) */
+    int32_t n_nodes;             /* <= 65536 (uint16 ids) */
+    int32_t k_nodes;             /* 1..16 */
+    int32_t n_frames;            /* >= 1 */
+    float r_node;                /* node influence radius r (0.1) */
+    int32_t lut_res;             /* look-up grid resolution */
+    float lut_min[3], lut_max[3];
+} nvr_warp_desc;
+
+typedef struct {                 /* device pointers */
+    const float *joints;         /* [n_joints][3] */
+    const float *bones;          /* [n_frames][n_joints][3][4] */
+    const float *node_dq;        /* [n_frames][n_nodes][8] real(w,x,y,z), dual(w,x,y,z) */
+    const float *node_pos;       /* [n_frames][n_nodes][3] deformed node positions */
+    const uint16_t *lut;         /* [n_frames][lut_res^3][k_nodes] */
+} nvr_warp_rig;
+
+/* x_can[n][3] = warp of x_live[n][3]; frame (nullable) gives each sample's
+ * frame (default 0).  n_dev (nullable) overrides n with a device count. */
+nvr_status nvr_warp_fwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t n,
+                        const int32_t *n_dev, const float *x_live, const int32_t *frame,
+                        float *x_can, nvr_stream stream);
+
+/* Backward of sum(dx_can . x_can): d_node_dq[n_frames][n_nodes][8] (acc)
+ * through the blend; d_bones[n_frames][n_joints][12] (acc, nullable) through
+ * y including y's effect on the node weights.  dx_can may be given as
+ * n_parts partial arrays of [n][3] laid out back to back, which are summed. */
+nvr_status nvr_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t n,
+                        const int32_t *n_dev, const float *x_live, const int32_t *frame,
+                        const float *dx_can, int32_t n_parts, float *d_node_dq,
+                        float *d_bones, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Density + colour networks of a field (Sec. 4.2: geometry network E_g and
+ * colour network E_c on the encoded features; widths from Instant-NGP):
+ * bias-free linear layers with ReLU on hidden layers; density outputs o[16],
+ * sigma = exp(clamp(o_0, -15, 15)); colour input [o, SH(d)] with real SH of
+ * `sh_degree` bands (d^2 coefficients, standard real basis, Y_1 ~ (y, z, x));
+ * rgb = sigmoid(last layer).  Parameters: one flat vector, each layer's
+ * W[out][in] row-major, density layers first.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_in;                /* encoding width, 1..64 */
+    int32_t n_density_hidden;    /* 1..4 */
+    int32_t density_hidden[4];   /* widths, 1..64 */
+    int32_t density_out;         /* 1..16 */
+    int32_t sh_degree;           /* 1..4 */
+    int32_t n_colour_hidden;     /* 1..4 */
+    int32_t colour_hidden[4];    /* widths, 1..64 */
+} nvr_mlp_desc;
+
+/* Number of parameters (host out). */
+nvr_status nvr_mlp_param_count(const nvr_mlp_desc *m, int64_t *count);
+
+/* sigma[n], rgb[n][3] from feat[n][n_in] (feat_dtype) and the view direction
+ * dirs[ray_id[i]] (ray_id nullable: dirs is per sample).  math = NVR_F32 runs
+ * the plain float32 kernel (params float32); math = NVR_BF16 runs the MFMA
+ * kernel (params bf16 copy, feat bf16; widths 64 / n_in <= 32 / density_out 16
+ * / 16 + SH <= 32 only). */
+nvr_status nvr_mlp_fwd(const nvr_mlp_desc *m, int64_t n, const int32_t *n_dev,
+                       const void *feat, nvr_dtype feat_dtype, const float *dirs,
+                       const int32_t *ray_id, const void *params, nvr_dtype math,
+                       float *sigma, float *rgb, nvr_stream stream);
+
+/* Backward from dsigma[n], drgb[n][3]: dparams (acc, f32, flat like params),
+ * dfeat[n][n_in] (overwritten, f32, nullable).  Recomputes the forward.
+ * workspace: nvr_mlp_workspace(m, math, n) bytes (NVR_F32: per-layer
+ * activations and their gradients, unit-major; NVR_BF16: per-workgroup
+ * partial weight gradients). */
+size_t nvr_mlp_workspace(const nvr_mlp_desc *m, nvr_dtype math, int64_t n);
+nvr_status nvr_mlp_bwd(const nvr_mlp_desc *m, int64_t n, const int32_t *n_dev,
+                       const void *feat, nvr_dtype feat_dtype, const float *dirs,
+                       const int32_t *ray_id, const void *params, nvr_dtype math,
+                       const float *dsigma, const float *drgb, float *dparams,
+                       float *dfeat, void *workspace, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Compositing (volume rendering of the density fields, Sec. 1 / Sec. 4.3;
+ * NeRF quadrature): tau_i = sigma_i dt_i, T_i = exp(-sum_{j<i} tau_j),
+ * w_i = T_i (1 - exp(-tau_i)); C = sum w_i c_i, D = sum w_i t_i, TN = T_n.
+ * A second sample list (b, nullable) is merged per ray by t (ties: list a
+ * first), as for a ray shared by the human and the object field.  t_stop > 0
+ * drops samples with T_i < t_stop (render only).
+ * ---------------------------------------------------------------------- */
+typedef struct {                 /* one ray-major sample list */
+    const int32_t *off;          /* [n_rays+1] */
+    const float *sigma;          /* [n] */
+    const float *rgb;            /* [n][3] */
+    const float *t;              /* [n] */
+    const float *dt;             /* [n] */
+} nvr_samples;
+
+nvr_status nvr_composite_fwd(int64_t n_rays, const nvr_samples *a, const nvr_samples *b,
+                             float t_stop, float *C, float *D, float *TN,
+                             nvr_stream stream);
+
+/* Closed-form backward: dsigma_i = dt_i (T_{i+1} u_i - sum_{k>i} w_k u_k),
+ * drgb_i = w_i dC, u_i = c_i.dC + t_i dD.  Outputs per list (overwritten);
+ * b outputs nullable iff b is. */
+nvr_status nvr_composite_bwd(int64_t n_rays, const nvr_samples *a, const nvr_samples *b,
+                             const float *C, const float *D, const float *dC,
+                             const float *dD, float *dsigma_a, float *drgb_a,
+                             float *dsigma_b, float *drgb_b, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Loss (Sec. 4.3, Eq. 8, read as squared L2 on colour and depth, mean over
+ * rays): L = (1/R) sum_r M_r (|C-C*|^2 + lambda_d (D-D*)^2).  Writes
+ * loss_dev[0] (overwritten), dC, dD (overwritten) times loss_scale_dev[0]
+ * (nullable = 1).  D_t and mask nullable.
+ * ---------------------------------------------------------------------- */
+nvr_status nvr_loss(int64_t n_rays, const float *C, const float *D, const float *C_t,
+                    const float *D_t, const float *mask, float lambda_d,
+                    const float *loss_scale_dev, float *loss_dev, float *dC, float *dD,
+                    nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Adam with loss scaling (optimiser not stated in the paper; Instant-NGP's):
+ * g = grad / S; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^k)) / (sqrt(v / (1-b2^k)) + eps), k = state->step + 1.
+ * skip_zero leaves entries with grad == 0 untouched.  The grad buffer is
+ * zeroed after use.  If state->finite == 0 nothing but the zeroing happens.
+ * copy (nullable) receives float16 / bfloat16 of the updated parameter.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t step;                /* completed updates */
+    int32_t finite;              /* 1 if every gradient of this step is finite */
+    float loss_scale;            /* S */
+    float pad;
+} nvr_train_state;               /* lives in DEVICE memory */
+
+typedef struct { float lr, beta1, beta2, eps; } nvr_adam_desc;
+
+/* state->finite = 1 (call before nvr_check_finite for a new step). */
+nvr_status nvr_state_begin(nvr_train_state *state_dev, nvr_stream stream);
+/* state->finite = 0 if any of g[n] is not finite. */
+nvr_status nvr_check_finite(int64_t n, const float *g, nvr_train_state *state_dev,
+                            nvr_stream stream);
+nvr_status nvr_adam(const nvr_adam_desc *a, int64_t n, float *param, float *m, float *v,
+                    float *grad, int32_t skip_zero, const nvr_train_state *state_dev,
+                    void *copy, nvr_dtype copy_dtype, nvr_stream stream);
+/* After every nvr_adam of a step: step += 1 if finite, else loss_scale /= 2. */
+nvr_status nvr_state_end(nvr_train_state *state_dev, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Whole step (Sec. 4.2 / 4.3: per training iteration sample rays, warp human
+ * samples, encode, run the networks, volume-render, back-propagate Eq. 8,
+ * update).  One or two fields (human with warp, object) over ray ranges;
+ * rays in both ranges are composited over the t-merged samples of both.
+ * Precision NVR_F32: plain float32 kernels, float32 tables and parameters.
+ * Precision NVR_BF16: float16 table copies + float32 masters, bf16 MFMA
+ * networks, level-split encoder; transmittance, losses and gradients float32.
+ * The context owns the per-sample workspace (sized on first use, grown on
+ * demand) and, if graphs are on, one captured HIP graph per field set.
+ * ---------------------------------------------------------------------- */
+typedef struct nvr_ctx nvr_ctx;
+
+typedef struct {
+    nvr_grid_desc grid;
+    nvr_mlp_desc mlp;
+    nvr_march_desc march;
+    int32_t has_warp;
+    nvr_warp_desc warp;
+    nvr_warp_rig rig;            /* device pointers, used iff has_warp */
+    int64_t ray_begin, ray_end;  /* rays this field covers */
+    const uint32_t *occ;         /* occupancy bitfield (nullable iff occ_res == 0) */
+    /* parameters, device: masters float32; copies used by NVR_BF16 */
+    float *table;                /* [n_entries][2] */
+    void *table_half;            /* [n_entries][2] float16 (NVR_BF16) */
+    float *params;               /* flat */
+    void *params_bf16;           /* flat bfloat16 (NVR_BF16) */
+    float *table_grad, *params_grad;          /* zero on entry, zeroed by the step */
+    float *table_m, *table_v, *params_m, *params_v;
+    float *node_dq_grad;         /* (acc, nullable) [n_frames][n_nodes][8] */
+    float *bones_grad;           /* (acc, nullable) [n_frames][n_joints][12] */
+} nvr_field;
+
+typedef struct {
+    int32_t n_fields;            /* 1 or 2 */
+    nvr_dtype precision;         /* NVR_F32 or NVR_BF16 */
+    int64_t n_rays;
+    int64_t max_samples;         /* per-field sample capacity */
+    float lambda_depth;
+    nvr_adam_desc adam;
+    int32_t apply_update;        /* 0: fwd + bwd only (gradients left in *_grad) */
+} nvr_step_desc;
+
+typedef struct {                 /* device pointers */
+    const float *o, *d;          /* [n_rays][3] */
+    const float *C_t;            /* [n_rays][3] */
+    const float *D_t;            /* [n_rays] nullable */
+    const float *mask;           /* [n_rays] nullable */
+} nvr_batch;
+
+nvr_status nvr_create(nvr_ctx **out, int32_t device, uint32_t flags);
+#define NVR_USE_GRAPH 1u
+void nvr_destroy(nvr_ctx *ctx);
+
+/* Forward half: march, warp, encode, networks, composite, loss.  Writes
+ * loss_dev[0], and (nullable) C_out[n_rays][3], D_out[n_rays]. */
+nvr_status nvr_train_step_fwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
+                              const nvr_batch *b, nvr_train_state *state_dev,
+                              float *loss_dev, float *C_out, float *D_out, nvr_stream stream);
+/* Backward half + update, using what nvr_train_step_fwd left in the context. */
+nvr_status nvr_train_step_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
+                              const nvr_batch *b, nvr_train_state *state_dev,
+                              nvr_stream stream);
+/* Both halves; with NVR_USE_GRAPH the sequence is captured once per
+ * (descriptor, field, batch) set and replayed. */
+nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
+                          const nvr_batch *b, nvr_train_state *state_dev, float *loss_dev,
+                          nvr_stream stream);
+/* Total kept samples of field f in the last forward (synchronises `stream`). */
+nvr_status nvr_last_sample_count(nvr_ctx *ctx, int32_t field, int64_t *count,
+                                 nvr_stream stream);
+
+/* Forward-only render of rays o, d (device, [n_rays][3]) over every field
+ * (ranges ignored: each field marches every ray; two fields are t-merged),
+ * dropping samples with T_i < t_stop.  Uses each field's fp16 / bf16 copies
+ * when precision is NVR_BF16.  rgb[n_rays][3], depth[n_rays]. */
+nvr_status nvr_render(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
+                      int64_t n_rays, const float *o, const float *d, float t_stop,
+                      float *rgb, float *depth, nvr_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NVR_H */

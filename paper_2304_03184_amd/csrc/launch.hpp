@@ -1,0 +1,54 @@
+// Internal launchers shared between the kernel files and the step driver.
+#pragma once
+#include "common.hpp"
+#include "grid_dev.hpp"
+#include "mlp_dev.hpp"
+#include "composite_dev.hpp"
+#include "optim_dev.hpp"
+
+namespace nvr {
+
+// march.hip
+struct MarchParams;
+nvr_status march_desc_check(const nvr_march_desc *m);
+size_t march_ws_bytes(int64_t n_rays);
+nvr_status run_march(const nvr_march_desc *m, int64_t n_rays, int64_t begin, int64_t end,
+                     const float *o, const float *d, const uint32_t *occ, int64_t capacity,
+                     int32_t *off, int32_t *ray_id, float *t, float *dt, float *x, int32_t *n_dev,
+                     int32_t *ws, hipStream_t st);
+
+// warp.hip
+struct WarpParams;
+nvr_status run_warp_fwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t cap,
+                        const int32_t *n_dev, const float *x, float *xc, hipStream_t st);
+nvr_status run_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t cap,
+                        const int32_t *n_dev, const float *x, const float *gz, int n_parts,
+                        int64_t part_stride, float *d_dq, float *d_bones, hipStream_t st);
+
+// mlp_plain.hip
+struct PlainView {
+    float *p;
+    int64_t su, ss;
+};
+size_t plain_workspace(const Net &net, int64_t cap);
+nvr_status plain_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap, PlainView F,
+                     const float *dirs, const int32_t *ray_id, const float *params, float *sigma,
+                     float *rgb, float *ws, hipStream_t st);
+nvr_status plain_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap, PlainView F,
+                     const float *params, const float *sigma, const float *rgb,
+                     const float *dsigma, const float *drgb, float *dparams, PlainView dF,
+                     bool want_dfeat, float *ws, hipStream_t st);
+
+// mlp_mfma.hip
+struct MfmaNet;
+nvr_status mfma_check(const Net &net);
+size_t mfma_ws_bytes(const Net &net, int64_t cap);
+nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
+                    const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
+                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st);
+nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
+                    const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
+                    const uint16_t *params, const float *dsigma, const float *drgb, float *dparams,
+                    float *dfeat, void *ws, hipStream_t st);
+
+}  // namespace nvr

@@ -1,0 +1,266 @@
+// Ray clipping and occupancy-skipping sample placement.
+//
+// Three launches, no host synchronisation:
+//   1. march_count  -- one thread per ray: clip, walk the steps, count kept
+//                      samples; 256-ray block scan in LDS -> local offsets,
+//                      block totals;
+//   2. scan_blocks  -- one workgroup scans the block totals, writes the total
+//                      sample count to n_dev and off[R];
+//   3. march_write  -- one thread per ray: walk again and write t, dt, x and
+//                      the ray id at its global offset (capacity-bounded).
+// The walk's integer decisions use IEEE float32 with one rounding per
+// operation (the __f*_rn intrinsics keep the compiler from fusing a
+// multiply-add), in the order fixed by the documented reading.
+#include "common.hpp"
+
+#include <cmath>
+
+namespace nvr {
+
+struct MarchParams {
+    float lo[3], hi[3];
+    float near_t, far_t, step;
+    float occ_scale[3];
+    int max_steps, occ_res;
+    int64_t begin, end;
+};
+
+struct RaySeg {
+    float tn, tf;
+};
+
+__device__ __forceinline__ RaySeg clip_ray(const MarchParams &p, const float *o, const float *d) {
+    float tn = p.near_t, tf = p.far_t;
+    float lo_t[3], hi_t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float inv = __fdiv_rn(1.0f, d[a]);
+        const float t0 = __fmul_rn(__fsub_rn(p.lo[a], o[a]), inv);
+        const float t1 = __fmul_rn(__fsub_rn(p.hi[a], o[a]), inv);
+        lo_t[a] = fminf(t0, t1);
+        hi_t[a] = fmaxf(t0, t1);
+    }
+    tn = fmaxf(fmaxf(fmaxf(lo_t[0], lo_t[1]), lo_t[2]), tn);
+    tf = fminf(fminf(fminf(hi_t[0], hi_t[1]), hi_t[2]), tf);
+    return {tn, tf};
+}
+
+__device__ __forceinline__ bool occupied(const MarchParams &p, const uint32_t *occ,
+                                         const float x[3]) {
+    if (p.occ_res == 0) return true;
+    int v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = __fmul_rn(__fsub_rn(x[a], p.lo[a]), p.occ_scale[a]);
+        int c = (int)floorf(u);
+        c = c < 0 ? 0 : (c > p.occ_res - 1 ? p.occ_res - 1 : c);
+        v[a] = c;
+    }
+    const uint32_t idx = (uint32_t)v[0] + (uint32_t)p.occ_res * ((uint32_t)v[1] +
+                                                                (uint32_t)p.occ_res * (uint32_t)v[2]);
+    return (occ[idx >> 5] >> (idx & 31u)) & 1u;
+}
+
+// Walks ray r; calls emit(i_kept, t, x) for every kept sample; returns the count.
+template <typename Emit>
+__device__ __forceinline__ int walk(const MarchParams &p, const uint32_t *occ, const float *o,
+                                    const float *d, Emit emit) {
+    const RaySeg s = clip_ray(p, o, d);
+    int kept = 0;
+    if (!(s.tf > s.tn)) return 0;
+    for (int i = 0; i < p.max_steps; ++i) {
+        const float t = __fadd_rn(s.tn, __fmul_rn(__fadd_rn((float)i, 0.5f), p.step));
+        if (!(t < s.tf)) break;
+        float x[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = __fadd_rn(o[a], __fmul_rn(t, d[a]));
+        if (occupied(p, occ, x)) {
+            emit(kept, t, x);
+            ++kept;
+        }
+    }
+    return kept;
+}
+
+constexpr int kMarchBlock = 256;
+
+__global__ void __launch_bounds__(kMarchBlock)
+march_count(MarchParams p, int64_t n_rays, const float *__restrict__ o,
+            const float *__restrict__ d, const uint32_t *__restrict__ occ,
+            int32_t *__restrict__ off, int32_t *__restrict__ block_sums) {
+    __shared__ int32_t buf[kMarchBlock];
+    const int64_t r = blockIdx.x * (int64_t)kMarchBlock + threadIdx.x;
+    int cnt = 0;
+    if (r < n_rays && r >= p.begin && r < p.end) {
+        float oo[3] = {o[3 * r], o[3 * r + 1], o[3 * r + 2]};
+        float dd[3] = {d[3 * r], d[3 * r + 1], d[3 * r + 2]};
+        cnt = walk(p, occ, oo, dd, [](int, float, const float *) {});
+    }
+    // inclusive Hillis-Steele scan in LDS
+    buf[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = 1; s < kMarchBlock; s <<= 1) {
+        int v = threadIdx.x >= s ? buf[threadIdx.x - s] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (r < n_rays) off[r] = buf[threadIdx.x] - cnt;   // exclusive, block-local
+    if (threadIdx.x == kMarchBlock - 1) block_sums[blockIdx.x] = buf[kMarchBlock - 1];
+}
+
+// Single workgroup: exclusive scan of nb block sums in place; total -> n_dev, off[n_rays].
+__global__ void __launch_bounds__(1024)
+scan_blocks(int64_t nb, int32_t *__restrict__ block_sums, int64_t n_rays, int64_t capacity,
+            int32_t *__restrict__ off, int32_t *__restrict__ n_dev) {
+    __shared__ int32_t buf[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int32_t v = i < nb ? block_sums[i] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 1; s < 1024; s <<= 1) {
+            int32_t u = threadIdx.x >= s ? buf[threadIdx.x - s] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += u;
+            __syncthreads();
+        }
+        if (i < nb) block_sums[i] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // offsets are clamped to the capacity so that no consumer reads past the
+        // sample arrays; n_dev keeps the true total (overflow detection)
+        off[n_rays] = carry < capacity ? carry : (int32_t)capacity;
+        *n_dev = carry;
+    }
+}
+
+__global__ void __launch_bounds__(kMarchBlock)
+march_write(MarchParams p, int64_t n_rays, const float *__restrict__ o,
+            const float *__restrict__ d, const uint32_t *__restrict__ occ,
+            const int32_t *__restrict__ block_sums, int64_t capacity, int32_t *__restrict__ off,
+            int32_t *__restrict__ ray_id, float *__restrict__ t_out, float *__restrict__ dt_out,
+            float *__restrict__ x_out) {
+    const int64_t r = blockIdx.x * (int64_t)kMarchBlock + threadIdx.x;
+    if (r >= n_rays) return;
+    const int64_t base = (int64_t)off[r] + block_sums[blockIdx.x];
+    off[r] = (int32_t)(base < capacity ? base : capacity);
+    if (r < p.begin || r >= p.end) return;
+    float oo[3] = {o[3 * r], o[3 * r + 1], o[3 * r + 2]};
+    float dd[3] = {d[3 * r], d[3 * r + 1], d[3 * r + 2]};
+    const float step = p.step;
+    walk(p, occ, oo, dd, [&](int k, float t, const float *x) {
+        const int64_t j = base + k;
+        if (j < capacity) {
+            ray_id[j] = (int32_t)r;
+            t_out[j] = t;
+            dt_out[j] = step;
+            x_out[3 * j] = x[0];
+            x_out[3 * j + 1] = x[1];
+            x_out[3 * j + 2] = x[2];
+        }
+    });
+}
+
+nvr_status make_march_params(const nvr_march_desc *m, int64_t begin, int64_t end,
+                             MarchParams *p) {
+    NVR_REQUIRE(m != nullptr, NVR_EINVAL, "march descriptor is NULL");
+    NVR_REQUIRE(m->max_steps >= 1 && m->max_steps <= 1024, NVR_EINVAL, "max_steps out of 1..1024");
+    NVR_REQUIRE(m->occ_res >= 0 && m->occ_res <= 1024, NVR_EINVAL, "occ_res out of 0..1024");
+    double side_max = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        NVR_REQUIRE(m->aabb_max[a] > m->aabb_min[a], NVR_EINVAL, "empty box on axis %d", a);
+        const double side = (double)m->aabb_max[a] - (double)m->aabb_min[a];
+        side_max = side > side_max ? side : side_max;
+        p->lo[a] = m->aabb_min[a];
+        p->hi[a] = m->aabb_max[a];
+        p->occ_scale[a] = m->occ_res > 0 ? (float)((double)m->occ_res / side) : 0.f;
+    }
+    p->near_t = m->near_t;
+    p->far_t = m->far_t;
+    p->step = m->step > 0.f ? m->step : (float)(std::sqrt(3.0) * side_max / (double)m->max_steps);
+    p->max_steps = m->max_steps;
+    p->occ_res = m->occ_res;
+    p->begin = begin;
+    p->end = end;
+    return NVR_OK;
+}
+
+int64_t march_blocks(int64_t n_rays) { return (n_rays + kMarchBlock - 1) / kMarchBlock; }
+
+nvr_status launch_march(const MarchParams &p, int64_t n_rays, const float *o, const float *d,
+                        const uint32_t *occ, int64_t capacity, int32_t *off, int32_t *ray_id,
+                        float *t, float *dt, float *x, int32_t *n_dev, int32_t *block_sums,
+                        hipStream_t st) {
+    const int64_t nb = march_blocks(n_rays);
+    if (nb > 0) {
+        march_count<<<(unsigned)nb, kMarchBlock, 0, st>>>(p, n_rays, o, d, occ, off, block_sums);
+        NVR_LAUNCHED();
+    }
+    scan_blocks<<<1, 1024, 0, st>>>(nb, block_sums, n_rays, capacity, off, n_dev);
+    NVR_LAUNCHED();
+    if (nb > 0) {
+        march_write<<<(unsigned)nb, kMarchBlock, 0, st>>>(p, n_rays, o, d, occ, block_sums,
+                                                          capacity, off, ray_id, t, dt, x);
+        NVR_LAUNCHED();
+    }
+    return NVR_OK;
+}
+
+}  // namespace nvr
+
+using namespace nvr;
+
+extern "C" size_t nvr_march_workspace(int64_t n_rays) {
+    if (n_rays < 0) return 0;
+    return sizeof(int32_t) * (size_t)(march_blocks(n_rays) + 1);
+}
+
+extern "C" nvr_status nvr_march(const nvr_march_desc *m, int64_t n_rays, int64_t ray_begin,
+                                int64_t ray_end, const float *o, const float *d,
+                                const uint32_t *occ, int64_t capacity, int32_t *off,
+                                int32_t *ray_id, float *t, float *dt, float *x, int32_t *n_dev,
+                                void *workspace, nvr_stream stream) {
+    clear_error();
+    MarchParams p;
+    NVR_TRY(make_march_params(m, ray_begin, ray_end, &p));
+    NVR_REQUIRE(n_rays >= 0 && n_rays < (1ll << 31), NVR_EINVAL, "n_rays out of range");
+    NVR_REQUIRE(ray_begin >= 0 && ray_begin <= ray_end && ray_end <= n_rays, NVR_EINVAL,
+                "ray range [%lld, %lld) not inside [0, %lld)", (long long)ray_begin,
+                (long long)ray_end, (long long)n_rays);
+    NVR_REQUIRE(capacity >= 0 && capacity < (1ll << 31), NVR_EINVAL, "capacity out of range");
+    NVR_REQUIRE(off && n_dev && workspace, NVR_EINVAL, "NULL off / n_dev / workspace");
+    NVR_REQUIRE(m->occ_res == 0 || occ != nullptr, NVR_EINVAL, "occ is NULL but occ_res > 0");
+    if (n_rays > 0) NVR_REQUIRE(o && d, NVR_EINVAL, "NULL rays");
+    if (capacity > 0) NVR_REQUIRE(ray_id && t && dt && x, NVR_EINVAL, "NULL sample arrays");
+    return launch_march(p, n_rays, o, d, occ, capacity, off, ray_id, t, dt, x, n_dev,
+                        (int32_t *)workspace, hs(stream));
+}
+
+#include "launch.hpp"
+
+namespace nvr {
+
+size_t march_ws_bytes(int64_t n_rays) { return nvr_march_workspace(n_rays); }
+
+nvr_status march_desc_check(const nvr_march_desc *m) {
+    MarchParams p;
+    return make_march_params(m, 0, 0, &p);
+}
+
+nvr_status run_march(const nvr_march_desc *m, int64_t n_rays, int64_t begin, int64_t end,
+                     const float *o, const float *d, const uint32_t *occ, int64_t capacity,
+                     int32_t *off, int32_t *ray_id, float *t, float *dt, float *x, int32_t *n_dev,
+                     int32_t *ws, hipStream_t st) {
+    MarchParams p;
+    NVR_TRY(make_march_params(m, begin, end, &p));
+    return launch_march(p, n_rays, o, d, occ, capacity, off, ray_id, t, dt, x, n_dev, ws, st);
+}
+
+}  // namespace nvr

@@ -1,0 +1,660 @@
+// Density + colour networks on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16
+// and v_mfma_f32_16x16x16_bf16), fp32 accumulation.
+//
+// Layout.  A wave works on column blocks of 16 samples.  In "orientation A"
+// a layer computes D = W X (rows = units, columns = samples): lane l holds
+// units 4g..4g+3 (g = l/16) of sample l%16, which is exactly the B-operand
+// layout the next layer needs once two 16-unit tiles are paired per lane (the
+// contraction index of the next layer is permuted to match, and the weight
+// fragments are built with the same permutation), so activations never leave
+// registers.  Swapping the two operands of the same MFMA gives "orientation
+// B", D = X W^T (rows = samples): lane l then holds samples 4g..4g+3 of unit
+// l%16, which is the operand layout of the weight-gradient contraction over
+// samples.  The backward therefore recomputes every layer in both
+// orientations and forms dW = dY X^T with no LDS transposes.
+//
+// Weight fragments (forward W and backward W^T, 38 KiB) are built in LDS once
+// per workgroup from the flat bf16 parameters; the per-wave weight gradients
+// stay in accumulation registers for the whole persistent loop, are summed
+// over the workgroup in LDS and written as one partial per workgroup, which a
+// final launch adds into dparams (no global atomics, deterministic order).
+//
+// Supported shape: n_in <= 32, one density hidden layer of 64, 16 density
+// outputs, 16 + SH <= 32 colour inputs, one or two colour hidden layers of 64.
+#include "common.hpp"
+#include "mlp_dev.hpp"
+#include "sh_dev.hpp"
+
+namespace nvr {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf8;
+typedef __attribute__((ext_vector_type(4))) short s4;
+typedef __attribute__((ext_vector_type(4))) float f4;
+
+constexpr int kMfmaBlock = 256;   // 4 waves
+
+__device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ short bfs(float v) {
+    return __builtin_bit_cast(short, (__bf16)v);
+}
+__device__ __forceinline__ float bf_of_bits(uint16_t b) { return bf16_bits_to_f32(b); }
+__device__ __forceinline__ bf8 pair8(f4 a, f4 b) {
+    bf8 r;
+    r[0] = (__bf16)a[0]; r[1] = (__bf16)a[1]; r[2] = (__bf16)a[2]; r[3] = (__bf16)a[3];
+    r[4] = (__bf16)b[0]; r[5] = (__bf16)b[1]; r[6] = (__bf16)b[2]; r[7] = (__bf16)b[3];
+    return r;
+}
+__device__ __forceinline__ s4 quad(f4 a) {
+    s4 r;
+    r[0] = bfs(a[0]); r[1] = bfs(a[1]); r[2] = bfs(a[2]); r[3] = bfs(a[3]);
+    return r;
+}
+__device__ __forceinline__ f4 relu4(f4 a) {
+    f4 r;
+    for (int i = 0; i < 4; ++i) r[i] = fmaxf(a[i], 0.f);
+    return r;
+}
+__device__ __forceinline__ f4 mask4(f4 g, f4 act) {
+    f4 r;
+    for (int i = 0; i < 4; ++i) r[i] = act[i] > 0.f ? g[i] : 0.f;
+    return r;
+}
+__device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
+
+// contraction index of a 64-wide hidden layer, K-step q, lane group g, slot j
+__device__ __forceinline__ int kh(int q, int g, int j) {
+    return j < 4 ? 32 * q + 4 * g + j : 32 * q + 16 + 4 * g + (j - 4);
+}
+// colour input: o units 0..15 then SH coefficients
+__device__ __forceinline__ int kc(int g, int j) { return j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4); }
+// feature index of slot (g, j) of the encoding operand
+template <bool PLANAR>
+__device__ __forceinline__ int kin(int g, int j) {
+    if (!PLANAR) return 8 * g + j;
+    const int p = 2 * g + (j >> 2), e = j & 3;
+    return 2 * (p + 8 * (e >> 1)) + (e & 1);
+}
+// feature index held by row r (0..15) of dfeat output tile m
+template <bool PLANAR>
+__device__ __forceinline__ int fo(int m, int r) {
+    if (!PLANAR) return 16 * m + r;
+    const int p = 2 * (r >> 2) + m, e = r & 3;
+    return 2 * (p + 8 * (e >> 1)) + (e & 1);
+}
+
+struct Frags {
+    bf8 d1[4][64];
+    bf8 d2[2][64];
+    bf8 c1[4][64];
+    bf8 c2[4][2][64];
+    bf8 c3[2][64];
+    s4 c3t[4][64];
+    bf8 c2t[4][2][64];
+    bf8 c1t[2][64];
+    s4 d2t[4][64];
+    bf8 d1t[2][2][64];
+};
+
+struct MfmaNet {
+    int n_in, nsh, nch;
+    int64_t off_d1, off_d2, off_c1, off_c2, off_c3;
+    int64_t n_params;
+};
+
+// Builds the LDS weight fragments from flat bf16 parameters.
+template <int NCH, bool PLANAR>
+__device__ void build_frags(Frags &F, const MfmaNet &net, const uint16_t *__restrict__ w) {
+    const int cin = 16 + net.nsh;
+    auto W = [&](int64_t off, int row, int col, int ncol) -> float {
+        return bf_of_bits(w[off + (int64_t)row * ncol + col]);
+    };
+    for (int e = threadIdx.x; e < 64 * 4; e += blockDim.x) {
+        const int m = e / 64, l = e % 64, r = l % 16, g = l / 16;
+        bf8 v;
+        for (int j = 0; j < 8; ++j) {
+            const int k = kin<PLANAR>(g, j);
+            v[j] = (__bf16)(k < net.n_in ? W(net.off_d1, 16 * m + r, k, net.n_in) : 0.f);
+        }
+        F.d1[m][l] = v;
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc(g, j);
+            v[j] = (__bf16)(k < cin ? W(net.off_c1, 16 * m + r, k, cin) : 0.f);
+        }
+        F.c1[m][l] = v;
+        s4 t;
+        for (int j = 0; j < 4; ++j)
+            t[j] = bfs(4 * g + j < 3 ? W(net.off_c3, 4 * g + j, 16 * m + r, 64) : 0.f);
+        F.c3t[m][l] = t;
+        for (int j = 0; j < 4; ++j) t[j] = bfs(W(net.off_d2, 4 * g + j, 16 * m + r, 64));
+        F.d2t[m][l] = t;
+        if (NCH == 2) {
+            for (int q = 0; q < 2; ++q) {
+                for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_c2, 16 * m + r, kh(q, g, j), 64);
+                F.c2[m][q][l] = v;
+                for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_c2, kh(q, g, j), 16 * m + r, 64);
+                F.c2t[m][q][l] = v;
+            }
+        }
+    }
+    for (int e = threadIdx.x; e < 64 * 2; e += blockDim.x) {
+        const int q = e / 64, l = e % 64, r = l % 16, g = l / 16;
+        bf8 v;
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_d2, r, kh(q, g, j), 64);
+        F.d2[q][l] = v;
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)(r < 3 ? W(net.off_c3, r, kh(q, g, j), 64) : 0.f);
+        F.c3[q][l] = v;
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_c1, kh(q, g, j), r, cin);
+        F.c1t[q][l] = v;
+        for (int m = 0; m < 2; ++m) {
+            const int f = fo<PLANAR>(m, r);
+            for (int j = 0; j < 8; ++j)
+                v[j] = (__bf16)(f < net.n_in ? W(net.off_d1, kh(q, g, j), f, net.n_in) : 0.f);
+            F.d1t[m][q][l] = v;
+        }
+    }
+}
+
+// Feature access.  Row-major: [cap][n_in] bf16; planar: [8][cap][4] bf16.
+template <bool PLANAR>
+__device__ __forceinline__ bf8 load_feat_a(const uint16_t *__restrict__ feat, int64_t s, int64_t cap,
+                                           int n_in, int g, bool valid) {
+    bf8 v;
+    if (!valid) {
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
+        return v;
+    }
+    if (PLANAR) {
+        const uint2 a = *reinterpret_cast<const uint2 *>(feat + ((int64_t)(2 * g) * cap + s) * 4);
+        const uint2 b = *reinterpret_cast<const uint2 *>(feat + ((int64_t)(2 * g + 1) * cap + s) * 4);
+        const uint32_t u[4] = {a.x, a.y, b.x, b.y};
+        for (int j = 0; j < 8; ++j)
+            v[j] = __builtin_bit_cast(__bf16, (uint16_t)((u[j >> 1] >> (16 * (j & 1))) & 0xffffu));
+        return v;
+    }
+    if (n_in == 32) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(feat + s * 32 + 8 * g);
+        const uint32_t u[4] = {a.x, a.y, a.z, a.w};
+        for (int j = 0; j < 8; ++j)
+            v[j] = __builtin_bit_cast(__bf16, (uint16_t)((u[j >> 1] >> (16 * (j & 1))) & 0xffffu));
+        return v;
+    }
+    for (int j = 0; j < 8; ++j) {
+        const int k = 8 * g + j;
+        v[j] = __builtin_bit_cast(__bf16, k < n_in ? feat[s * n_in + k] : (uint16_t)0);
+    }
+    return v;
+}
+
+template <bool PLANAR>
+__device__ __forceinline__ float load_feat_one(const uint16_t *__restrict__ feat, int64_t s,
+                                               int64_t cap, int n_in, int f) {
+    if (f >= n_in) return 0.f;
+    if (PLANAR) {
+        const int level = f >> 1, plane = level & 7, e = 2 * (level >> 3) + (f & 1);
+        return bf_of_bits(feat[((int64_t)plane * cap + s) * 4 + e]);
+    }
+    return bf_of_bits(feat[s * n_in + f]);
+}
+
+__device__ __forceinline__ float pick16(const float *sh, int k) {
+    float v = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v = (k == i) ? sh[i] : v;
+    return v;
+}
+
+// Orientation-A forward of one column block.
+template <int NCH>
+struct FwdA {
+    f4 hd[4];
+    bf8 hdb[2];
+    f4 o;
+    bf8 cin;
+    f4 h1[4];
+    bf8 h1b[2];
+    f4 h2[4];
+    bf8 h2b[2];
+    f4 z;
+};
+
+template <int NCH>
+__device__ __forceinline__ void forward_a(const Frags &F, int l, int g, bf8 xf, const float *dir,
+                                         int nsh, FwdA<NCH> &a) {
+    for (int m = 0; m < 4; ++m) a.hd[m] = relu4(mfma32(F.d1[m][l], xf, zero4()));
+    a.hdb[0] = pair8(a.hd[0], a.hd[1]);
+    a.hdb[1] = pair8(a.hd[2], a.hd[3]);
+    a.o = mfma32(F.d2[0][l], a.hdb[0], zero4());
+    a.o = mfma32(F.d2[1][l], a.hdb[1], a.o);
+    float sh[16];
+    for (int k = 0; k < 16; ++k) sh[k] = 0.f;
+    sh_eval(dir[0], dir[1], dir[2], nsh == 1 ? 1 : (nsh == 4 ? 2 : (nsh == 9 ? 3 : 4)), sh);
+    f4 s4v;
+    for (int j = 0; j < 4; ++j) {
+        const int k = 4 * g + j;
+        s4v[j] = k < nsh ? pick16(sh, k) : 0.f;
+    }
+    a.cin = pair8(a.o, s4v);
+    for (int m = 0; m < 4; ++m) a.h1[m] = relu4(mfma32(F.c1[m][l], a.cin, zero4()));
+    a.h1b[0] = pair8(a.h1[0], a.h1[1]);
+    a.h1b[1] = pair8(a.h1[2], a.h1[3]);
+    if (NCH == 2) {
+        for (int m = 0; m < 4; ++m) {
+            f4 acc = mfma32(F.c2[m][0][l], a.h1b[0], zero4());
+            a.h2[m] = relu4(mfma32(F.c2[m][1][l], a.h1b[1], acc));
+        }
+        a.h2b[0] = pair8(a.h2[0], a.h2[1]);
+        a.h2b[1] = pair8(a.h2[2], a.h2[3]);
+        a.z = mfma32(F.c3[0][l], a.h2b[0], zero4());
+        a.z = mfma32(F.c3[1][l], a.h2b[1], a.z);
+    } else {
+        a.z = mfma32(F.c3[0][l], a.h1b[0], zero4());
+        a.z = mfma32(F.c3[1][l], a.h1b[1], a.z);
+    }
+}
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.f / (1.f + expf(-x)); }
+__device__ __forceinline__ float clamp_sigma(float o) {
+    return fminf(fmaxf(o, -kSigmaClamp), kSigmaClamp);
+}
+
+template <int NCH, bool PLANAR>
+__global__ void __launch_bounds__(kMfmaBlock)
+mlp_fwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+             const uint16_t *__restrict__ feat, const float *__restrict__ dirs,
+             const int32_t *__restrict__ ray_id, const uint16_t *__restrict__ params,
+             float *__restrict__ sigma, float *__restrict__ rgb) {
+    __shared__ Frags F;
+    build_frags<NCH, PLANAR>(F, net, params);
+    __syncthreads();
+    const int64_t count = count_of(n, n_dev, cap);
+    const int l = threadIdx.x % 64, g = l / 16, c = l % 16;
+    const int64_t wave = blockIdx.x * (int64_t)(kMfmaBlock / 64) + threadIdx.x / 64;
+    const int64_t nwaves = (int64_t)gridDim.x * (kMfmaBlock / 64);
+    for (int64_t cb = wave; cb * 16 < count; cb += nwaves) {
+        const int64_t s = cb * 16 + c;
+        const bool valid = s < count;
+        const bf8 xf = load_feat_a<PLANAR>(feat, s, cap, net.n_in, g, valid);
+        float dir[3] = {0.f, 0.f, 1.f};
+        if (valid) {
+            const int64_t r = ray_id ? ray_id[s] : s;
+            dir[0] = dirs[3 * r];
+            dir[1] = dirs[3 * r + 1];
+            dir[2] = dirs[3 * r + 2];
+        }
+        FwdA<NCH> a;
+        forward_a<NCH>(F, l, g, xf, dir, net.nsh, a);
+        if (valid && g == 0) {
+            sigma[s] = expf(clamp_sigma(a.o[0]));
+            rgb[3 * s] = sigmoidf_(a.z[0]);
+            rgb[3 * s + 1] = sigmoidf_(a.z[1]);
+            rgb[3 * s + 2] = sigmoidf_(a.z[2]);
+        }
+    }
+}
+
+// Weight-gradient accumulators (orientation D[o][i]: lane holds i = l%16,
+// o = 4g..4g+3 of each 16 x 16 tile).
+template <int NCH>
+struct DW {
+    f4 d1[4][2];
+    f4 d2[4];
+    f4 c1[4][2];
+    f4 c2[4][4];
+    f4 c3[4];
+};
+
+template <int NCH, bool PLANAR>
+__global__ void __launch_bounds__(kMfmaBlock)
+mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+             const uint16_t *__restrict__ feat, const float *__restrict__ dirs,
+             const int32_t *__restrict__ ray_id, const uint16_t *__restrict__ params,
+             const float *__restrict__ dsigma, const float *__restrict__ drgb,
+             float *__restrict__ dfeat, float *__restrict__ partial) {
+    __shared__ Frags F;
+    build_frags<NCH, PLANAR>(F, net, params);
+    __syncthreads();
+    const int64_t count = count_of(n, n_dev, cap);
+    const int l = threadIdx.x % 64, g = l / 16, c = l % 16;
+    const int64_t wave = blockIdx.x * (int64_t)(kMfmaBlock / 64) + threadIdx.x / 64;
+    const int64_t nwaves = (int64_t)gridDim.x * (kMfmaBlock / 64);
+    DW<NCH> acc;
+    for (int a = 0; a < 4; ++a) {
+        acc.d2[a] = zero4();
+        acc.c3[a] = zero4();
+        for (int b = 0; b < 2; ++b) {
+            acc.d1[a][b] = zero4();
+            acc.c1[a][b] = zero4();
+        }
+        for (int b = 0; b < 4; ++b) acc.c2[a][b] = zero4();
+    }
+    const int nsh = net.nsh;
+    const int deg = nsh == 1 ? 1 : (nsh == 4 ? 2 : (nsh == 9 ? 3 : 4));
+    for (int64_t cb = wave; cb * 16 < count; cb += nwaves) {
+        const int64_t base = cb * 16;
+        const int64_t s = base + c;
+        const bool valid = s < count;
+        // ------------------------------------------------ orientation A forward
+        const bf8 xf = load_feat_a<PLANAR>(feat, s, cap, net.n_in, g, valid);
+        float dir[3] = {0.f, 0.f, 1.f};
+        float ds = 0.f, dr[3] = {0.f, 0.f, 0.f};
+        if (valid) {
+            const int64_t r = ray_id ? ray_id[s] : s;
+            dir[0] = dirs[3 * r];
+            dir[1] = dirs[3 * r + 1];
+            dir[2] = dirs[3 * r + 2];
+            ds = dsigma[s];
+            dr[0] = drgb[3 * s];
+            dr[1] = drgb[3 * s + 1];
+            dr[2] = drgb[3 * s + 2];
+        }
+        FwdA<NCH> a;
+        forward_a<NCH>(F, l, g, xf, dir, nsh, a);
+        // ------------------------------------------------ orientation A backward
+        f4 dz = zero4();
+        if (g == 0) {
+            for (int i = 0; i < 3; ++i) {
+                const float v = sigmoidf_(a.z[i]);
+                dz[i] = dr[i] * v * (1.f - v);
+            }
+        }
+        const s4 dzq = quad(dz);
+        f4 dh2[4], dh1[4];
+        bf8 dh2b[2], dh1b[2];
+        if (NCH == 2) {
+            for (int m = 0; m < 4; ++m) dh2[m] = mask4(mfma16(F.c3t[m][l], dzq, zero4()), a.h2[m]);
+            dh2b[0] = pair8(dh2[0], dh2[1]);
+            dh2b[1] = pair8(dh2[2], dh2[3]);
+            for (int m = 0; m < 4; ++m) {
+                f4 t = mfma32(F.c2t[m][0][l], dh2b[0], zero4());
+                dh1[m] = mask4(mfma32(F.c2t[m][1][l], dh2b[1], t), a.h1[m]);
+            }
+        } else {
+            for (int m = 0; m < 4; ++m) dh1[m] = mask4(mfma16(F.c3t[m][l], dzq, zero4()), a.h1[m]);
+        }
+        dh1b[0] = pair8(dh1[0], dh1[1]);
+        dh1b[1] = pair8(dh1[2], dh1[3]);
+        f4 dO = mfma32(F.c1t[0][l], dh1b[0], zero4());
+        dO = mfma32(F.c1t[1][l], dh1b[1], dO);
+        if (g == 0 && fabsf(a.o[0]) < kSigmaClamp) dO[0] += ds * expf(a.o[0]);
+        const s4 dOq = quad(dO);
+        f4 dhd[4];
+        for (int m = 0; m < 4; ++m) dhd[m] = mask4(mfma16(F.d2t[m][l], dOq, zero4()), a.hd[m]);
+        const bf8 dhdb0 = pair8(dhd[0], dhd[1]), dhdb1 = pair8(dhd[2], dhd[3]);
+        if (dfeat != nullptr) {
+            for (int m = 0; m < 2; ++m) {
+                f4 df = mfma32(F.d1t[m][0][l], dhdb0, zero4());
+                df = mfma32(F.d1t[m][1][l], dhdb1, df);
+                if (valid) {
+                    if (PLANAR) {
+                        *reinterpret_cast<f4 *>(dfeat + ((int64_t)(2 * g + m) * cap + s) * 4) = df;
+                    } else if (net.n_in == 32) {
+                        *reinterpret_cast<f4 *>(dfeat + s * 32 + 16 * m + 4 * g) = df;
+                    } else {
+                        for (int i = 0; i < 4; ++i) {
+                            const int f = 16 * m + 4 * g + i;
+                            if (f < net.n_in) dfeat[s * net.n_in + f] = df[i];
+                        }
+                    }
+                }
+            }
+        }
+        // ------------------------------------------------ orientation B (transposed) copies
+        // samples of this lane in the B layout: base + 4g + i
+        f4 x0b[2];
+        for (int t = 0; t < 2; ++t)
+            for (int i = 0; i < 4; ++i) {
+                const int64_t si = base + 4 * g + i;
+                x0b[t][i] = si < count ? load_feat_one<PLANAR>(feat, si, cap, net.n_in, 16 * t + c) : 0.f;
+            }
+        f4 hdB[4];
+        for (int t = 0; t < 4; ++t) hdB[t] = relu4(mfma32(xf, F.d1[t][l], zero4()));
+        f4 oB = mfma32(a.hdb[0], F.d2[0][l], zero4());
+        oB = mfma32(a.hdb[1], F.d2[1][l], oB);
+        f4 shB;
+        f4 dsB = zero4();
+        f4 drB = zero4();
+        for (int i = 0; i < 4; ++i) {
+            const int64_t si = base + 4 * g + i;
+            shB[i] = 0.f;
+            if (si < count) {
+                const int64_t r = ray_id ? ray_id[si] : si;
+                float sh[16];
+                for (int k = 0; k < 16; ++k) sh[k] = 0.f;
+                sh_eval(dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2], deg, sh);
+                shB[i] = c < nsh ? pick16(sh, c) : 0.f;
+                if (c == 0) dsB[i] = dsigma[si];
+                if (c < 3) drB[i] = drgb[3 * si + c];
+            }
+        }
+        f4 h1B[4];
+        {
+            const bf8 cin = a.cin;
+            for (int t = 0; t < 4; ++t) h1B[t] = relu4(mfma32(cin, F.c1[t][l], zero4()));
+        }
+        f4 h2B[4];
+        f4 zB;
+        if (NCH == 2) {
+            for (int t = 0; t < 4; ++t) {
+                f4 u = mfma32(a.h1b[0], F.c2[t][0][l], zero4());
+                h2B[t] = relu4(mfma32(a.h1b[1], F.c2[t][1][l], u));
+            }
+            zB = mfma32(a.h2b[0], F.c3[0][l], zero4());
+            zB = mfma32(a.h2b[1], F.c3[1][l], zB);
+        } else {
+            zB = mfma32(a.h1b[0], F.c3[0][l], zero4());
+            zB = mfma32(a.h1b[1], F.c3[1][l], zB);
+        }
+        // ------------------------------------------------ orientation B backward
+        f4 dzB = zero4();
+        if (c < 3)
+            for (int i = 0; i < 4; ++i) {
+                const float v = sigmoidf_(zB[i]);
+                dzB[i] = drB[i] * v * (1.f - v);
+            }
+        f4 dh2B[4], dh1B[4];
+        if (NCH == 2) {
+            for (int t = 0; t < 4; ++t) dh2B[t] = mask4(mfma16(dzq, F.c3t[t][l], zero4()), h2B[t]);
+            for (int t = 0; t < 4; ++t) {
+                f4 u = mfma32(dh2b[0], F.c2t[t][0][l], zero4());
+                dh1B[t] = mask4(mfma32(dh2b[1], F.c2t[t][1][l], u), h1B[t]);
+            }
+        } else {
+            for (int t = 0; t < 4; ++t) dh1B[t] = mask4(mfma16(dzq, F.c3t[t][l], zero4()), h1B[t]);
+        }
+        f4 dOB = mfma32(dh1b[0], F.c1t[0][l], zero4());
+        dOB = mfma32(dh1b[1], F.c1t[1][l], dOB);
+        if (c == 0)
+            for (int i = 0; i < 4; ++i)
+                if (fabsf(oB[i]) < kSigmaClamp) dOB[i] += dsB[i] * expf(oB[i]);
+        f4 dhdB[4];
+        for (int t = 0; t < 4; ++t) dhdB[t] = mask4(mfma16(dOq, F.d2t[t][l], zero4()), hdB[t]);
+        // ------------------------------------------------ weight gradients (K = 16 samples)
+        const s4 x0q[2] = {quad(x0b[0]), quad(x0b[1])};
+        for (int mo = 0; mo < 4; ++mo) {
+            const s4 gq = quad(dhdB[mo]);
+            for (int ti = 0; ti < 2; ++ti) acc.d1[mo][ti] = mfma16(gq, x0q[ti], acc.d1[mo][ti]);
+        }
+        {
+            const s4 gq = quad(dOB);
+            for (int ti = 0; ti < 4; ++ti) acc.d2[ti] = mfma16(gq, quad(hdB[ti]), acc.d2[ti]);
+        }
+        {
+            const s4 cq[2] = {quad(oB), quad(shB)};
+            for (int mo = 0; mo < 4; ++mo) {
+                const s4 gq = quad(dh1B[mo]);
+                for (int ti = 0; ti < 2; ++ti) acc.c1[mo][ti] = mfma16(gq, cq[ti], acc.c1[mo][ti]);
+            }
+        }
+        if (NCH == 2) {
+            s4 hq[4];
+            for (int ti = 0; ti < 4; ++ti) hq[ti] = quad(h1B[ti]);
+            for (int mo = 0; mo < 4; ++mo) {
+                const s4 gq = quad(dh2B[mo]);
+                for (int ti = 0; ti < 4; ++ti) acc.c2[mo][ti] = mfma16(gq, hq[ti], acc.c2[mo][ti]);
+            }
+        }
+        {
+            const s4 gq = quad(dzB);
+            for (int ti = 0; ti < 4; ++ti)
+                acc.c3[ti] = mfma16(gq, quad(NCH == 2 ? h2B[ti] : h1B[ti]), acc.c3[ti]);
+        }
+    }
+    // ---------------------------------------------------- workgroup reduction
+    __syncthreads();                       // fragments no longer needed
+    float *red = reinterpret_cast<float *>(&F);
+    const int np = (int)net.n_params;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) red[i] = 0.f;
+    __syncthreads();
+    const int cin = 16 + nsh;
+    auto put = [&](int64_t off, int ncol, int nrow, int mo, int ti, f4 v) {
+        const int col = 16 * ti + c;
+        if (col >= ncol) return;
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * mo + 4 * g + r;
+            if (row < nrow) atomicAdd(red + (off - net.off_d1) + row * ncol + col, v[r]);
+        }
+    };
+    for (int mo = 0; mo < 4; ++mo)
+        for (int ti = 0; ti < 2; ++ti) {
+            put(net.off_d1, net.n_in, 64, mo, ti, acc.d1[mo][ti]);
+            put(net.off_c1, cin, 64, mo, ti, acc.c1[mo][ti]);
+        }
+    for (int ti = 0; ti < 4; ++ti) {
+        put(net.off_d2, 64, 16, 0, ti, acc.d2[ti]);
+        put(net.off_c3, 64, 3, 0, ti, acc.c3[ti]);
+    }
+    if (NCH == 2)
+        for (int mo = 0; mo < 4; ++mo)
+            for (int ti = 0; ti < 4; ++ti) put(net.off_c2, 64, 64, mo, ti, acc.c2[mo][ti]);
+    __syncthreads();
+    float *dst = partial + (int64_t)blockIdx.x * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = red[i];
+}
+
+__global__ void reduce_partials(int nblocks, int np, const float *__restrict__ partial,
+                                float *__restrict__ dparams) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int b = 0; b < nblocks; ++b) acc += partial[(int64_t)b * np + i];
+        dparams[i] += acc;
+    }
+}
+
+nvr_status make_mfma_net(const Net &net, MfmaNet *m) {
+    NVR_REQUIRE(net.n_density == 2 && net.out[0] == 64, NVR_EUNSUPPORTED,
+                "bf16 MFMA networks need one density hidden layer of width 64");
+    NVR_REQUIRE(net.n_in <= 32, NVR_EUNSUPPORTED, "bf16 MFMA networks need n_in <= 32");
+    NVR_REQUIRE(net.dout == 16, NVR_EUNSUPPORTED, "bf16 MFMA networks need 16 density outputs");
+    NVR_REQUIRE(16 + net.n_sh <= 32, NVR_EUNSUPPORTED, "bf16 MFMA networks need 16 + SH <= 32");
+    const int nch = net.n_layers - net.n_density - 1;
+    NVR_REQUIRE(nch == 1 || nch == 2, NVR_EUNSUPPORTED, "bf16 MFMA networks need 1 or 2 colour hidden layers");
+    for (int k = net.n_density; k < net.n_layers - 1; ++k)
+        NVR_REQUIRE(net.out[k] == 64, NVR_EUNSUPPORTED, "bf16 MFMA colour hidden width must be 64");
+    m->n_in = net.n_in;
+    m->nsh = net.n_sh;
+    m->nch = nch;
+    m->off_d1 = net.woff[0];
+    m->off_d2 = net.woff[1];
+    m->off_c1 = net.woff[2];
+    m->off_c2 = nch == 2 ? net.woff[3] : 0;
+    m->off_c3 = net.woff[2 + nch];
+    m->n_params = net.woff[net.n_layers];
+    NVR_REQUIRE(m->n_params * 4 <= (int64_t)sizeof(Frags), NVR_EUNSUPPORTED, "too many parameters");
+    return NVR_OK;
+}
+
+unsigned mfma_blocks(int64_t cap) {
+    const int64_t cbs = (cap + 15) / 16;
+    int64_t b = (cbs + 3) / 4;
+    if (b > 512) b = 512;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+size_t mfma_workspace(const MfmaNet &m, int64_t cap) {
+    return sizeof(float) * (size_t)mfma_blocks(cap) * (size_t)m.n_params;
+}
+
+nvr_status mfma_forward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64_t cap,
+                        const uint16_t *feat, bool planar, const float *dirs,
+                        const int32_t *ray_id, const uint16_t *params, float *sigma, float *rgb,
+                        hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    const unsigned gr = mfma_blocks(cap);
+#define NVR_FWD(NCH, PL)                                                                       \
+    mlp_fwd_mfma<NCH, PL><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id,     \
+                                                     params, sigma, rgb)
+    if (m.nch == 2) {
+        if (planar) NVR_FWD(2, true); else NVR_FWD(2, false);
+    } else {
+        if (planar) NVR_FWD(1, true); else NVR_FWD(1, false);
+    }
+#undef NVR_FWD
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
+nvr_status mfma_backward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64_t cap,
+                         const uint16_t *feat, bool planar, const float *dirs,
+                         const int32_t *ray_id, const uint16_t *params, const float *dsigma,
+                         const float *drgb, float *dparams, float *dfeat, float *partial,
+                         hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    const unsigned gr = mfma_blocks(cap);
+#define NVR_BWD(NCH, PL)                                                                       \
+    mlp_bwd_mfma<NCH, PL><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id,     \
+                                                     params, dsigma, drgb, dfeat, partial)
+    if (m.nch == 2) {
+        if (planar) NVR_BWD(2, true); else NVR_BWD(2, false);
+    } else {
+        if (planar) NVR_BWD(1, true); else NVR_BWD(1, false);
+    }
+#undef NVR_BWD
+    NVR_LAUNCHED();
+    reduce_partials<<<grid_for(m.n_params, 256, 64), 256, 0, st>>>((int)gr, (int)m.n_params, partial,
+                                                                   dparams);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
+}  // namespace nvr
+
+#include "launch.hpp"
+
+namespace nvr {
+
+nvr_status mfma_check(const Net &net) {
+    MfmaNet m;
+    return make_mfma_net(net, &m);
+}
+
+size_t mfma_ws_bytes(const Net &net, int64_t cap) {
+    MfmaNet m;
+    if (make_mfma_net(net, &m) != NVR_OK) return 0;
+    return mfma_workspace(m, cap);
+}
+
+nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
+                    const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
+                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st) {
+    MfmaNet m;
+    NVR_TRY(make_mfma_net(net, &m));
+    return mfma_forward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, sigma, rgb, st);
+}
+
+nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
+                    const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
+                    const uint16_t *params, const float *dsigma, const float *drgb, float *dparams,
+                    float *dfeat, void *ws, hipStream_t st) {
+    MfmaNet m;
+    NVR_TRY(make_mfma_net(net, &m));
+    return mfma_backward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, dsigma, drgb,
+                         dparams, dfeat, (float *)ws, st);
+}
+
+}  // namespace nvr

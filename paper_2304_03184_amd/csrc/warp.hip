@@ -1,0 +1,395 @@
+// Hybrid warp of live samples into the canonical space and its backward.
+//
+// Per sample (one thread): inverse skinning over the k nearest joints, then
+// the inverse dual-quaternion blend over the nodes listed for the sample's
+// live voxel (the O(1) look-up of the paper's fast search), then the rigid
+// transform of the blend.  The joint table lives in LDS; node motions and
+// positions are read through the caches (1024 nodes x 44 B).
+//
+// Backward recomputes the forward and accumulates node-motion gradients in
+// an LDS copy of the gradient table (when it fits in 64 KiB), flushed once
+// per workgroup with global atomics; otherwise it uses global atomics.
+//
+// Float32 decisions (no fused multiply-add, one rounding per operation): the
+// look-up voxel, the squared joint distances that choose the joints, and the
+// sign of <q_r,i, q_r,first>.
+#include "common.hpp"
+
+namespace nvr {
+
+constexpr int kMaxJoints = 64;
+constexpr int kMaxKJ = 8;
+constexpr int kMaxKN = 16;
+constexpr int kWarpBlock = 256;
+
+struct WarpParams {
+    int n_joints, k_joints, n_nodes, k_nodes, n_frames, lut_res;
+    float inv_two_sigma2;      // 1 / (2 sigma_skin^2)
+    float inv_r2;              // 1 / r^2
+    float lut_lo[3], lut_scale[3];
+};
+
+struct Q4 { float w, x, y, z; };
+
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 add3(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 mul3(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
+
+// v rotated by unit quaternion (w, u): v + 2w (u x v) + 2 u x (u x v)
+__device__ __forceinline__ float3 qrot(float w, float3 u, float3 v) {
+    const float3 uv = cross3(u, v);
+    return add3(add3(v, mul3(2.f * w, uv)), mul3(2.f, cross3(u, uv)));
+}
+
+struct WarpFwd {
+    int jsel[kMaxKJ];
+    float lw[kMaxKJ];
+    int nid[kMaxKN];
+    float w[kMaxKN];
+    float s[kMaxKN];
+    float3 y;
+    float c[8];
+    float nr;
+    int frame;
+    float3 z;
+};
+
+// Forward of one sample; `J` is the joint table (LDS).
+__device__ __forceinline__ void warp_one(const WarpParams &p, const float *__restrict__ J,
+                                         const nvr_warp_rig &rig, float3 x, int frame,
+                                         WarpFwd &f) {
+    f.frame = frame;
+    // --- choose the k nearest joints by float32 squared distance (ties: lower index)
+    float bd[kMaxKJ];
+    for (int k = 0; k < p.k_joints; ++k) {
+        bd[k] = INFINITY;
+        f.jsel[k] = 0x7fffffff;
+    }
+    for (int j = 0; j < p.n_joints; ++j) {
+        const float dx = __fsub_rn(x.x, J[3 * j]);
+        const float dy = __fsub_rn(x.y, J[3 * j + 1]);
+        const float dz = __fsub_rn(x.z, J[3 * j + 2]);
+        const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+        if (d2 < bd[p.k_joints - 1]) {
+            int k = p.k_joints - 1;
+            while (k > 0 && d2 < bd[k - 1]) {
+                bd[k] = bd[k - 1];
+                f.jsel[k] = f.jsel[k - 1];
+                --k;
+            }
+            bd[k] = d2;
+            f.jsel[k] = j;
+        }
+    }
+    // --- skinning weights and y = sum_j w_j (R_j x + t_j)
+    float wsum = 0.f;
+    for (int k = 0; k < p.k_joints; ++k) {
+        f.lw[k] = expf(-(bd[k] - bd[0]) * p.inv_two_sigma2);
+        wsum += f.lw[k];
+    }
+    const float iw = 1.f / wsum;
+    float3 y = make_float3(0.f, 0.f, 0.f);
+    const float *B = rig.bones + (size_t)frame * p.n_joints * 12;
+    for (int k = 0; k < p.k_joints; ++k) {
+        f.lw[k] *= iw;
+        const float *M = B + 12 * f.jsel[k];
+        const float3 yj = make_float3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3],
+                                      M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
+                                      M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
+        y = add3(y, mul3(f.lw[k], yj));
+    }
+    f.y = y;
+    // --- node set of the live voxel
+    int v[3];
+    const float xs[3] = {x.x, x.y, x.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = __fmul_rn(__fsub_rn(xs[a], p.lut_lo[a]), p.lut_scale[a]);
+        int c = (int)floorf(u);
+        v[a] = c < 0 ? 0 : (c > p.lut_res - 1 ? p.lut_res - 1 : c);
+    }
+    const size_t vox = (size_t)v[0] + (size_t)p.lut_res * ((size_t)v[1] + (size_t)p.lut_res * v[2]);
+    const uint16_t *ids = rig.lut + ((size_t)frame * p.lut_res * p.lut_res * p.lut_res + vox) * p.k_nodes;
+    const float *DQ = rig.node_dq + (size_t)frame * p.n_nodes * 8;
+    const float *G = rig.node_pos + (size_t)frame * p.n_nodes * 3;
+    float e2[kMaxKN];
+    float e2min = INFINITY;
+    for (int k = 0; k < p.k_nodes; ++k) {
+        int id = ids[k];
+        id = id < p.n_nodes ? id : p.n_nodes - 1;   // ids are documented to be < n_nodes
+        f.nid[k] = id;
+        const float3 g = make_float3(G[3 * id], G[3 * id + 1], G[3 * id + 2]);
+        const float3 dd = sub3(y, g);
+        e2[k] = dot3(dd, dd);
+        e2min = fminf(e2min, e2[k]);
+    }
+    const float *q0 = DQ + 8 * f.nid[0];
+    float b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < p.k_nodes; ++k) {
+        const float *q = DQ + 8 * f.nid[k];
+        float qq[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) qq[c] = q[c];
+        const float dot = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(qq[0], q0[0]), __fmul_rn(qq[1], q0[1])),
+                                              __fmul_rn(qq[2], q0[2])),
+                                    __fmul_rn(qq[3], q0[3]));
+        f.s[k] = dot >= 0.f ? 1.f : -1.f;
+        f.w[k] = expf(-(e2[k] - e2min) * p.inv_r2);
+        const float sw = f.s[k] * f.w[k];
+        // conjugate of both parts: (w, -x, -y, -z)
+        b[0] += sw * qq[0];
+        b[1] -= sw * qq[1];
+        b[2] -= sw * qq[2];
+        b[3] -= sw * qq[3];
+        b[4] += sw * qq[4];
+        b[5] -= sw * qq[5];
+        b[6] -= sw * qq[6];
+        b[7] -= sw * qq[7];
+    }
+    const float nr = sqrtf(b[0] * b[0] + b[1] * b[1] + b[2] * b[2] + b[3] * b[3]);
+    f.nr = nr;
+    const float inr = 1.f / nr;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) f.c[c] = b[c] * inr;
+    const float3 vr = make_float3(f.c[1], f.c[2], f.c[3]);
+    const float3 vd = make_float3(f.c[5], f.c[6], f.c[7]);
+    const float wr = f.c[0], wd = f.c[4];
+    // translation 2 vec(c_d conj(c_r)) = 2 (w_r v_d - w_d v_r + v_r x v_d)
+    const float3 tr = mul3(2.f, add3(sub3(mul3(wr, vd), mul3(wd, vr)), cross3(vr, vd)));
+    f.z = add3(qrot(wr, vr, y), tr);
+}
+
+__global__ void __launch_bounds__(kWarpBlock)
+warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__restrict__ n_dev,
+                int64_t cap, const float *__restrict__ x, const int32_t *__restrict__ frame,
+                float *__restrict__ xc) {
+    __shared__ float J[3 * kMaxJoints];
+    for (int i = threadIdx.x; i < 3 * p.n_joints; i += blockDim.x) J[i] = rig.joints[i];
+    __syncthreads();
+    const int64_t count = count_of(n, n_dev, cap);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        WarpFwd f;
+        const int fr = frame ? frame[i] : 0;
+        warp_one(p, J, rig, make_float3(x[3 * i], x[3 * i + 1], x[3 * i + 2]), fr, f);
+        xc[3 * i] = f.z.x;
+        xc[3 * i + 1] = f.z.y;
+        xc[3 * i + 2] = f.z.z;
+    }
+}
+
+template <bool LDS_ACC>
+__global__ void __launch_bounds__(kWarpBlock)
+warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__restrict__ n_dev,
+                int64_t cap, const float *__restrict__ x, const int32_t *__restrict__ frame,
+                const float *__restrict__ gz_parts, int n_parts, int64_t part_stride,
+                float *__restrict__ d_dq, float *__restrict__ d_bones) {
+    extern __shared__ float lds[];
+    float *J = lds;                                   // [3 * n_joints]
+    float *acc = lds + 3 * kMaxJoints;                // [n_frames * n_nodes * 8] if LDS_ACC
+    for (int i = threadIdx.x; i < 3 * p.n_joints; i += blockDim.x) J[i] = rig.joints[i];
+    const int n_acc = p.n_frames * p.n_nodes * 8;
+    if (LDS_ACC)
+        for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0.f;
+    __syncthreads();
+    const int64_t count = count_of(n, n_dev, cap);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float3 gz = make_float3(0.f, 0.f, 0.f);
+        for (int q = 0; q < n_parts; ++q) {
+            const float *g = gz_parts + (size_t)q * part_stride + 3 * i;
+            gz = add3(gz, make_float3(g[0], g[1], g[2]));
+        }
+        if (gz.x == 0.f && gz.y == 0.f && gz.z == 0.f) continue;
+        WarpFwd f;
+        const int fr = frame ? frame[i] : 0;
+        const float3 xv = make_float3(x[3 * i], x[3 * i + 1], x[3 * i + 2]);
+        warp_one(p, J, rig, xv, fr, f);
+        const float3 y = f.y;
+        const float wr = f.c[0], wd = f.c[4];
+        const float3 vr = make_float3(f.c[1], f.c[2], f.c[3]);
+        const float3 vd = make_float3(f.c[5], f.c[6], f.c[7]);
+        // d z / d c (rotation + translation terms) and d z / d y = R(c_r)
+        const float3 vxy = cross3(vr, y);
+        float gc[8];
+        const float gw_rot = 2.f * dot3(gz, vxy);
+        const float3 gv_rot = add3(mul3(2.f * wr, cross3(y, gz)),
+                                   mul3(2.f, sub3(add3(mul3(dot3(gz, vr), y), mul3(dot3(vr, y), gz)),
+                                                  mul3(2.f * dot3(gz, y), vr))));
+        gc[0] = gw_rot + 2.f * dot3(gz, vd);
+        const float3 gvr = add3(gv_rot, mul3(2.f, add3(mul3(-wd, gz), cross3(vd, gz))));
+        gc[1] = gvr.x;
+        gc[2] = gvr.y;
+        gc[3] = gvr.z;
+        gc[4] = -2.f * dot3(gz, vr);
+        const float3 gvd = mul3(2.f, add3(mul3(wr, gz), cross3(gz, vr)));
+        gc[5] = gvd.x;
+        gc[6] = gvd.y;
+        gc[7] = gvd.z;
+        // R(c_r)^T gz = rotation by the conjugate
+        float3 gy = qrot(wr, make_float3(-vr.x, -vr.y, -vr.z), gz);
+        // normalisation c = b / |b_r|
+        float dotc = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) dotc += f.c[c] * gc[c];
+        const float inr = 1.f / f.nr;
+        float gb[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) gb[c] = gc[c] * inr;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gb[c] -= f.c[c] * dotc * inr;
+        const float cs[8] = {1.f, -1.f, -1.f, -1.f, 1.f, -1.f, -1.f, -1.f};
+        const float *DQ = rig.node_dq + (size_t)fr * p.n_nodes * 8;
+        const float *G = rig.node_pos + (size_t)fr * p.n_nodes * 3;
+        for (int k = 0; k < p.k_nodes; ++k) {
+            const int id = f.nid[k];
+            const float sw = f.s[k] * f.w[k];
+            const float *q = DQ + 8 * id;
+            float gwk = 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float v = sw * cs[c] * gb[c];
+                const size_t a = ((size_t)fr * p.n_nodes + id) * 8 + c;
+                if (LDS_ACC) atomicAdd(acc + a, v);
+                else unsafeAtomicAdd(d_dq + a, v);
+                gwk += cs[c] * q[c] * gb[c];
+            }
+            // weight w_k depends on y: dw/dy = w (-2 (y - g) / r^2)
+            const float3 g = make_float3(G[3 * id], G[3 * id + 1], G[3 * id + 2]);
+            gy = add3(gy, mul3(f.s[k] * gwk * f.w[k] * (-2.f * p.inv_r2), sub3(y, g)));
+        }
+        if (d_bones != nullptr) {
+            for (int k = 0; k < p.k_joints; ++k) {
+                float *dB = d_bones + ((size_t)fr * p.n_joints + f.jsel[k]) * 12;
+                const float lw = f.lw[k];
+                const float gys[3] = {gy.x, gy.y, gy.z};
+                const float xh[4] = {xv.x, xv.y, xv.z, 1.f};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < 4; ++bb) unsafeAtomicAdd(dB + 4 * a + bb, lw * gys[a] * xh[bb]);
+            }
+        }
+    }
+    if (LDS_ACC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < n_acc; i += blockDim.x) {
+            const float v = acc[i];
+            if (v != 0.f) unsafeAtomicAdd(d_dq + i, v);
+        }
+    }
+}
+
+nvr_status make_warp_params(const nvr_warp_desc *w, const nvr_warp_rig *rig, WarpParams *p) {
+    NVR_REQUIRE(w && rig, NVR_EINVAL, "NULL warp descriptor or rig");
+    NVR_REQUIRE(w->n_joints >= 1 && w->n_joints <= kMaxJoints, NVR_EINVAL, "n_joints out of 1..64");
+    NVR_REQUIRE(w->k_joints >= 1 && w->k_joints <= kMaxKJ && w->k_joints <= w->n_joints, NVR_EINVAL,
+                "k_joints out of range");
+    NVR_REQUIRE(w->n_nodes >= 1 && w->n_nodes <= 65536, NVR_EINVAL, "n_nodes out of 1..65536");
+    NVR_REQUIRE(w->k_nodes >= 1 && w->k_nodes <= kMaxKN && w->k_nodes <= w->n_nodes, NVR_EINVAL,
+                "k_nodes out of range");
+    NVR_REQUIRE(w->n_frames >= 1, NVR_EINVAL, "n_frames < 1");
+    NVR_REQUIRE(w->sigma_skin > 0.f && w->r_node > 0.f, NVR_EINVAL, "non-positive widths");
+    NVR_REQUIRE(w->lut_res >= 1 && w->lut_res <= 1024, NVR_EINVAL, "lut_res out of 1..1024");
+    NVR_REQUIRE(rig->joints && rig->bones && rig->node_dq && rig->node_pos && rig->lut, NVR_EINVAL,
+                "NULL rig array");
+    p->n_joints = w->n_joints;
+    p->k_joints = w->k_joints;
+    p->n_nodes = w->n_nodes;
+    p->k_nodes = w->k_nodes;
+    p->n_frames = w->n_frames;
+    p->lut_res = w->lut_res;
+    p->inv_two_sigma2 = (float)(1.0 / (2.0 * (double)w->sigma_skin * (double)w->sigma_skin));
+    p->inv_r2 = (float)(1.0 / ((double)w->r_node * (double)w->r_node));
+    for (int a = 0; a < 3; ++a) {
+        NVR_REQUIRE(w->lut_max[a] > w->lut_min[a], NVR_EINVAL, "empty look-up box");
+        p->lut_lo[a] = w->lut_min[a];
+        p->lut_scale[a] = (float)((double)w->lut_res / ((double)w->lut_max[a] - (double)w->lut_min[a]));
+    }
+    return NVR_OK;
+}
+
+nvr_status launch_warp_fwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t n,
+                           const int32_t *n_dev, int64_t cap, const float *x, const int32_t *frame,
+                           float *xc, hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    warp_fwd_kernel<<<grid_for(cap, kWarpBlock, 2048), kWarpBlock, 0, st>>>(p, rig, n, n_dev, cap, x,
+                                                                             frame, xc);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
+nvr_status launch_warp_bwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t n,
+                           const int32_t *n_dev, int64_t cap, const float *x, const int32_t *frame,
+                           const float *gz, int n_parts, int64_t part_stride, float *d_dq,
+                           float *d_bones, hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    const size_t acc_bytes = sizeof(float) * (size_t)p.n_frames * p.n_nodes * 8;
+    const size_t base = sizeof(float) * 3 * kMaxJoints;
+    if (acc_bytes <= 64 * 1024) {
+        warp_bwd_kernel<true><<<grid_for(cap, kWarpBlock, 512), kWarpBlock, base + acc_bytes, st>>>(
+            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones);
+    } else {
+        warp_bwd_kernel<false><<<grid_for(cap, kWarpBlock, 2048), kWarpBlock, base, st>>>(
+            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones);
+    }
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
+}  // namespace nvr
+
+using namespace nvr;
+
+extern "C" nvr_status nvr_warp_fwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t n,
+                                   const int32_t *n_dev, const float *x_live, const int32_t *frame,
+                                   float *x_can, nvr_stream stream) {
+    clear_error();
+    WarpParams p;
+    NVR_TRY(make_warp_params(w, rig, &p));
+    NVR_REQUIRE(n >= 0, NVR_EINVAL, "n < 0");
+    if (n == 0) return NVR_OK;
+    NVR_REQUIRE(x_live && x_can, NVR_EINVAL, "NULL array");
+    return launch_warp_fwd(p, *rig, n, n_dev, n, x_live, frame, x_can, hs(stream));
+}
+
+extern "C" nvr_status nvr_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t n,
+                                   const int32_t *n_dev, const float *x_live, const int32_t *frame,
+                                   const float *dx_can, int32_t n_parts, float *d_node_dq,
+                                   float *d_bones, nvr_stream stream) {
+    clear_error();
+    WarpParams p;
+    NVR_TRY(make_warp_params(w, rig, &p));
+    NVR_REQUIRE(n >= 0, NVR_EINVAL, "n < 0");
+    NVR_REQUIRE(n_parts >= 1 && n_parts <= 64, NVR_EINVAL, "n_parts out of 1..64");
+    if (n == 0) return NVR_OK;
+    NVR_REQUIRE(x_live && dx_can && d_node_dq, NVR_EINVAL, "NULL array");
+    return launch_warp_bwd(p, *rig, n, n_dev, n, x_live, frame, dx_can, n_parts, 3 * n, d_node_dq,
+                           d_bones, hs(stream));
+}
+
+#include "launch.hpp"
+
+namespace nvr {
+
+nvr_status run_warp_fwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t cap,
+                        const int32_t *n_dev, const float *x, float *xc, hipStream_t st) {
+    WarpParams p;
+    NVR_TRY(make_warp_params(w, rig, &p));
+    return launch_warp_fwd(p, *rig, cap, n_dev, cap, x, nullptr, xc, st);
+}
+
+nvr_status run_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t cap,
+                        const int32_t *n_dev, const float *x, const float *gz, int n_parts,
+                        int64_t part_stride, float *d_dq, float *d_bones, hipStream_t st) {
+    WarpParams p;
+    NVR_TRY(make_warp_params(w, rig, &p));
+    return launch_warp_bwd(p, *rig, cap, n_dev, cap, x, nullptr, gz, n_parts, part_stride, d_dq,
+                           d_bones, st);
+}
+
+}  // namespace nvr

@@ -1,0 +1,135 @@
+"""Radiance-field state on the device and the whole-step driver.
+
+A ``Field`` owns one field's parameter masters, their fp16 / bf16 copies,
+gradients and Adam moments (device tensors); a ``Trainer`` owns an nvr
+context and calls the library's fused training step and renderer.  Only
+argument marshalling happens here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import ops
+from ._lib import call
+
+
+class Field:
+    def __init__(self, work, fcfg, table, params, occ_words=None, rig=None, warp_desc=None,
+                 ray_range=None, device="cuda"):
+        self.work, self.fcfg = work, fcfg
+        self.grid = ops.grid_desc_of(fcfg)
+        self.mlp = ops.mlp_desc_of(fcfg)
+        self.march = ops.march_desc_of(work, fcfg)
+        n_e = self.grid.n_entries
+        table = torch.as_tensor(np.asarray(table, np.float32)).reshape(n_e, 2)
+        params = torch.as_tensor(np.asarray(params, np.float32)).reshape(-1)
+        assert params.numel() == ops.mlp_param_count(self.mlp)
+        self.table = table.to(device).contiguous()
+        self.params = params.to(device).contiguous()
+        self.table_half = self.table.to(torch.float16)
+        self.params_bf16 = self.params.to(torch.bfloat16)
+        self.table_grad = torch.zeros_like(self.table)
+        self.params_grad = torch.zeros_like(self.params)
+        self.table_m = torch.zeros_like(self.table)
+        self.table_v = torch.zeros_like(self.table)
+        self.params_m = torch.zeros_like(self.params)
+        self.params_v = torch.zeros_like(self.params)
+        self.occ = None
+        if occ_words is not None and fcfg.occ_res > 0:
+            self.occ = torch.from_numpy(np.asarray(occ_words, np.uint32).view(np.int32)).to(device)
+        self.rig = rig
+        self.warp = warp_desc
+        self.node_dq_grad = self.bones_grad = None
+        if rig is not None:
+            self.node_dq_grad = torch.zeros_like(rig.node_dq)
+            self.bones_grad = torch.zeros_like(rig.bones)
+        self.ray_range = ray_range
+
+    def c(self, n_rays):
+        f = L.Field()
+        f.grid, f.mlp, f.march = self.grid, self.mlp, self.march
+        lo, hi = self.ray_range if self.ray_range is not None else (0, n_rays)
+        f.ray_begin, f.ray_end = lo, hi
+        p = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        f.occ = p(self.occ)
+        f.table, f.table_half = p(self.table), p(self.table_half)
+        f.params, f.params_bf16 = p(self.params), p(self.params_bf16)
+        f.table_grad, f.params_grad = p(self.table_grad), p(self.params_grad)
+        f.table_m, f.table_v = p(self.table_m), p(self.table_v)
+        f.params_m, f.params_v = p(self.params_m), p(self.params_v)
+        if self.rig is not None:
+            f.has_warp = 1
+            f.warp = self.warp
+            f.rig = self.rig.c()
+            f.node_dq_grad, f.bones_grad = p(self.node_dq_grad), p(self.bones_grad)
+        return f
+
+
+class Trainer:
+    """Owns an nvr context; runs training steps and renders."""
+
+    def __init__(self, fields, n_rays, max_samples, precision=L.NVR_F32, lambda_depth=0.0,
+                 adam=None, use_graph=False, loss_scale=1.0, device_index=0):
+        self.fields = list(fields)
+        self.n_rays = n_rays
+        ctx = C.c_void_p()
+        call("nvr_create", C.byref(ctx), device_index, L.NVR_USE_GRAPH if use_graph else 0)
+        self.ctx = ctx
+        self.desc = L.StepDesc(len(self.fields), precision, n_rays, max_samples, lambda_depth,
+                               adam or ops.adam_desc(), 1)
+        self._cf = [f.c(n_rays) for f in self.fields]
+        self._arr = (C.POINTER(L.Field) * len(self._cf))(*[C.pointer(f) for f in self._cf])
+        self.state = ops.new_state(loss_scale)
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        self.batch = None
+
+    def set_batch(self, o, d, C_t, D_t=None, mask=None):
+        self._batch_tensors = (o, d, C_t, D_t, mask)
+        p = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        self.batch = L.Batch(p(o), p(d), p(C_t), p(D_t), p(mask))
+
+    def step(self):
+        call("nvr_train_step", self.ctx, C.byref(self.desc), self._arr, C.byref(self.batch),
+             ops._p(self.state), ops._p(self.loss), ops._stream())
+        return self.loss
+
+    def forward(self, C_out=None, D_out=None):
+        call("nvr_train_step_fwd", self.ctx, C.byref(self.desc), self._arr, C.byref(self.batch),
+             ops._p(self.state), ops._p(self.loss), ops._p(C_out), ops._p(D_out), ops._stream())
+        return self.loss
+
+    def backward(self, apply_update=True):
+        self.desc.apply_update = 1 if apply_update else 0
+        try:
+            call("nvr_train_step_bwd", self.ctx, C.byref(self.desc), self._arr,
+                 C.byref(self.batch), ops._p(self.state), ops._stream())
+        finally:
+            self.desc.apply_update = 1
+
+    def sample_count(self, field=0):
+        n = C.c_int64()
+        call("nvr_last_sample_count", self.ctx, field, C.byref(n), ops._stream())
+        return n.value
+
+    def render(self, o, d, t_stop=1e-4):
+        n = o.shape[0]
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=o.device)
+        depth = torch.empty(n, dtype=torch.float32, device=o.device)
+        call("nvr_render", self.ctx, C.byref(self.desc), self._arr, n, ops._p(o), ops._p(d),
+             t_stop, ops._p(rgb), ops._p(depth), ops._stream())
+        return rgb, depth
+
+    def close(self):
+        if self.ctx:
+            L.lib().nvr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

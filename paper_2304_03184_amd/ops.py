@@ -1,0 +1,331 @@
+"""Torch-facing wrappers of the nvr C ABI.
+
+Each function only marshals arguments (device pointers of torch tensors, the
+current HIP stream) into the corresponding entry point of libnvr.so; every
+step of the computation runs in the library's kernels.  The autograd
+Functions pair each forward entry point with its hand-written backward.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import torch
+
+from . import _lib as L
+from ._lib import call
+
+F32, F16, BF16 = L.NVR_F32, L.NVR_F16, L.NVR_BF16
+_DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _f3(v):
+    return (C.c_float * 3)(*[float(a) for a in v])
+
+
+def _dev(t, dtype=None):
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    if dtype is not None:
+        assert t.dtype == dtype, f"expected {dtype}, got {t.dtype}"
+    return t
+
+
+# ---------------------------------------------------------------- descriptors
+def grid_desc(n_levels, n_features, log2_table, res_min, res_max, aabb_min, aabb_max):
+    g = L.GridDesc()
+    call("nvr_grid_init", C.byref(g), n_levels, n_features, log2_table, res_min, res_max,
+         _f3(aabb_min), _f3(aabb_max))
+    return g
+
+
+def grid_desc_of(fcfg):
+    return grid_desc(fcfg.n_levels, fcfg.n_features, fcfg.log2_table, fcfg.res_min,
+                     fcfg.res_max, fcfg.aabb_min, fcfg.aabb_max)
+
+
+def march_desc(aabb_min, aabb_max, near=0.0, far=1e30, step=0.0, max_steps=128, occ_res=0):
+    return L.MarchDesc(_f3(aabb_min), _f3(aabb_max), near, far, step, max_steps, occ_res)
+
+
+def march_desc_of(work, fcfg):
+    return march_desc(fcfg.aabb_min, fcfg.aabb_max, work.near, work.far, work.fixed_step,
+                      work.max_steps, fcfg.occ_res)
+
+
+def mlp_desc(n_in, density_hidden, density_out, sh_degree, colour_hidden):
+    dh = (C.c_int32 * 4)(*density_hidden)
+    ch = (C.c_int32 * 4)(*colour_hidden)
+    return L.MlpDesc(n_in, len(density_hidden), dh, density_out, sh_degree, len(colour_hidden), ch)
+
+
+def mlp_desc_of(fcfg):
+    return mlp_desc(fcfg.enc_width, fcfg.density_hidden, fcfg.density_out, fcfg.sh_degree,
+                    fcfg.colour_hidden)
+
+
+def mlp_param_count(md):
+    n = C.c_int64()
+    call("nvr_mlp_param_count", C.byref(md), C.byref(n))
+    return n.value
+
+
+def warp_desc(n_joints=24, k_joints=4, sigma_skin=0.1, n_nodes=1024, k_nodes=8, n_frames=1,
+              r_node=0.1, lut_res=128, lut_min=(-1.0,) * 3, lut_max=(1.0,) * 3):
+    return L.WarpDesc(n_joints, k_joints, sigma_skin, n_nodes, k_nodes, n_frames, r_node,
+                      lut_res, _f3(lut_min), _f3(lut_max))
+
+
+class Rig:
+    """Device copies of the warp inputs (joints, bones, node motions, look-up)."""
+
+    def __init__(self, joints, bones, node_dq, node_pos, lut):
+        self.joints, self.bones, self.node_dq, self.node_pos, self.lut = \
+            joints, bones, node_dq, node_pos, lut
+
+    @classmethod
+    def from_numpy(cls, rig, device="cuda"):
+        import numpy as np
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)  # noqa: E731
+        lut = torch.from_numpy(np.ascontiguousarray(rig["knn"]).view(np.int16)).to(device)
+        return cls(t(rig["joints"], torch.float32), t(rig["bones"], torch.float32),
+                   t(rig["node_dq"], torch.float32), t(rig["node_pos"], torch.float32), lut)
+
+    def c(self):
+        return L.WarpRig(self.joints.data_ptr(), self.bones.data_ptr(), self.node_dq.data_ptr(),
+                         self.node_pos.data_ptr(), self.lut.data_ptr())
+
+
+# ---------------------------------------------------------------- encode
+def encode_fwd(g, x, table, feat_dtype=torch.float32):
+    _dev(x, torch.float32)
+    _dev(table)
+    n = x.shape[0]
+    feat = torch.empty((n, g.n_levels * g.n_features), dtype=feat_dtype, device=x.device)
+    call("nvr_encode_fwd", C.byref(g), n, _p(x), _p(table), _DT[table.dtype], _p(feat),
+         _DT[feat_dtype], _stream())
+    return feat
+
+
+def encode_bwd(g, x, table, dfeat, dtable, dx=None):
+    _dev(dfeat, torch.float32)
+    _dev(dtable, torch.float32)
+    call("nvr_encode_bwd", C.byref(g), x.shape[0], _p(x), _p(table), _DT[table.dtype],
+         _p(dfeat), _p(dtable), _p(dx), _stream())
+
+
+class EncodeFn(torch.autograd.Function):
+    """feat = encode(x, table); backward scatters into the table gradient and
+    (when x requires grad) accumulates the position gradient."""
+
+    @staticmethod
+    def forward(ctx, x, table, g):
+        ctx.g = g
+        ctx.save_for_backward(x, table)
+        return encode_fwd(g, x.contiguous(), table.contiguous(), torch.float32)
+
+    @staticmethod
+    def backward(ctx, dfeat):
+        x, table = ctx.saved_tensors
+        dtable = torch.zeros(table.shape, dtype=torch.float32, device=table.device)
+        dx = torch.zeros_like(x) if ctx.needs_input_grad[0] else None
+        encode_bwd(ctx.g, x, table, dfeat.contiguous().float(), dtable, dx)
+        return dx, dtable.to(table.dtype), None
+
+
+# ---------------------------------------------------------------- march
+def march(md, o, d, occ=None, capacity=None, ray_begin=0, ray_end=None, sync=True):
+    n_rays = o.shape[0]
+    ray_end = n_rays if ray_end is None else ray_end
+    cap = n_rays * md.max_steps if capacity is None else capacity
+    dev = o.device
+    off = torch.empty(n_rays + 1, dtype=torch.int32, device=dev)
+    ray_id = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    t = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    dt = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    x = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+    n_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(L.lib().nvr_march_workspace(n_rays), 4), dtype=torch.uint8, device=dev)
+    call("nvr_march", C.byref(md), n_rays, ray_begin, ray_end, _p(o), _p(d), _p(occ), cap,
+         _p(off), _p(ray_id), _p(t), _p(dt), _p(x), _p(n_dev), _p(ws), _stream())
+    out = dict(off=off, ray_id=ray_id, t=t, dt=dt, x=x, n_dev=n_dev, capacity=cap)
+    if sync:
+        n = int(n_dev.item())
+        if n > cap:
+            raise L.NvrError("nvr_march", L.NVR_EOVERFLOW, f"{n} samples > capacity {cap}")
+        for k in ("ray_id", "t", "dt", "x"):
+            out[k] = out[k][:n]
+        out["n"] = n
+    return out
+
+
+# ---------------------------------------------------------------- warp
+def warp_fwd(wd, rig, x, n_dev=None):
+    xc = torch.empty_like(x)
+    call("nvr_warp_fwd", C.byref(wd), C.byref(rig.c()), x.shape[0], _p(n_dev), _p(x), None,
+         _p(xc), _stream())
+    return xc
+
+
+def warp_bwd(wd, rig, x, dxc, d_node_dq, d_bones=None, n_parts=1):
+    call("nvr_warp_bwd", C.byref(wd), C.byref(rig.c()), x.shape[0], None, _p(x), None,
+         _p(dxc), n_parts, _p(d_node_dq), _p(d_bones), _stream())
+
+
+class WarpFn(torch.autograd.Function):
+    """x_can = warp(x_live); backward to node motions and bones."""
+
+    @staticmethod
+    def forward(ctx, x, node_dq, bones, wd, rig):
+        ctx.wd, ctx.rig = wd, rig
+        ctx.save_for_backward(x)
+        return warp_fwd(wd, rig, x.contiguous())
+
+    @staticmethod
+    def backward(ctx, dxc):
+        (x,) = ctx.saved_tensors
+        d_dq = torch.zeros_like(ctx.rig.node_dq)
+        d_b = torch.zeros_like(ctx.rig.bones)
+        warp_bwd(ctx.wd, ctx.rig, x, dxc.contiguous(), d_dq, d_b)
+        return None, d_dq, d_b, None, None
+
+
+# ---------------------------------------------------------------- networks
+def mlp_fwd(md, feat, dirs, params, ray_id=None, math_dtype=F32):
+    n = feat.shape[0]
+    sigma = torch.empty(n, dtype=torch.float32, device=feat.device)
+    rgb = torch.empty((n, 3), dtype=torch.float32, device=feat.device)
+    call("nvr_mlp_fwd", C.byref(md), n, None, _p(feat), _DT[feat.dtype], _p(dirs), _p(ray_id),
+         _p(params), math_dtype, _p(sigma), _p(rgb), _stream())
+    return sigma, rgb
+
+
+def mlp_bwd(md, feat, dirs, params, dsigma, drgb, dparams, ray_id=None, math_dtype=F32,
+            want_dfeat=True):
+    n = feat.shape[0]
+    dfeat = torch.empty((n, md.n_in), dtype=torch.float32, device=feat.device) \
+        if want_dfeat else None
+    ws = torch.empty(max(L.lib().nvr_mlp_workspace(C.byref(md), math_dtype, n), 4),
+                     dtype=torch.uint8, device=feat.device)
+    call("nvr_mlp_bwd", C.byref(md), n, None, _p(feat), _DT[feat.dtype], _p(dirs), _p(ray_id),
+         _p(params), math_dtype, _p(dsigma), _p(drgb), _p(dparams), _p(dfeat), _p(ws), _stream())
+    return dfeat
+
+
+class FieldNetFn(torch.autograd.Function):
+    """(sigma, rgb) = networks(feat, dirs); backward recomputes the forward."""
+
+    @staticmethod
+    def forward(ctx, feat, params, dirs, ray_id, md, math_dtype):
+        ctx.md, ctx.math = md, math_dtype
+        ctx.save_for_backward(feat, params, dirs, ray_id)
+        return mlp_fwd(md, feat, dirs, params, ray_id, math_dtype)
+
+    @staticmethod
+    def backward(ctx, dsigma, drgb):
+        feat, params, dirs, ray_id = ctx.saved_tensors
+        dparams = torch.zeros(params.shape, dtype=torch.float32, device=params.device)
+        dfeat = mlp_bwd(ctx.md, feat, dirs, params, dsigma.contiguous(), drgb.contiguous(),
+                        dparams, ray_id, ctx.math)
+        return dfeat.to(feat.dtype), dparams.to(params.dtype), None, None, None, None
+
+
+# ---------------------------------------------------------------- compositing
+def samples(off, sigma, rgb, t, dt):
+    return L.Samples(off.data_ptr(), sigma.data_ptr(), rgb.data_ptr(), t.data_ptr(),
+                     dt.data_ptr())
+
+
+def composite_fwd(a, b=None, n_rays=None, t_stop=0.0, device="cuda"):
+    C_ = torch.empty((n_rays, 3), dtype=torch.float32, device=device)
+    D = torch.empty(n_rays, dtype=torch.float32, device=device)
+    TN = torch.empty(n_rays, dtype=torch.float32, device=device)
+    call("nvr_composite_fwd", n_rays, C.byref(a), C.byref(b) if b is not None else None,
+         t_stop, _p(C_), _p(D), _p(TN), _stream())
+    return C_, D, TN
+
+
+def composite_bwd(a, na, C_, D, dC, dD, b=None, nb=0, device="cuda"):
+    n_rays = C_.shape[0]
+    dsa = torch.empty(max(na, 1), dtype=torch.float32, device=device)
+    dra = torch.empty((max(na, 1), 3), dtype=torch.float32, device=device)
+    dsb = drb = None
+    if b is not None:
+        dsb = torch.empty(max(nb, 1), dtype=torch.float32, device=device)
+        drb = torch.empty((max(nb, 1), 3), dtype=torch.float32, device=device)
+    call("nvr_composite_bwd", n_rays, C.byref(a), C.byref(b) if b is not None else None,
+         _p(C_), _p(D), _p(dC), _p(dD), _p(dsa), _p(dra), _p(dsb), _p(drb), _stream())
+    return dsa[:na], dra[:na], (dsb[:nb] if dsb is not None else None), \
+        (drb[:nb] if drb is not None else None)
+
+
+class CompositeFn(torch.autograd.Function):
+    """(C, D) = composite(sigma, rgb) of one ray-major sample list."""
+
+    @staticmethod
+    def forward(ctx, sigma, rgb, t, dt, off):
+        a = samples(off, sigma, rgb, t, dt)
+        C_, D, _ = composite_fwd(a, n_rays=off.shape[0] - 1, device=sigma.device)
+        ctx.save_for_backward(sigma, rgb, t, dt, off, C_, D)
+        return C_, D
+
+    @staticmethod
+    def backward(ctx, dC, dD):
+        sigma, rgb, t, dt, off, C_, D = ctx.saved_tensors
+        a = samples(off, sigma, rgb, t, dt)
+        dsig, drgb, _, _ = composite_bwd(a, sigma.shape[0], C_, D, dC.contiguous(),
+                                         dD.contiguous(), device=sigma.device)
+        return dsig, drgb, None, None, None
+
+
+# ---------------------------------------------------------------- loss / Adam
+def loss(C_, D, C_t, D_t=None, mask=None, lambda_d=0.0, loss_scale=None):
+    n = C_.shape[0]
+    out = torch.empty(1, dtype=torch.float32, device=C_.device)
+    dC = torch.empty_like(C_)
+    dD = torch.empty_like(D)
+    call("nvr_loss", n, _p(C_), _p(D), _p(C_t), _p(D_t), _p(mask), lambda_d, _p(loss_scale),
+         _p(out), _p(dC), _p(dD), _stream())
+    return out, dC, dD
+
+
+def adam_desc(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15):
+    return L.AdamDesc(lr, beta1, beta2, eps)
+
+
+def new_state(loss_scale=1.0, device="cuda"):
+    """Device-resident nvr_train_state: int32 step, int32 finite, f32 scale, pad."""
+    s = torch.zeros(4, dtype=torch.int32, device=device)
+    s.view(torch.float32)[2] = loss_scale
+    s[1] = 1
+    return s
+
+
+def state_values(state):
+    s = state.cpu()
+    return dict(step=int(s[0]), finite=int(s[1]), loss_scale=float(s.view(torch.float32)[2]))
+
+
+def adam(ad, param, m, v, grad, state, skip_zero=False, copy=None):
+    call("nvr_adam", C.byref(ad), param.numel(), _p(param), _p(m), _p(v), _p(grad),
+         1 if skip_zero else 0, _p(state), _p(copy), _DT[copy.dtype] if copy is not None else 0,
+         _stream())
+
+
+def state_begin(state):
+    call("nvr_state_begin", _p(state), _stream())
+
+
+def check_finite(g, state):
+    call("nvr_check_finite", g.numel(), _p(g), _p(state), _stream())
+
+
+def state_end(state):
+    call("nvr_state_end", _p(state), _stream())
