@@ -9,8 +9,8 @@
 //   3. march_write  -- one thread per ray: walk again and write t, dt, x and
 //                      the ray id at its global offset (capacity-bounded).
 // The walk's integer decisions use IEEE float32 with one rounding per
-// operation (the __f*_rn intrinsics keep the compiler from fusing a
-// multiply-add), in the order fixed by the documented reading.
+// operation (floating-point contraction is switched off in those functions,
+// so no multiply-add is fused), in the order fixed by the documented reading.
 #include "common.hpp"
 
 #include <cmath>
@@ -30,13 +30,14 @@ struct RaySeg {
 };
 
 __device__ __forceinline__ RaySeg clip_ray(const MarchParams &p, const float *o, const float *d) {
+#pragma clang fp contract(off)
     float tn = p.near_t, tf = p.far_t;
     float lo_t[3], hi_t[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float inv = __fdiv_rn(1.0f, d[a]);
-        const float t0 = __fmul_rn(__fsub_rn(p.lo[a], o[a]), inv);
-        const float t1 = __fmul_rn(__fsub_rn(p.hi[a], o[a]), inv);
+        const float inv = 1.0f / d[a];
+        const float t0 = (p.lo[a] - o[a]) * inv;
+        const float t1 = (p.hi[a] - o[a]) * inv;
         lo_t[a] = fminf(t0, t1);
         hi_t[a] = fmaxf(t0, t1);
     }
@@ -47,11 +48,12 @@ __device__ __forceinline__ RaySeg clip_ray(const MarchParams &p, const float *o,
 
 __device__ __forceinline__ bool occupied(const MarchParams &p, const uint32_t *occ,
                                          const float x[3]) {
+#pragma clang fp contract(off)
     if (p.occ_res == 0) return true;
     int v[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float u = __fmul_rn(__fsub_rn(x[a], p.lo[a]), p.occ_scale[a]);
+        const float u = (x[a] - p.lo[a]) * p.occ_scale[a];
         int c = (int)floorf(u);
         c = c < 0 ? 0 : (c > p.occ_res - 1 ? p.occ_res - 1 : c);
         v[a] = c;
@@ -65,15 +67,16 @@ __device__ __forceinline__ bool occupied(const MarchParams &p, const uint32_t *o
 template <typename Emit>
 __device__ __forceinline__ int walk(const MarchParams &p, const uint32_t *occ, const float *o,
                                     const float *d, Emit emit) {
+#pragma clang fp contract(off)
     const RaySeg s = clip_ray(p, o, d);
     int kept = 0;
     if (!(s.tf > s.tn)) return 0;
     for (int i = 0; i < p.max_steps; ++i) {
-        const float t = __fadd_rn(s.tn, __fmul_rn(__fadd_rn((float)i, 0.5f), p.step));
+        const float t = s.tn + ((float)i + 0.5f) * p.step;
         if (!(t < s.tf)) break;
         float x[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) x[a] = __fadd_rn(o[a], __fmul_rn(t, d[a]));
+        for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
         if (occupied(p, occ, x)) {
             emit(kept, t, x);
             ++kept;

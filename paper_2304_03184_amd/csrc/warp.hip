@@ -45,6 +45,28 @@ __device__ __forceinline__ float3 qrot(float w, float3 u, float3 v) {
     return add3(add3(v, mul3(2.f * w, uv)), mul3(2.f, cross3(u, uv)));
 }
 
+// ---- float32 decisions: one rounding per operation, no contraction
+__device__ __forceinline__ float joint_d2(float3 x, const float *J) {
+#pragma clang fp contract(off)
+    const float dx = x.x - J[0];
+    const float dy = x.y - J[1];
+    const float dz = x.z - J[2];
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ int lut_cell(float x, float lo, float scale, int res) {
+#pragma clang fp contract(off)
+    const float u = (x - lo) * scale;
+    const int c = (int)floorf(u);
+    return c < 0 ? 0 : (c > res - 1 ? res - 1 : c);
+}
+
+__device__ __forceinline__ float sign_dot(const float *q, const float *q0) {
+#pragma clang fp contract(off)
+    const float dot = ((q[0] * q0[0] + q[1] * q0[1]) + q[2] * q0[2]) + q[3] * q0[3];
+    return dot >= 0.f ? 1.f : -1.f;
+}
+
 struct WarpFwd {
     int jsel[kMaxKJ];
     float lw[kMaxKJ];
@@ -70,10 +92,7 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
         f.jsel[k] = 0x7fffffff;
     }
     for (int j = 0; j < p.n_joints; ++j) {
-        const float dx = __fsub_rn(x.x, J[3 * j]);
-        const float dy = __fsub_rn(x.y, J[3 * j + 1]);
-        const float dz = __fsub_rn(x.z, J[3 * j + 2]);
-        const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+        const float d2 = joint_d2(x, J + 3 * j);
         if (d2 < bd[p.k_joints - 1]) {
             int k = p.k_joints - 1;
             while (k > 0 && d2 < bd[k - 1]) {
@@ -107,11 +126,7 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
     int v[3];
     const float xs[3] = {x.x, x.y, x.z};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float u = __fmul_rn(__fsub_rn(xs[a], p.lut_lo[a]), p.lut_scale[a]);
-        int c = (int)floorf(u);
-        v[a] = c < 0 ? 0 : (c > p.lut_res - 1 ? p.lut_res - 1 : c);
-    }
+    for (int a = 0; a < 3; ++a) v[a] = lut_cell(xs[a], p.lut_lo[a], p.lut_scale[a], p.lut_res);
     const size_t vox = (size_t)v[0] + (size_t)p.lut_res * ((size_t)v[1] + (size_t)p.lut_res * v[2]);
     const uint16_t *ids = rig.lut + ((size_t)frame * p.lut_res * p.lut_res * p.lut_res + vox) * p.k_nodes;
     const float *DQ = rig.node_dq + (size_t)frame * p.n_nodes * 8;
@@ -134,10 +149,7 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
         float qq[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) qq[c] = q[c];
-        const float dot = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(qq[0], q0[0]), __fmul_rn(qq[1], q0[1])),
-                                              __fmul_rn(qq[2], q0[2])),
-                                    __fmul_rn(qq[3], q0[3]));
-        f.s[k] = dot >= 0.f ? 1.f : -1.f;
+        f.s[k] = sign_dot(qq, q0);
         f.w[k] = expf(-(e2[k] - e2min) * p.inv_r2);
         const float sw = f.s[k] * f.w[k];
         // conjugate of both parts: (w, -x, -y, -z)
