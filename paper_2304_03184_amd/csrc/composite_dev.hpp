@@ -10,13 +10,25 @@ struct RayAcc {
     float tau;   // sum of tau over the composited samples
 };
 
-// Iterates the samples of ray r in t order over one or two lists.
+// One composited sample of a ray.
+struct Sample {
+    float sigma, c0, c1, c2, t, dt;
+    int which;      // 0: first list, 1: second list
+    int64_t k;      // index in its list
+};
+
+// Iterates the samples of ray r in t order over one or two lists (ties go to
+// the first list).  Each branch loads its own list's values: selecting a list
+// by reference (`which ? b : a`) and loading through the selected pointers
+// was compiled with the pointer copy executed for the wrong lanes (a lane
+// taking from the second list while the first was not exhausted read the
+// first list), so the walk never selects pointers at run time.
 struct MergedWalk {
-    const nvr_samples &a, &b;
-    bool has_b;
+    nvr_samples a, b;
     int64_t i, ie, j, je;
-    __device__ MergedWalk(const nvr_samples &a_, const nvr_samples &b_, bool hb, int64_t r)
-        : a(a_), b(b_), has_b(hb) {
+    __device__ __forceinline__ MergedWalk(const nvr_samples &a_, const nvr_samples &b_, bool has_b,
+                                          int64_t r)
+        : a(a_), b(b_) {
         i = a.off[r];
         ie = a.off[r + 1];
         if (has_b) {
@@ -26,16 +38,28 @@ struct MergedWalk {
             j = je = 0;
         }
     }
-    // returns false when exhausted; sets which (0: a, 1: b) and idx
-    __device__ __forceinline__ bool next(int &which, int64_t &idx) {
-        if (i < ie && (j >= je || a.t[i] <= b.t[j])) {
-            which = 0;
-            idx = i++;
+    __device__ __forceinline__ bool next(Sample &s) {
+        const bool take_a = i < ie && (j >= je || a.t[i] <= b.t[j]);
+        if (take_a) {
+            s.which = 0;
+            s.k = i++;
+            s.sigma = a.sigma[s.k];
+            s.c0 = a.rgb[3 * s.k];
+            s.c1 = a.rgb[3 * s.k + 1];
+            s.c2 = a.rgb[3 * s.k + 2];
+            s.t = a.t[s.k];
+            s.dt = a.dt[s.k];
             return true;
         }
         if (j < je) {
-            which = 1;
-            idx = j++;
+            s.which = 1;
+            s.k = j++;
+            s.sigma = b.sigma[s.k];
+            s.c0 = b.rgb[3 * s.k];
+            s.c1 = b.rgb[3 * s.k + 1];
+            s.c2 = b.rgb[3 * s.k + 2];
+            s.t = b.t[s.k];
+            s.dt = b.dt[s.k];
             return true;
         }
         return false;
@@ -46,18 +70,16 @@ __device__ __forceinline__ RayAcc ray_forward(const nvr_samples &a, const nvr_sa
                                               int64_t r, float t_stop) {
     RayAcc acc{{0.f, 0.f, 0.f}, 0.f, 0.f};
     MergedWalk w(a, b, has_b, r);
-    int which;
-    int64_t k;
-    while (w.next(which, k)) {
-        const nvr_samples &L = which ? b : a;
-        const float tau = L.sigma[k] * L.dt[k];
+    Sample s;
+    while (w.next(s)) {
+        const float tau = s.sigma * s.dt;
         const float T = expf(-acc.tau);
         if (t_stop > 0.f && T < t_stop) break;
         const float wgt = T * (1.f - expf(-tau));
-        acc.c[0] += wgt * L.rgb[3 * k];
-        acc.c[1] += wgt * L.rgb[3 * k + 1];
-        acc.c[2] += wgt * L.rgb[3 * k + 2];
-        acc.d += wgt * L.t[k];
+        acc.c[0] += wgt * s.c0;
+        acc.c[1] += wgt * s.c1;
+        acc.c[2] += wgt * s.c2;
+        acc.d += wgt * s.t;
         acc.tau += tau;
     }
     return acc;
@@ -70,30 +92,32 @@ __device__ __forceinline__ void ray_backward(const nvr_samples &a, const nvr_sam
                                              float gd, float *dsa, float *dra, float *dsb,
                                              float *drb) {
     MergedWalk w(a, b, has_b, r);
-    int which;
-    int64_t k;
+    Sample s;
     float csum = 0.f, pc0 = 0.f, pc1 = 0.f, pc2 = 0.f, pd = 0.f;
-    while (w.next(which, k)) {
-        const nvr_samples &L = which ? b : a;
-        const float tau = L.sigma[k] * L.dt[k];
+    while (w.next(s)) {
+        const float tau = s.sigma * s.dt;
         const float T = expf(-csum);
         const float Tn = expf(-(csum + tau));
         const float wgt = T * (1.f - expf(-tau));
-        const float c0 = L.rgb[3 * k], c1 = L.rgb[3 * k + 1], c2 = L.rgb[3 * k + 2];
-        const float tk = L.t[k];
-        pc0 += wgt * c0;
-        pc1 += wgt * c1;
-        pc2 += wgt * c2;
-        pd += wgt * tk;
-        const float u = c0 * gc[0] + c1 * gc[1] + c2 * gc[2] + tk * gd;
+        pc0 += wgt * s.c0;
+        pc1 += wgt * s.c1;
+        pc2 += wgt * s.c2;
+        pd += wgt * s.t;
+        const float u = s.c0 * gc[0] + s.c1 * gc[1] + s.c2 * gc[2] + s.t * gd;
         const float suffix = (C[0] - pc0) * gc[0] + (C[1] - pc1) * gc[1] + (C[2] - pc2) * gc[2] +
                              (D - pd) * gd;
-        float *ds = which ? dsb : dsa;
-        float *dr = which ? drb : dra;
-        ds[k] = L.dt[k] * (Tn * u - suffix);
-        dr[3 * k] = wgt * gc[0];
-        dr[3 * k + 1] = wgt * gc[1];
-        dr[3 * k + 2] = wgt * gc[2];
+        const float ds = s.dt * (Tn * u - suffix);
+        if (s.which == 0) {
+            dsa[s.k] = ds;
+            dra[3 * s.k] = wgt * gc[0];
+            dra[3 * s.k + 1] = wgt * gc[1];
+            dra[3 * s.k + 2] = wgt * gc[2];
+        } else {
+            dsb[s.k] = ds;
+            drb[3 * s.k] = wgt * gc[0];
+            drb[3 * s.k + 1] = wgt * gc[1];
+            drb[3 * s.k + 2] = wgt * gc[2];
+        }
         csum += tau;
     }
 }
