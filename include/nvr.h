@@ -97,6 +97,16 @@ nvr_status nvr_encode_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
                           const float *dfeat, float *dtable, float *dx,
                           nvr_stream stream);
 
+/* Same gradients as nvr_encode_bwd for a float16 table, without a global
+ * atomic per contribution: the contributions are binned by 16384-entry table
+ * tiles (count, scan, append) and each tile is summed in LDS and added into
+ * dtable once.  dtable must be 8-byte aligned; workspace (device, 256-byte
+ * aligned) of nvr_encode_bwd_workspace(g, n) bytes, owned by the caller. */
+size_t nvr_encode_bwd_workspace(const nvr_grid_desc *g, int64_t n);
+nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, const float *x,
+                                 const void *table, const float *dfeat, float *dtable,
+                                 float *dx, void *workspace, nvr_stream stream);
+
 /* ------------------------------------------------------------------------
  * Ray marching with occupancy skipping (the back-end is built on Instant-NGP,
  * Sec. 4.3; its marcher is not described in the paper).  Per ray: clip

@@ -89,6 +89,8 @@ _SIGS = {
     "nvr_grid_init": (i32, [P(GridDesc), i32, i32, i32, i32, i32, P(f32), P(f32)]),
     "nvr_encode_fwd": (i32, [P(GridDesc), i64, vp, vp, i32, vp, i32, vp]),
     "nvr_encode_bwd": (i32, [P(GridDesc), i64, vp, vp, i32, vp, vp, vp, vp]),
+    "nvr_encode_bwd_workspace": (C.c_size_t, [P(GridDesc), i64]),
+    "nvr_encode_bwd_binned": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_march_workspace": (C.c_size_t, [i64]),
     "nvr_march": (i32, [P(MarchDesc), i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp,
                         vp, vp]),

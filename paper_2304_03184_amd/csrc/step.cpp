@@ -3,6 +3,7 @@
 // every launch is sized without reading the device-side sample count) and,
 // with NVR_USE_GRAPH, one captured HIP graph per (descriptor, fields, batch).
 #include "launch.hpp"
+#include "scatter_dev.hpp"
 
 #include <cstring>
 #include <map>
@@ -15,7 +16,7 @@ struct FieldWs {
     int64_t cap = 0, n_rays = 0;
     int precision = -1;
     int has_warp = 0, n_in = 0;
-    size_t mlp_bytes = 0;
+    size_t mlp_bytes = 0, scatter_bytes = 0;
     void *block = nullptr;          // one allocation, carved below
     int32_t *off, *ray_id, *n_dev, *march_ws;
     float *t, *dt, *x, *xc;
@@ -24,6 +25,7 @@ struct FieldWs {
     float *dfeat;                   // f32 planar [8][cap][4] | f32 [cap][n_in]
     float *dx;                      // [8][cap][3] (split) | [cap][3] (plain)
     void *mlp_ws;
+    void *scatter_ws;               // binned table-gradient scatter (bf16 training)
 };
 
 struct GraphEntry {
@@ -72,11 +74,14 @@ static nvr_status field_check(const nvr_field *f, const nvr_step_desc *s, Net *n
 }
 
 static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &net, int precision,
-                            int64_t n_rays, int64_t cap) {
+                            int64_t n_rays, int64_t cap, bool train) {
     FieldWs &w = ctx->ws[k];
     const size_t mlp_bytes = precision == NVR_BF16 ? mfma_ws_bytes(net, cap) : plain_workspace(net, cap);
+    const size_t scatter_bytes = (train && precision == NVR_BF16)
+                                     ? scatter_ws_bytes(make_grid_params(&f->grid), cap) : 0;
     if (w.block && w.cap >= cap && w.n_rays >= n_rays && w.precision == precision &&
-        w.has_warp == f->has_warp && w.n_in == net.n_in && w.mlp_bytes >= mlp_bytes)
+        w.has_warp == f->has_warp && w.n_in == net.n_in && w.mlp_bytes >= mlp_bytes &&
+        w.scatter_bytes >= scatter_bytes)
         return NVR_OK;
     if (w.block) {
         NVR_HIP(hipDeviceSynchronize());
@@ -91,7 +96,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     }
     const bool bf = precision == NVR_BF16;
     const int nin = net.n_in;
-    size_t sz[16] = {
+    size_t sz[17] = {
         sizeof(int32_t) * (size_t)(n_rays + 1),             // off
         sizeof(int32_t) * (size_t)cap,                      // ray_id
         sizeof(int32_t) * 4,                                // n_dev
@@ -108,6 +113,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         sizeof(float) * (bf ? 32 : nin) * (size_t)cap,      // dfeat
         f->has_warp ? sizeof(float) * 3 * (bf ? kXcds : 1) * (size_t)cap : 0,  // dx
         mlp_bytes,                                                             // mlp
+        scatter_bytes,                                                         // scatter
     };
     size_t total = 0;
     for (size_t s : sz) total += up(s);
@@ -119,8 +125,8 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         return NVR_ENOMEM;
     }
     char *p = (char *)blk;
-    void *ptr[16];
-    for (int i = 0; i < 16; ++i) {
+    void *ptr[17];
+    for (int i = 0; i < 17; ++i) {
         ptr[i] = sz[i] ? p : nullptr;
         p += up(sz[i]);
     }
@@ -131,6 +137,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.has_warp = f->has_warp;
     w.n_in = net.n_in;
     w.mlp_bytes = mlp_bytes;
+    w.scatter_bytes = scatter_bytes;
     w.off = (int32_t *)ptr[0];
     w.ray_id = (int32_t *)ptr[1];
     w.n_dev = (int32_t *)ptr[2];
@@ -147,6 +154,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.dfeat = (float *)ptr[13];
     w.dx = (float *)ptr[14];
     w.mlp_ws = ptr[15];
+    w.scatter_ws = ptr[16];
     return NVR_OK;
 }
 
@@ -225,8 +233,8 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
             NVR_TRY(mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
                              (const uint16_t *)f->params_bf16, w.dsigma, w.drgb, f->params_grad,
                              w.dfeat, w.mlp_ws, st));
-            NVR_TRY(launch_encode_bwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.dfeat,
-                                      f->table_grad, f->has_warp ? w.dx : nullptr, true, st));
+            NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
+                                   f->has_warp ? w.dx : nullptr, true, w.scatter_ws, st));
             if (f->has_warp)
                 NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, kXcds, 3 * cap,
                                      f->node_dq_grad, f->bones_grad, st));
@@ -265,8 +273,14 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
 static nvr_status prepare(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
                           const Net *nets) {
     NVR_HIP(hipSetDevice(ctx->device));
+    if (s->precision == NVR_BF16)
+        for (int k = 0; k < s->n_fields; ++k) {
+            NVR_TRY(scatter_check(make_grid_params(&fields[k]->grid)));
+            NVR_REQUIRE((size_t)s->max_samples * fields[k]->grid.n_levels * 8 < (1ull << 32),
+                        NVR_EINVAL, "max_samples too large for the binned scatter");
+        }
     for (int k = 0; k < s->n_fields; ++k)
-        NVR_TRY(ensure_ws(ctx, k, fields[k], nets[k], s->precision, s->n_rays, s->max_samples));
+        NVR_TRY(ensure_ws(ctx, k, fields[k], nets[k], s->precision, s->n_rays, s->max_samples, true));
     if (s->precision == NVR_BF16)
         for (int k = 0; k < s->n_fields; ++k)
             NVR_REQUIRE(fields[k]->params_m && fields[k]->params_v && fields[k]->table_m &&
@@ -433,7 +447,7 @@ extern "C" nvr_status nvr_render(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field
     if (chunk < 1) chunk = 1;
     if (chunk > n_rays) chunk = n_rays;
     for (int k = 0; k < s->n_fields; ++k)
-        NVR_TRY(ensure_ws(ctx, k, fields[k], nets[k], s->precision, chunk, chunk * max_steps));
+        NVR_TRY(ensure_ws(ctx, k, fields[k], nets[k], s->precision, chunk, chunk * max_steps, false));
     for (int64_t r0 = 0; r0 < n_rays; r0 += chunk) {
         const int64_t nr = (n_rays - r0) < chunk ? (n_rays - r0) : chunk;
         for (int k = 0; k < s->n_fields; ++k)

