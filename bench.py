@@ -152,8 +152,10 @@ def main():
 
 
 def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
-    """Times the level-split encode backward (the hash-table scatter) alone with
-    HIP events on the current stream, on this workload's own samples."""
+    """Times the hash-grid backward (the binned table-gradient scatter: count,
+    scan, tile-bucketed append, per-tile LDS sum, split-tile reduce) alone with
+    HIP events on the current stream, on this workload's own samples; the
+    forward gather is timed beside it."""
     md = O.march_desc_of(w, f)
     m = O.march(md, o_d, d_d, fld.occ, capacity=cap)
     n = m["n"]
@@ -162,41 +164,51 @@ def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
     rng = np.random.default_rng(5)
     dfeat = torch.from_numpy(rng.normal(size=(n, 32)).astype(np.float32) * 1e-3).cuda()
     dtab = torch.zeros_like(fld.table)
-    for _ in range(3):
-        O.encode_bwd(g, x, fld.table_half, dfeat, dtab)
-    reps = 10
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        O.encode_bwd(g, x, fld.table_half, dfeat, dtab)
-    e1.record()
-    torch.cuda.synchronize()
-    t_bwd = e0.elapsed_time(e1) / reps * 1e-3
-    # forward gather too (context)
-    for _ in range(3):
+    nb = L.lib().nvr_encode_bwd_workspace(__import__("ctypes").byref(g), n)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    import ctypes as C
+
+    def bwd():
+        L.call("nvr_encode_bwd_binned", C.byref(g), n, O._p(x), O._p(fld.table_half), O._p(dfeat),
+               O._p(dtab), None, O._p(ws), O._stream())
+
+    def fwd():
         O.encode_fwd(g, x, fld.table_half, torch.bfloat16)
-    e0.record()
-    for _ in range(reps):
-        O.encode_fwd(g, x, fld.table_half, torch.bfloat16)
-    e1.record()
-    torch.cuda.synchronize()
-    t_fwd = e0.elapsed_time(e1) / reps * 1e-3
+
+    def timed(fn, reps=10):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_bwd = timed(bwd)
+    t_fwd = timed(fwd)
     L_ = f.n_levels
-    # algorithmic bytes per sample: position 12 B + dfeat 4*2L B read; per level
-    # 8 corners x F=2 fp32 atomic adds (read + write: 2 x 4 B each)
-    bwd_bytes = n * (12 + 4 * 2 * L_ + L_ * 8 * 2 * 4 * 2)
-    # forward: position 12 B + per level 8 corners x 4 B (fp16 x2) + 2L bf16 out
-    fwd_bytes = n * (12 + L_ * 8 * 4 + 2 * 2 * L_)
-    log(f"[bench] encode bwd {t_bwd * 1e3:.3f} ms, fwd {t_fwd * 1e3:.3f} ms over {n} samples")
-    achieved = bwd_bytes / t_bwd / 1e9
-    return {"kernel": "encode_bwd_split (hash-table scatter, fp32 atomics)",
+    # algorithmic bytes per sample (per-unit figures of the scatter and gather):
+    #   backward: position 12 B + dfeat 2L x 4 B + L x 8 corners x F=2 fp32 gradient
+    #             contributions of 4 B (the 1,024 B / sample table-gradient RMW at L = 16)
+    #   forward:  position 12 B + L x 8 corners x 4 B (fp16 x 2) + 2L bf16 features
+    bwd_bpu = 12 + 4 * 2 * L_ + L_ * 8 * 2 * 4
+    fwd_bpu = 12 + L_ * 8 * 4 + 2 * 2 * L_
+    log(f"[bench] hash-grid backward (binned) {t_bwd * 1e3:.3f} ms, forward gather "
+        f"{t_fwd * 1e3:.3f} ms over {n} samples")
+    achieved = bwd_bpu * n / t_bwd / 1e9
+    return {"kernel": "hash-grid backward: binned table-gradient scatter "
+                      "(scatter_count + scatter_scan + scatter_emit + scatter_accum + scatter_reduce)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "samples_per_launch": n, "bytes_per_sample": bwd_bytes / n,
+            "samples_per_launch": n, "bytes_per_sample": bwd_bpu,
             "avg_launch_ms": t_bwd * 1e3,
-            "encode_fwd": {"avg_launch_ms": t_fwd * 1e3, "bytes_per_sample": fwd_bytes / n,
-                           "achieved_GBs": fwd_bytes / t_fwd / 1e9}}
+            "encode_fwd": {"kernel": "encode_fwd_split (level-split gather, fp16 table)",
+                           "avg_launch_ms": t_fwd * 1e3, "bytes_per_sample": fwd_bpu,
+                           "achieved_GBs": fwd_bpu * n / t_fwd / 1e9,
+                           "frac": fwd_bpu * n / t_fwd / 1e9 / HBM_PEAK_GBS}}
 
 
 def time_render(O, L, F, torch, w, f, table, params, occ, dev):

@@ -9,15 +9,18 @@
 //           16384-entry table tile holding its entry; per-workgroup LDS
 //           histograms are added into per-tile counts;
 //   scan    one workgroup turns the counts into tile ranges, resets the append
-//           cursors and splits every tile into work items of <= 2^18 records;
+//           cursors and splits every tile into work items of <= 2^21 records
+//           (a hashed-level tile is one item; the coarse dense tiles, which
+//           every sample hits, are split);
 //   emit    the contributions (entry, w * dfeat_0, w * dfeat_1) are recomputed
 //           and appended to their tile's range: ranks come from LDS counters,
 //           one global atomic per (workgroup chunk, tile) reserves the space;
 //           the position gradient (for the warp) is formed here as well;
 //   accum   each work item sums its records into an LDS copy of the tile
-//           (ds_add_f32) and adds the tile into the gradient table once: a plain
-//           read-modify-write when the tile is a single item (it owns it),
-//           atomics for the few heavy tiles split over several items.
+//           (ds_add_f32); a tile that is a single item is added into the
+//           gradient table directly (plain read-modify-write, it owns the tile),
+//           the items of a split tile write their sums to partial slabs which
+//           a last launch adds up per entry -- no global atomics at all.
 //
 // Levels are split over the XCDs as in the forward (workgroup b serves level
 // group b % 8) in count and emit.
@@ -29,10 +32,14 @@ namespace nvr {
 
 constexpr int kTileBits = 14;
 constexpr int kTileEntries = 1 << kTileBits;
-constexpr uint32_t kItemRecords = 1u << 18;
+constexpr uint32_t kItemRecords = 1u << 21;
 constexpr int kBinBlock = 256;
 constexpr int kAccumBlock = 1024;
 constexpr int kMaxLpg = 4;   // levels per group (L <= 32)
+
+static int64_t max_items_of(int64_t cap, int L, int nt) {
+    return (int64_t)cap * L * 8 / kItemRecords + nt + 1;
+}
 
 int scatter_tiles(const GridParams &p) {
     return (int)(((int64_t)p.off[p.L] + kTileEntries - 1) >> kTileBits);
@@ -47,6 +54,8 @@ size_t scatter_ws_bytes(const GridParams &p, int64_t cap) {
     b += sizeof(uint32_t) * max_rec;                     // keys
     b = (b + 255) & ~size_t(255);
     b += sizeof(float2) * max_rec;                       // values
+    b = (b + 255) & ~size_t(255);
+    b += sizeof(float) * 2 * kTileEntries * (size_t)max_items_of(cap, p.L, nt);  // partial slabs
     return b;
 }
 
@@ -54,6 +63,7 @@ struct ScatterWs {
     uint32_t *count, *start, *cursor, *item_start, *n_items;
     uint32_t *keys;
     float2 *vals;
+    float *partial;       // [max_items][2 * kTileEntries]
 };
 
 static ScatterWs carve_scatter(const GridParams &p, void *ws, int64_t cap) {
@@ -72,6 +82,9 @@ static ScatterWs carve_scatter(const GridParams &p, void *ws, int64_t cap) {
     b += sizeof(uint32_t) * max_rec;
     b = (b + 255) & ~size_t(255);
     w.vals = (float2 *)((char *)ws + b);
+    b += sizeof(float2) * max_rec;
+    b = (b + 255) & ~size_t(255);
+    w.partial = (float *)((char *)ws + b);
     return w;
 }
 
@@ -278,7 +291,7 @@ __global__ void __launch_bounds__(kAccumBlock)
 scatter_accum(int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
               const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
               const uint32_t *__restrict__ keys, const float2 *__restrict__ vals,
-              float *__restrict__ dtable) {
+              float *__restrict__ dtable, float *__restrict__ partial) {
     extern __shared__ float acc[];    // [2 * kTileEntries]
     const uint32_t items = *n_items;
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
@@ -298,25 +311,59 @@ scatter_accum(int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ star
         for (int i = threadIdx.x; i < 2 * kTileEntries; i += blockDim.x) acc[i] = 0.f;
         __syncthreads();
         const uint32_t tbase = (uint32_t)t << kTileBits;
-        for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-            const uint32_t loc = keys[r] - tbase;
-            if (loc < (uint32_t)kTileEntries) {   // every record of the range is in the tile
-                const float2 v = vals[r];
-                atomicAdd(&acc[2 * loc], v.x);
-                atomicAdd(&acc[2 * loc + 1], v.y);
+        // kUnroll records per thread are loaded before any is added, so that
+        // each wave keeps several global loads in flight
+        constexpr int kUnroll = 8;
+        for (uint32_t r = r0 + threadIdx.x; r < r1; r += kUnroll * blockDim.x) {
+            uint32_t loc[kUnroll];
+            float2 v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t ru = r + u * blockDim.x;
+                loc[u] = 0xffffffffu;
+                if (ru < r1) {
+                    loc[u] = keys[ru] - tbase;
+                    v[u] = vals[ru];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (loc[u] < (uint32_t)kTileEntries) {   // every record of the range is in the tile
+                    atomicAdd(&acc[2 * loc[u]], v[u].x);
+                    atomicAdd(&acc[2 * loc[u] + 1], v[u].y);
+                }
             }
         }
         __syncthreads();
         const uint32_t ne = (n_entries - tbase) < (uint32_t)kTileEntries ? (n_entries - tbase)
                                                                           : (uint32_t)kTileEntries;
-        for (uint32_t i = threadIdx.x; i < 2 * ne; i += blockDim.x) {
-            const float v = acc[i];
-            if (v != 0.f) {
-                if (owner) dtable[2 * (size_t)tbase + i] += v;
-                else unsafeAtomicAdd(dtable + 2 * (size_t)tbase + i, v);
+        if (owner) {
+            for (uint32_t i = threadIdx.x; i < 2 * ne; i += blockDim.x) {
+                const float v = acc[i];
+                if (v != 0.f) dtable[2 * (size_t)tbase + i] += v;
             }
+        } else {
+            float *slab = partial + (size_t)it * (2 * kTileEntries);
+            for (uint32_t i = threadIdx.x; i < 2 * ne; i += blockDim.x) slab[i] = acc[i];
         }
         __syncthreads();
+    }
+}
+
+// Adds the partial slabs of every split tile into the gradient table.
+__global__ void __launch_bounds__(256)
+scatter_reduce(int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ item_start,
+               const float *__restrict__ partial, float *__restrict__ dtable) {
+    const int t = blockIdx.y;
+    const uint32_t i0 = item_start[t], i1 = item_start[t + 1];
+    if (i1 - i0 <= 1u) return;                 // single-item tiles are already added
+    const uint32_t tbase = (uint32_t)t << kTileBits;
+    const uint32_t ne2 = 2 * ((n_entries - tbase) < (uint32_t)kTileEntries ? (n_entries - tbase)
+                                                                              : (uint32_t)kTileEntries);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne2; i += gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (uint32_t it = i0; it < i1; ++it) acc += partial[(size_t)it * (2 * kTileEntries) + i];
+        if (acc != 0.f) dtable[2 * (size_t)tbase + i] += acc;
     }
 }
 
@@ -364,7 +411,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
 #undef NVR_EMIT_L
 #undef NVR_EMIT
     NVR_LAUNCHED();
-    const int64_t max_items = (int64_t)cap * p.L * 8 / kItemRecords + nt + 1;
+    const int64_t max_items = max_items_of(cap, p.L, nt);
     const unsigned ga = (unsigned)(max_items < 2048 ? max_items : 2048);
     static bool lds_ok = false;   // opt in to more than 64 KiB of dynamic LDS
     if (!lds_ok) {
@@ -374,7 +421,10 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
         lds_ok = true;
     }
     scatter_accum<<<ga, kAccumBlock, sizeof(float) * 2 * kTileEntries, st>>>(
-        nt, p.off[p.L], w.start, w.item_start, w.n_items, w.keys, w.vals, dtable);
+        nt, p.off[p.L], w.start, w.item_start, w.n_items, w.keys, w.vals, dtable, w.partial);
+    NVR_LAUNCHED();
+    scatter_reduce<<<dim3(2 * kTileEntries / 256, nt), 256, 0, st>>>(nt, p.off[p.L], w.item_start,
+                                                                      w.partial, dtable);
     NVR_LAUNCHED();
     return NVR_OK;
 }
