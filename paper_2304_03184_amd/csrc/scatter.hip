@@ -6,21 +6,25 @@
 // makes ~1.7 G of them.  Instead the scatter becomes a bucketed reduction:
 //
 //   count   every (sample, level, corner) contribution is assigned to the
-//           16384-entry table tile holding its entry; per-workgroup LDS
-//           histograms are added into per-tile counts;
+//           table tile (2^tb entries, tb >= 12) holding its entry; per-workgroup
+//           LDS histograms are added into per-tile counts;
 //   scan    one workgroup turns the counts into tile ranges, resets the append
-//           cursors and splits every tile into work items of <= 2^21 records
+//           cursors and splits every tile into work items of <= 2^19 records
 //           (a hashed-level tile is one item; the coarse dense tiles, which
 //           every sample hits, are split);
 //   emit    the contributions (entry, w * dfeat_0, w * dfeat_1) are recomputed
 //           and appended to their tile's range: ranks come from LDS counters,
 //           one global atomic per (workgroup chunk, tile) reserves the space;
 //           the position gradient (for the warp) is formed here as well;
-//   accum   each work item sums its records into an LDS copy of the tile
-//           (ds_add_f32); a tile that is a single item is added into the
-//           gradient table directly (plain read-modify-write, it owns the tile),
-//           the items of a split tile write their sums to partial slabs which
-//           a last launch adds up per entry -- no global atomics at all.
+//   accum   one wavefront per work item sums its records into its own LDS
+//           copy of the tile.  LDS float atomics cost about three cycles per
+//           lane, so there are none: the lanes of one instruction that name the
+//           same entry are serialised by a tag write and read-back (one winner
+//           per entry and round does a plain read-add-write; a wave's LDS
+//           operations complete in order).  A tile that is a single item is
+//           added into the gradient table directly (it owns the tile), the
+//           items of a split tile write their sums to partial slabs which a
+//           last launch adds up per entry -- no global float atomics at all.
 //
 // Levels are split over the XCDs as in the forward (workgroup b serves level
 // group b % 8) in count and emit.
@@ -30,20 +34,32 @@
 
 namespace nvr {
 
-constexpr int kTileBits = 14;
-constexpr int kTileEntries = 1 << kTileBits;
-constexpr uint32_t kItemRecords = 1u << 21;
+constexpr int kMinTileBits = 12;   // 32 KiB of float2 sums + 4 KiB of tags per wave
+constexpr int kMaxTileBits = 14;
+constexpr int kMaxTiles = 8192;
+constexpr uint32_t kItemRecords = 1u << 19;
 constexpr int kBinBlock = 256;
-constexpr int kAccumBlock = 1024;
 constexpr int kMaxLpg = 4;   // levels per group (L <= 32)
+constexpr int kMaxLevelTiles = 2048;   // tiles one level may span
+constexpr size_t kRecPad = 512;   // records of padding after keys and values (one accum window)
 
 static int64_t max_items_of(int64_t cap, int L, int nt) {
     return (int64_t)cap * L * 8 / kItemRecords + nt + 1;
 }
 
-int scatter_tiles(const GridParams &p) {
-    return (int)(((int64_t)p.off[p.L] + kTileEntries - 1) >> kTileBits);
+// smallest tile size (>= 2^12 entries) that keeps the tile count <= 8192
+static int tile_bits(const GridParams &p) {
+    int tb = kMinTileBits;
+    while (tb < kMaxTileBits && (((int64_t)p.off[p.L] + (1ll << tb) - 1) >> tb) > kMaxTiles) ++tb;
+    return tb;
 }
+
+int scatter_tiles(const GridParams &p) {
+    const int tb = tile_bits(p);
+    return (int)(((int64_t)p.off[p.L] + (1ll << tb) - 1) >> tb);
+}
+
+static size_t accum_lds_bytes(int tb) { return (sizeof(float2) + 1) << tb; }
 
 size_t scatter_ws_bytes(const GridParams &p, int64_t cap) {
     const int nt = scatter_tiles(p);
@@ -51,11 +67,11 @@ size_t scatter_ws_bytes(const GridParams &p, int64_t cap) {
     size_t b = 0;
     b += sizeof(uint32_t) * (size_t)(4 * (nt + 1) + 4);  // counts, starts, cursors, items, n
     b = (b + 255) & ~size_t(255);
-    b += sizeof(uint32_t) * max_rec;                     // keys
+    b += sizeof(uint32_t) * (max_rec + kRecPad);         // keys
     b = (b + 255) & ~size_t(255);
-    b += sizeof(float2) * max_rec;                       // values
+    b += sizeof(float2) * (max_rec + kRecPad);           // values
     b = (b + 255) & ~size_t(255);
-    b += sizeof(float) * 2 * kTileEntries * (size_t)max_items_of(cap, p.L, nt);  // partial slabs
+    b += (sizeof(float2) << tile_bits(p)) * (size_t)max_items_of(cap, p.L, nt);  // partial slabs
     return b;
 }
 
@@ -63,7 +79,7 @@ struct ScatterWs {
     uint32_t *count, *start, *cursor, *item_start, *n_items;
     uint32_t *keys;
     float2 *vals;
-    float *partial;       // [max_items][2 * kTileEntries]
+    float2 *partial;      // [max_items][tile entries]
 };
 
 static ScatterWs carve_scatter(const GridParams &p, void *ws, int64_t cap) {
@@ -79,12 +95,12 @@ static ScatterWs carve_scatter(const GridParams &p, void *ws, int64_t cap) {
     size_t b = sizeof(uint32_t) * (size_t)(4 * (nt + 1) + 4);
     b = (b + 255) & ~size_t(255);
     w.keys = (uint32_t *)((char *)ws + b);
-    b += sizeof(uint32_t) * max_rec;
+    b += sizeof(uint32_t) * (max_rec + kRecPad);
     b = (b + 255) & ~size_t(255);
     w.vals = (float2 *)((char *)ws + b);
-    b += sizeof(float2) * max_rec;
+    b += sizeof(float2) * (max_rec + kRecPad);
     b = (b + 255) & ~size_t(255);
-    w.partial = (float *)((char *)ws + b);
+    w.partial = (float2 *)((char *)ws + b);
     return w;
 }
 
@@ -94,8 +110,8 @@ __global__ void zero_u32(uint32_t *p, int n) {
 
 // ---------------------------------------------------------------- count
 __global__ void __launch_bounds__(kBinBlock)
-scatter_count(GridParams p, int n_tiles, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
-              const float *__restrict__ x, uint32_t *__restrict__ tile_count) {
+scatter_count(GridParams p, int tb, int n_tiles, int64_t n, const int32_t *__restrict__ n_dev,
+              int64_t cap, const float *__restrict__ x, uint32_t *__restrict__ tile_count) {
     extern __shared__ uint32_t hist[];
     for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) hist[t] = 0u;
     __syncthreads();
@@ -114,7 +130,7 @@ scatter_count(GridParams p, int n_tiles, int64_t n, const int32_t *__restrict__ 
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const uint32_t e = p.off[l] + corner_index(p, l, lp, k);
-                    atomicAdd(&hist[e >> kTileBits], 1u);
+                    atomicAdd(&hist[e >> tb], 1u);
                 }
             }
         }
@@ -172,29 +188,58 @@ scatter_scan(int n_tiles, const uint32_t *__restrict__ tile_count, uint32_t *__r
 }
 
 // ---------------------------------------------------------------- emit
+// In-place exclusive prefix sum of a[0, n) by the whole workgroup (part holds
+// blockDim.x partial sums).  Starts and ends with a barrier.
+__device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
+    __syncthreads();
+    const int nt = blockDim.x;
+    const int seg = (n + nt - 1) / nt;
+    const int i0 = threadIdx.x * seg;
+    const int i1 = i0 + seg < n ? i0 + seg : n;
+    uint32_t s = 0;
+    for (int i = i0; i < i1; ++i) s += a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < nt; d <<= 1) {
+        const uint32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - s;
+    for (int i = i0; i < i1; ++i) {
+        const uint32_t c = a[i];
+        a[i] = run;
+        run += c;
+    }
+    __syncthreads();
+}
+
+// One chunk of blockDim.x samples and one level at a time: the chunk's 8 records
+// per sample are ranked within their tiles (LDS counters), space is reserved
+// per tile with one global atomic, the records are staged in LDS in tile order
+// and then written out by consecutive threads to consecutive positions, so
+// that each tile's run is stored contiguously.
 template <bool PLANAR, int LPG>
 __global__ void __launch_bounds__(kBinBlock)
-scatter_emit(GridParams p, int n_tiles, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+scatter_emit(GridParams p, int tb, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const float *__restrict__ x, const uint32_t *__restrict__ table,
-             const float *__restrict__ dfeat, const uint32_t *__restrict__ start,
-             uint32_t *__restrict__ cursor, uint32_t *__restrict__ keys, float2 *__restrict__ vals,
-             float *__restrict__ dx_parts) {
-    extern __shared__ uint32_t lds[];
-    uint32_t *hist = lds;                 // [n_tiles] ranks
-    uint32_t *base = lds + n_tiles;       // [n_tiles] reserved positions
-    uint32_t *end = lds + 2 * n_tiles;    // [n_tiles] end of each tile's range
-    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) end[t] = start[t + 1];
+             const float *__restrict__ dfeat, uint32_t n_records, uint32_t *__restrict__ cursor,
+             uint32_t *__restrict__ keys, float2 *__restrict__ vals, float *__restrict__ dx_parts) {
+    __shared__ uint32_t hist[kMaxLevelTiles];   // per-tile counts, then local offsets
+    __shared__ uint32_t delta[kMaxLevelTiles];  // global position minus local offset
+    __shared__ uint32_t part[kBinBlock];
+    __shared__ uint32_t skey[8 * kBinBlock];
+    __shared__ float2 sval[8 * kBinBlock];
     const int64_t count = count_of(n, n_dev, cap);
     const int g = blockIdx.x % kXcds;
     const int64_t chunks = gridDim.x / kXcds;
     const int lpg = LPG;
     for (int64_t c = blockIdx.x / kXcds; c * blockDim.x < count; c += chunks) {
-        for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) hist[t] = 0u;
-        __syncthreads();
         const int64_t s = c * blockDim.x + threadIdx.x;
         const bool valid = s < count;
-        uint32_t ent[LPG * 8], rank[LPG * 8];
-        float v0[LPG * 8], v1[LPG * 8];
+        const int64_t left = count - c * blockDim.x;
+        const uint32_t n_rec = 8u * (uint32_t)(left < (int64_t)blockDim.x ? left : blockDim.x);
         float d0 = 0.f, d1 = 0.f, d2 = 0.f;
         float px = 0.f, py = 0.f, pz = 0.f;
         if (valid) {
@@ -202,14 +247,18 @@ scatter_emit(GridParams p, int n_tiles, int64_t n, const int32_t *__restrict__ n
             py = x[3 * s + 1];
             pz = x[3 * s + 2];
         }
-#pragma unroll
         for (int m = 0; m < LPG; ++m) {
             const int l = g + kXcds * m;
-            const bool on = valid && l < p.L;
-            float g0 = 0.f, g1 = 0.f;
-            LevelPos lp;
-            if (on) {
-                lp = level_pos(p, l, px, py, pz);
+            if (l >= p.L) break;                       // the same for the whole workgroup
+            const int t_lo = (int)((uint32_t)p.off[l] >> tb);
+            const int n_lt = (int)((uint32_t)(p.off[l + 1] - 1) >> tb) - t_lo + 1;
+            for (int t = threadIdx.x; t < n_lt; t += blockDim.x) hist[t] = 0u;
+            __syncthreads();
+            uint32_t ent[8], rank[8];
+            float v0[8], v1[8];
+            if (valid) {
+                const LevelPos lp = level_pos(p, l, px, py, pz);
+                float g0, g1;
                 if (PLANAR) {
                     const float *src = dfeat + ((size_t)g * cap + s) * (2 * lpg) + 2 * m;
                     g0 = src[0];
@@ -218,18 +267,15 @@ scatter_emit(GridParams p, int n_tiles, int64_t n, const int32_t *__restrict__ n
                     g0 = dfeat[(size_t)s * (2 * p.L) + 2 * l];
                     g1 = dfeat[(size_t)s * (2 * p.L) + 2 * l + 1];
                 }
-            }
-            float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+                float e0 = 0.f, e1 = 0.f, e2 = 0.f;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int r = 8 * m + k;
-                if (on) {
+                for (int k = 0; k < 8; ++k) {
                     const float w = corner_weight(lp, k);
                     const uint32_t e = p.off[l] + corner_index(p, l, lp, k);
-                    ent[r] = e;
-                    v0[r] = w * g0;
-                    v1[r] = w * g1;
-                    rank[r] = atomicAdd(&hist[e >> kTileBits], 1u);
+                    ent[k] = e;
+                    v0[k] = w * g0;
+                    v1[k] = w * g1;
+                    rank[k] = atomicAdd(&hist[(int)(e >> tb) - t_lo], 1u);
                     if (dx_parts != nullptr) {
                         const uint32_t v = table[e];
                         const float tg = f16_bits_to_f32((uint16_t)(v & 0xffffu)) * g0 +
@@ -239,36 +285,41 @@ scatter_emit(GridParams p, int n_tiles, int64_t n, const int32_t *__restrict__ n
                         e1 += dw.y * tg;
                         e2 += dw.z * tg;
                     }
-                } else {
-                    ent[r] = 0xffffffffu;
+                }
+                if (dx_parts != nullptr) {
+                    const float N = (float)p.res[l];
+                    if (lp.inside[0]) d0 += e0 * N * (float)p.inv_side[0];
+                    if (lp.inside[1]) d1 += e1 * N * (float)p.inv_side[1];
+                    if (lp.inside[2]) d2 += e2 * N * (float)p.inv_side[2];
                 }
             }
-            if (on && dx_parts != nullptr) {
-                const float N = (float)p.res[l];
-                if (lp.inside[0]) d0 += e0 * N * (float)p.inv_side[0];
-                if (lp.inside[1]) d1 += e1 * N * (float)p.inv_side[1];
-                if (lp.inside[2]) d2 += e2 * N * (float)p.inv_side[2];
+            __syncthreads();
+            for (int t = threadIdx.x; t < n_lt; t += blockDim.x) {
+                const uint32_t h = hist[t];
+                delta[t] = h ? atomicAdd(&cursor[t_lo + t], h) : 0u;
             }
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-            const uint32_t h = hist[t];
-            base[t] = h ? atomicAdd(&cursor[t], h) : 0u;
-        }
-        __syncthreads();
+            block_exclusive_scan(hist, n_lt, part);
+            for (int t = threadIdx.x; t < n_lt; t += blockDim.x) delta[t] -= hist[t];
+            if (valid) {
 #pragma unroll
-        for (int r = 0; r < LPG * 8; ++r) {
-            const uint32_t e = ent[r];
-            if (e != 0xffffffffu) {
-                const uint32_t t = e >> kTileBits;
-                const uint32_t pos = base[t] + rank[r];
-                // the count pass saw the same contributions; the guard keeps a
-                // record inside its tile's range whatever happens
-                if (pos < end[t]) {
-                    keys[pos] = e;
-                    vals[pos] = make_float2(v0[r], v1[r]);
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t slot = hist[(int)(ent[k] >> tb) - t_lo] + rank[k];
+                    skey[slot] = ent[k];
+                    sval[slot] = make_float2(v0[k], v1[k]);
                 }
             }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < n_rec; i += blockDim.x) {
+                const uint32_t e = skey[i];
+                // the count pass saw the same contributions, so pos stays inside
+                // the tile's range; the bound keeps every store inside the buffers
+                const uint32_t pos = delta[(int)(e >> tb) - t_lo] + i;
+                if (pos < n_records) {
+                    keys[pos] = e;
+                    vals[pos] = sval[i];
+                }
+            }
+            __syncthreads();
         }
         if (valid && dx_parts != nullptr) {
             if (PLANAR) {   // per-group partials, summed by the consumer
@@ -282,17 +333,20 @@ scatter_emit(GridParams p, int n_tiles, int64_t n, const int32_t *__restrict__ n
                 unsafeAtomicAdd(dx_parts + 3 * s + 2, d2);
             }
         }
-        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------- accumulate
-__global__ void __launch_bounds__(kAccumBlock)
-scatter_accum(int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
+// One wavefront (the whole workgroup) per work item.
+__global__ void __launch_bounds__(64)
+scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
               const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
               const uint32_t *__restrict__ keys, const float2 *__restrict__ vals,
-              float *__restrict__ dtable, float *__restrict__ partial) {
-    extern __shared__ float acc[];    // [2 * kTileEntries]
+              float2 *__restrict__ dtable, float2 *__restrict__ partial) {
+    extern __shared__ float2 acc[];                                   // [te] sums
+    const uint32_t te = 1u << tb;
+    uint8_t *tag = reinterpret_cast<uint8_t *>(acc + te);            // [te]
+    const uint32_t lane = threadIdx.x;
     const uint32_t items = *n_items;
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
         // tile of this item: last t with item_start[t] <= it
@@ -308,69 +362,122 @@ scatter_accum(int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ star
         const uint32_t r1e = r0 + kItemRecords;
         const uint32_t r1 = r1e < start[t + 1] ? r1e : start[t + 1];
         const bool owner = (item_start[t + 1] - item_start[t]) == 1u;
-        for (int i = threadIdx.x; i < 2 * kTileEntries; i += blockDim.x) acc[i] = 0.f;
-        __syncthreads();
-        const uint32_t tbase = (uint32_t)t << kTileBits;
-        // kUnroll records per thread are loaded before any is added, so that
-        // each wave keeps several global loads in flight
-        constexpr int kUnroll = 8;
-        for (uint32_t r = r0 + threadIdx.x; r < r1; r += kUnroll * blockDim.x) {
-            uint32_t loc[kUnroll];
-            float2 v[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t ru = r + u * blockDim.x;
-                loc[u] = 0xffffffffu;
-                if (ru < r1) {
-                    loc[u] = keys[ru] - tbase;
-                    v[u] = vals[ru];
-                }
+        for (uint32_t i = lane; i < te; i += 64) acc[i] = make_float2(0.f, 0.f);
+        const uint32_t tbase = (uint32_t)t << tb;
+        // Each lane takes kPer consecutive records of a 64 * kPer window (two
+        // 16-byte key loads, four 16-byte value loads), so a run of equal keys
+        // -- consecutive samples in one coarse cell -- spreads over the rounds
+        // of one lane instead of the lanes of one instruction.  Windows start
+        // 8-aligned at or below r0; records outside [r0, r1) are masked off and
+        // the buffers carry one window of padding.  The next window is loaded
+        // while the current one is added.
+        constexpr uint32_t kPer = 8;
+        constexpr uint32_t kWin = 64u * kPer;
+        const uint32_t b0 = r0 & ~(kPer - 1u);
+        uint4 ka, kb;
+        float4 va, vb, vc, vd;
+        {
+            const uint32_t i = b0 + lane * kPer;
+            ka = *reinterpret_cast<const uint4 *>(keys + i);
+            kb = *reinterpret_cast<const uint4 *>(keys + i + 4);
+            va = *reinterpret_cast<const float4 *>(vals + i);
+            vb = *reinterpret_cast<const float4 *>(vals + i + 2);
+            vc = *reinterpret_cast<const float4 *>(vals + i + 4);
+            vd = *reinterpret_cast<const float4 *>(vals + i + 6);
+        }
+        for (uint32_t base = b0; base < r1; base += kWin) {
+            const uint32_t key[kPer] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+            const float v0[kPer] = {va.x, va.z, vb.x, vb.z, vc.x, vc.z, vd.x, vd.z};
+            const float v1[kPer] = {va.y, va.w, vb.y, vb.w, vc.y, vc.w, vd.y, vd.w};
+            const uint32_t nb = base + kWin;
+            if (nb < r1) {
+                const uint32_t i = nb + lane * kPer;
+                ka = *reinterpret_cast<const uint4 *>(keys + i);
+                kb = *reinterpret_cast<const uint4 *>(keys + i + 4);
+                va = *reinterpret_cast<const float4 *>(vals + i);
+                vb = *reinterpret_cast<const float4 *>(vals + i + 2);
+                vc = *reinterpret_cast<const float4 *>(vals + i + 4);
+                vd = *reinterpret_cast<const float4 *>(vals + i + 6);
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                if (loc[u] < (uint32_t)kTileEntries) {   // every record of the range is in the tile
-                    atomicAdd(&acc[2 * loc[u]], v[u].x);
-                    atomicAdd(&acc[2 * loc[u] + 1], v[u].y);
+            for (uint32_t u = 0; u < kPer; ++u) {
+                const uint32_t rec = base + lane * kPer + u;
+                const uint32_t loc = key[u] - tbase;
+                // every record of the range is in the tile; the bound is a guard
+                bool pend = rec >= r0 && rec < r1 && loc < te;
+                // one round: every pending lane writes its lane id to the tag of
+                // its entry and reads it back; exactly one lane per entry sees its
+                // own id and adds (the others retry in the next round)
+                while (__ballot(pend)) {
+                    // wavefront-scope relaxed atomics: plain LDS byte accesses
+                    // that the compiler may neither drop nor merge
+                    if (pend)
+                        __hip_atomic_store(tag + loc, (uint8_t)lane, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    if (pend && __hip_atomic_load(tag + loc, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WAVEFRONT) == (uint8_t)lane) {
+                        float2 a = acc[loc];
+                        a.x += v0[u];
+                        a.y += v1[u];
+                        acc[loc] = a;
+                        pend = false;
+                    }
                 }
             }
         }
-        __syncthreads();
-        const uint32_t ne = (n_entries - tbase) < (uint32_t)kTileEntries ? (n_entries - tbase)
-                                                                          : (uint32_t)kTileEntries;
+        const uint32_t ne = (n_entries - tbase) < te ? (n_entries - tbase) : te;
         if (owner) {
-            for (uint32_t i = threadIdx.x; i < 2 * ne; i += blockDim.x) {
-                const float v = acc[i];
-                if (v != 0.f) dtable[2 * (size_t)tbase + i] += v;
+            for (uint32_t i = lane; i < ne; i += 64) {
+                const float2 a = acc[i];
+                if (a.x != 0.f || a.y != 0.f) {
+                    float2 d = dtable[tbase + i];
+                    d.x += a.x;
+                    d.y += a.y;
+                    dtable[tbase + i] = d;
+                }
             }
         } else {
-            float *slab = partial + (size_t)it * (2 * kTileEntries);
-            for (uint32_t i = threadIdx.x; i < 2 * ne; i += blockDim.x) slab[i] = acc[i];
+            float2 *slab = partial + (size_t)it * te;
+            for (uint32_t i = lane; i < ne; i += 64) slab[i] = acc[i];
         }
-        __syncthreads();
     }
 }
 
 // Adds the partial slabs of every split tile into the gradient table.
 __global__ void __launch_bounds__(256)
-scatter_reduce(int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ item_start,
-               const float *__restrict__ partial, float *__restrict__ dtable) {
+scatter_reduce(int tb, uint32_t n_entries, const uint32_t *__restrict__ item_start,
+               const float2 *__restrict__ partial, float2 *__restrict__ dtable) {
     const int t = blockIdx.y;
     const uint32_t i0 = item_start[t], i1 = item_start[t + 1];
     if (i1 - i0 <= 1u) return;                 // single-item tiles are already added
-    const uint32_t tbase = (uint32_t)t << kTileBits;
-    const uint32_t ne2 = 2 * ((n_entries - tbase) < (uint32_t)kTileEntries ? (n_entries - tbase)
-                                                                              : (uint32_t)kTileEntries);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne2; i += gridDim.x * blockDim.x) {
-        float acc = 0.f;
-        for (uint32_t it = i0; it < i1; ++it) acc += partial[(size_t)it * (2 * kTileEntries) + i];
-        if (acc != 0.f) dtable[2 * (size_t)tbase + i] += acc;
+    const uint32_t te = 1u << tb;
+    const uint32_t tbase = (uint32_t)t << tb;
+    const uint32_t ne = (n_entries - tbase) < te ? (n_entries - tbase) : te;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += gridDim.x * blockDim.x) {
+        float a0 = 0.f, a1 = 0.f;
+        for (uint32_t it = i0; it < i1; ++it) {
+            const float2 v = partial[(size_t)it * te + i];
+            a0 += v.x;
+            a1 += v.y;
+        }
+        if (a0 != 0.f || a1 != 0.f) {
+            float2 d = dtable[tbase + i];
+            d.x += a0;
+            d.y += a1;
+            dtable[tbase + i] = d;
+        }
     }
 }
 
 nvr_status scatter_check(const GridParams &p) {
     const int nt = scatter_tiles(p);
-    NVR_REQUIRE(nt >= 1 && nt <= 8192, NVR_EUNSUPPORTED, "binned scatter needs <= 8192 tiles");
+    NVR_REQUIRE(nt >= 1 && nt <= kMaxTiles, NVR_EUNSUPPORTED,
+                "binned scatter needs <= 8192 tiles of <= 2^14 entries");
     NVR_REQUIRE((p.L + kXcds - 1) / kXcds <= kMaxLpg, NVR_EUNSUPPORTED, "too many levels");
+    const int tb = tile_bits(p);
+    for (int l = 0; l < p.L; ++l)
+        NVR_REQUIRE(((p.off[l + 1] - 1) >> tb) - (p.off[l] >> tb) + 1 <= kMaxLevelTiles,
+                    NVR_EUNSUPPORTED, "a level spans too many scatter tiles");
     return NVR_OK;
 }
 
@@ -379,22 +486,25 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
                           float *dx_parts, bool planar, void *ws, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
+    const int tb = tile_bits(p);
     const int nt = scatter_tiles(p);
     ScatterWs w = carve_scatter(p, ws, cap);
+    const uint32_t n_records = (uint32_t)((uint64_t)cap * p.L * 8 < 0xffffffffull
+                                              ? (uint64_t)cap * p.L * 8 : 0xffffffffull);
     zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>(w.count, nt + 1);
     NVR_LAUNCHED();
     const unsigned chunks = grid_for(cap, kBinBlock, 512);
     const unsigned gr = chunks * kXcds;
-    scatter_count<<<gr, kBinBlock, sizeof(uint32_t) * nt, st>>>(p, nt, n, n_dev, cap, x, w.count);
+    scatter_count<<<gr, kBinBlock, sizeof(uint32_t) * nt, st>>>(p, tb, nt, n, n_dev, cap, x,
+                                                                  w.count);
     NVR_LAUNCHED();
     scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items);
     NVR_LAUNCHED();
     const int lpg = (p.L + kXcds - 1) / kXcds;
-    const size_t emit_lds = 3 * sizeof(uint32_t) * nt;
 #define NVR_EMIT(PL, LP)                                                                       \
-    scatter_emit<PL, LP><<<gr, kBinBlock, emit_lds, st>>>(p, nt, n, n_dev, cap, x,             \
+    scatter_emit<PL, LP><<<gr, kBinBlock, 0, st>>>(p, tb, n, n_dev, cap, x,                    \
                                                           (const uint32_t *)table, dfeat,       \
-                                                          w.start, w.cursor, w.keys, w.vals,   \
+                                                          n_records, w.cursor, w.keys, w.vals, \
                                                           dx_parts)
 #define NVR_EMIT_L(PL)                                                                         \
     switch (lpg) {                                                                             \
@@ -412,19 +522,22 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
 #undef NVR_EMIT
     NVR_LAUNCHED();
     const int64_t max_items = max_items_of(cap, p.L, nt);
-    const unsigned ga = (unsigned)(max_items < 2048 ? max_items : 2048);
-    static bool lds_ok = false;   // opt in to more than 64 KiB of dynamic LDS
-    if (!lds_ok) {
-        NVR_HIP(hipFuncSetAttribute((const void *)scatter_accum,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(sizeof(float) * 2 * kTileEntries)));
-        lds_ok = true;
+    const unsigned ga = (unsigned)(max_items < 4096 ? max_items : 4096);
+    const size_t acc_lds = accum_lds_bytes(tb);
+    if (acc_lds > 65536) {   // opt in to more than 64 KiB of dynamic LDS
+        static bool lds_ok = false;
+        if (!lds_ok) {
+            NVR_HIP(hipFuncSetAttribute((const void *)scatter_accum,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)accum_lds_bytes(kMaxTileBits)));
+            lds_ok = true;
+        }
     }
-    scatter_accum<<<ga, kAccumBlock, sizeof(float) * 2 * kTileEntries, st>>>(
-        nt, p.off[p.L], w.start, w.item_start, w.n_items, w.keys, w.vals, dtable, w.partial);
+    scatter_accum<<<ga, 64, acc_lds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
+                                           w.keys, w.vals, (float2 *)dtable, w.partial);
     NVR_LAUNCHED();
-    scatter_reduce<<<dim3(2 * kTileEntries / 256, nt), 256, 0, st>>>(nt, p.off[p.L], w.item_start,
-                                                                      w.partial, dtable);
+    scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
+        tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
     NVR_LAUNCHED();
     return NVR_OK;
 }
