@@ -6,10 +6,10 @@
 // makes ~1.7 G of them.  Instead the scatter becomes a bucketed reduction:
 //
 //   count   every (sample, level, corner) contribution is assigned to the
-//           table tile (2^tb entries, tb >= 12) holding its entry; per-workgroup
+//           table tile (2^tb entries, tb >= 10) holding its entry; per-workgroup
 //           LDS histograms are added into per-tile counts;
 //   scan    one workgroup turns the counts into tile ranges, resets the append
-//           cursors and splits every tile into work items of <= 2^19 records
+//           cursors and splits every tile into work items of <= 2^17 records
 //           (a hashed-level tile is one item; the coarse dense tiles, which
 //           every sample hits, are split);
 //   emit    the contributions (entry, w * dfeat_0, w * dfeat_1) are recomputed
@@ -34,20 +34,23 @@
 
 namespace nvr {
 
-constexpr int kMinTileBits = 12;   // 32 KiB of float2 sums + 4 KiB of tags per wave
+constexpr int kMinTileBits = 10;   // 8 KiB of float2 sums + 1 KiB of tags per wave
 constexpr int kMaxTileBits = 14;
 constexpr int kMaxTiles = 8192;
-constexpr uint32_t kItemRecords = 1u << 19;
-constexpr int kBinBlock = 256;
+constexpr uint32_t kItemRecords = 1u << 17;
+constexpr int kBinBlock = 256;     // count
+constexpr int kEmitBlock = 1024;   // emit: samples per chunk
 constexpr int kMaxLpg = 4;   // levels per group (L <= 32)
 constexpr int kMaxLevelTiles = 2048;   // tiles one level may span
+constexpr size_t kEmitLds = sizeof(uint32_t) * (2 * kMaxLevelTiles + kEmitBlock + 8 * kEmitBlock) +
+                            sizeof(float2) * 8 * kEmitBlock;   // 116 KiB
 constexpr size_t kRecPad = 512;   // records of padding after keys and values (one accum window)
 
 static int64_t max_items_of(int64_t cap, int L, int nt) {
     return (int64_t)cap * L * 8 / kItemRecords + nt + 1;
 }
 
-// smallest tile size (>= 2^12 entries) that keeps the tile count <= 8192
+// smallest tile size (>= 2^10 entries) that keeps the tile count <= 8192
 static int tile_bits(const GridParams &p) {
     int tb = kMinTileBits;
     while (tb < kMaxTileBits && (((int64_t)p.off[p.L] + (1ll << tb) - 1) >> tb) > kMaxTiles) ++tb;
@@ -221,16 +224,17 @@ __device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
 // and then written out by consecutive threads to consecutive positions, so
 // that each tile's run is stored contiguously.
 template <bool PLANAR, int LPG>
-__global__ void __launch_bounds__(kBinBlock)
+__global__ void __launch_bounds__(kEmitBlock)
 scatter_emit(GridParams p, int tb, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const float *__restrict__ x, const uint32_t *__restrict__ table,
              const float *__restrict__ dfeat, uint32_t n_records, uint32_t *__restrict__ cursor,
              uint32_t *__restrict__ keys, float2 *__restrict__ vals, float *__restrict__ dx_parts) {
-    __shared__ uint32_t hist[kMaxLevelTiles];   // per-tile counts, then local offsets
-    __shared__ uint32_t delta[kMaxLevelTiles];  // global position minus local offset
-    __shared__ uint32_t part[kBinBlock];
-    __shared__ uint32_t skey[8 * kBinBlock];
-    __shared__ float2 sval[8 * kBinBlock];
+    extern __shared__ uint32_t lds[];
+    uint32_t *hist = lds;                               // [kMaxLevelTiles] counts, then offsets
+    uint32_t *delta = hist + kMaxLevelTiles;            // [kMaxLevelTiles] global - local position
+    uint32_t *part = delta + kMaxLevelTiles;            // [kEmitBlock]
+    uint32_t *skey = part + kEmitBlock;                 // [8 * kEmitBlock] staged records
+    float2 *sval = reinterpret_cast<float2 *>(skey + 8 * kEmitBlock);
     const int64_t count = count_of(n, n_dev, cap);
     const int g = blockIdx.x % kXcds;
     const int64_t chunks = gridDim.x / kXcds;
@@ -427,13 +431,22 @@ scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restric
         }
         const uint32_t ne = (n_entries - tbase) < te ? (n_entries - tbase) : te;
         if (owner) {
-            for (uint32_t i = lane; i < ne; i += 64) {
-                const float2 a = acc[i];
-                if (a.x != 0.f || a.y != 0.f) {
-                    float2 d = dtable[tbase + i];
-                    d.x += a.x;
-                    d.y += a.y;
-                    dtable[tbase + i] = d;
+            // 16 entries per lane at a time: all table loads are issued before
+            // the first add (indices past the tile end are clamped, not stored)
+            for (uint32_t i0 = 0; i0 < ne; i0 += 64u * 16u) {
+                float2 a[16], d[16];
+#pragma unroll
+                for (uint32_t j = 0; j < 16; ++j) {
+                    const uint32_t i = i0 + 64u * j + lane;
+                    const uint32_t ic = i < ne ? i : ne - 1u;
+                    a[j] = acc[ic];
+                    d[j] = dtable[tbase + ic];
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < 16; ++j) {
+                    const uint32_t i = i0 + 64u * j + lane;
+                    if (i < ne && (a[j].x != 0.f || a[j].y != 0.f))
+                        dtable[tbase + i] = make_float2(d[j].x + a[j].x, d[j].y + a[j].y);
                 }
             }
         } else {
@@ -495,6 +508,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     NVR_LAUNCHED();
     const unsigned chunks = grid_for(cap, kBinBlock, 512);
     const unsigned gr = chunks * kXcds;
+    const unsigned gre = grid_for(cap, kEmitBlock, 64) * kXcds;
     scatter_count<<<gr, kBinBlock, sizeof(uint32_t) * nt, st>>>(p, tb, nt, n, n_dev, cap, x,
                                                                   w.count);
     NVR_LAUNCHED();
@@ -502,7 +516,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     NVR_LAUNCHED();
     const int lpg = (p.L + kXcds - 1) / kXcds;
 #define NVR_EMIT(PL, LP)                                                                       \
-    scatter_emit<PL, LP><<<gr, kBinBlock, 0, st>>>(p, tb, n, n_dev, cap, x,                    \
+    scatter_emit<PL, LP><<<gre, kEmitBlock, kEmitLds, st>>>(p, tb, n, n_dev, cap, x,           \
                                                           (const uint32_t *)table, dfeat,       \
                                                           n_records, w.cursor, w.keys, w.vals, \
                                                           dx_parts)
@@ -513,6 +527,16 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     case 3: NVR_EMIT(PL, 3); break;                                                            \
     default: NVR_EMIT(PL, 4); break;                                                           \
     }
+    static bool emit_lds_ok = false;   // opt in to 116 KiB of dynamic LDS (every instance)
+    if (!emit_lds_ok) {
+        const void *fns[] = {(const void *)scatter_emit<true, 1>, (const void *)scatter_emit<true, 2>,
+                             (const void *)scatter_emit<true, 3>, (const void *)scatter_emit<true, 4>,
+                             (const void *)scatter_emit<false, 1>, (const void *)scatter_emit<false, 2>,
+                             (const void *)scatter_emit<false, 3>, (const void *)scatter_emit<false, 4>};
+        for (const void *f : fns)
+            NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kEmitLds));
+        emit_lds_ok = true;
+    }
     if (planar) {
         NVR_EMIT_L(true)
     } else {
@@ -522,7 +546,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
 #undef NVR_EMIT
     NVR_LAUNCHED();
     const int64_t max_items = max_items_of(cap, p.L, nt);
-    const unsigned ga = (unsigned)(max_items < 4096 ? max_items : 4096);
+    const unsigned ga = (unsigned)(max_items < 65535 ? max_items : 65535);
     const size_t acc_lds = accum_lds_bytes(tb);
     if (acc_lds > 65536) {   // opt in to more than 64 KiB of dynamic LDS
         static bool lds_ok = false;
