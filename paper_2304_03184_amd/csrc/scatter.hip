@@ -15,7 +15,12 @@
 //   emit    the contributions (entry, w * dfeat_0, w * dfeat_1) are recomputed
 //           and appended to their tile's range: ranks come from LDS counters,
 //           one global atomic per (workgroup chunk, tile) reserves the space;
-//           the position gradient (for the warp) is formed here as well;
+//           the position gradient (for the warp) is formed here as well.  A
+//           record is 8 bytes: the two values rounded to nearest at
+//           23 - kb mantissa bits, kb = ceil(tb / 2), whose low kb bits then
+//           carry the entry's index inside the tile (high half in the first
+//           value, low half in the second) -- the tile itself is implied by
+//           the range the record sits in;
 //   accum   one wavefront per work item sums its records into its own LDS
 //           copy of the tile.  LDS float atomics cost about three cycles per
 //           lane, so there are none: the lanes of one instruction that name the
@@ -42,9 +47,9 @@ constexpr int kBinBlock = 256;     // count
 constexpr int kEmitBlock = 1024;   // emit: samples per chunk
 constexpr int kMaxLpg = 4;   // levels per group (L <= 32)
 constexpr int kMaxLevelTiles = 2048;   // tiles one level may span
-constexpr size_t kEmitLds = sizeof(uint32_t) * (2 * kMaxLevelTiles + kEmitBlock + 8 * kEmitBlock) +
-                            sizeof(float2) * 8 * kEmitBlock;   // 116 KiB
-constexpr size_t kRecPad = 512;   // records of padding after keys and values (one accum window)
+constexpr size_t kEmitLds = sizeof(uint32_t) * (2 * kMaxLevelTiles + kEmitBlock) +
+                            (sizeof(uint2) + sizeof(uint16_t)) * 8 * kEmitBlock;   // 100 KiB
+constexpr size_t kRecPad = 512;   // records of padding after the record buffer (one accum window)
 
 static int64_t max_items_of(int64_t cap, int L, int nt) {
     return (int64_t)cap * L * 8 / kItemRecords + nt + 1;
@@ -70,9 +75,7 @@ size_t scatter_ws_bytes(const GridParams &p, int64_t cap) {
     size_t b = 0;
     b += sizeof(uint32_t) * (size_t)(4 * (nt + 1) + 4);  // counts, starts, cursors, items, n
     b = (b + 255) & ~size_t(255);
-    b += sizeof(uint32_t) * (max_rec + kRecPad);         // keys
-    b = (b + 255) & ~size_t(255);
-    b += sizeof(float2) * (max_rec + kRecPad);           // values
+    b += sizeof(uint2) * (max_rec + kRecPad);            // packed records
     b = (b + 255) & ~size_t(255);
     b += (sizeof(float2) << tile_bits(p)) * (size_t)max_items_of(cap, p.L, nt);  // partial slabs
     return b;
@@ -80,8 +83,7 @@ size_t scatter_ws_bytes(const GridParams &p, int64_t cap) {
 
 struct ScatterWs {
     uint32_t *count, *start, *cursor, *item_start, *n_items;
-    uint32_t *keys;
-    float2 *vals;
+    uint2 *rec;           // packed records
     float2 *partial;      // [max_items][tile entries]
 };
 
@@ -97,11 +99,8 @@ static ScatterWs carve_scatter(const GridParams &p, void *ws, int64_t cap) {
     w.n_items = u + 4 * (nt + 1);
     size_t b = sizeof(uint32_t) * (size_t)(4 * (nt + 1) + 4);
     b = (b + 255) & ~size_t(255);
-    w.keys = (uint32_t *)((char *)ws + b);
-    b += sizeof(uint32_t) * (max_rec + kRecPad);
-    b = (b + 255) & ~size_t(255);
-    w.vals = (float2 *)((char *)ws + b);
-    b += sizeof(float2) * (max_rec + kRecPad);
+    w.rec = (uint2 *)((char *)ws + b);
+    b += sizeof(uint2) * (max_rec + kRecPad);
     b = (b + 255) & ~size_t(255);
     w.partial = (float2 *)((char *)ws + b);
     return w;
@@ -191,6 +190,19 @@ scatter_scan(int n_tiles, const uint32_t *__restrict__ tile_count, uint32_t *__r
 }
 
 // ---------------------------------------------------------------- emit
+// Packed record: each value rounded to nearest (ties away from zero) at its
+// low kb mantissa bits, which then hold half of the in-tile index.  A non-finite
+// value stays non-finite.
+__device__ inline uint32_t round_low_bits(float v, int kb) {
+    const uint32_t b = __float_as_uint(v) + (1u << (kb - 1));
+    return b & ~((1u << kb) - 1u);
+}
+
+__device__ inline uint2 pack_record(uint32_t loc, int kb, float v0, float v1) {
+    const uint32_t m = (1u << kb) - 1u;
+    return make_uint2(round_low_bits(v0, kb) | (loc >> kb), round_low_bits(v1, kb) | (loc & m));
+}
+
 // In-place exclusive prefix sum of a[0, n) by the whole workgroup (part holds
 // blockDim.x partial sums).  Starts and ends with a barrier.
 __device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
@@ -228,17 +240,18 @@ __global__ void __launch_bounds__(kEmitBlock)
 scatter_emit(GridParams p, int tb, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const float *__restrict__ x, const uint32_t *__restrict__ table,
              const float *__restrict__ dfeat, uint32_t n_records, uint32_t *__restrict__ cursor,
-             uint32_t *__restrict__ keys, float2 *__restrict__ vals, float *__restrict__ dx_parts) {
+             uint2 *__restrict__ recs, float *__restrict__ dx_parts) {
     extern __shared__ uint32_t lds[];
     uint32_t *hist = lds;                               // [kMaxLevelTiles] counts, then offsets
     uint32_t *delta = hist + kMaxLevelTiles;            // [kMaxLevelTiles] global - local position
     uint32_t *part = delta + kMaxLevelTiles;            // [kEmitBlock]
-    uint32_t *skey = part + kEmitBlock;                 // [8 * kEmitBlock] staged records
-    float2 *sval = reinterpret_cast<float2 *>(skey + 8 * kEmitBlock);
+    uint2 *srec = reinterpret_cast<uint2 *>(part + kEmitBlock);   // [8 * kEmitBlock] staged
+    uint16_t *stile = reinterpret_cast<uint16_t *>(srec + 8 * kEmitBlock);   // their tiles - t_lo
     const int64_t count = count_of(n, n_dev, cap);
     const int g = blockIdx.x % kXcds;
     const int64_t chunks = gridDim.x / kXcds;
     const int lpg = LPG;
+    const int kb = (tb + 1) >> 1;
     for (int64_t c = blockIdx.x / kXcds; c * blockDim.x < count; c += chunks) {
         const int64_t s = c * blockDim.x + threadIdx.x;
         const bool valid = s < count;
@@ -308,20 +321,16 @@ scatter_emit(GridParams p, int tb, int64_t n, const int32_t *__restrict__ n_dev,
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const uint32_t slot = hist[(int)(ent[k] >> tb) - t_lo] + rank[k];
-                    skey[slot] = ent[k];
-                    sval[slot] = make_float2(v0[k], v1[k]);
+                    srec[slot] = pack_record(ent[k] & ((1u << tb) - 1u), kb, v0[k], v1[k]);
+                    stile[slot] = (uint16_t)((int)(ent[k] >> tb) - t_lo);
                 }
             }
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < n_rec; i += blockDim.x) {
-                const uint32_t e = skey[i];
                 // the count pass saw the same contributions, so pos stays inside
-                // the tile's range; the bound keeps every store inside the buffers
-                const uint32_t pos = delta[(int)(e >> tb) - t_lo] + i;
-                if (pos < n_records) {
-                    keys[pos] = e;
-                    vals[pos] = sval[i];
-                }
+                // the tile's range; the bound keeps every store inside the buffer
+                const uint32_t pos = delta[stile[i]] + i;
+                if (pos < n_records) recs[pos] = srec[i];
             }
             __syncthreads();
         }
@@ -345,8 +354,8 @@ scatter_emit(GridParams p, int tb, int64_t n, const int32_t *__restrict__ n_dev,
 __global__ void __launch_bounds__(64)
 scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
               const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
-              const uint32_t *__restrict__ keys, const float2 *__restrict__ vals,
-              float2 *__restrict__ dtable, float2 *__restrict__ partial) {
+              const uint2 *__restrict__ recs, float2 *__restrict__ dtable,
+              float2 *__restrict__ partial) {
     extern __shared__ float2 acc[];                                   // [te] sums
     const uint32_t te = 1u << tb;
     uint8_t *tag = reinterpret_cast<uint8_t *>(acc + te);            // [te]
@@ -368,40 +377,44 @@ scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restric
         const bool owner = (item_start[t + 1] - item_start[t]) == 1u;
         for (uint32_t i = lane; i < te; i += 64) acc[i] = make_float2(0.f, 0.f);
         const uint32_t tbase = (uint32_t)t << tb;
-        // Each lane takes kPer consecutive records of a 64 * kPer window (two
-        // 16-byte key loads, four 16-byte value loads), so a run of equal keys
-        // -- consecutive samples in one coarse cell -- spreads over the rounds
-        // of one lane instead of the lanes of one instruction.  Windows start
-        // 8-aligned at or below r0; records outside [r0, r1) are masked off and
-        // the buffers carry one window of padding.  The next window is loaded
-        // while the current one is added.
+        // Each lane takes kPer consecutive records of a 64 * kPer window (four
+        // 16-byte loads), so a run of equal entries -- consecutive samples in
+        // one coarse cell -- spreads over the rounds of one lane instead of the
+        // lanes of one instruction.  Windows start 8-aligned at or below r0;
+        // records outside [r0, r1) are masked off and the buffer carries one
+        // window of padding.  The next window is loaded while the current one
+        // is added.
         constexpr uint32_t kPer = 8;
         constexpr uint32_t kWin = 64u * kPer;
+        const int kb = (tb + 1) >> 1;
+        const uint32_t kmask = (1u << kb) - 1u;
         const uint32_t b0 = r0 & ~(kPer - 1u);
-        uint4 ka, kb;
-        float4 va, vb, vc, vd;
+        uint4 qa, qb, qc, qd;
         {
-            const uint32_t i = b0 + lane * kPer;
-            ka = *reinterpret_cast<const uint4 *>(keys + i);
-            kb = *reinterpret_cast<const uint4 *>(keys + i + 4);
-            va = *reinterpret_cast<const float4 *>(vals + i);
-            vb = *reinterpret_cast<const float4 *>(vals + i + 2);
-            vc = *reinterpret_cast<const float4 *>(vals + i + 4);
-            vd = *reinterpret_cast<const float4 *>(vals + i + 6);
+            const uint4 *q = reinterpret_cast<const uint4 *>(recs + b0 + lane * kPer);
+            qa = q[0];
+            qb = q[1];
+            qc = q[2];
+            qd = q[3];
         }
         for (uint32_t base = b0; base < r1; base += kWin) {
-            const uint32_t key[kPer] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
-            const float v0[kPer] = {va.x, va.z, vb.x, vb.z, vc.x, vc.z, vd.x, vd.z};
-            const float v1[kPer] = {va.y, va.w, vb.y, vb.w, vc.y, vc.w, vd.y, vd.w};
+            const uint32_t hw[kPer] = {qa.x, qa.z, qb.x, qb.z, qc.x, qc.z, qd.x, qd.z};
+            const uint32_t lw[kPer] = {qa.y, qa.w, qb.y, qb.w, qc.y, qc.w, qd.y, qd.w};
             const uint32_t nb = base + kWin;
             if (nb < r1) {
-                const uint32_t i = nb + lane * kPer;
-                ka = *reinterpret_cast<const uint4 *>(keys + i);
-                kb = *reinterpret_cast<const uint4 *>(keys + i + 4);
-                va = *reinterpret_cast<const float4 *>(vals + i);
-                vb = *reinterpret_cast<const float4 *>(vals + i + 2);
-                vc = *reinterpret_cast<const float4 *>(vals + i + 4);
-                vd = *reinterpret_cast<const float4 *>(vals + i + 6);
+                const uint4 *q = reinterpret_cast<const uint4 *>(recs + nb + lane * kPer);
+                qa = q[0];
+                qb = q[1];
+                qc = q[2];
+                qd = q[3];
+            }
+            uint32_t key[kPer];
+            float v0[kPer], v1[kPer];
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; ++u) {
+                key[u] = tbase + (((hw[u] & kmask) << kb) | (lw[u] & kmask));
+                v0[u] = __uint_as_float(hw[u] & ~kmask);
+                v1[u] = __uint_as_float(lw[u] & ~kmask);
             }
 #pragma unroll
             for (uint32_t u = 0; u < kPer; ++u) {
@@ -518,7 +531,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
 #define NVR_EMIT(PL, LP)                                                                       \
     scatter_emit<PL, LP><<<gre, kEmitBlock, kEmitLds, st>>>(p, tb, n, n_dev, cap, x,           \
                                                           (const uint32_t *)table, dfeat,       \
-                                                          n_records, w.cursor, w.keys, w.vals, \
+                                                          n_records, w.cursor, w.rec,          \
                                                           dx_parts)
 #define NVR_EMIT_L(PL)                                                                         \
     switch (lpg) {                                                                             \
@@ -527,7 +540,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     case 3: NVR_EMIT(PL, 3); break;                                                            \
     default: NVR_EMIT(PL, 4); break;                                                           \
     }
-    static bool emit_lds_ok = false;   // opt in to 116 KiB of dynamic LDS (every instance)
+    static bool emit_lds_ok = false;   // opt in to 100 KiB of dynamic LDS (every instance)
     if (!emit_lds_ok) {
         const void *fns[] = {(const void *)scatter_emit<true, 1>, (const void *)scatter_emit<true, 2>,
                              (const void *)scatter_emit<true, 3>, (const void *)scatter_emit<true, 4>,
@@ -558,7 +571,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
         }
     }
     scatter_accum<<<ga, 64, acc_lds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
-                                           w.keys, w.vals, (float2 *)dtable, w.partial);
+                                           w.rec, (float2 *)dtable, w.partial);
     NVR_LAUNCHED();
     scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
         tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
