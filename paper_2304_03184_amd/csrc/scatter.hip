@@ -204,7 +204,7 @@ __device__ inline uint2 pack_record(uint32_t loc, int kb, float v0, float v1) {
 }
 
 // In-place exclusive prefix sum of a[0, n) by the whole workgroup (part holds
-// blockDim.x partial sums).  Starts and ends with a barrier.
+// one partial per wavefront).  Starts and ends with a barrier.
 __device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
     __syncthreads();
     const int nt = blockDim.x;
@@ -213,15 +213,18 @@ __device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
     const int i1 = i0 + seg < n ? i0 + seg : n;
     uint32_t s = 0;
     for (int i = i0; i < i1; ++i) s += a[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int d = 1; d < nt; d <<= 1) {
-        const uint32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    // inclusive scan inside the wavefront
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += v;
     }
-    uint32_t run = part[threadIdx.x] - s;
+    if (lane == 63) part[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - s;
+    for (int w = 0; w < wave; ++w) run += part[w];
     for (int i = i0; i < i1; ++i) {
         const uint32_t c = a[i];
         a[i] = run;

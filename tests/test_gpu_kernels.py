@@ -131,7 +131,7 @@ def test_encode_split_fp16_table():
 
 def test_encode_binned_heavy_tiles_and_empty():
     # 300k samples in a small region: the coarse tiles are split over many work
-    # items (atomics between items), the rest owned by single items
+    # items (partial slabs summed by a last pass), the rest owned by single items
     I = field_inputs(2, 8)
     f, lay = I["fcfg"], I["lay"]
     O = ops()
