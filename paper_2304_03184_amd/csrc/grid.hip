@@ -125,15 +125,22 @@ encode_bwd_plain(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
 // Block b serves level group g = b % 8 over sample chunks b/8, b/8 + nb/8, ...
 // PLANAR output: plane g holds, per sample, the LPG levels of the group
 // (level g + 8m at elements 2m, 2m+1); otherwise row-major [n][2L].
-template <bool PLANAR, typename OutT>
+// COUNT: the corners are also counted per table tile of 2^tb entries (LDS
+// histogram per level of the group, added into the global counts at the end).
+template <bool PLANAR, typename OutT, bool COUNT>
 __global__ void __launch_bounds__(256)
 encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
                  const float *__restrict__ x, const uint32_t *__restrict__ table,
-                 OutT *__restrict__ feat) {
+                 OutT *__restrict__ feat, TileCounter cnt) {
+    extern __shared__ uint32_t hist[];    // COUNT: [lpg][cnt.level_tiles]
     const int64_t count = count_of(n, n_dev, cap);
     const int g = blockIdx.x % kXcds;
     const int64_t chunks = gridDim.x / kXcds;
     const int lpg = (p.L + kXcds - 1) / kXcds;
+    if (COUNT) {
+        for (int i = threadIdx.x; i < lpg * cnt.level_tiles; i += blockDim.x) hist[i] = 0u;
+        __syncthreads();
+    }
     for (int64_t c = blockIdx.x / kXcds; c * blockDim.x < count; c += chunks) {
         const int64_t s = c * blockDim.x + threadIdx.x;
         if (s >= count) break;
@@ -143,10 +150,17 @@ encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
             float a0 = 0.f, a1 = 0.f;
             if (l < p.L) {
                 LevelPos lp = level_pos(p, l, px, py, pz);
-                uint32_t v[8];
+                uint32_t e[8], v[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    v[k] = table[p.off[l] + corner_index(p, l, lp, k)];
+                for (int k = 0; k < 8; ++k) {
+                    e[k] = p.off[l] + corner_index(p, l, lp, k);
+                    v[k] = table[e[k]];
+                }
+                if (COUNT) {
+                    uint32_t *h = hist + m * cnt.level_tiles - (int)((uint32_t)p.off[l] >> cnt.tb);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) atomicAdd(&h[e[k] >> cnt.tb], 1u);
+                }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     float w = corner_weight(lp, k);
@@ -158,6 +172,19 @@ encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
                 store2(feat + ((size_t)g * cap + s) * (2 * lpg) + 2 * m, a0, a1);
             } else if (l < p.L) {
                 store2(feat + (size_t)s * (2 * p.L) + 2 * l, a0, a1);
+            }
+        }
+    }
+    if (COUNT) {
+        __syncthreads();
+        for (int m = 0; m < lpg; ++m) {
+            const int l = g + kXcds * m;
+            if (l >= p.L) break;
+            const int t_lo = (int)((uint32_t)p.off[l] >> cnt.tb);
+            const int n_lt = (int)((uint32_t)(p.off[l + 1] - 1) >> cnt.tb) - t_lo + 1;
+            for (int t = threadIdx.x; t < n_lt; t += blockDim.x) {
+                const uint32_t h = hist[m * cnt.level_tiles + t];
+                if (h) atomicAdd(&cnt.count[t_lo + t], h);
             }
         }
     }
@@ -231,8 +258,11 @@ encode_bwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
 // ---------------------------------------------------------------- launchers
 nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
-                             void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st) {
+                             void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st,
+                             const TileCounter *counter) {
     if (cap <= 0) return NVR_OK;
+    NVR_REQUIRE(counter == nullptr || (table_dtype != NVR_F32 && planar && feat_dtype == NVR_BF16),
+                NVR_EUNSUPPORTED, "tile counting needs the planar bf16 gather");
     if (table_dtype == NVR_F32) {
         unsigned gr = grid_for(cap * p.L, 256);
         if (feat_dtype == NVR_F32)
@@ -248,9 +278,15 @@ nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_de
         unsigned chunks = grid_for(cap, 256, 1024);
         unsigned gr = chunks * kXcds;
         const uint32_t *tb = (const uint32_t *)table;
+        const TileCounter none{nullptr, 0, 0};
 #define NVR_SPLIT_FWD(PL, T)                                                                  \
-    encode_fwd_split<PL, T><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x, tb, (T *)feat)
-        if (planar) {
+    encode_fwd_split<PL, T, false><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x, tb, (T *)feat, none)
+        if (counter != nullptr) {
+            const int lpg = (p.L + kXcds - 1) / kXcds;
+            const size_t lds = sizeof(uint32_t) * lpg * counter->level_tiles;
+            encode_fwd_split<true, bf16_t, true><<<gr, 256, lds, st>>>(p, n, n_dev, cap, x, tb,
+                                                                        (bf16_t *)feat, *counter);
+        } else if (planar) {
             if (feat_dtype == NVR_F32) NVR_SPLIT_FWD(true, float);
             else if (feat_dtype == NVR_BF16) NVR_SPLIT_FWD(true, bf16_t);
             else NVR_SPLIT_FWD(true, f16_t);

@@ -89,10 +89,19 @@ __device__ __forceinline__ void store2(f16_t *o, float a, float b) {
     *reinterpret_cast<uint32_t *>(o) = v;
 }
 
+// Per-tile contribution counts of the binned table scatter, formed by the
+// forward gather of a training step (it visits the same corners).
+struct TileCounter {
+    uint32_t *count;    // [n_tiles], zeroed before the forward
+    int tb;             // log2 of the entries per tile
+    int level_tiles;    // most tiles one level spans
+};
+
 // launchers (grid.hip)
 nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
-                             void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st);
+                             void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st,
+                             const TileCounter *counter = nullptr);
 nvr_status launch_encode_bwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
                              const float *dfeat, float *dtable, float *dx, bool planar,

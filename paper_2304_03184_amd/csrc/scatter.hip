@@ -510,9 +510,30 @@ nvr_status scatter_check(const GridParams &p) {
     return NVR_OK;
 }
 
+static int level_tiles(const GridParams &p, int tb) {
+    int most = 1;
+    for (int l = 0; l < p.L; ++l) {
+        const int n = (int)(((p.off[l + 1] - 1) >> tb) - (p.off[l] >> tb) + 1);
+        most = n > most ? n : most;
+    }
+    return most;
+}
+
+TileCounter scatter_counter(const GridParams &p, void *ws) {
+    const int tb = tile_bits(p);
+    return TileCounter{(uint32_t *)ws, tb, level_tiles(p, tb)};
+}
+
+nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st) {
+    const int nt = scatter_tiles(p);
+    zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>((uint32_t *)ws, nt + 1);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
-                          float *dx_parts, bool planar, void *ws, hipStream_t st) {
+                          float *dx_parts, bool planar, void *ws, hipStream_t st, bool counted) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
     const int tb = tile_bits(p);
@@ -520,14 +541,15 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     ScatterWs w = carve_scatter(p, ws, cap);
     const uint32_t n_records = (uint32_t)((uint64_t)cap * p.L * 8 < 0xffffffffull
                                               ? (uint64_t)cap * p.L * 8 : 0xffffffffull);
-    zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>(w.count, nt + 1);
-    NVR_LAUNCHED();
-    const unsigned chunks = grid_for(cap, kBinBlock, 512);
-    const unsigned gr = chunks * kXcds;
     const unsigned gre = grid_for(cap, kEmitBlock, 64) * kXcds;
-    scatter_count<<<gr, kBinBlock, sizeof(uint32_t) * nt, st>>>(p, tb, nt, n, n_dev, cap, x,
-                                                                  w.count);
-    NVR_LAUNCHED();
+    if (!counted) {
+        zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>(w.count, nt + 1);
+        NVR_LAUNCHED();
+        const unsigned gr = grid_for(cap, kBinBlock, 512) * kXcds;
+        scatter_count<<<gr, kBinBlock, sizeof(uint32_t) * nt, st>>>(p, tb, nt, n, n_dev, cap, x,
+                                                                      w.count);
+        NVR_LAUNCHED();
+    }
     scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items);
     NVR_LAUNCHED();
     const int lpg = (p.L + kXcds - 1) / kXcds;

@@ -7,10 +7,16 @@ namespace nvr {
 int scatter_tiles(const GridParams &p);
 size_t scatter_ws_bytes(const GridParams &p, int64_t cap);
 nvr_status scatter_check(const GridParams &p);
+// The tile counter inside a scatter workspace, and a launch that zeroes it.
+TileCounter scatter_counter(const GridParams &p, void *ws);
+nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st);
 // dtable (acc) += binned scatter of w * dfeat; dx_parts: planar -> [8][cap][3]
-// partials, row-major -> [n][3] (acc, via atomics); nullable.
+// partials, row-major -> [n][3] (acc, via atomics); nullable.  counted: the
+// tile counts in ws were already formed (zeroed, then counted by the forward
+// gather over the same positions); otherwise they are counted here.
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
-                          float *dx_parts, bool planar, void *ws, hipStream_t st);
+                          float *dx_parts, bool planar, void *ws, hipStream_t st,
+                          bool counted = false);
 
 }  // namespace nvr

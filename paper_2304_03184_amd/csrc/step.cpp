@@ -161,7 +161,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
 // march -> [warp] -> encode -> networks for one field over rays [begin, end)
 static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const Net &net,
                                 int precision, int64_t n_rays, int64_t begin, int64_t end,
-                                const float *o, const float *d, hipStream_t st) {
+                                const float *o, const float *d, bool train, hipStream_t st) {
     FieldWs &w = ctx->ws[k];
     const int64_t cap = w.cap;
     NVR_TRY(run_march(&f->march, n_rays, begin, end, o, d, f->occ, cap, w.off, w.ray_id, w.t, w.dt,
@@ -173,8 +173,15 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
     }
     const GridParams gp = make_grid_params(&f->grid);
     if (precision == NVR_BF16) {
+        // a training forward also counts the table-gradient scatter's tiles
+        TileCounter counter{};
+        const bool count = train && w.scatter_ws != nullptr;
+        if (count) {
+            counter = scatter_counter(gp, w.scatter_ws);
+            NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
+        }
         NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat, NVR_BF16,
-                                  true, st));
+                                  true, st, count ? &counter : nullptr));
         NVR_TRY(mfma_fwd(net, 0, w.n_dev, cap, (const uint16_t *)w.feat, true, d, w.ray_id,
                          (const uint16_t *)f->params_bf16, w.sigma, w.rgb, st));
     } else {
@@ -210,7 +217,7 @@ static nvr_status enqueue_fwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                               float *loss, float *C_out, float *D_out, hipStream_t st) {
     for (int k = 0; k < s->n_fields; ++k)
         NVR_TRY(field_forward(ctx, k, fields[k], nets[k], s->precision, s->n_rays, fields[k]->ray_begin,
-                              fields[k]->ray_end, b->o, b->d, st));
+                              fields[k]->ray_end, b->o, b->d, /*train=*/true, st));
     const nvr_samples a = samples_of(ctx->ws[0]);
     nvr_samples bb;
     if (s->n_fields == 2) bb = samples_of(ctx->ws[1]);
@@ -234,7 +241,8 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                              (const uint16_t *)f->params_bf16, w.dsigma, w.drgb, f->params_grad,
                              w.dfeat, w.mlp_ws, st));
             NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
-                                   f->has_warp ? w.dx : nullptr, true, w.scatter_ws, st));
+                                   f->has_warp ? w.dx : nullptr, true, w.scatter_ws, st,
+                                   /*counted=*/true));
             if (f->has_warp)
                 NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, kXcds, 3 * cap,
                                      f->node_dq_grad, f->bones_grad, st));
@@ -452,7 +460,7 @@ extern "C" nvr_status nvr_render(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field
         const int64_t nr = (n_rays - r0) < chunk ? (n_rays - r0) : chunk;
         for (int k = 0; k < s->n_fields; ++k)
             NVR_TRY(field_forward(ctx, k, fields[k], nets[k], s->precision, nr, 0, nr, o + 3 * r0,
-                                  d + 3 * r0, st));
+                                  d + 3 * r0, /*train=*/false, st));
         const nvr_samples a = samples_of(ctx->ws[0]);
         nvr_samples bb;
         if (s->n_fields == 2) bb = samples_of(ctx->ws[1]);
