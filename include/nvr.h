@@ -64,7 +64,10 @@ const char *nvr_version(void);
  * weights over the 8 corners; a level with (N_l+1)^3 <= T vertices is
  * indexed densely (cx + (N_l+1)(cy + (N_l+1) cz)), else by
  * (cx*1 ^ cy*2654435761 ^ cz*805459861) mod 2^32 & (T-1).
- * Table layout: [n_entries][F] with level l at entries offset[l]..offset[l+1).
+ * Table layout: [n_entries][F] with level l at entries offset[l]..offset[l+1);
+ * each level's slice is its vertex count rounded up to a multiple of 8 entries
+ * (the padding entries are never read or written by the encoding, and the
+ * aligned slices let the gather fetch x-neighbouring corners together).
  * ---------------------------------------------------------------------- */
 #define NVR_MAX_LEVELS 32
 typedef struct {

@@ -53,9 +53,11 @@ class Layout:
         self.res = level_resolutions(n_levels, res_min, res_max)
         self.dense = [(n + 1) ** 3 <= self.T for n in self.res]
         self.size = [(n + 1) ** 3 if dn else self.T for n, dn in zip(self.res, self.dense)]
+        # each level's slice starts at a multiple of 8 entries; the entries
+        # between a level's last vertex and the next slice are never addressed
         self.offset = [0]
         for s in self.size:
-            self.offset.append(self.offset[-1] + s)
+            self.offset.append(self.offset[-1] + (s + 7) // 8 * 8)
         self.n_entries = self.offset[-1]
         self.lo = np.asarray(aabb_min, np.float64)
         self.hi = np.asarray(aabb_max, np.float64)

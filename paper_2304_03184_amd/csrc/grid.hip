@@ -50,7 +50,8 @@ nvr_status check_grid(const nvr_grid_desc *g) {
         NVR_REQUIRE(g->res[l] >= 1 && g->res[l] <= (1 << 20), NVR_EINVAL, "res[%d] invalid", l);
         int64_t v = (int64_t)(g->res[l] + 1) * (g->res[l] + 1) * (g->res[l] + 1);
         NVR_REQUIRE((g->dense[l] != 0) == (v <= T), NVR_EINVAL, "dense[%d] inconsistent", l);
-        NVR_REQUIRE(g->offset[l + 1] - g->offset[l] == (g->dense[l] ? v : T), NVR_EINVAL,
+        const int64_t slice = ((g->dense[l] ? v : T) + 7) / 8 * 8;
+        NVR_REQUIRE(g->offset[l + 1] - g->offset[l] == slice, NVR_EINVAL,
                     "offset[%d] inconsistent with the level size", l + 1);
     }
     NVR_REQUIRE(g->offset[0] == 0, NVR_EINVAL, "offset[0] must be 0");
@@ -127,7 +128,19 @@ encode_bwd_plain(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
 // (level g + 8m at elements 2m, 2m+1); otherwise row-major [n][2L].
 // COUNT: the corners are also counted per table tile of 2^tb entries (LDS
 // histogram per level of the group, added into the global counts at the end).
-template <bool PLANAR, typename OutT, bool COUNT>
+// i-th 32-bit word of q (i in 0..3)
+__device__ __forceinline__ uint32_t pick4(const uint4 &q, uint32_t i) {
+    const uint32_t lo = (i & 1u) ? q.y : q.x;
+    const uint32_t hi = (i & 1u) ? q.w : q.z;
+    return (i & 2u) ? hi : lo;
+}
+
+// QUAD (16-byte aligned table, level slices at multiples of 8 entries): the two
+// corners of a cell edge along x are fetched with one 16-byte load of the
+// aligned group of 4 entries holding the first; the second is in the same group
+// unless the group boundary falls between them (a quarter of the cases for both
+// the dense and the hashed index), and only then is it loaded on its own.
+template <bool PLANAR, typename OutT, bool COUNT, bool QUAD>
 __global__ void __launch_bounds__(256)
 encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
                  const float *__restrict__ x, const uint32_t *__restrict__ table,
@@ -152,9 +165,27 @@ encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
                 LevelPos lp = level_pos(p, l, px, py, pz);
                 uint32_t e[8], v[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    e[k] = p.off[l] + corner_index(p, l, lp, k);
-                    v[k] = table[e[k]];
+                for (int k = 0; k < 8; ++k) e[k] = p.off[l] + corner_index(p, l, lp, k);
+                if (QUAD) {
+                    uint4 q[4];
+                    uint32_t far_v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        q[j] = *reinterpret_cast<const uint4 *>(table + (e[2 * j] & ~3u));
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        far_v[j] = 0u;
+                        if ((e[2 * j] ^ e[2 * j + 1]) > 3u) far_v[j] = table[e[2 * j + 1]];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        v[2 * j] = pick4(q[j], e[2 * j] & 3u);
+                        v[2 * j + 1] = (e[2 * j] ^ e[2 * j + 1]) > 3u ? far_v[j]
+                                                                      : pick4(q[j], e[2 * j + 1] & 3u);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) v[k] = table[e[k]];
                 }
                 if (COUNT) {
                     uint32_t *h = hist + m * cnt.level_tiles - (int)((uint32_t)p.off[l] >> cnt.tb);
@@ -279,13 +310,25 @@ nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_de
         unsigned gr = chunks * kXcds;
         const uint32_t *tb = (const uint32_t *)table;
         const TileCounter none{nullptr, 0, 0};
+        const bool quad = ((uintptr_t)table & 15u) == 0;   // level slices are 8-entry aligned
 #define NVR_SPLIT_FWD(PL, T)                                                                  \
-    encode_fwd_split<PL, T, false><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x, tb, (T *)feat, none)
+    do {                                                                                      \
+        if (quad)                                                                             \
+            encode_fwd_split<PL, T, false, true><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x, tb, \
+                                                                     (T *)feat, none);        \
+        else                                                                                  \
+            encode_fwd_split<PL, T, false, false><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x,    \
+                                                                      tb, (T *)feat, none);   \
+    } while (0)
         if (counter != nullptr) {
             const int lpg = (p.L + kXcds - 1) / kXcds;
             const size_t lds = sizeof(uint32_t) * lpg * counter->level_tiles;
-            encode_fwd_split<true, bf16_t, true><<<gr, 256, lds, st>>>(p, n, n_dev, cap, x, tb,
-                                                                        (bf16_t *)feat, *counter);
+            if (quad)
+                encode_fwd_split<true, bf16_t, true, true><<<gr, 256, lds, st>>>(
+                    p, n, n_dev, cap, x, tb, (bf16_t *)feat, *counter);
+            else
+                encode_fwd_split<true, bf16_t, true, false><<<gr, 256, lds, st>>>(
+                    p, n, n_dev, cap, x, tb, (bf16_t *)feat, *counter);
         } else if (planar) {
             if (feat_dtype == NVR_F32) NVR_SPLIT_FWD(true, float);
             else if (feat_dtype == NVR_BF16) NVR_SPLIT_FWD(true, bf16_t);
@@ -364,7 +407,7 @@ extern "C" nvr_status nvr_grid_init(nvr_grid_desc *g, int32_t n_levels, int32_t 
         const int64_t v = (int64_t)(N + 1) * (N + 1) * (N + 1);
         g->dense[l] = v <= T ? 1 : 0;
         g->offset[l] = off;
-        off += g->dense[l] ? v : T;
+        off += ((g->dense[l] ? v : T) + 7) / 8 * 8;   // slices start at multiples of 8 entries
     }
     g->offset[n_levels] = off;
     for (int a = 0; a < 3; ++a) {

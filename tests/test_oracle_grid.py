@@ -24,7 +24,12 @@ def test_level_resolutions_endpoints_and_totals():
     lay = grid.Layout.from_field(synth.config(2).fields[0])
     assert lay.dense == [True] * 5 + [False] * 11
     assert lay.size[:5] == [17 ** 3, 23 ** 3, 31 ** 3, 43 ** 3, 59 ** 3]
-    assert lay.n_entries == 17 ** 3 + 23 ** 3 + 31 ** 3 + 43 ** 3 + 59 ** 3 + 11 * 2 ** 19
+    # slices are padded to multiples of 8 entries: 4913 -> 4920, 12167 -> 12168,
+    # 29791 -> 29792, 79507 -> 79512, 205379 -> 205384; 2^19 is already aligned
+    assert lay.offset[:6] == [0, 4920, 17088, 46880, 126392, 331776]
+    assert all(o % 8 == 0 for o in lay.offset)
+    assert all(b - a >= s for a, b, s in zip(lay.offset, lay.offset[1:], lay.size))
+    assert lay.n_entries == 331776 + 11 * 2 ** 19
 
 
 def test_hash_spot_values(golden_dir):
