@@ -1,26 +1,66 @@
 // Volume-rendering compositing (forward, closed-form backward), the colour /
 // depth loss, and the fused per-ray "composite -> loss -> composite backward"
-// kernel used by the training step.  One thread per ray walks its samples in
-// t order; a ray shared by two fields walks both sample lists merged by t
-// (ties: the first list).  Transmittance is exp(-running sum of tau) in fp32.
+// kernel used by the training step.  A group of 16 lanes composites one ray:
+// its samples are loaded 16 at a time (coalesced), transmittance is
+// exp(-prefix sum of tau) in fp32 from a scan over the group's lanes, and the
+// backward's suffix sums come from a second scan.  A ray with samples in both
+// fields' lists (merged by t, ties: the first list) is walked by the group's
+// first lane in t order.
 #include "common.hpp"
 #include "composite_dev.hpp"
 
 namespace nvr {
 
+// Totals of ray r on every lane of its group.
+__device__ __forceinline__ RayAcc group_ray_forward(const nvr_samples &a, const nvr_samples &b,
+                                                    bool has_b, int64_t r, int gl, float t_stop) {
+    const int64_t ia = a.off[r], iae = a.off[r + 1];
+    const int64_t jb = has_b ? b.off[r] : 0, jbe = has_b ? b.off[r + 1] : 0;
+    if (ia < iae && jb < jbe) {
+        RayAcc acc{{0.f, 0.f, 0.f}, 0.f, 0.f};
+        if (gl == 0) acc = ray_forward(a, b, has_b, r, t_stop);
+        for (int k = 0; k < 3; ++k) acc.c[k] = group_bcast(acc.c[k], 0);
+        acc.d = group_bcast(acc.d, 0);
+        acc.tau = group_bcast(acc.tau, 0);
+        return acc;
+    }
+    if (jb < jbe) return group_forward(b, jb, jbe, gl, t_stop);
+    return group_forward(a, ia, iae, gl, t_stop);
+}
+
+__device__ __forceinline__ void group_ray_backward(const nvr_samples &a, const nvr_samples &b,
+                                                   bool has_b, int64_t r, int gl, const float *C,
+                                                   float D, const float *gc, float gd, float *dsa,
+                                                   float *dra, float *dsb, float *drb) {
+    const int64_t ia = a.off[r], iae = a.off[r + 1];
+    const int64_t jb = has_b ? b.off[r] : 0, jbe = has_b ? b.off[r + 1] : 0;
+    if (ia < iae && jb < jbe) {
+        if (gl == 0) ray_backward(a, b, has_b, r, C, D, gc, gd, dsa, dra, dsb, drb);
+    } else if (jb < jbe) {
+        group_backward(b, jb, jbe, gl, C, D, gc, gd, dsb, drb);
+    } else {
+        group_backward(a, ia, iae, gl, C, D, gc, gd, dsa, dra);
+    }
+}
+
 __global__ void __launch_bounds__(256)
 composite_fwd_kernel(int64_t n_rays, nvr_samples a, nvr_samples b, bool has_b, float t_stop,
                      float *__restrict__ C, float *__restrict__ D, float *__restrict__ TN) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n_rays) return;
-    RayAcc acc = ray_forward(a, b, has_b, r, t_stop);
-    if (C) {
-        C[3 * r] = acc.c[0];
-        C[3 * r + 1] = acc.c[1];
-        C[3 * r + 2] = acc.c[2];
+    const int gl = threadIdx.x % kGroup;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kGroup);
+    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kGroup; r < n_rays;
+         r += stride) {   // r is the same on the whole group
+        RayAcc acc = group_ray_forward(a, b, has_b, r, gl, t_stop);
+        if (gl == 0) {
+            if (C) {
+                C[3 * r] = acc.c[0];
+                C[3 * r + 1] = acc.c[1];
+                C[3 * r + 2] = acc.c[2];
+            }
+            if (D) D[r] = acc.d;
+            if (TN) TN[r] = expf(-acc.tau);
+        }
     }
-    if (D) D[r] = acc.d;
-    if (TN) TN[r] = expf(-acc.tau);
 }
 
 __global__ void __launch_bounds__(256)
@@ -29,11 +69,14 @@ composite_bwd_kernel(int64_t n_rays, nvr_samples a, nvr_samples b, bool has_b,
                      const float *__restrict__ dC, const float *__restrict__ dD,
                      float *__restrict__ dsa, float *__restrict__ dra, float *__restrict__ dsb,
                      float *__restrict__ drb) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n_rays) return;
-    const float cc[3] = {C[3 * r], C[3 * r + 1], C[3 * r + 2]};
-    const float gc[3] = {dC[3 * r], dC[3 * r + 1], dC[3 * r + 2]};
-    ray_backward(a, b, has_b, r, cc, D[r], gc, dD ? dD[r] : 0.f, dsa, dra, dsb, drb);
+    const int gl = threadIdx.x % kGroup;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kGroup);
+    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kGroup; r < n_rays;
+         r += stride) {   // r is the same on the whole group
+        const float cc[3] = {C[3 * r], C[3 * r + 1], C[3 * r + 2]};
+        const float gc[3] = {dC[3 * r], dC[3 * r + 1], dC[3 * r + 2]};
+        group_ray_backward(a, b, has_b, r, gl, cc, D[r], gc, dD ? dD[r] : 0.f, dsa, dra, dsb, drb);
+    }
 }
 
 __global__ void fill_zero(float *p, int64_t n) {
@@ -96,20 +139,26 @@ composite_loss_fused(int64_t n_rays, nvr_samples a, nvr_samples b, bool has_b,
                      float *__restrict__ C_out, float *__restrict__ D_out,
                      float *__restrict__ dsa, float *__restrict__ dra, float *__restrict__ dsb,
                      float *__restrict__ drb) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int gl = threadIdx.x % kGroup;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kGroup);
     float l = 0.f;
-    if (r < n_rays) {
-        RayAcc acc = ray_forward(a, b, has_b, r, 0.f);
+    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kGroup; r < n_rays;
+         r += stride) {   // r is the same on the whole group
+        RayAcc acc = group_ray_forward(a, b, has_b, r, gl, 0.f);
         const float S = state ? state->loss_scale : 1.f;
         float gc[3], gd;
-        l = ray_loss(r, acc.c, acc.d, C_t, D_t, mask, lambda_d, 1.f / (float)n_rays, S, gc, &gd);
-        if (C_out) {
-            C_out[3 * r] = acc.c[0];
-            C_out[3 * r + 1] = acc.c[1];
-            C_out[3 * r + 2] = acc.c[2];
+        const float lr = ray_loss(r, acc.c, acc.d, C_t, D_t, mask, lambda_d, 1.f / (float)n_rays, S,
+                                  gc, &gd);
+        if (gl == 0) l += lr;            // counted once per ray
+        if (gl == 0) {
+            if (C_out) {
+                C_out[3 * r] = acc.c[0];
+                C_out[3 * r + 1] = acc.c[1];
+                C_out[3 * r + 2] = acc.c[2];
+            }
+            if (D_out) D_out[r] = acc.d;
         }
-        if (D_out) D_out[r] = acc.d;
-        if (dsa) ray_backward(a, b, has_b, r, acc.c, acc.d, gc, gd, dsa, dra, dsb, drb);
+        if (dsa) group_ray_backward(a, b, has_b, r, gl, acc.c, acc.d, gc, gd, dsa, dra, dsb, drb);
     }
     block_sum_atomic(l, loss);
 }
@@ -129,7 +178,7 @@ nvr_status launch_composite_loss(int64_t n_rays, const nvr_samples &a, const nvr
     NVR_TRY(launch_fill_zero(loss, 1, st));
     if (n_rays <= 0) return NVR_OK;
     nvr_samples bb = b ? *b : nvr_samples{};
-    composite_loss_fused<<<(unsigned)((n_rays + 255) / 256), 256, 0, st>>>(
+    composite_loss_fused<<<grid_for(n_rays * kGroup, 256, 65536), 256, 0, st>>>(
         n_rays, a, bb, b != nullptr, C_t, D_t, mask, lambda_d, state, loss, C_out, D_out, dsa, dra,
         dsb, drb);
     NVR_LAUNCHED();
@@ -140,8 +189,8 @@ nvr_status launch_composite_fwd(int64_t n_rays, const nvr_samples &a, const nvr_
                                 float t_stop, float *C, float *D, float *TN, hipStream_t st) {
     if (n_rays <= 0) return NVR_OK;
     nvr_samples bb = b ? *b : nvr_samples{};
-    composite_fwd_kernel<<<(unsigned)((n_rays + 255) / 256), 256, 0, st>>>(n_rays, a, bb, b != nullptr,
-                                                                          t_stop, C, D, TN);
+    composite_fwd_kernel<<<grid_for(n_rays * kGroup, 256, 65536), 256, 0, st>>>(
+        n_rays, a, bb, b != nullptr, t_stop, C, D, TN);
     NVR_LAUNCHED();
     return NVR_OK;
 }
@@ -184,7 +233,7 @@ extern "C" nvr_status nvr_composite_bwd(int64_t n_rays, const nvr_samples *a, co
     }
     NVR_REQUIRE(C && D && dC && dsigma_a && drgb_a, NVR_EINVAL, "NULL array");
     nvr_samples bb = b ? *b : nvr_samples{};
-    composite_bwd_kernel<<<(unsigned)((n_rays + 255) / 256), 256, 0, hs(stream)>>>(
+    composite_bwd_kernel<<<grid_for(n_rays * kGroup, 256, 65536), 256, 0, hs(stream)>>>(
         n_rays, *a, bb, b != nullptr, C, D, dC, dD, dsigma_a, drgb_a, dsigma_b, drgb_b);
     NVR_LAUNCHED();
     return NVR_OK;
