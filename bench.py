@@ -84,7 +84,9 @@ def main():
 
     def timed_steps(precision, steps, warmup, graph):
         fld = F.Field(w, f, table, params, occ_words=occ)
-        tr = F.Trainer([fld], R, cap, precision=precision, use_graph=graph)
+        # the BF16 step tunes its launch shapes in its first (warm-up) step
+        tr = F.Trainer([fld], R, cap, precision=precision, use_graph=graph,
+                       autotune=precision == L.NVR_BF16)
         tr.set_batch(o_d, d_d, C_d)
         for _ in range(warmup):
             tr.step()
@@ -101,7 +103,9 @@ def main():
 
     log(f"[bench] bf16 fused step: {R} rays, warmup {args.warmup}, steps {args.steps}")
     tr, fld, dt_bf, n_samp, loss_bf = timed_steps(L.NVR_BF16, args.steps, args.warmup, True)
-    log(f"[bench] bf16 fused: {dt_bf * 1e3:.3f} ms/step, {n_samp} samples, loss {loss_bf:.5f}")
+    shape = tr.launch_shape(0)
+    log(f"[bench] bf16 fused: {dt_bf * 1e3:.3f} ms/step, {n_samp} samples, loss {loss_bf:.5f}, "
+        f"launch shape {shape}")
 
     # ---------------------------------------------------------------- dominant kernel
     # the level-split hash-grid scatter (encode backward) on this step's own samples
@@ -141,7 +145,9 @@ def main():
         "data": "synthetic (seeded rays, occupancy, tables, weights, targets)",
         "config": {"workload": w.name, "rays_per_step": R, "samples_per_step": n_samp,
                    "levels": f.n_levels, "log2_table": f.log2_table, "res": [f.res_min, f.res_max],
-                   "occupancy": f"{f.occ_res}^3 noise, 30% set", "graph": True},
+                   "occupancy": f"{f.occ_res}^3 noise, 30% set", "graph": True,
+                   "launch_shape": dict(zip(["gather_chunks", "mlp_fwd_blocks", "mlp_bwd_blocks",
+                                             "emit_chunks", "composite_blocks", "tuned"], shape))},
         "fp32_plain": {"rays_per_s": R / dt_32, "ms_per_step": dt_32 * 1e3,
                        "speedup_bf16_over_fp32": dt_32 / dt_bf, "loss": loss_32},
         "render": render,

@@ -17,6 +17,7 @@ NVR_OK, NVR_EINVAL, NVR_EUNSUPPORTED, NVR_EHIP, NVR_ENOMEM, NVR_ENONFINITE, NVR_
     0, -1, -2, -3, -4, -5, -6
 NVR_F32, NVR_F16, NVR_BF16 = 0, 1, 2
 NVR_USE_GRAPH = 1
+NVR_AUTOTUNE = 2
 MAX_LEVELS = 32
 
 
@@ -114,6 +115,7 @@ _SIGS = {
     "nvr_train_step_fwd": (i32, [vp, P(StepDesc), P(P(Field)), P(Batch), vp, vp, vp, vp, vp]),
     "nvr_train_step_bwd": (i32, [vp, P(StepDesc), P(P(Field)), P(Batch), vp, vp]),
     "nvr_train_step": (i32, [vp, P(StepDesc), P(P(Field)), P(Batch), vp, vp, vp]),
+    "nvr_launch_shape": (i32, [vp, i32, P(i32)]),
     "nvr_last_sample_count": (i32, [vp, i32, P(i64), vp]),
     "nvr_render": (i32, [vp, P(StepDesc), P(P(Field)), i64, vp, vp, f32, vp, vp, vp]),
 }

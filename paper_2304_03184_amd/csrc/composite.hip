@@ -174,11 +174,11 @@ nvr_status launch_composite_loss(int64_t n_rays, const nvr_samples &a, const nvr
                                  const float *C_t, const float *D_t, const float *mask,
                                  float lambda_d, const nvr_train_state *state, float *loss,
                                  float *C_out, float *D_out, float *dsa, float *dra, float *dsb,
-                                 float *drb, hipStream_t st) {
+                                 float *drb, hipStream_t st, int blocks) {
     NVR_TRY(launch_fill_zero(loss, 1, st));
     if (n_rays <= 0) return NVR_OK;
     nvr_samples bb = b ? *b : nvr_samples{};
-    composite_loss_fused<<<grid_for(n_rays * kGroup, 256, 65536), 256, 0, st>>>(
+    composite_loss_fused<<<grid_for(n_rays * kGroup, 256, blocks > 0 ? blocks : 65536), 256, 0, st>>>(
         n_rays, a, bb, b != nullptr, C_t, D_t, mask, lambda_d, state, loss, C_out, D_out, dsa, dra,
         dsb, drb);
     NVR_LAUNCHED();

@@ -227,7 +227,7 @@ nvr_status launch_composite_loss(int64_t n_rays, const nvr_samples &a, const nvr
                                  const float *C_t, const float *D_t, const float *mask,
                                  float lambda_d, const nvr_train_state *state, float *loss,
                                  float *C_out, float *D_out, float *dsa, float *dra, float *dsb,
-                                 float *drb, hipStream_t st);
+                                 float *drb, hipStream_t st, int blocks = 0);
 nvr_status launch_composite_fwd(int64_t n_rays, const nvr_samples &a, const nvr_samples *b,
                                 float t_stop, float *C, float *D, float *TN, hipStream_t st);
 

@@ -290,7 +290,7 @@ encode_bwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
 nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
                              void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st,
-                             const TileCounter *counter) {
+                             const TileCounter *counter, int chunks_cap) {
     if (cap <= 0) return NVR_OK;
     NVR_REQUIRE(counter == nullptr || (table_dtype != NVR_F32 && planar && feat_dtype == NVR_BF16),
                 NVR_EUNSUPPORTED, "tile counting needs the planar bf16 gather");
@@ -306,7 +306,7 @@ nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_de
             encode_fwd_plain<f16_t><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x, (const float2 *)table,
                                                         (f16_t *)feat);
     } else {
-        unsigned chunks = grid_for(cap, 256, 1024);
+        unsigned chunks = grid_for(cap, 256, chunks_cap > 0 ? chunks_cap : 1024);
         unsigned gr = chunks * kXcds;
         const uint32_t *tb = (const uint32_t *)table;
         const TileCounter none{nullptr, 0, 0};

@@ -101,7 +101,7 @@ struct TileCounter {
 nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
                              void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st,
-                             const TileCounter *counter = nullptr);
+                             const TileCounter *counter = nullptr, int chunks = 0);
 nvr_status launch_encode_bwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
                              const float *dfeat, float *dtable, float *dx, bool planar,

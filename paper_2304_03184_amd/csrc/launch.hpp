@@ -43,12 +43,16 @@ nvr_status plain_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t ca
 struct MfmaNet;
 nvr_status mfma_check(const Net &net);
 size_t mfma_ws_bytes(const Net &net, int64_t cap);
+// blocks: workgroups of the persistent network kernels (0: default; the
+// backward's is capped by its workspace); dparams == nullptr skips the final
+// reduction of the per-workgroup weight-gradient partials.
 nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
-                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st);
+                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st,
+                    int blocks = 0);
 nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
                     const uint16_t *params, const float *dsigma, const float *drgb, float *dparams,
-                    float *dfeat, void *ws, hipStream_t st);
+                    float *dfeat, void *ws, hipStream_t st, int blocks = 0);
 
 }  // namespace nvr

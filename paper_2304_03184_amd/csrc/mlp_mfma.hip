@@ -583,9 +583,9 @@ size_t mfma_workspace(const MfmaNet &m, int64_t cap) {
 nvr_status mfma_forward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64_t cap,
                         const uint16_t *feat, bool planar, const float *dirs,
                         const int32_t *ray_id, const uint16_t *params, float *sigma, float *rgb,
-                        hipStream_t st) {
+                        hipStream_t st, int blocks = 0) {
     if (cap <= 0) return NVR_OK;
-    const unsigned gr = mfma_blocks(cap);
+    const unsigned gr = blocks > 0 ? (unsigned)blocks : mfma_blocks(cap);
 #define NVR_FWD(NCH, PL)                                                                       \
     mlp_fwd_mfma<NCH, PL><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id,     \
                                                      params, sigma, rgb)
@@ -603,9 +603,11 @@ nvr_status mfma_backward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int6
                          const uint16_t *feat, bool planar, const float *dirs,
                          const int32_t *ray_id, const uint16_t *params, const float *dsigma,
                          const float *drgb, float *dparams, float *dfeat, float *partial,
-                         hipStream_t st) {
+                         hipStream_t st, int blocks = 0) {
     if (cap <= 0) return NVR_OK;
-    const unsigned gr = mfma_blocks(cap);
+    // the partials workspace holds mfma_blocks(cap) workgroups
+    const unsigned gr = blocks > 0 && (unsigned)blocks < mfma_blocks(cap) ? (unsigned)blocks
+                                                                          : mfma_blocks(cap);
 #define NVR_BWD(NCH, PL)                                                                       \
     mlp_bwd_mfma<NCH, PL><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id,     \
                                                      params, dsigma, drgb, dfeat, partial)
@@ -616,6 +618,7 @@ nvr_status mfma_backward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int6
     }
 #undef NVR_BWD
     NVR_LAUNCHED();
+    if (dparams == nullptr) return NVR_OK;
     reduce_partials<<<grid_for(m.n_params, 256, 64), 256, 0, st>>>((int)gr, (int)m.n_params, partial,
                                                                    dparams);
     NVR_LAUNCHED();
@@ -641,20 +644,21 @@ size_t mfma_ws_bytes(const Net &net, int64_t cap) {
 
 nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
-                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st) {
+                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st, int blocks) {
     MfmaNet m;
     NVR_TRY(make_mfma_net(net, &m));
-    return mfma_forward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, sigma, rgb, st);
+    return mfma_forward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, sigma, rgb, st,
+                        blocks);
 }
 
 nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
                     const uint16_t *params, const float *dsigma, const float *drgb, float *dparams,
-                    float *dfeat, void *ws, hipStream_t st) {
+                    float *dfeat, void *ws, hipStream_t st, int blocks) {
     MfmaNet m;
     NVR_TRY(make_mfma_net(net, &m));
     return mfma_backward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, dsigma, drgb,
-                         dparams, dfeat, (float *)ws, st);
+                         dparams, dfeat, (float *)ws, st, blocks);
 }
 
 }  // namespace nvr

@@ -533,7 +533,8 @@ nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st) {
 
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
-                          float *dx_parts, bool planar, void *ws, hipStream_t st, bool counted) {
+                          float *dx_parts, bool planar, void *ws, hipStream_t st, bool counted,
+                          int emit_chunks) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
     const int tb = tile_bits(p);
@@ -541,7 +542,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     ScatterWs w = carve_scatter(p, ws, cap);
     const uint32_t n_records = (uint32_t)((uint64_t)cap * p.L * 8 < 0xffffffffull
                                               ? (uint64_t)cap * p.L * 8 : 0xffffffffull);
-    const unsigned gre = grid_for(cap, kEmitBlock, 64) * kXcds;
+    const unsigned gre = grid_for(cap, kEmitBlock, emit_chunks > 0 ? emit_chunks : 64) * kXcds;
     if (!counted) {
         zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>(w.count, nt + 1);
         NVR_LAUNCHED();
@@ -583,6 +584,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
 #undef NVR_EMIT_L
 #undef NVR_EMIT
     NVR_LAUNCHED();
+    if (dtable == nullptr) return NVR_OK;   // scan + emit only
     const int64_t max_items = max_items_of(cap, p.L, nt);
     const unsigned ga = (unsigned)(max_items < 65535 ? max_items : 65535);
     const size_t acc_lds = accum_lds_bytes(tb);
@@ -602,6 +604,14 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
         tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
     NVR_LAUNCHED();
     return NVR_OK;
+}
+
+nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_t *n_dev,
+                                    int64_t cap, const float *x, const void *table,
+                                    const float *dfeat, bool planar, void *ws, hipStream_t st,
+                                    int emit_chunks) {
+    return launch_scatter(p, n, n_dev, cap, x, table, dfeat, nullptr, nullptr, planar, ws, st,
+                          /*counted=*/true, emit_chunks);
 }
 
 }  // namespace nvr

@@ -26,6 +26,10 @@ struct FieldWs {
     float *dx;                      // [8][cap][3] (split) | [cap][3] (plain)
     void *mlp_ws;
     void *scatter_ws;               // binned table-gradient scatter (bf16 training)
+    // launch shapes of the BF16 step's kernels (0: built-in default), set by
+    // the autotuner for this capacity
+    int enc_chunks = 0, mlp_fwd_blocks = 0, mlp_bwd_blocks = 0, emit_chunks = 0;
+    bool tuned = false;
 };
 
 struct GraphEntry {
@@ -40,6 +44,7 @@ struct nvr_ctx {
     uint32_t flags = 0;
     hipStream_t capture = nullptr;
     nvr::FieldWs ws[2];
+    int comp_blocks = 0;           // compositing workgroups (autotuned; 0: default)
     float *ray_buf = nullptr;      // render: C, D per ray chunk
     int64_t ray_buf_n = 0;
     std::map<std::string, nvr::GraphEntry> graphs;
@@ -155,6 +160,8 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.dx = (float *)ptr[14];
     w.mlp_ws = ptr[15];
     w.scatter_ws = ptr[16];
+    w.enc_chunks = w.mlp_fwd_blocks = w.mlp_bwd_blocks = w.emit_chunks = 0;
+    w.tuned = false;
     return NVR_OK;
 }
 
@@ -181,9 +188,9 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
             NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
         }
         NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat, NVR_BF16,
-                                  true, st, count ? &counter : nullptr));
+                                  true, st, count ? &counter : nullptr, w.enc_chunks));
         NVR_TRY(mfma_fwd(net, 0, w.n_dev, cap, (const uint16_t *)w.feat, true, d, w.ray_id,
-                         (const uint16_t *)f->params_bf16, w.sigma, w.rgb, st));
+                         (const uint16_t *)f->params_bf16, w.sigma, w.rgb, st, w.mlp_fwd_blocks));
     } else {
         NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table, NVR_F32, w.feat, NVR_F32, false,
                                   st));
@@ -224,7 +231,7 @@ static nvr_status enqueue_fwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
     return launch_composite_loss(s->n_rays, a, s->n_fields == 2 ? &bb : nullptr, b->C_t, b->D_t, b->mask,
                                  s->lambda_depth, state, loss, C_out, D_out, ctx->ws[0].dsigma,
                                  ctx->ws[0].drgb, s->n_fields == 2 ? ctx->ws[1].dsigma : nullptr,
-                                 s->n_fields == 2 ? ctx->ws[1].drgb : nullptr, st);
+                                 s->n_fields == 2 ? ctx->ws[1].drgb : nullptr, st, ctx->comp_blocks);
 }
 
 static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
@@ -239,10 +246,10 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
         if (s->precision == NVR_BF16) {
             NVR_TRY(mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
                              (const uint16_t *)f->params_bf16, w.dsigma, w.drgb, f->params_grad,
-                             w.dfeat, w.mlp_ws, st));
+                             w.dfeat, w.mlp_ws, st, w.mlp_bwd_blocks));
             NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
                                    f->has_warp ? w.dx : nullptr, true, w.scatter_ws, st,
-                                   /*counted=*/true));
+                                   /*counted=*/true, w.emit_chunks));
             if (f->has_warp)
                 NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, kXcds, 3 * cap,
                                      f->node_dq_grad, f->bones_grad, st));
@@ -294,6 +301,111 @@ static nvr_status prepare(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const
             NVR_REQUIRE(fields[k]->params_m && fields[k]->params_v && fields[k]->table_m &&
                             fields[k]->table_v && fields[k]->table_grad && fields[k]->params_grad,
                         NVR_EINVAL, "NULL optimiser buffers");
+    return NVR_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Best of `reps` timed launches (after one untimed) on stream st.
+template <class F>
+static nvr_status time_best(hipStream_t st, F &&launch, float *best_ms, int reps = 3) {
+    hipEvent_t e0, e1;
+    NVR_HIP(hipEventCreate(&e0));
+    NVR_HIP(hipEventCreate(&e1));
+    nvr_status r = launch();
+    float best = 1e30f;
+    for (int i = 0; i < reps && r == NVR_OK; ++i) {
+        (void)hipEventRecord(e0, st);
+        r = launch();
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best = ms < best ? ms : best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best_ms = best;
+    return r;
+}
+
+// Picks the candidate of `cands` (n of them) with the shortest launch.
+template <class F>
+static nvr_status pick(hipStream_t st, const int *cands, int n, int *out, F &&launch_with) {
+    float best = 1e30f;
+    int arg = cands[0];
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        NVR_TRY(time_best(st, [&] { return launch_with(cands[i]); }, &ms));
+        if (ms < best) {
+            best = ms;
+            arg = cands[i];
+        }
+    }
+    *out = arg;
+    return NVR_OK;
+}
+
+// Tunes the launch shapes of the BF16 step on its real inputs (eager, before
+// any graph capture): one forward fills the sample buffers, then every
+// tunable kernel is timed per candidate shape.  Only launches without side
+// effects on the optimiser state are repeated: the gather (its tile counts
+// are reset each time), the network forward, the compositing + loss (it
+// zeroes the loss first), the network backward without the reduction into
+// the weight gradients, and the scatter's scan + emit.  Results do not
+// depend on the shapes except for the summation order of the gradients.
+static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
+                           const nvr_batch *b, const Net *nets, nvr_train_state *state,
+                           float *loss, hipStream_t st) {
+    NVR_TRY(enqueue_fwd(ctx, s, fields, b, nets, state, loss, nullptr, nullptr, st));
+    static const int enc[] = {256, 512, 1024, 2048};
+    static const int mlp_f[] = {256, 512, 1024, 2048};
+    static const int mlp_b[] = {128, 256, 512};
+    static const int emit[] = {32, 64, 128};
+    static const int comp[] = {4096, 16384, 65536};
+    for (int k = 0; k < s->n_fields; ++k) {
+        const nvr_field *f = fields[k];
+        FieldWs &w = ctx->ws[k];
+        const int64_t cap = w.cap;
+        const float *pos = f->has_warp ? w.xc : w.x;
+        const GridParams gp = make_grid_params(&f->grid);
+        const TileCounter counter = scatter_counter(gp, w.scatter_ws);
+        NVR_TRY(pick(st, enc, 4, &w.enc_chunks, [&](int c) {
+            NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
+            return launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat,
+                                     NVR_BF16, true, st, &counter, c);
+        }));
+        NVR_TRY(pick(st, mlp_f, 4, &w.mlp_fwd_blocks, [&](int c) {
+            return mfma_fwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d,
+                            w.ray_id, (const uint16_t *)f->params_bf16, w.sigma, w.rgb, st, c);
+        }));
+    }
+    const nvr_samples sa = samples_of(ctx->ws[0]);
+    nvr_samples sb;
+    if (s->n_fields == 2) sb = samples_of(ctx->ws[1]);
+    NVR_TRY(pick(st, comp, 3, &ctx->comp_blocks, [&](int c) {
+        return launch_composite_loss(s->n_rays, sa, s->n_fields == 2 ? &sb : nullptr, b->C_t, b->D_t,
+                                     b->mask, s->lambda_depth, state, loss, nullptr, nullptr,
+                                     ctx->ws[0].dsigma, ctx->ws[0].drgb,
+                                     s->n_fields == 2 ? ctx->ws[1].dsigma : nullptr,
+                                     s->n_fields == 2 ? ctx->ws[1].drgb : nullptr, st, c);
+    }));
+    for (int k = 0; k < s->n_fields; ++k) {
+        const nvr_field *f = fields[k];
+        FieldWs &w = ctx->ws[k];
+        const int64_t cap = w.cap;
+        const float *pos = f->has_warp ? w.xc : w.x;
+        const GridParams gp = make_grid_params(&f->grid);
+        NVR_TRY(pick(st, mlp_b, 3, &w.mlp_bwd_blocks, [&](int c) {
+            return mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
+                            (const uint16_t *)f->params_bf16, w.dsigma, w.drgb, nullptr, w.dfeat,
+                            w.mlp_ws, st, c);
+        }));
+        NVR_TRY(pick(st, emit, 3, &w.emit_chunks, [&](int c) {
+            return launch_scatter_emit_only(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, true,
+                                            w.scatter_ws, st, c);
+        }));
+        w.tuned = true;
+    }
     return NVR_OK;
 }
 
@@ -384,6 +496,19 @@ extern "C" nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_f
     NVR_REQUIRE(loss_dev && state_dev, NVR_EINVAL, "NULL loss or state");
     NVR_TRY(prepare(ctx, s, fields, nets));
     hipStream_t st = hs(stream);
+    if ((ctx->flags & NVR_AUTOTUNE) && s->precision == NVR_BF16) {
+        bool need = false;
+        for (int k = 0; k < s->n_fields; ++k) need |= !ctx->ws[k].tuned;
+        if (need) {
+            NVR_TRY(autotune(ctx, s, fields, b, nets, state_dev, loss_dev, st));
+            // graphs captured with the old shapes
+            for (auto &g : ctx->graphs) {
+                if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+                if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+            }
+            ctx->graphs.clear();
+        }
+    }
     if (!(ctx->flags & NVR_USE_GRAPH)) {
         NVR_TRY(enqueue_fwd(ctx, s, fields, b, nets, state_dev, loss_dev, nullptr, nullptr, st));
         return enqueue_bwd(ctx, s, fields, b, nets, state_dev, st);
@@ -409,6 +534,19 @@ extern "C" nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_f
         it = ctx->graphs.emplace(key, ge).first;
     }
     NVR_HIP(hipGraphLaunch(it->second.exec, st));
+    return NVR_OK;
+}
+
+extern "C" nvr_status nvr_launch_shape(const nvr_ctx *ctx, int32_t field, int32_t *shape) {
+    clear_error();
+    NVR_REQUIRE(ctx && shape && (field == 0 || field == 1), NVR_EINVAL, "bad arguments");
+    const FieldWs &w = ctx->ws[field];
+    shape[0] = w.enc_chunks;
+    shape[1] = w.mlp_fwd_blocks;
+    shape[2] = w.mlp_bwd_blocks;
+    shape[3] = w.emit_chunks;
+    shape[4] = ctx->comp_blocks;
+    shape[5] = w.tuned ? 1 : 0;
     return NVR_OK;
 }
 

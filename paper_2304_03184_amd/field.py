@@ -73,11 +73,12 @@ class Trainer:
     """Owns an nvr context; runs training steps and renders."""
 
     def __init__(self, fields, n_rays, max_samples, precision=L.NVR_F32, lambda_depth=0.0,
-                 adam=None, use_graph=False, loss_scale=1.0, device_index=0):
+                 adam=None, use_graph=False, loss_scale=1.0, device_index=0, autotune=False):
         self.fields = list(fields)
         self.n_rays = n_rays
         ctx = C.c_void_p()
-        call("nvr_create", C.byref(ctx), device_index, L.NVR_USE_GRAPH if use_graph else 0)
+        flags = (L.NVR_USE_GRAPH if use_graph else 0) | (L.NVR_AUTOTUNE if autotune else 0)
+        call("nvr_create", C.byref(ctx), device_index, flags)
         self.ctx = ctx
         self.desc = L.StepDesc(len(self.fields), precision, n_rays, max_samples, lambda_depth,
                                adam or ops.adam_desc(), 1)
@@ -109,6 +110,13 @@ class Trainer:
                  C.byref(self.batch), ops._p(self.state), ops._stream())
         finally:
             self.desc.apply_update = 1
+
+    def launch_shape(self, field=0):
+        """Launch shapes in use for `field` (gather chunks, network forward and
+        backward workgroups, emit chunks, compositing workgroups, tuned flag)."""
+        out = (C.c_int32 * 6)()
+        call("nvr_launch_shape", self.ctx, field, out)
+        return list(out)
 
     def sample_count(self, field=0):
         n = C.c_int64()

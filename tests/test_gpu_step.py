@@ -143,6 +143,37 @@ def test_graph_replay_matches_eager():
     assert np.mean(diff > 1e-5) < 1e-4 and diff.max() < 4e-2
 
 
+def test_autotuned_step_matches_default_shapes():
+    # the autotuner only changes launch shapes: four graph steps with tuned
+    # shapes agree with four eager steps at the default shapes (up to the
+    # summation order of the gradients, as in the replay test above)
+    I = _cfg2_small(900, seed_offset=5)
+    L, F, O = lib()
+    w, f = I["work"], I["fcfg"]
+    outs, shapes = [], None
+    for tune in (False, True):
+        fld = F.Field(w, f, I["table"], I["params"], occ_words=I["occ"])
+        tr = F.Trainer([fld], w.n_rays, w.n_rays * 128, precision=L.NVR_BF16, use_graph=tune,
+                       autotune=tune)
+        tr.set_batch(dev(I["o"]), dev(I["d"]), dev(I["Ct"]))
+        ls = [float(tr.step().item()) for _ in range(4)]
+        torch.cuda.synchronize()
+        if tune:
+            shapes = tr.launch_shape(0)
+        else:
+            assert tr.launch_shape(0) == [0, 0, 0, 0, 0, 0]
+        outs.append((ls, host(fld.params), host(fld.table)))
+        tr.close()
+    assert shapes[0] in (256, 512, 1024, 2048) and shapes[1] in (256, 512, 1024, 2048)
+    assert shapes[2] in (128, 256, 512) and shapes[3] in (32, 64, 128)
+    assert shapes[4] in (4096, 16384, 65536) and shapes[5] == 1
+    (l0, p0, t0), (l1, p1, t1) = outs
+    np.testing.assert_allclose(l1, l0, rtol=1e-5)
+    np.testing.assert_allclose(p1, p0, rtol=0, atol=1e-4)
+    diff = np.abs(t1 - t0)
+    assert np.mean(diff > 1e-5) < 1e-4 and diff.max() < 4e-2
+
+
 def _human(n_rays, knn_res=32, n_nodes=512, seed=0):
     f = synth.FieldCfg(occ_res=64)
     w = synth.WorkCfg("h", n_rays, (f,), warp=True)
