@@ -214,9 +214,12 @@ nvr_status nvr_mlp_param_count(const nvr_mlp_desc *m, int64_t *count);
 
 /* sigma[n], rgb[n][3] from feat[n][n_in] (feat_dtype) and the view direction
  * dirs[ray_id[i]] (ray_id nullable: dirs is per sample).  math = NVR_F32 runs
- * the plain float32 kernel (params float32); math = NVR_BF16 runs the MFMA
- * kernel (params bf16 copy, feat bf16; widths 64 / n_in <= 32 / density_out 16
- * / 16 + SH <= 32 only). */
+ * the plain float32 kernel (params float32).  math = NVR_F16 and NVR_BF16 run
+ * the MFMA kernel (widths 64 / n_in <= 32 / density_out 16 / 16 + SH <= 32
+ * only) with fp32 accumulation: NVR_F16 takes fp16 features and the float32
+ * parameters (converted to fp16 fragments), NVR_BF16 bf16 features and a bf16
+ * parameter copy; the forward runs in that type, every backward product in
+ * bf16. */
 nvr_status nvr_mlp_fwd(const nvr_mlp_desc *m, int64_t n, const int32_t *n_dev,
                        const void *feat, nvr_dtype feat_dtype, const float *dirs,
                        const int32_t *ray_id, const void *params, nvr_dtype math,

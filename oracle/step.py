@@ -126,12 +126,12 @@ def forward_all(work, state: StepState, o, d, ranges, grid_box=None, t_stop=0.0)
 
 
 def train_step(work, state: StepState, o, d, C_t, D_t, ranges, grid_box=None,
-               adam=None, apply=True):
-    """One fwd + bwd (+ Adam if ``apply``).  Returns dict(loss, grads per field,
-    C, D, fwd)."""
+               adam=None, apply=True, mask=None):
+    """One fwd + bwd (+ Adam if ``apply``); ``mask`` is the per-ray M(r) of
+    Eq. 8 (None: every ray).  Returns dict(loss, grads per field, C, D, fwd)."""
     adam = adam or optim.Adam()
     fw = forward_all(work, state, o, d, ranges, grid_box)
-    L, dC, dD = optim.loss(fw["C"], fw["D"], C_t, D_t, work.lambda_depth)
+    L, dC, dD = optim.loss(fw["C"], fw["D"], C_t, D_t, work.lambda_depth, mask)
     dsig, drgb = composite.backward(fw["off"], fw["sigma"], fw["rgb"], fw["t"], fw["dt"],
                                     dC * state.loss_scale, dD * state.loss_scale)
     grads = []

@@ -292,8 +292,8 @@ nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_de
                              void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st,
                              const TileCounter *counter, int chunks_cap) {
     if (cap <= 0) return NVR_OK;
-    NVR_REQUIRE(counter == nullptr || (table_dtype != NVR_F32 && planar && feat_dtype == NVR_BF16),
-                NVR_EUNSUPPORTED, "tile counting needs the planar bf16 gather");
+    NVR_REQUIRE(counter == nullptr || (table_dtype != NVR_F32 && planar && feat_dtype == NVR_F16),
+                NVR_EUNSUPPORTED, "tile counting needs the planar fp16 gather");
     if (table_dtype == NVR_F32) {
         unsigned gr = grid_for(cap * p.L, 256);
         if (feat_dtype == NVR_F32)
@@ -324,11 +324,11 @@ nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_de
             const int lpg = (p.L + kXcds - 1) / kXcds;
             const size_t lds = sizeof(uint32_t) * lpg * counter->level_tiles;
             if (quad)
-                encode_fwd_split<true, bf16_t, true, true><<<gr, 256, lds, st>>>(
-                    p, n, n_dev, cap, x, tb, (bf16_t *)feat, *counter);
+                encode_fwd_split<true, f16_t, true, true><<<gr, 256, lds, st>>>(
+                    p, n, n_dev, cap, x, tb, (f16_t *)feat, *counter);
             else
-                encode_fwd_split<true, bf16_t, true, false><<<gr, 256, lds, st>>>(
-                    p, n, n_dev, cap, x, tb, (bf16_t *)feat, *counter);
+                encode_fwd_split<true, f16_t, true, false><<<gr, 256, lds, st>>>(
+                    p, n, n_dev, cap, x, tb, (f16_t *)feat, *counter);
         } else if (planar) {
             if (feat_dtype == NVR_F32) NVR_SPLIT_FWD(true, float);
             else if (feat_dtype == NVR_BF16) NVR_SPLIT_FWD(true, bf16_t);

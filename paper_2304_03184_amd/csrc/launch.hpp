@@ -46,13 +46,15 @@ size_t mfma_ws_bytes(const Net &net, int64_t cap);
 // blocks: workgroups of the persistent network kernels (0: default; the
 // backward's is capped by its workspace); dparams == nullptr skips the final
 // reduction of the per-workgroup weight-gradient partials.
+// f16: fp16 forward (feat fp16, params the fp32 masters); otherwise bf16
+// forward (feat bf16, params the bf16 copy).  Backward products are bf16.
 nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
-                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st,
+                    const void *params, bool f16, float *sigma, float *rgb, hipStream_t st,
                     int blocks = 0);
 nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
-                    const uint16_t *params, const float *dsigma, const float *drgb, float *dparams,
-                    float *dfeat, void *ws, hipStream_t st, int blocks = 0);
+                    const void *params, bool f16, const float *dsigma, const float *drgb,
+                    float *dparams, float *dfeat, void *ws, hipStream_t st, int blocks = 0);
 
 }  // namespace nvr

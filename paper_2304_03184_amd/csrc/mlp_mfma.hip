@@ -1,5 +1,11 @@
-// Density + colour networks on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16
-// and v_mfma_f32_16x16x16_bf16), fp32 accumulation.
+// Density + colour networks on the matrix cores, fp32 accumulation.  The
+// forward (features, weights, activations) runs in FT: fp16
+// (v_mfma_f32_16x16x32_f16, 10-bit mantissa; weights converted from the fp32
+// masters) or bf16 (v_mfma_f32_16x16x32_bf16, weights from a bf16 copy).  All
+// backward products (gradients times transposed weights, weight gradients)
+// run in bf16 (v_mfma_f32_16x16x32_bf16 / 16x16x16_bf16), whose fp32 exponent
+// range needs no loss scaling.  An encoding rounded to bf16 (8-bit mantissa)
+// measurably slows training of a hash-grid field; rounded to fp16 it does not.
 //
 // Layout.  A wave works on column blocks of 16 samples.  In "orientation A"
 // a layer computes D = W X (rows = units, columns = samples): lane l holds
@@ -21,6 +27,8 @@
 //
 // Supported shape: n_in <= 32, one density hidden layer of 64, 16 density
 // outputs, 16 + SH <= 32 colour inputs, one or two colour hidden layers of 64.
+#include <type_traits>
+
 #include "common.hpp"
 #include "mlp_dev.hpp"
 #include "sh_dev.hpp"
@@ -28,13 +36,22 @@
 namespace nvr {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf8;
+typedef __attribute__((ext_vector_type(8))) _Float16 h8;
 typedef __attribute__((ext_vector_type(4))) short s4;
 typedef __attribute__((ext_vector_type(4))) float f4;
+
+// forward operand vector of element type FT
+template <typename FT> struct Vec8;
+template <> struct Vec8<__bf16> { typedef bf8 type; };
+template <> struct Vec8<_Float16> { typedef h8 type; };
 
 constexpr int kMfmaBlock = 256;   // 4 waves
 
 __device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma32(h8 a, h8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -48,6 +65,22 @@ __device__ __forceinline__ bf8 pair8(f4 a, f4 b) {
     r[0] = (__bf16)a[0]; r[1] = (__bf16)a[1]; r[2] = (__bf16)a[2]; r[3] = (__bf16)a[3];
     r[4] = (__bf16)b[0]; r[5] = (__bf16)b[1]; r[6] = (__bf16)b[2]; r[7] = (__bf16)b[3];
     return r;
+}
+// the same in the forward type
+template <typename FT>
+__device__ __forceinline__ typename Vec8<FT>::type packf(f4 a, f4 b) {
+    typename Vec8<FT>::type r;
+    r[0] = (FT)a[0]; r[1] = (FT)a[1]; r[2] = (FT)a[2]; r[3] = (FT)a[3];
+    r[4] = (FT)b[0]; r[5] = (FT)b[1]; r[6] = (FT)b[2]; r[7] = (FT)b[3];
+    return r;
+}
+// a stored feature (16-bit pattern of FT) as float
+template <typename FT> __device__ __forceinline__ float feat_bits_to_f32(uint16_t b);
+template <> __device__ __forceinline__ float feat_bits_to_f32<__bf16>(uint16_t b) {
+    return bf16_bits_to_f32(b);
+}
+template <> __device__ __forceinline__ float feat_bits_to_f32<_Float16>(uint16_t b) {
+    return f16_bits_to_f32(b);
 }
 __device__ __forceinline__ s4 quad(f4 a) {
     s4 r;
@@ -87,13 +120,15 @@ __device__ __forceinline__ int fo(int m, int r) {
     return 2 * (p + 8 * (e >> 1)) + (e & 1);
 }
 
+template <typename FT>
 struct Frags {
-    bf8 d1[4][64];
-    bf8 d2[2][64];
-    bf8 c1[4][64];
-    bf8 c2[4][2][64];
-    bf8 c3[2][64];
-    s4 c3t[4][64];
+    typedef typename Vec8<FT>::type V;
+    V d1[4][64];          // forward fragments (FT)
+    V d2[2][64];
+    V c1[4][64];
+    V c2[4][2][64];
+    V c3[2][64];
+    s4 c3t[4][64];        // backward (transposed) fragments (bf16)
     bf8 c2t[4][2][64];
     bf8 c1t[2][64];
     s4 d2t[4][64];
@@ -106,26 +141,31 @@ struct MfmaNet {
     int64_t n_params;
 };
 
-// Builds the LDS weight fragments from flat bf16 parameters.
-template <int NCH, bool PLANAR>
-__device__ void build_frags(Frags &F, const MfmaNet &net, const uint16_t *__restrict__ w) {
+// Builds the LDS weight fragments from the flat parameters: fp32 masters for
+// an fp16 forward, the bf16 copy for a bf16 forward.
+template <int NCH, bool PLANAR, typename FT>
+__device__ void build_frags(Frags<FT> &F, const MfmaNet &net, const void *__restrict__ wp) {
     const int cin = 16 + net.nsh;
     auto W = [&](int64_t off, int row, int col, int ncol) -> float {
-        return bf_of_bits(w[off + (int64_t)row * ncol + col]);
+        const int64_t i = off + (int64_t)row * ncol + col;
+        if (std::is_same<FT, _Float16>::value) return reinterpret_cast<const float *>(wp)[i];
+        return bf_of_bits(reinterpret_cast<const uint16_t *>(wp)[i]);
     };
+    typedef typename Vec8<FT>::type V;
     for (int e = threadIdx.x; e < 64 * 4; e += blockDim.x) {
         const int m = e / 64, l = e % 64, r = l % 16, g = l / 16;
         bf8 v;
+        V vf;
         for (int j = 0; j < 8; ++j) {
             const int k = kin<PLANAR>(g, j);
-            v[j] = (__bf16)(k < net.n_in ? W(net.off_d1, 16 * m + r, k, net.n_in) : 0.f);
+            vf[j] = (FT)(k < net.n_in ? W(net.off_d1, 16 * m + r, k, net.n_in) : 0.f);
         }
-        F.d1[m][l] = v;
+        F.d1[m][l] = vf;
         for (int j = 0; j < 8; ++j) {
             const int k = kc(g, j);
-            v[j] = (__bf16)(k < cin ? W(net.off_c1, 16 * m + r, k, cin) : 0.f);
+            vf[j] = (FT)(k < cin ? W(net.off_c1, 16 * m + r, k, cin) : 0.f);
         }
-        F.c1[m][l] = v;
+        F.c1[m][l] = vf;
         s4 t;
         for (int j = 0; j < 4; ++j)
             t[j] = bfs(4 * g + j < 3 ? W(net.off_c3, 4 * g + j, 16 * m + r, 64) : 0.f);
@@ -134,8 +174,8 @@ __device__ void build_frags(Frags &F, const MfmaNet &net, const uint16_t *__rest
         F.d2t[m][l] = t;
         if (NCH == 2) {
             for (int q = 0; q < 2; ++q) {
-                for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_c2, 16 * m + r, kh(q, g, j), 64);
-                F.c2[m][q][l] = v;
+                for (int j = 0; j < 8; ++j) vf[j] = (FT)W(net.off_c2, 16 * m + r, kh(q, g, j), 64);
+                F.c2[m][q][l] = vf;
                 for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_c2, kh(q, g, j), 16 * m + r, 64);
                 F.c2t[m][q][l] = v;
             }
@@ -144,10 +184,11 @@ __device__ void build_frags(Frags &F, const MfmaNet &net, const uint16_t *__rest
     for (int e = threadIdx.x; e < 64 * 2; e += blockDim.x) {
         const int q = e / 64, l = e % 64, r = l % 16, g = l / 16;
         bf8 v;
-        for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_d2, r, kh(q, g, j), 64);
-        F.d2[q][l] = v;
-        for (int j = 0; j < 8; ++j) v[j] = (__bf16)(r < 3 ? W(net.off_c3, r, kh(q, g, j), 64) : 0.f);
-        F.c3[q][l] = v;
+        V vf;
+        for (int j = 0; j < 8; ++j) vf[j] = (FT)W(net.off_d2, r, kh(q, g, j), 64);
+        F.d2[q][l] = vf;
+        for (int j = 0; j < 8; ++j) vf[j] = (FT)(r < 3 ? W(net.off_c3, r, kh(q, g, j), 64) : 0.f);
+        F.c3[q][l] = vf;
         for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(net.off_c1, kh(q, g, j), r, cin);
         F.c1t[q][l] = v;
         for (int m = 0; m < 2; ++m) {
@@ -159,13 +200,15 @@ __device__ void build_frags(Frags &F, const MfmaNet &net, const uint16_t *__rest
     }
 }
 
-// Feature access.  Row-major: [cap][n_in] bf16; planar: [8][cap][4] bf16.
-template <bool PLANAR>
-__device__ __forceinline__ bf8 load_feat_a(const uint16_t *__restrict__ feat, int64_t s, int64_t cap,
-                                           int n_in, int g, bool valid) {
-    bf8 v;
+// Feature access (16-bit patterns of FT).  Row-major: [cap][n_in]; planar:
+// [8][cap][4].
+template <bool PLANAR, typename FT>
+__device__ __forceinline__ typename Vec8<FT>::type load_feat_a(const uint16_t *__restrict__ feat,
+                                                               int64_t s, int64_t cap, int n_in,
+                                                               int g, bool valid) {
+    typename Vec8<FT>::type v;
     if (!valid) {
-        for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
+        for (int j = 0; j < 8; ++j) v[j] = (FT)0.f;
         return v;
     }
     if (PLANAR) {
@@ -173,32 +216,32 @@ __device__ __forceinline__ bf8 load_feat_a(const uint16_t *__restrict__ feat, in
         const uint2 b = *reinterpret_cast<const uint2 *>(feat + ((int64_t)(2 * g + 1) * cap + s) * 4);
         const uint32_t u[4] = {a.x, a.y, b.x, b.y};
         for (int j = 0; j < 8; ++j)
-            v[j] = __builtin_bit_cast(__bf16, (uint16_t)((u[j >> 1] >> (16 * (j & 1))) & 0xffffu));
+            v[j] = __builtin_bit_cast(FT, (uint16_t)((u[j >> 1] >> (16 * (j & 1))) & 0xffffu));
         return v;
     }
     if (n_in == 32) {
         const uint4 a = *reinterpret_cast<const uint4 *>(feat + s * 32 + 8 * g);
         const uint32_t u[4] = {a.x, a.y, a.z, a.w};
         for (int j = 0; j < 8; ++j)
-            v[j] = __builtin_bit_cast(__bf16, (uint16_t)((u[j >> 1] >> (16 * (j & 1))) & 0xffffu));
+            v[j] = __builtin_bit_cast(FT, (uint16_t)((u[j >> 1] >> (16 * (j & 1))) & 0xffffu));
         return v;
     }
     for (int j = 0; j < 8; ++j) {
         const int k = 8 * g + j;
-        v[j] = __builtin_bit_cast(__bf16, k < n_in ? feat[s * n_in + k] : (uint16_t)0);
+        v[j] = __builtin_bit_cast(FT, k < n_in ? feat[s * n_in + k] : (uint16_t)0);
     }
     return v;
 }
 
-template <bool PLANAR>
+template <bool PLANAR, typename FT>
 __device__ __forceinline__ float load_feat_one(const uint16_t *__restrict__ feat, int64_t s,
                                                int64_t cap, int n_in, int f) {
     if (f >= n_in) return 0.f;
     if (PLANAR) {
         const int level = f >> 1, plane = level & 7, e = 2 * (level >> 3) + (f & 1);
-        return bf_of_bits(feat[((int64_t)plane * cap + s) * 4 + e]);
+        return feat_bits_to_f32<FT>(feat[((int64_t)plane * cap + s) * 4 + e]);
     }
-    return bf_of_bits(feat[s * n_in + f]);
+    return feat_bits_to_f32<FT>(feat[s * n_in + f]);
 }
 
 __device__ __forceinline__ float pick16(const float *sh, int k) {
@@ -209,25 +252,27 @@ __device__ __forceinline__ float pick16(const float *sh, int k) {
 }
 
 // Orientation-A forward of one column block.
-template <int NCH>
+template <int NCH, typename FT>
 struct FwdA {
+    typedef typename Vec8<FT>::type V;
     f4 hd[4];
-    bf8 hdb[2];
+    V hdb[2];
     f4 o;
-    bf8 cin;
+    V cin;
     f4 h1[4];
-    bf8 h1b[2];
+    V h1b[2];
     f4 h2[4];
-    bf8 h2b[2];
+    V h2b[2];
     f4 z;
 };
 
-template <int NCH>
-__device__ __forceinline__ void forward_a(const Frags &F, int l, int g, bf8 xf, const float *dir,
-                                         int nsh, FwdA<NCH> &a) {
+template <int NCH, typename FT>
+__device__ __forceinline__ void forward_a(const Frags<FT> &F, int l, int g,
+                                         typename Vec8<FT>::type xf, const float *dir, int nsh,
+                                         FwdA<NCH, FT> &a) {
     for (int m = 0; m < 4; ++m) a.hd[m] = relu4(mfma32(F.d1[m][l], xf, zero4()));
-    a.hdb[0] = pair8(a.hd[0], a.hd[1]);
-    a.hdb[1] = pair8(a.hd[2], a.hd[3]);
+    a.hdb[0] = packf<FT>(a.hd[0], a.hd[1]);
+    a.hdb[1] = packf<FT>(a.hd[2], a.hd[3]);
     a.o = mfma32(F.d2[0][l], a.hdb[0], zero4());
     a.o = mfma32(F.d2[1][l], a.hdb[1], a.o);
     float sh[16];
@@ -238,17 +283,17 @@ __device__ __forceinline__ void forward_a(const Frags &F, int l, int g, bf8 xf, 
         const int k = 4 * g + j;
         s4v[j] = k < nsh ? pick16(sh, k) : 0.f;
     }
-    a.cin = pair8(a.o, s4v);
+    a.cin = packf<FT>(a.o, s4v);
     for (int m = 0; m < 4; ++m) a.h1[m] = relu4(mfma32(F.c1[m][l], a.cin, zero4()));
-    a.h1b[0] = pair8(a.h1[0], a.h1[1]);
-    a.h1b[1] = pair8(a.h1[2], a.h1[3]);
+    a.h1b[0] = packf<FT>(a.h1[0], a.h1[1]);
+    a.h1b[1] = packf<FT>(a.h1[2], a.h1[3]);
     if (NCH == 2) {
         for (int m = 0; m < 4; ++m) {
             f4 acc = mfma32(F.c2[m][0][l], a.h1b[0], zero4());
             a.h2[m] = relu4(mfma32(F.c2[m][1][l], a.h1b[1], acc));
         }
-        a.h2b[0] = pair8(a.h2[0], a.h2[1]);
-        a.h2b[1] = pair8(a.h2[2], a.h2[3]);
+        a.h2b[0] = packf<FT>(a.h2[0], a.h2[1]);
+        a.h2b[1] = packf<FT>(a.h2[2], a.h2[3]);
         a.z = mfma32(F.c3[0][l], a.h2b[0], zero4());
         a.z = mfma32(F.c3[1][l], a.h2b[1], a.z);
     } else {
@@ -262,14 +307,14 @@ __device__ __forceinline__ float clamp_sigma(float o) {
     return fminf(fmaxf(o, -kSigmaClamp), kSigmaClamp);
 }
 
-template <int NCH, bool PLANAR>
+template <int NCH, bool PLANAR, typename FT>
 __global__ void __launch_bounds__(kMfmaBlock)
 mlp_fwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const uint16_t *__restrict__ feat, const float *__restrict__ dirs,
-             const int32_t *__restrict__ ray_id, const uint16_t *__restrict__ params,
+             const int32_t *__restrict__ ray_id, const void *__restrict__ params,
              float *__restrict__ sigma, float *__restrict__ rgb) {
-    __shared__ Frags F;
-    build_frags<NCH, PLANAR>(F, net, params);
+    __shared__ Frags<FT> F;
+    build_frags<NCH, PLANAR, FT>(F, net, params);
     __syncthreads();
     const int64_t count = count_of(n, n_dev, cap);
     const int l = threadIdx.x % 64, g = l / 16, c = l % 16;
@@ -278,7 +323,7 @@ mlp_fwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
     for (int64_t cb = wave; cb * 16 < count; cb += nwaves) {
         const int64_t s = cb * 16 + c;
         const bool valid = s < count;
-        const bf8 xf = load_feat_a<PLANAR>(feat, s, cap, net.n_in, g, valid);
+        const typename Vec8<FT>::type xf = load_feat_a<PLANAR, FT>(feat, s, cap, net.n_in, g, valid);
         float dir[3] = {0.f, 0.f, 1.f};
         if (valid) {
             const int64_t r = ray_id ? ray_id[s] : s;
@@ -286,8 +331,8 @@ mlp_fwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
             dir[1] = dirs[3 * r + 1];
             dir[2] = dirs[3 * r + 2];
         }
-        FwdA<NCH> a;
-        forward_a<NCH>(F, l, g, xf, dir, net.nsh, a);
+        FwdA<NCH, FT> a;
+        forward_a<NCH, FT>(F, l, g, xf, dir, net.nsh, a);
         if (valid && g == 0) {
             sigma[s] = expf(clamp_sigma(a.o[0]));
             rgb[3 * s] = sigmoidf_(a.z[0]);
@@ -308,15 +353,15 @@ struct DW {
     f4 c3[4];
 };
 
-template <int NCH, bool PLANAR>
+template <int NCH, bool PLANAR, typename FT>
 __global__ void __launch_bounds__(kMfmaBlock)
 mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const uint16_t *__restrict__ feat, const float *__restrict__ dirs,
-             const int32_t *__restrict__ ray_id, const uint16_t *__restrict__ params,
+             const int32_t *__restrict__ ray_id, const void *__restrict__ params,
              const float *__restrict__ dsigma, const float *__restrict__ drgb,
              float *__restrict__ dfeat, float *__restrict__ partial) {
-    __shared__ Frags F;
-    build_frags<NCH, PLANAR>(F, net, params);
+    __shared__ Frags<FT> F;
+    build_frags<NCH, PLANAR, FT>(F, net, params);
     __syncthreads();
     const int64_t count = count_of(n, n_dev, cap);
     const int l = threadIdx.x % 64, g = l / 16, c = l % 16;
@@ -339,7 +384,7 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
         const int64_t s = base + c;
         const bool valid = s < count;
         // ------------------------------------------------ orientation A forward
-        const bf8 xf = load_feat_a<PLANAR>(feat, s, cap, net.n_in, g, valid);
+        const typename Vec8<FT>::type xf = load_feat_a<PLANAR, FT>(feat, s, cap, net.n_in, g, valid);
         float dir[3] = {0.f, 0.f, 1.f};
         float ds = 0.f, dr[3] = {0.f, 0.f, 0.f};
         if (valid) {
@@ -352,8 +397,8 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
             dr[1] = drgb[3 * s + 1];
             dr[2] = drgb[3 * s + 2];
         }
-        FwdA<NCH> a;
-        forward_a<NCH>(F, l, g, xf, dir, nsh, a);
+        FwdA<NCH, FT> a;
+        forward_a<NCH, FT>(F, l, g, xf, dir, nsh, a);
         // ------------------------------------------------ orientation A backward
         f4 dz = zero4();
         if (g == 0) {
@@ -409,7 +454,7 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
         for (int t = 0; t < 2; ++t)
             for (int i = 0; i < 4; ++i) {
                 const int64_t si = base + 4 * g + i;
-                x0b[t][i] = si < count ? load_feat_one<PLANAR>(feat, si, cap, net.n_in, 16 * t + c) : 0.f;
+                x0b[t][i] = si < count ? load_feat_one<PLANAR, FT>(feat, si, cap, net.n_in, 16 * t + c) : 0.f;
             }
         f4 hdB[4];
         for (int t = 0; t < 4; ++t) hdB[t] = relu4(mfma32(xf, F.d1[t][l], zero4()));
@@ -432,10 +477,7 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
             }
         }
         f4 h1B[4];
-        {
-            const bf8 cin = a.cin;
-            for (int t = 0; t < 4; ++t) h1B[t] = relu4(mfma32(cin, F.c1[t][l], zero4()));
-        }
+        for (int t = 0; t < 4; ++t) h1B[t] = relu4(mfma32(a.cin, F.c1[t][l], zero4()));
         f4 h2B[4];
         f4 zB;
         if (NCH == 2) {
@@ -564,7 +606,7 @@ nvr_status make_mfma_net(const Net &net, MfmaNet *m) {
     m->off_c2 = nch == 2 ? net.woff[3] : 0;
     m->off_c3 = net.woff[2 + nch];
     m->n_params = net.woff[net.n_layers];
-    NVR_REQUIRE(m->n_params * 4 <= (int64_t)sizeof(Frags), NVR_EUNSUPPORTED, "too many parameters");
+    NVR_REQUIRE(m->n_params * 4 <= (int64_t)sizeof(Frags<__bf16>), NVR_EUNSUPPORTED, "too many parameters");
     return NVR_OK;
 }
 
@@ -582,18 +624,25 @@ size_t mfma_workspace(const MfmaNet &m, int64_t cap) {
 
 nvr_status mfma_forward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64_t cap,
                         const uint16_t *feat, bool planar, const float *dirs,
-                        const int32_t *ray_id, const uint16_t *params, float *sigma, float *rgb,
-                        hipStream_t st, int blocks = 0) {
+                        const int32_t *ray_id, const void *params, bool f16, float *sigma,
+                        float *rgb, hipStream_t st, int blocks = 0) {
     if (cap <= 0) return NVR_OK;
     const unsigned gr = blocks > 0 ? (unsigned)blocks : mfma_blocks(cap);
-#define NVR_FWD(NCH, PL)                                                                       \
-    mlp_fwd_mfma<NCH, PL><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id,     \
-                                                     params, sigma, rgb)
-    if (m.nch == 2) {
-        if (planar) NVR_FWD(2, true); else NVR_FWD(2, false);
-    } else {
-        if (planar) NVR_FWD(1, true); else NVR_FWD(1, false);
+#define NVR_FWD(NCH, PL, FT)                                                                   \
+    mlp_fwd_mfma<NCH, PL, FT><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id, \
+                                                         params, sigma, rgb)
+#define NVR_FWD_T(FT)                                                                          \
+    if (m.nch == 2) {                                                                          \
+        if (planar) NVR_FWD(2, true, FT); else NVR_FWD(2, false, FT);                          \
+    } else {                                                                                   \
+        if (planar) NVR_FWD(1, true, FT); else NVR_FWD(1, false, FT);                          \
     }
+    if (f16) {
+        NVR_FWD_T(_Float16)
+    } else {
+        NVR_FWD_T(__bf16)
+    }
+#undef NVR_FWD_T
 #undef NVR_FWD
     NVR_LAUNCHED();
     return NVR_OK;
@@ -601,21 +650,28 @@ nvr_status mfma_forward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64
 
 nvr_status mfma_backward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64_t cap,
                          const uint16_t *feat, bool planar, const float *dirs,
-                         const int32_t *ray_id, const uint16_t *params, const float *dsigma,
+                         const int32_t *ray_id, const void *params, bool f16, const float *dsigma,
                          const float *drgb, float *dparams, float *dfeat, float *partial,
                          hipStream_t st, int blocks = 0) {
     if (cap <= 0) return NVR_OK;
     // the partials workspace holds mfma_blocks(cap) workgroups
     const unsigned gr = blocks > 0 && (unsigned)blocks < mfma_blocks(cap) ? (unsigned)blocks
                                                                           : mfma_blocks(cap);
-#define NVR_BWD(NCH, PL)                                                                       \
-    mlp_bwd_mfma<NCH, PL><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id,     \
-                                                     params, dsigma, drgb, dfeat, partial)
-    if (m.nch == 2) {
-        if (planar) NVR_BWD(2, true); else NVR_BWD(2, false);
-    } else {
-        if (planar) NVR_BWD(1, true); else NVR_BWD(1, false);
+#define NVR_BWD(NCH, PL, FT)                                                                   \
+    mlp_bwd_mfma<NCH, PL, FT><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id, \
+                                                         params, dsigma, drgb, dfeat, partial)
+#define NVR_BWD_T(FT)                                                                          \
+    if (m.nch == 2) {                                                                          \
+        if (planar) NVR_BWD(2, true, FT); else NVR_BWD(2, false, FT);                          \
+    } else {                                                                                   \
+        if (planar) NVR_BWD(1, true, FT); else NVR_BWD(1, false, FT);                          \
     }
+    if (f16) {
+        NVR_BWD_T(_Float16)
+    } else {
+        NVR_BWD_T(__bf16)
+    }
+#undef NVR_BWD_T
 #undef NVR_BWD
     NVR_LAUNCHED();
     if (dparams == nullptr) return NVR_OK;
@@ -644,20 +700,21 @@ size_t mfma_ws_bytes(const Net &net, int64_t cap) {
 
 nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
-                    const uint16_t *params, float *sigma, float *rgb, hipStream_t st, int blocks) {
+                    const void *params, bool f16, float *sigma, float *rgb, hipStream_t st,
+                    int blocks) {
     MfmaNet m;
     NVR_TRY(make_mfma_net(net, &m));
-    return mfma_forward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, sigma, rgb, st,
+    return mfma_forward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, f16, sigma, rgb, st,
                         blocks);
 }
 
 nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
-                    const uint16_t *params, const float *dsigma, const float *drgb, float *dparams,
-                    float *dfeat, void *ws, hipStream_t st, int blocks) {
+                    const void *params, bool f16, const float *dsigma, const float *drgb,
+                    float *dparams, float *dfeat, void *ws, hipStream_t st, int blocks) {
     MfmaNet m;
     NVR_TRY(make_mfma_net(net, &m));
-    return mfma_backward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, dsigma, drgb,
+    return mfma_backward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, f16, dsigma, drgb,
                          dparams, dfeat, (float *)ws, st, blocks);
 }
 

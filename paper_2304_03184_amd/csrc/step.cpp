@@ -187,10 +187,11 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
             counter = scatter_counter(gp, w.scatter_ws);
             NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
         }
-        NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat, NVR_BF16,
+        // fp16 features and fp16 forward; the networks' backward products run in bf16
+        NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat, NVR_F16,
                                   true, st, count ? &counter : nullptr, w.enc_chunks));
         NVR_TRY(mfma_fwd(net, 0, w.n_dev, cap, (const uint16_t *)w.feat, true, d, w.ray_id,
-                         (const uint16_t *)f->params_bf16, w.sigma, w.rgb, st, w.mlp_fwd_blocks));
+                         f->params, true, w.sigma, w.rgb, st, w.mlp_fwd_blocks));
     } else {
         NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table, NVR_F32, w.feat, NVR_F32, false,
                                   st));
@@ -245,8 +246,8 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
         const GridParams gp = make_grid_params(&f->grid);
         if (s->precision == NVR_BF16) {
             NVR_TRY(mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
-                             (const uint16_t *)f->params_bf16, w.dsigma, w.drgb, f->params_grad,
-                             w.dfeat, w.mlp_ws, st, w.mlp_bwd_blocks));
+                             f->params, true, w.dsigma, w.drgb, f->params_grad, w.dfeat, w.mlp_ws,
+                             st, w.mlp_bwd_blocks));
             NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
                                    f->has_warp ? w.dx : nullptr, true, w.scatter_ws, st,
                                    /*counted=*/true, w.emit_chunks));
@@ -372,11 +373,11 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         NVR_TRY(pick(st, enc, 4, &w.enc_chunks, [&](int c) {
             NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
             return launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat,
-                                     NVR_BF16, true, st, &counter, c);
+                                     NVR_F16, true, st, &counter, c);
         }));
         NVR_TRY(pick(st, mlp_f, 4, &w.mlp_fwd_blocks, [&](int c) {
             return mfma_fwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d,
-                            w.ray_id, (const uint16_t *)f->params_bf16, w.sigma, w.rgb, st, c);
+                            w.ray_id, f->params, true, w.sigma, w.rgb, st, c);
         }));
     }
     const nvr_samples sa = samples_of(ctx->ws[0]);
@@ -397,8 +398,7 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         const GridParams gp = make_grid_params(&f->grid);
         NVR_TRY(pick(st, mlp_b, 3, &w.mlp_bwd_blocks, [&](int c) {
             return mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
-                            (const uint16_t *)f->params_bf16, w.dsigma, w.drgb, nullptr, w.dfeat,
-                            w.mlp_ws, st, c);
+                            f->params, true, w.dsigma, w.drgb, nullptr, w.dfeat, w.mlp_ws, st, c);
         }));
         NVR_TRY(pick(st, emit, 3, &w.emit_chunks, [&](int c) {
             return launch_scatter_emit_only(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, true,
@@ -612,7 +612,7 @@ extern "C" nvr_status nvr_render(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field
 extern "C" size_t nvr_mlp_workspace(const nvr_mlp_desc *m, nvr_dtype math, int64_t n) {
     Net net;
     if (build_net(m, &net) != NVR_OK || n < 0) return 0;
-    if (math == NVR_BF16) return mfma_ws_bytes(net, n);
+    if (math == NVR_BF16 || math == NVR_F16) return mfma_ws_bytes(net, n);
     return plain_workspace(net, n);
 }
 
@@ -620,11 +620,11 @@ static nvr_status mlp_args(const nvr_mlp_desc *m, int64_t n, const void *feat, n
                            const float *dirs, const void *params, nvr_dtype math, Net *net) {
     NVR_TRY(build_net(m, net));
     NVR_REQUIRE(n >= 0 && n < (1ll << 31), NVR_EINVAL, "n out of range");
-    NVR_REQUIRE(math == NVR_F32 || math == NVR_BF16, NVR_EINVAL, "math must be F32 or BF16");
-    if (math == NVR_BF16) {
+    if (math == NVR_BF16 || math == NVR_F16) {
         NVR_TRY(mfma_check(*net));
-        NVR_REQUIRE(feat_dtype == NVR_BF16, NVR_EINVAL, "bf16 networks take bf16 features");
+        NVR_REQUIRE(feat_dtype == math, NVR_EINVAL, "MFMA networks take features of the math type");
     } else {
+        NVR_REQUIRE(math == NVR_F32, NVR_EINVAL, "math must be F32, F16 or BF16");
         NVR_REQUIRE(feat_dtype == NVR_F32, NVR_EINVAL, "f32 networks take f32 features");
     }
     if (n > 0) NVR_REQUIRE(feat && dirs && params, NVR_EINVAL, "NULL array");
@@ -641,9 +641,9 @@ extern "C" nvr_status nvr_mlp_fwd(const nvr_mlp_desc *m, int64_t n, const int32_
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(sigma && rgb, NVR_EINVAL, "NULL output");
     hipStream_t st = hs(stream);
-    if (math == NVR_BF16)
-        return mfma_fwd(net, n, n_dev, n, (const uint16_t *)feat, false, dirs, ray_id,
-                        (const uint16_t *)params, sigma, rgb, st);
+    if (math == NVR_BF16 || math == NVR_F16)
+        return mfma_fwd(net, n, n_dev, n, (const uint16_t *)feat, false, dirs, ray_id, params,
+                        math == NVR_F16, sigma, rgb, st);
     // the plain forward stores activations: use a transient workspace
     float *ws = nullptr;
     NVR_HIP(hipMallocAsync((void **)&ws, plain_workspace(net, n), st));
@@ -664,9 +664,9 @@ extern "C" nvr_status nvr_mlp_bwd(const nvr_mlp_desc *m, int64_t n, const int32_
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(dsigma && drgb && dparams && workspace, NVR_EINVAL, "NULL array");
     hipStream_t st = hs(stream);
-    if (math == NVR_BF16)
-        return mfma_bwd(net, n, n_dev, n, (const uint16_t *)feat, false, dirs, ray_id,
-                        (const uint16_t *)params, dsigma, drgb, dparams, dfeat, workspace, st);
+    if (math == NVR_BF16 || math == NVR_F16)
+        return mfma_bwd(net, n, n_dev, n, (const uint16_t *)feat, false, dirs, ray_id, params,
+                        math == NVR_F16, dsigma, drgb, dparams, dfeat, workspace, st);
     // plain: recompute the forward into the workspace, then back-propagate
     float *sig = nullptr;
     NVR_HIP(hipMallocAsync((void **)&sig, sizeof(float) * 4 * (size_t)n, st));

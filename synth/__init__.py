@@ -445,3 +445,110 @@ def pixel_rays(R, c, w, h, f, pix=None):
     d = _unit(dc @ R.T)
     o = np.broadcast_to(c, d.shape).copy()
     return o.astype(np.float32), d.astype(np.float32)
+
+
+def keyframe_occupancy(scene, res, aabb_min, aabb_max, band_voxels=2.0):
+    """Voxels inside a sphere or whose centre lies within ``band_voxels`` voxel
+    sizes of a sphere surface or of the back plane."""
+    lo = np.asarray(aabb_min, float)
+    hi = np.asarray(aabb_max, float)
+    vox = float(np.max((hi - lo) / res))
+    g = (np.arange(res) + 0.5) / res
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    p = lo + np.stack([x, y, z], -1) * (hi - lo)
+    occ = np.abs(p[..., 2] - scene["plane_z"]) <= band_voxels * vox
+    for c, r in zip(scene["centres"], scene["radii"]):
+        occ |= np.linalg.norm(p - c, axis=-1) - r <= band_voxels * vox
+    return occ, pack_bits(occ)
+
+
+def _inside(p, box):
+    lo, hi = np.asarray(box[0], float), np.asarray(box[1], float)
+    return np.all((p >= lo) & (p <= hi), axis=-1)
+
+
+def keyframe_batch(scene, cams, n_rays, rng, box, w=1280, h=720, f=1000.0, depth_noise=0.005):
+    """One training batch drawn uniformly over the pixels of the key frames:
+    rays, target colours and along-ray depths (the z-depth in the camera gets
+    N(0, depth_noise) noise, then is converted to the distance along the ray),
+    and the loss mask: 1 for rays whose first hit lies inside ``box`` (the
+    field's box; other targets are out of the field's reach)."""
+    cam = rng.integers(0, len(cams), size=n_rays)
+    pix = rng.integers(0, w * h, size=n_rays)
+    o = np.empty((n_rays, 3), np.float32)
+    d = np.empty((n_rays, 3), np.float32)
+    cosz = np.empty(n_rays)
+    for k, (R, c) in enumerate(cams):
+        sel = np.nonzero(cam == k)[0]
+        if sel.size == 0:
+            continue
+        ok, dk = pixel_rays(R, c, w, h, f, pix[sel])
+        o[sel], d[sel] = ok, dk
+        cosz[sel] = dk.astype(np.float64) @ R[:, 2]
+    t, col = scene_trace(scene, o, d)
+    hit = np.isfinite(t)
+    zdepth = np.where(hit, t * cosz, 0.0) + rng.normal(0.0, depth_noise, size=n_rays)
+    D = np.where(hit, zdepth / cosz, 0.0)
+    p = o.astype(np.float64) + np.where(hit, t, 0.0)[:, None] * d.astype(np.float64)
+    mask = hit & _inside(p, box)
+    return (o, d, col.astype(np.float32), D.astype(np.float32), mask.astype(np.float32))
+
+
+def keyframe_eval_view(scene, box, w=160, h=90, f=125.0, angle_deg=20.0, radius=2.0,
+                       height=0.3):
+    """A novel view between key frames (same arc, angle in degrees from the
+    arc centre): rays, ground-truth colours and the mask of pixels whose first
+    hit lies inside ``box``."""
+    a = math.radians(angle_deg)
+    c = np.array([radius * math.sin(a), height, radius * math.cos(a)])
+    fwd = _unit(-c)
+    right = _unit(np.cross(fwd, [0, 1, 0]))
+    up = np.cross(right, fwd)
+    R = np.stack([right, up, fwd], 1)
+    o, d = pixel_rays(R, c, w, h, f)
+    t, col = scene_trace(scene, o, d)
+    hit = np.isfinite(t)
+    p = o.astype(np.float64) + np.where(hit, t, 0.0)[:, None] * d.astype(np.float64)
+    return o, d, col.astype(np.float32), hit & _inside(p, box)
+
+
+def keyframe_workload(seed_offset=0):
+    """Key-frame refinement inputs: (work, field cfg, scene, 8 key-frame
+    cameras, packed analytic occupancy, rng).  The caller draws the table and
+    weights from ``rng`` next (table first), and the batch of step i from
+    ``keyframe_step_rng(work, i)``."""
+    work = config(5)
+    fcfg = work.fields[0]
+    rng = rng_for(work.seed + seed_offset)
+    scene = keyframe_scene(rng)
+    cams = look_at_cameras(8)
+    _, words = keyframe_occupancy(scene, fcfg.occ_res, fcfg.aabb_min, fcfg.aabb_max)
+    return work, fcfg, scene, cams, words, rng
+
+
+def keyframe_step_rng(work, step):
+    return rng_for(work.seed * 1000 + 7 + step)
+
+
+def two_field_workload(scale=1.0 / 64, seed_offset=0):
+    """Human (hybrid warp) + object fields over uneven ray ranges with shared
+    rays, at ``scale`` of the full ray counts: (work, (human cfg, object cfg),
+    rig, rays o, d, targets C, D, ray ranges, packed occupancies, rng).  The
+    caller draws the two tables and weights from ``rng`` next (human table,
+    human weights, object table, object weights)."""
+    work = config(4, scale)
+    fh, fo = work.fields
+    ex = work.extra
+    rng = rng_for(work.seed + seed_offset)
+    rig = human_rig(rng, n_nodes=ex["n_nodes"], k_nodes=ex["k_nodes"], knn_res=ex["knn_res"])
+    n = work.n_rays
+    h_end = ex["human_only"] + ex["shared"]
+    o_begin = ex["human_only"]
+    o, d = sphere_rays(n, rng, aim_lo=(-0.3, -0.8, -0.2), aim_hi=(0.6, 0.8, 0.3))
+    _, occ_h = occupancy_from_points(rig["node_live"][0], 0.12, fh.occ_res, fh.aabb_min,
+                                     fh.aabb_max)
+    _, occ_o = occupancy_from_points(object_points(rng), 0.1, fo.occ_res, fo.aabb_min,
+                                     fo.aabb_max)
+    C = uniform_targets(n, rng)
+    D = rng.uniform(1.0, 3.0, size=n).astype(np.float32)
+    return work, (fh, fo), rig, o, d, C, D, [(0, h_end), (o_begin, n)], (occ_h, occ_o), rng

@@ -1,0 +1,115 @@
+"""Writes the FP64 oracle's multi-step training curves that the GPU tests
+compare against (test infrastructure; calls only ``oracle/`` and ``synth/``).
+
+* ``curve_human_object_r64.txt``: the two-field workload (human field behind
+  the hybrid warp + object field, shared rays composited as one merged list,
+  colour + depth loss, Eq. 8) at 1/64 of its ray counts, one fixed batch,
+  Adam, loss per step.
+* ``curve_keyframes_4096.txt``: key-frame refinement (rays drawn per step from
+  eight 1280x720 key frames of the analytic scene, colour + depth loss with
+  the mask M(r) of Eq. 8 set for rays whose first hit lies in the field's box,
+  Adam), 4096 rays per step; loss per step and the PSNR (over the pixels whose
+  hit lies in the box) of a 160x90 novel view rendered with early termination
+  every ``--eval-every`` steps.
+
+Usage (from the repository root):
+    python tests/golden/make_curves.py human_object --steps 500
+    python tests/golden/make_curves.py keyframes --steps 2000 --eval-every 250
+"""
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import grid as ogrid, step as ostep  # noqa: E402
+
+
+def human_object_state():
+    work, (fh, fo), rig, o, d, C, D, ranges, (occ_h, occ_o), rng = synth.two_field_workload()
+    table_h = synth.uniform_table(ogrid.Layout.from_field(fh).n_entries, 2, rng)
+    params_h = synth.xavier_params(fh.layer_shapes(), rng)
+    table_o = synth.uniform_table(ogrid.Layout.from_field(fo).n_entries, 2, rng)
+    params_o = synth.xavier_params(fo.layer_shapes(), rng)
+    st = ostep.StepState([ostep.FieldState(fh, table_h, params_h, occ_words=occ_h, rig=rig),
+                          ostep.FieldState(fo, table_o, params_o, occ_words=occ_o)])
+    return work, st, o, d, C, D, ranges
+
+
+def keyframe_state():
+    work, f, scene, cams, occ, rng = synth.keyframe_workload()
+    table = synth.uniform_table(ogrid.Layout.from_field(f).n_entries, 2, rng)
+    params = synth.xavier_params(f.layer_shapes(), rng)
+    st = ostep.StepState([ostep.FieldState(f, table, params, occ_words=occ)])
+    return work, f, scene, cams, st
+
+
+def psnr(c, gt, mask):
+    e = (np.asarray(c, np.float64) - gt)[mask]
+    return -10.0 * math.log10(float(np.mean(e * e)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["human_object", "keyframes"])
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--rays", type=int, default=4096)
+    ap.add_argument("--eval-every", type=int, default=250)
+    args = ap.parse_args()
+    t0 = time.time()
+    if args.which == "human_object":
+        work, st, o, d, C, D, ranges = human_object_state()
+        box = ((-1.0,) * 3, (1.0,) * 3)
+        path = os.path.join(HERE, "curve_human_object_r64.txt")
+        rows = []
+        for i in range(args.steps):
+            r = ostep.train_step(work, st, o, d, C, D, ranges, box, apply=True)
+            rows.append((i, r["loss"]))
+            print(f"step {i} loss {r['loss']:.8f} ({time.time() - t0:.0f} s)", flush=True)
+        with open(path, "w") as fh:
+            fh.write("# FP64 oracle: two-field workload at 1/64 of its rays (3750 rays, human\n"
+                     "# [0, 2812), object [2500, 3750)), one fixed batch, Adam lr 1e-2,\n"
+                     "# colour + depth loss (Eq. 8, lambda_d = 1).\n"
+                     f"# written by: python tests/golden/make_curves.py human_object --steps {args.steps}\n"
+                     "# columns: step loss\n")
+            for i, l in rows:
+                fh.write(f"{i} {l:.10e}\n")
+    else:
+        work, f, scene, cams, st = keyframe_state()
+        box = (f.aabb_min, f.aabb_max)
+        eo, ed, egt, emask = synth.keyframe_eval_view(scene, box)
+        path = os.path.join(HERE, f"curve_keyframes_{args.rays}.txt")
+        rows = []
+        for i in range(args.steps):
+            o, d, C, D, M = synth.keyframe_batch(scene, cams, args.rays,
+                                                 synth.keyframe_step_rng(work, i), box)
+            r = ostep.train_step(work, st, o, d, C, D, [(0, args.rays)], apply=True, mask=M)
+            p = float("nan")
+            if (i + 1) % args.eval_every == 0:
+                rc, _ = ostep.render(work, st, eo, ed, [(0, eo.shape[0])], t_stop=1e-4)
+                p = psnr(rc, egt, emask)
+            rows.append((i, r["loss"], p))
+            print(f"step {i} loss {r['loss']:.8f} psnr {p:.4f} ({time.time() - t0:.0f} s)",
+                  flush=True)
+        with open(path, "w") as fh:
+            fh.write("# FP64 oracle: key-frame refinement, rays drawn per step from eight\n"
+                     f"# 1280x720 key frames of the analytic scene, {args.rays} rays per step,\n"
+                     "# Adam lr 1e-2, masked colour + depth loss (Eq. 8, lambda_d = 1); PSNR\n"
+                     "# over the in-box pixels of a 160x90 novel view (t_stop 1e-4) every "
+                     f"{args.eval_every} steps (nan elsewhere).\n"
+                     f"# written by: python tests/golden/make_curves.py keyframes --steps {args.steps} "
+                     f"--rays {args.rays} --eval-every {args.eval_every}\n"
+                     "# columns: step loss psnr_db\n")
+            for i, l, p in rows:
+                fh.write(f"{i} {l:.10e} {p:.6f}\n")
+    print("wrote", path, f"in {time.time() - t0:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

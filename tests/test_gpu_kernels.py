@@ -244,6 +244,29 @@ def test_mlp_bf16_mfma(k):
     assert rel_err(host(dfeat), rf) < 3e-2
 
 
+@pytest.mark.parametrize("k", [2])
+def test_mlp_f16_forward_mfma(k):
+    # fp16 forward (fp16 features, fp32 parameters converted to fp16 fragments,
+    # fp16 activations), bf16 backward products
+    O = ops()
+    n = 5000
+    f, params, feat, d, ray, dsig, drgb = _net_inputs(k, n, 90 + k)
+    md = O.mlp_desc_of(f)
+    pf = dev(params)
+    fh = dev(feat).to(torch.float16)
+    sig, rgb = O.mlp_fwd(md, fh, dev(d), pf, dev(ray), O.F16)
+    shv = osh.sh_encode(d[ray], f.sh_degree)
+    rs, rr, cache = onet.forward(f, f16_round(params), f16_round(feat), shv)
+    # fp16 activations: relative rounding 2^-11 per layer
+    np.testing.assert_allclose(host(rgb), rr, rtol=0, atol=4e-3)
+    assert rel_err(host(sig), rs) < 1e-2
+    dparams = torch.zeros(params.size, device="cuda")
+    dfeat = O.mlp_bwd(md, fh, dev(d), pf, dev(dsig), dev(drgb), dparams, dev(ray), O.F16)
+    rp, rf = onet.backward(f, cache, dsig, drgb)
+    assert rel_err(host(dparams), rp) < 3e-2
+    assert rel_err(host(dfeat), rf) < 3e-2
+
+
 # ------------------------------------------------------------------ compositing
 def _ragged(rng, R, maxs, sig_scale=30.0):
     counts = rng.integers(0, maxs, size=R)
