@@ -16,8 +16,10 @@
 // registers.  Swapping the two operands of the same MFMA gives "orientation
 // B", D = X W^T (rows = samples): lane l then holds samples 4g..4g+3 of unit
 // l%16, which is the operand layout of the weight-gradient contraction over
-// samples.  The backward therefore recomputes every layer in both
-// orientations and forms dW = dY X^T with no LDS transposes.
+// samples.  The backward computes every layer once in orientation A; each
+// wave stages its activation and gradient tiles (bf16, unit-major 16 x 16) in
+// its own 15 KiB of LDS and reads them back as "4 samples of one unit"
+// operands for dW = dY X^T (one 8-byte read per tile and lane).
 //
 // Weight fragments (forward W and backward W^T, 38 KiB) are built in LDS once
 // per workgroup from the flat bf16 parameters; the per-wave weight gradients
@@ -98,6 +100,21 @@ __device__ __forceinline__ f4 mask4(f4 g, f4 act) {
     return r;
 }
 __device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
+
+// Per-wave staging tiles of the backward: 16 units x 16 samples, bf16 bits,
+// unit-major.  A lane of orientation A (sample c, rows 4g..4g+3) writes its
+// four values; a lane reading operand rows (unit u, samples 4g..4g+3) gets
+// 8 contiguous bytes.
+constexpr int kTiles = 30;
+constexpr int TX = 0, THD = 2, TCI = 6, TH1 = 8, TH2 = 12;          // activations
+constexpr int TDHD = 16, TDO = 20, TDH1 = 21, TDH2 = 25, TDZ = 29;  // gradients
+__device__ __forceinline__ void stage4(uint16_t *tile, int g, int c, f4 v) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile[(4 * g + j) * 16 + c] = (uint16_t)bfs(v[j]);
+}
+__device__ __forceinline__ s4 unstage(const uint16_t *tile, int u, int g) {
+    return *reinterpret_cast<const s4 *>(tile + u * 16 + 4 * g);
+}
 
 // contraction index of a 64-wide hidden layer, K-step q, lane group g, slot j
 __device__ __forceinline__ int kh(int q, int g, int j) {
@@ -264,6 +281,7 @@ struct FwdA {
     f4 h2[4];
     V h2b[2];
     f4 z;
+    f4 sh4;    // SH coefficients 4g..4g+3 of this lane's sample
 };
 
 template <int NCH, typename FT>
@@ -283,6 +301,7 @@ __device__ __forceinline__ void forward_a(const Frags<FT> &F, int l, int g,
         const int k = 4 * g + j;
         s4v[j] = k < nsh ? pick16(sh, k) : 0.f;
     }
+    a.sh4 = s4v;
     a.cin = packf<FT>(a.o, s4v);
     for (int m = 0; m < 4; ++m) a.h1[m] = relu4(mfma32(F.c1[m][l], a.cin, zero4()));
     a.h1b[0] = packf<FT>(a.h1[0], a.h1[1]);
@@ -361,10 +380,13 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
              const float *__restrict__ dsigma, const float *__restrict__ drgb,
              float *__restrict__ dfeat, float *__restrict__ partial) {
     __shared__ Frags<FT> F;
+    __shared__ uint16_t stage[kMfmaBlock / 64][kTiles][256];
     build_frags<NCH, PLANAR, FT>(F, net, params);
+    const int l = threadIdx.x % 64, g = l / 16, c = l % 16;
+    uint16_t (*tw)[256] = stage[threadIdx.x / 64];
+    for (int i = l; i < kTiles * 256; i += 64) tw[i / 256][i % 256] = 0;   // unused rows stay 0
     __syncthreads();
     const int64_t count = count_of(n, n_dev, cap);
-    const int l = threadIdx.x % 64, g = l / 16, c = l % 16;
     const int64_t wave = blockIdx.x * (int64_t)(kMfmaBlock / 64) + threadIdx.x / 64;
     const int64_t nwaves = (int64_t)gridDim.x * (kMfmaBlock / 64);
     DW<NCH> acc;
@@ -399,6 +421,19 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
         }
         FwdA<NCH, FT> a;
         forward_a<NCH, FT>(F, l, g, xf, dir, nsh, a);
+        // activations of this block -> staging tiles (features at their index)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = kin<PLANAR>(g, j);
+            if (k < net.n_in) tw[TX + (k >> 4)][(k & 15) * 16 + c] = (uint16_t)bfs((float)xf[j]);
+        }
+        for (int m = 0; m < 4; ++m) {
+            stage4(tw[THD + m], g, c, a.hd[m]);
+            stage4(tw[TH1 + m], g, c, a.h1[m]);
+            if (NCH == 2) stage4(tw[TH2 + m], g, c, a.h2[m]);
+        }
+        stage4(tw[TCI], g, c, a.o);
+        stage4(tw[TCI + 1], g, c, a.sh4);
         // ------------------------------------------------ orientation A backward
         f4 dz = zero4();
         if (g == 0) {
@@ -448,102 +483,48 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
                 }
             }
         }
-        // ------------------------------------------------ orientation B (transposed) copies
-        // samples of this lane in the B layout: base + 4g + i
-        f4 x0b[2];
-        for (int t = 0; t < 2; ++t)
-            for (int i = 0; i < 4; ++i) {
-                const int64_t si = base + 4 * g + i;
-                x0b[t][i] = si < count ? load_feat_one<PLANAR, FT>(feat, si, cap, net.n_in, 16 * t + c) : 0.f;
-            }
-        f4 hdB[4];
-        for (int t = 0; t < 4; ++t) hdB[t] = relu4(mfma32(xf, F.d1[t][l], zero4()));
-        f4 oB = mfma32(a.hdb[0], F.d2[0][l], zero4());
-        oB = mfma32(a.hdb[1], F.d2[1][l], oB);
-        f4 shB;
-        f4 dsB = zero4();
-        f4 drB = zero4();
-        for (int i = 0; i < 4; ++i) {
-            const int64_t si = base + 4 * g + i;
-            shB[i] = 0.f;
-            if (si < count) {
-                const int64_t r = ray_id ? ray_id[si] : si;
-                float sh[16];
-                for (int k = 0; k < 16; ++k) sh[k] = 0.f;
-                sh_eval(dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2], deg, sh);
-                shB[i] = c < nsh ? pick16(sh, c) : 0.f;
-                if (c == 0) dsB[i] = dsigma[si];
-                if (c < 3) drB[i] = drgb[3 * si + c];
-            }
+        // gradients of this block -> staging tiles
+        stage4(tw[TDZ], g, c, dz);
+        stage4(tw[TDO], g, c, dO);
+        for (int m = 0; m < 4; ++m) {
+            stage4(tw[TDHD + m], g, c, dhd[m]);
+            stage4(tw[TDH1 + m], g, c, dh1[m]);
+            if (NCH == 2) stage4(tw[TDH2 + m], g, c, dh2[m]);
         }
-        f4 h1B[4];
-        for (int t = 0; t < 4; ++t) h1B[t] = relu4(mfma32(a.cin, F.c1[t][l], zero4()));
-        f4 h2B[4];
-        f4 zB;
-        if (NCH == 2) {
-            for (int t = 0; t < 4; ++t) {
-                f4 u = mfma32(a.h1b[0], F.c2[t][0][l], zero4());
-                h2B[t] = relu4(mfma32(a.h1b[1], F.c2[t][1][l], u));
-            }
-            zB = mfma32(a.h2b[0], F.c3[0][l], zero4());
-            zB = mfma32(a.h2b[1], F.c3[1][l], zB);
-        } else {
-            zB = mfma32(a.h1b[0], F.c3[0][l], zero4());
-            zB = mfma32(a.h1b[1], F.c3[1][l], zB);
-        }
-        // ------------------------------------------------ orientation B backward
-        f4 dzB = zero4();
-        if (c < 3)
-            for (int i = 0; i < 4; ++i) {
-                const float v = sigmoidf_(zB[i]);
-                dzB[i] = drB[i] * v * (1.f - v);
-            }
-        f4 dh2B[4], dh1B[4];
-        if (NCH == 2) {
-            for (int t = 0; t < 4; ++t) dh2B[t] = mask4(mfma16(dzq, F.c3t[t][l], zero4()), h2B[t]);
-            for (int t = 0; t < 4; ++t) {
-                f4 u = mfma32(dh2b[0], F.c2t[t][0][l], zero4());
-                dh1B[t] = mask4(mfma32(dh2b[1], F.c2t[t][1][l], u), h1B[t]);
-            }
-        } else {
-            for (int t = 0; t < 4; ++t) dh1B[t] = mask4(mfma16(dzq, F.c3t[t][l], zero4()), h1B[t]);
-        }
-        f4 dOB = mfma32(dh1b[0], F.c1t[0][l], zero4());
-        dOB = mfma32(dh1b[1], F.c1t[1][l], dOB);
-        if (c == 0)
-            for (int i = 0; i < 4; ++i)
-                if (fabsf(oB[i]) < kSigmaClamp) dOB[i] += dsB[i] * expf(oB[i]);
-        f4 dhdB[4];
-        for (int t = 0; t < 4; ++t) dhdB[t] = mask4(mfma16(dOq, F.d2t[t][l], zero4()), hdB[t]);
         // ------------------------------------------------ weight gradients (K = 16 samples)
-        const s4 x0q[2] = {quad(x0b[0]), quad(x0b[1])};
-        for (int mo = 0; mo < 4; ++mo) {
-            const s4 gq = quad(dhdB[mo]);
-            for (int ti = 0; ti < 2; ++ti) acc.d1[mo][ti] = mfma16(gq, x0q[ti], acc.d1[mo][ti]);
-        }
+        // a wave's LDS operations complete in order, so its reads see its writes
         {
-            const s4 gq = quad(dOB);
-            for (int ti = 0; ti < 4; ++ti) acc.d2[ti] = mfma16(gq, quad(hdB[ti]), acc.d2[ti]);
-        }
-        {
-            const s4 cq[2] = {quad(oB), quad(shB)};
+            const s4 x0 = unstage(tw[TX], c, g), x1 = unstage(tw[TX + 1], c, g);
             for (int mo = 0; mo < 4; ++mo) {
-                const s4 gq = quad(dh1B[mo]);
-                for (int ti = 0; ti < 2; ++ti) acc.c1[mo][ti] = mfma16(gq, cq[ti], acc.c1[mo][ti]);
+                const s4 gq = unstage(tw[TDHD + mo], c, g);
+                acc.d1[mo][0] = mfma16(gq, x0, acc.d1[mo][0]);
+                acc.d1[mo][1] = mfma16(gq, x1, acc.d1[mo][1]);
+            }
+        }
+        {
+            const s4 gq = unstage(tw[TDO], c, g);
+            for (int ti = 0; ti < 4; ++ti) acc.d2[ti] = mfma16(gq, unstage(tw[THD + ti], c, g), acc.d2[ti]);
+        }
+        {
+            const s4 c0 = unstage(tw[TCI], c, g), c1v = unstage(tw[TCI + 1], c, g);
+            for (int mo = 0; mo < 4; ++mo) {
+                const s4 gq = unstage(tw[TDH1 + mo], c, g);
+                acc.c1[mo][0] = mfma16(gq, c0, acc.c1[mo][0]);
+                acc.c1[mo][1] = mfma16(gq, c1v, acc.c1[mo][1]);
             }
         }
         if (NCH == 2) {
             s4 hq[4];
-            for (int ti = 0; ti < 4; ++ti) hq[ti] = quad(h1B[ti]);
+            for (int ti = 0; ti < 4; ++ti) hq[ti] = unstage(tw[TH1 + ti], c, g);
             for (int mo = 0; mo < 4; ++mo) {
-                const s4 gq = quad(dh2B[mo]);
+                const s4 gq = unstage(tw[TDH2 + mo], c, g);
                 for (int ti = 0; ti < 4; ++ti) acc.c2[mo][ti] = mfma16(gq, hq[ti], acc.c2[mo][ti]);
             }
         }
         {
-            const s4 gq = quad(dzB);
-            for (int ti = 0; ti < 4; ++ti)
-                acc.c3[ti] = mfma16(gq, quad(NCH == 2 ? h2B[ti] : h1B[ti]), acc.c3[ti]);
+            const s4 gq = unstage(tw[TDZ], c, g);
+            const int th = NCH == 2 ? TH2 : TH1;
+            for (int ti = 0; ti < 4; ++ti) acc.c3[ti] = mfma16(gq, unstage(tw[th + ti], c, g), acc.c3[ti]);
         }
     }
     // ---------------------------------------------------- workgroup reduction
