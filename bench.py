@@ -147,7 +147,8 @@ def main():
                    "levels": f.n_levels, "log2_table": f.log2_table, "res": [f.res_min, f.res_max],
                    "occupancy": f"{f.occ_res}^3 noise, 30% set", "graph": True,
                    "launch_shape": dict(zip(["gather_chunks", "mlp_fwd_blocks", "mlp_bwd_blocks",
-                                             "emit_chunks", "composite_blocks", "tuned"], shape))},
+                                             "emit_chunks", "composite_blocks", "tuned",
+                                             "emit_chunk_samples"], shape))},
         "fp32_plain": {"rays_per_s": R / dt_32, "ms_per_step": dt_32 * 1e3,
                        "speedup_bf16_over_fp32": dt_32 / dt_bf, "loss": loss_32},
         "render": render,

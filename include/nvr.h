@@ -358,8 +358,8 @@ nvr_status nvr_create(nvr_ctx **out, int32_t device, uint32_t flags);
 #define NVR_USE_GRAPH 1u
 /* NVR_AUTOTUNE: the first BF16 nvr_train_step at a new workspace capacity
  * times candidate launch shapes of its kernels on its own inputs and stream
- * (gather and emit chunks per level group, network and compositing
- * workgroups), keeps the fastest per field, and (re)captures its graph with
+ * (gather chunks per level group, emit chunk size and count, network and
+ * compositing workgroups), keeps the fastest per field, and (re)captures its graph with
  * them.  Only shape-independent results are produced: the tuned step differs
  * from an untuned one only in the summation order of gradients. */
 #define NVR_AUTOTUNE 2u
@@ -382,8 +382,9 @@ nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const
 /* Total kept samples of field f in the last forward (synchronises `stream`). */
 /* Launch shapes in use for `field` (0 or 1): shape[0] gather chunks per level
  * group, [1] network forward workgroups, [2] network backward workgroups,
- * [3] emit chunks per level group, [4] compositing workgroups (0 = built-in
- * default), [5] 1 if tuned.  shape is a host array of 6. */
+ * [3] emit chunks per level group, [4] compositing workgroups, [5] 1 if
+ * tuned, [6] emit samples per chunk (512 or 1024); 0 = built-in default.
+ * shape is a host array of 7. */
 nvr_status nvr_launch_shape(const nvr_ctx *ctx, int32_t field, int32_t *shape);
 
 nvr_status nvr_last_sample_count(nvr_ctx *ctx, int32_t field, int64_t *count,

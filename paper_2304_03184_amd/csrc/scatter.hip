@@ -44,11 +44,14 @@ constexpr int kMaxTileBits = 14;
 constexpr int kMaxTiles = 8192;
 constexpr uint32_t kItemRecords = 1u << 17;
 constexpr int kBinBlock = 256;     // count
-constexpr int kEmitBlock = 1024;   // emit: samples per chunk
+constexpr int kEmitBlock = 1024;   // emit: samples per chunk (default; 512 also built)
 constexpr int kMaxLpg = 4;   // levels per group (L <= 32)
 constexpr int kMaxLevelTiles = 2048;   // tiles one level may span
-constexpr size_t kEmitLds = sizeof(uint32_t) * (2 * kMaxLevelTiles + kEmitBlock) +
-                            (sizeof(uint2) + sizeof(uint16_t)) * 8 * kEmitBlock;   // 100 KiB
+// emit LDS: per-level tile counts / offsets and deltas (lt each), one partial
+// per wave, and the staged records with their tiles (8 per sample)
+static size_t emit_lds_bytes(int block, int lt) {
+    return sizeof(uint32_t) * (2 * (size_t)lt + 16) + (sizeof(uint2) + sizeof(uint16_t)) * 8 * block;
+}
 constexpr size_t kRecPad = 512;   // records of padding after the record buffer (one accum window)
 
 static int64_t max_items_of(int64_t cap, int L, int nt) {
@@ -238,18 +241,18 @@ __device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
 // per tile with one global atomic, the records are staged in LDS in tile order
 // and then written out by consecutive threads to consecutive positions, so
 // that each tile's run is stored contiguously.
-template <bool PLANAR, int LPG>
-__global__ void __launch_bounds__(kEmitBlock)
-scatter_emit(GridParams p, int tb, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
-             const float *__restrict__ x, const uint32_t *__restrict__ table,
+template <bool PLANAR, int LPG, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict__ n_dev,
+             int64_t cap, const float *__restrict__ x, const uint32_t *__restrict__ table,
              const float *__restrict__ dfeat, uint32_t n_records, uint32_t *__restrict__ cursor,
              uint2 *__restrict__ recs, float *__restrict__ dx_parts) {
     extern __shared__ uint32_t lds[];
-    uint32_t *hist = lds;                               // [kMaxLevelTiles] counts, then offsets
-    uint32_t *delta = hist + kMaxLevelTiles;            // [kMaxLevelTiles] global - local position
-    uint32_t *part = delta + kMaxLevelTiles;            // [kEmitBlock]
-    uint2 *srec = reinterpret_cast<uint2 *>(part + kEmitBlock);   // [8 * kEmitBlock] staged
-    uint16_t *stile = reinterpret_cast<uint16_t *>(srec + 8 * kEmitBlock);   // their tiles - t_lo
+    uint32_t *hist = lds;                               // [lt] counts, then offsets
+    uint32_t *delta = hist + lt;                        // [lt] global - local position
+    uint32_t *part = delta + lt;                        // [16] one per wave
+    uint2 *srec = reinterpret_cast<uint2 *>(part + 16);               // [8 * BLOCK] staged
+    uint16_t *stile = reinterpret_cast<uint16_t *>(srec + 8 * BLOCK);  // their tiles - t_lo
     const int64_t count = count_of(n, n_dev, cap);
     const int g = blockIdx.x % kXcds;
     const int64_t chunks = gridDim.x / kXcds;
@@ -534,7 +537,7 @@ nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st) {
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
                           float *dx_parts, bool planar, void *ws, hipStream_t st, bool counted,
-                          int emit_chunks) {
+                          int emit_chunks, int emit_block) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
     const int tb = tile_bits(p);
@@ -542,7 +545,10 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     ScatterWs w = carve_scatter(p, ws, cap);
     const uint32_t n_records = (uint32_t)((uint64_t)cap * p.L * 8 < 0xffffffffull
                                               ? (uint64_t)cap * p.L * 8 : 0xffffffffull);
-    const unsigned gre = grid_for(cap, kEmitBlock, emit_chunks > 0 ? emit_chunks : 64) * kXcds;
+    const int eb = emit_block == 512 ? 512 : kEmitBlock;
+    const unsigned gre = grid_for(cap, eb, emit_chunks > 0 ? emit_chunks : 64) * kXcds;
+    const int lt = level_tiles(p, tb);
+    const size_t elds = emit_lds_bytes(eb, lt);
     if (!counted) {
         zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>(w.count, nt + 1);
         NVR_LAUNCHED();
@@ -555,10 +561,15 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     NVR_LAUNCHED();
     const int lpg = (p.L + kXcds - 1) / kXcds;
 #define NVR_EMIT(PL, LP)                                                                       \
-    scatter_emit<PL, LP><<<gre, kEmitBlock, kEmitLds, st>>>(p, tb, n, n_dev, cap, x,           \
-                                                          (const uint32_t *)table, dfeat,       \
-                                                          n_records, w.cursor, w.rec,          \
-                                                          dx_parts)
+    do {                                                                                       \
+        if (eb == 512)                                                                         \
+            scatter_emit<PL, LP, 512><<<gre, 512, elds, st>>>(p, tb, lt, n, n_dev, cap, x,     \
+                (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts);         \
+        else                                                                                   \
+            scatter_emit<PL, LP, kEmitBlock><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n,      \
+                n_dev, cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec,     \
+                dx_parts);                                                                     \
+    } while (0)
 #define NVR_EMIT_L(PL)                                                                         \
     switch (lpg) {                                                                             \
     case 1: NVR_EMIT(PL, 1); break;                                                            \
@@ -566,14 +577,23 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     case 3: NVR_EMIT(PL, 3); break;                                                            \
     default: NVR_EMIT(PL, 4); break;                                                           \
     }
-    static bool emit_lds_ok = false;   // opt in to 100 KiB of dynamic LDS (every instance)
+    static bool emit_lds_ok = false;   // opt in to more than 64 KiB of dynamic LDS
     if (!emit_lds_ok) {
-        const void *fns[] = {(const void *)scatter_emit<true, 1>, (const void *)scatter_emit<true, 2>,
-                             (const void *)scatter_emit<true, 3>, (const void *)scatter_emit<true, 4>,
-                             (const void *)scatter_emit<false, 1>, (const void *)scatter_emit<false, 2>,
-                             (const void *)scatter_emit<false, 3>, (const void *)scatter_emit<false, 4>};
+        const int most = (int)emit_lds_bytes(kEmitBlock, kMaxLevelTiles);
+        const void *fns[] = {(const void *)scatter_emit<true, 1, kEmitBlock>,
+                             (const void *)scatter_emit<true, 2, kEmitBlock>,
+                             (const void *)scatter_emit<true, 3, kEmitBlock>,
+                             (const void *)scatter_emit<true, 4, kEmitBlock>,
+                             (const void *)scatter_emit<false, 1, kEmitBlock>,
+                             (const void *)scatter_emit<false, 2, kEmitBlock>,
+                             (const void *)scatter_emit<false, 3, kEmitBlock>,
+                             (const void *)scatter_emit<false, 4, kEmitBlock>,
+                             (const void *)scatter_emit<true, 1, 512>, (const void *)scatter_emit<true, 2, 512>,
+                             (const void *)scatter_emit<true, 3, 512>, (const void *)scatter_emit<true, 4, 512>,
+                             (const void *)scatter_emit<false, 1, 512>, (const void *)scatter_emit<false, 2, 512>,
+                             (const void *)scatter_emit<false, 3, 512>, (const void *)scatter_emit<false, 4, 512>};
         for (const void *f : fns)
-            NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kEmitLds));
+            NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, most));
         emit_lds_ok = true;
     }
     if (planar) {
@@ -609,9 +629,9 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
 nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_t *n_dev,
                                     int64_t cap, const float *x, const void *table,
                                     const float *dfeat, bool planar, void *ws, hipStream_t st,
-                                    int emit_chunks) {
+                                    int emit_chunks, int emit_block) {
     return launch_scatter(p, n, n_dev, cap, x, table, dfeat, nullptr, nullptr, planar, ws, st,
-                          /*counted=*/true, emit_chunks);
+                          /*counted=*/true, emit_chunks, emit_block);
 }
 
 }  // namespace nvr

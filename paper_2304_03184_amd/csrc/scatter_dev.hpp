@@ -17,11 +17,11 @@ nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st);
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
                           float *dx_parts, bool planar, void *ws, hipStream_t st,
-                          bool counted = false, int emit_chunks = 0);
+                          bool counted = false, int emit_chunks = 0, int emit_block = 0);
 // the scan and emit passes alone (tile counts already formed), for tuning
 nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_t *n_dev,
                                     int64_t cap, const float *x, const void *table,
                                     const float *dfeat, bool planar, void *ws, hipStream_t st,
-                                    int emit_chunks);
+                                    int emit_chunks, int emit_block);
 
 }  // namespace nvr

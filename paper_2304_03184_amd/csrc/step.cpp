@@ -28,7 +28,7 @@ struct FieldWs {
     void *scatter_ws;               // binned table-gradient scatter (bf16 training)
     // launch shapes of the BF16 step's kernels (0: built-in default), set by
     // the autotuner for this capacity
-    int enc_chunks = 0, mlp_fwd_blocks = 0, mlp_bwd_blocks = 0, emit_chunks = 0;
+    int enc_chunks = 0, mlp_fwd_blocks = 0, mlp_bwd_blocks = 0, emit_chunks = 0, emit_block = 0;
     bool tuned = false;
 };
 
@@ -160,7 +160,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.dx = (float *)ptr[14];
     w.mlp_ws = ptr[15];
     w.scatter_ws = ptr[16];
-    w.enc_chunks = w.mlp_fwd_blocks = w.mlp_bwd_blocks = w.emit_chunks = 0;
+    w.enc_chunks = w.mlp_fwd_blocks = w.mlp_bwd_blocks = w.emit_chunks = w.emit_block = 0;
     w.tuned = false;
     return NVR_OK;
 }
@@ -250,7 +250,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                              st, w.mlp_bwd_blocks));
             NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
                                    f->has_warp ? w.dx : nullptr, true, w.scatter_ws, st,
-                                   /*counted=*/true, w.emit_chunks));
+                                   /*counted=*/true, w.emit_chunks, w.emit_block));
             if (f->has_warp)
                 NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, kXcds, 3 * cap,
                                      f->node_dq_grad, f->bones_grad, st));
@@ -361,7 +361,9 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
     static const int enc[] = {256, 512, 1024, 2048};
     static const int mlp_f[] = {256, 512, 1024, 2048};
     static const int mlp_b[] = {128, 256, 512};
-    static const int emit[] = {32, 64, 128};
+    // emit: (samples per chunk, chunks per level group)
+    static const int emit[] = {1024 * 1000 + 32, 1024 * 1000 + 64, 1024 * 1000 + 128,
+                               512 * 1000 + 64, 512 * 1000 + 128, 512 * 1000 + 256};
     static const int comp[] = {4096, 16384, 65536};
     for (int k = 0; k < s->n_fields; ++k) {
         const nvr_field *f = fields[k];
@@ -400,10 +402,13 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
             return mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
                             f->params, true, w.dsigma, w.drgb, nullptr, w.dfeat, w.mlp_ws, st, c);
         }));
-        NVR_TRY(pick(st, emit, 3, &w.emit_chunks, [&](int c) {
+        int e = 0;
+        NVR_TRY(pick(st, emit, 6, &e, [&](int c) {
             return launch_scatter_emit_only(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, true,
-                                            w.scatter_ws, st, c);
+                                            w.scatter_ws, st, c % 1000, c / 1000);
         }));
+        w.emit_chunks = e % 1000;
+        w.emit_block = e / 1000;
         w.tuned = true;
     }
     return NVR_OK;
@@ -547,6 +552,7 @@ extern "C" nvr_status nvr_launch_shape(const nvr_ctx *ctx, int32_t field, int32_
     shape[3] = w.emit_chunks;
     shape[4] = ctx->comp_blocks;
     shape[5] = w.tuned ? 1 : 0;
+    shape[6] = w.emit_block;
     return NVR_OK;
 }
 

@@ -113,8 +113,9 @@ class Trainer:
 
     def launch_shape(self, field=0):
         """Launch shapes in use for `field` (gather chunks, network forward and
-        backward workgroups, emit chunks, compositing workgroups, tuned flag)."""
-        out = (C.c_int32 * 6)()
+        backward workgroups, emit chunks, compositing workgroups, tuned flag,
+        emit samples per chunk)."""
+        out = (C.c_int32 * 7)()
         call("nvr_launch_shape", self.ctx, field, out)
         return list(out)
 
