@@ -422,30 +422,47 @@ scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restric
                 v0[u] = __uint_as_float(hw[u] & ~kmask);
                 v1[u] = __uint_as_float(lw[u] & ~kmask);
             }
+            // one round per record slot u: every pending lane writes its lane id
+            // to the tag of its entry and reads it back; exactly one lane per
+            // entry sees its own id and adds.  The few losers (two lanes naming
+            // one entry) are retried after all slots had their first round,
+            // and only in slots that still have pending lanes.
+            uint32_t loc[kPer];
+            bool pend[kPer];
 #pragma unroll
             for (uint32_t u = 0; u < kPer; ++u) {
                 const uint32_t rec = base + lane * kPer + u;
-                const uint32_t loc = key[u] - tbase;
+                loc[u] = key[u] - tbase;
                 // every record of the range is in the tile; the bound is a guard
-                bool pend = rec >= r0 && rec < r1 && loc < te;
-                // one round: every pending lane writes its lane id to the tag of
-                // its entry and reads it back; exactly one lane per entry sees its
-                // own id and adds (the others retry in the next round)
-                while (__ballot(pend)) {
-                    // wavefront-scope relaxed atomics: plain LDS byte accesses
-                    // that the compiler may neither drop nor merge
-                    if (pend)
-                        __hip_atomic_store(tag + loc, (uint8_t)lane, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    if (pend && __hip_atomic_load(tag + loc, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_WAVEFRONT) == (uint8_t)lane) {
-                        float2 a = acc[loc];
-                        a.x += v0[u];
-                        a.y += v1[u];
-                        acc[loc] = a;
-                        pend = false;
-                    }
+                pend[u] = rec >= r0 && rec < r1 && loc[u] < te;
+            }
+            auto round = [&](uint32_t u) {
+                // wavefront-scope relaxed atomics: plain LDS byte accesses that
+                // the compiler may neither drop nor merge
+                if (pend[u])
+                    __hip_atomic_store(tag + loc[u], (uint8_t)lane, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                if (pend[u] && __hip_atomic_load(tag + loc[u], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WAVEFRONT) == (uint8_t)lane) {
+                    float2 a = acc[loc[u]];
+                    a.x += v0[u];
+                    a.y += v1[u];
+                    acc[loc[u]] = a;
+                    pend[u] = false;
                 }
+            };
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; ++u) round(u);
+            bool left = false;
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; ++u) left |= pend[u];
+            while (__ballot(left)) {
+#pragma unroll
+                for (uint32_t u = 0; u < kPer; ++u)
+                    if (__ballot(pend[u])) round(u);
+                left = false;
+#pragma unroll
+                for (uint32_t u = 0; u < kPer; ++u) left |= pend[u];
             }
         }
         const uint32_t ne = (n_entries - tbase) < te ? (n_entries - tbase) : te;
