@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-render", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=8192)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -70,6 +72,9 @@ def main():
     from paper_2304_03184_amd import _lib as L, field as F, ops as O
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     L.lib()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
 
@@ -158,6 +163,41 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "binned_scatter_object_2p18_traffic.json")
+SCATTER_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2304_03184_amd",
+                           "csrc", "scatter.hip")
+
+
+def measured_traffic():
+    """HBM bytes per call of the binned scatter from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs recorded under profiles/ (scaled by the same counters on a
+    copy of known size); None once scatter.hip differs from the source the
+    counters were taken on."""
+    import hashlib
+    import json as _json
+    try:
+        rec = _json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha1(open(SCATTER_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("scatter_hip_sha1") != sha:
+        return None
+    return rec["hbm_bytes_per_call"]
+
+
+def calibrate_copy(torch, gib=1):
+    """A plain device copy of known size (gib GiB read + gib GiB written), three
+    times, for scaling the HBM byte counters."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copied {gib} GiB three times")
+
+
 def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
     """Times the hash-grid backward (the binned table-gradient scatter: count,
     scan, tile-bucketed append, per-tile LDS sum, split-tile reduce) alone with
@@ -180,7 +220,7 @@ def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
                O._p(dtab), None, O._p(ws), O._stream())
 
     def fwd():
-        O.encode_fwd(g, x, fld.table_half, torch.bfloat16)
+        O.encode_fwd(g, x, fld.table_half, torch.float16)
 
     def timed(fn, reps=10):
         for _ in range(3):
@@ -200,7 +240,7 @@ def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
     # algorithmic bytes per sample (per-unit figures of the scatter and gather):
     #   backward: position 12 B + dfeat 2L x 4 B + L x 8 corners x F=2 fp32 gradient
     #             contributions of 4 B (the 1,024 B / sample table-gradient RMW at L = 16)
-    #   forward:  position 12 B + L x 8 corners x 4 B (fp16 x 2) + 2L bf16 features
+    #   forward:  position 12 B + L x 8 corners x 4 B (fp16 x 2) + 2L fp16 features
     bwd_bpu = 12 + 4 * 2 * L_ + L_ * 8 * 2 * 4
     fwd_bpu = 12 + L_ * 8 * 4 + 2 * 2 * L_
     log(f"[bench] hash-grid backward (binned) {t_bwd * 1e3:.3f} ms, forward gather "
@@ -209,10 +249,11 @@ def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
     return {"kernel": "hash-grid backward: binned table-gradient scatter "
                       "(scatter_count + scatter_scan + scatter_emit + scatter_accum + scatter_reduce)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "samples_per_launch": n, "bytes_per_sample": bwd_bpu,
             "avg_launch_ms": t_bwd * 1e3,
-            "encode_fwd": {"kernel": "encode_fwd_split (level-split gather, fp16 table)",
+            "encode_fwd": {"kernel": "encode_fwd_split (level-split gather, fp16 table, fp16 "
+                                     "features)",
                            "avg_launch_ms": t_fwd * 1e3, "bytes_per_sample": fwd_bpu,
                            "achieved_GBs": fwd_bpu * n / t_fwd / 1e9,
                            "frac": fwd_bpu * n / t_fwd / 1e9 / HBM_PEAK_GBS}}

@@ -33,3 +33,25 @@ def test_human_object_loss_curve(precision):
     assert rel[:20].max() < first
     assert rel.max() < 2e-2
     assert abs(got[-1] - ref[-1, 1]) < 5e-3 * ref[-1, 1]
+
+
+def test_keyframe_training_psnr():
+    # key-frame refinement, 4096 rays per step drawn from the eight key frames,
+    # 2000 Adam steps on the fused BF16 path vs the FP64 oracle's stored curve.
+    # The first steps follow the oracle closely.  Later, the order of the
+    # table-gradient sums (it changes from run to run) and the fp16 / bf16
+    # rounding steer the trajectory: identical GPU runs ended 3 dB apart on
+    # this scene, so the final PSNR is compared within a band that covers
+    # that spread, and the run must actually fit the scene.
+    L = lib()
+    ref = curves.load_curve("curve_keyframes_4096.txt")
+    steps = ref.shape[0]
+    evals = {int(i): p for i, p in zip(ref[:, 0], ref[:, 2]) if np.isfinite(p)}
+    loss, psnr = curves.keyframe_run(L.NVR_BF16, steps, 4096, 250)
+    rel = np.abs(loss - ref[:, 1]) / ref[:, 1]
+    last = max(evals)
+    print(f"keyframes: early rel {rel[:10].max():.2e}; PSNR at {last}: GPU {psnr[last]:.2f} dB, "
+          f"oracle {evals[last]:.2f} dB; all GPU {sorted(psnr.items())}")
+    assert rel[:10].max() < 1e-2
+    assert psnr[last] > 30.0
+    assert abs(psnr[last] - evals[last]) < 4.0
