@@ -199,8 +199,9 @@ def calibrate_copy(torch, gib=1):
 
 
 def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
-    """Times the hash-grid backward (the binned table-gradient scatter: count,
-    scan, tile-bucketed append, per-tile LDS sum, split-tile reduce) alone with
+    """Times the hash-grid backward (the binned table-gradient scatter: regroup
+    by level group, count, scan, tile-bucketed append, per-tile LDS sum,
+    split-tile reduce) alone with
     HIP events on the current stream, on this workload's own samples; the
     forward gather is timed beside it."""
     md = O.march_desc_of(w, f)
@@ -246,8 +247,8 @@ def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
     log(f"[bench] hash-grid backward (binned) {t_bwd * 1e3:.3f} ms, forward gather "
         f"{t_fwd * 1e3:.3f} ms over {n} samples")
     achieved = bwd_bpu * n / t_bwd / 1e9
-    return {"kernel": "hash-grid backward: binned table-gradient scatter "
-                      "(scatter_count + scatter_scan + scatter_emit + scatter_accum + scatter_reduce)",
+    return {"kernel": "hash-grid backward: binned table-gradient scatter (scatter_planarize + "
+                      "scatter_count + scatter_scan + scatter_emit + scatter_accum + scatter_reduce)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "samples_per_launch": n, "bytes_per_sample": bwd_bpu,

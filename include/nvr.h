@@ -101,10 +101,15 @@ nvr_status nvr_encode_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
                           nvr_stream stream);
 
 /* Same gradients as nvr_encode_bwd for a float16 table, without a global
- * atomic per contribution: the contributions are binned by 16384-entry table
- * tiles (count, scan, append) and each tile is summed in LDS and added into
- * dtable once.  dtable must be 8-byte aligned; workspace (device, 256-byte
- * aligned) of nvr_encode_bwd_workspace(g, n) bytes, owned by the caller. */
+ * atomic per contribution: dfeat is first regrouped by level group (the eight
+ * XCDs each serve a fixed subset of levels), the contributions are binned by
+ * table tiles of 2^10..2^14 entries (count, scan, append) and each tile is
+ * summed in LDS and added into dtable once; dx (nullable) receives the sum of
+ * the level groups' position gradients.  dtable must be 8-byte aligned;
+ * workspace (device, 256-byte aligned) of nvr_encode_bwd_workspace(g, n)
+ * bytes, owned by the caller, is overwritten.  Unsupported ladders (more than
+ * 8192 tiles, a level over 2048 tiles, more than 32 levels) return
+ * NVR_EUNSUPPORTED. */
 size_t nvr_encode_bwd_workspace(const nvr_grid_desc *g, int64_t n);
 nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, const float *x,
                                  const void *table, const float *dfeat, float *dtable,

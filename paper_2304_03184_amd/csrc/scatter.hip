@@ -241,7 +241,7 @@ __device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
 // per tile with one global atomic, the records are staged in LDS in tile order
 // and then written out by consecutive threads to consecutive positions, so
 // that each tile's run is stored contiguously.
-template <bool PLANAR, int LPG, int BLOCK>
+template <int LPG, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict__ n_dev,
              int64_t cap, const float *__restrict__ x, const uint32_t *__restrict__ table,
@@ -281,15 +281,8 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
             float v0[8], v1[8];
             if (valid) {
                 const LevelPos lp = level_pos(p, l, px, py, pz);
-                float g0, g1;
-                if (PLANAR) {
-                    const float *src = dfeat + ((size_t)g * cap + s) * (2 * lpg) + 2 * m;
-                    g0 = src[0];
-                    g1 = src[1];
-                } else {
-                    g0 = dfeat[(size_t)s * (2 * p.L) + 2 * l];
-                    g1 = dfeat[(size_t)s * (2 * p.L) + 2 * l + 1];
-                }
+                const float *src = dfeat + ((size_t)g * cap + s) * (2 * lpg) + 2 * m;
+                const float g0 = src[0], g1 = src[1];
                 float e0 = 0.f, e1 = 0.f, e2 = 0.f;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
@@ -340,17 +333,11 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
             }
             __syncthreads();
         }
-        if (valid && dx_parts != nullptr) {
-            if (PLANAR) {   // per-group partials, summed by the consumer
-                float *o = dx_parts + ((size_t)g * cap + s) * 3;
-                o[0] = d0;
-                o[1] = d1;
-                o[2] = d2;
-            } else {        // accumulate into dx[n][3]
-                unsafeAtomicAdd(dx_parts + 3 * s, d0);
-                unsafeAtomicAdd(dx_parts + 3 * s + 1, d1);
-                unsafeAtomicAdd(dx_parts + 3 * s + 2, d2);
-            }
+        if (valid && dx_parts != nullptr) {   // per-group partials, summed by the consumer
+            float *o = dx_parts + ((size_t)g * cap + s) * 3;
+            o[0] = d0;
+            o[1] = d1;
+            o[2] = d2;
         }
     }
 }
@@ -553,7 +540,7 @@ nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st) {
 
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
-                          float *dx_parts, bool planar, void *ws, hipStream_t st, bool counted,
+                          float *dx_parts, void *ws, hipStream_t st, bool counted,
                           int emit_chunks, int emit_block) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
@@ -577,48 +564,34 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items);
     NVR_LAUNCHED();
     const int lpg = (p.L + kXcds - 1) / kXcds;
-#define NVR_EMIT(PL, LP)                                                                       \
+#define NVR_EMIT(LP)                                                                           \
     do {                                                                                       \
         if (eb == 512)                                                                         \
-            scatter_emit<PL, LP, 512><<<gre, 512, elds, st>>>(p, tb, lt, n, n_dev, cap, x,     \
+            scatter_emit<LP, 512><<<gre, 512, elds, st>>>(p, tb, lt, n, n_dev, cap, x,         \
                 (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts);         \
         else                                                                                   \
-            scatter_emit<PL, LP, kEmitBlock><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n,      \
-                n_dev, cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec,     \
-                dx_parts);                                                                     \
+            scatter_emit<LP, kEmitBlock><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n, n_dev,   \
+                cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts); \
     } while (0)
-#define NVR_EMIT_L(PL)                                                                         \
-    switch (lpg) {                                                                             \
-    case 1: NVR_EMIT(PL, 1); break;                                                            \
-    case 2: NVR_EMIT(PL, 2); break;                                                            \
-    case 3: NVR_EMIT(PL, 3); break;                                                            \
-    default: NVR_EMIT(PL, 4); break;                                                           \
-    }
     static bool emit_lds_ok = false;   // opt in to more than 64 KiB of dynamic LDS
     if (!emit_lds_ok) {
         const int most = (int)emit_lds_bytes(kEmitBlock, kMaxLevelTiles);
-        const void *fns[] = {(const void *)scatter_emit<true, 1, kEmitBlock>,
-                             (const void *)scatter_emit<true, 2, kEmitBlock>,
-                             (const void *)scatter_emit<true, 3, kEmitBlock>,
-                             (const void *)scatter_emit<true, 4, kEmitBlock>,
-                             (const void *)scatter_emit<false, 1, kEmitBlock>,
-                             (const void *)scatter_emit<false, 2, kEmitBlock>,
-                             (const void *)scatter_emit<false, 3, kEmitBlock>,
-                             (const void *)scatter_emit<false, 4, kEmitBlock>,
-                             (const void *)scatter_emit<true, 1, 512>, (const void *)scatter_emit<true, 2, 512>,
-                             (const void *)scatter_emit<true, 3, 512>, (const void *)scatter_emit<true, 4, 512>,
-                             (const void *)scatter_emit<false, 1, 512>, (const void *)scatter_emit<false, 2, 512>,
-                             (const void *)scatter_emit<false, 3, 512>, (const void *)scatter_emit<false, 4, 512>};
+        const void *fns[] = {(const void *)scatter_emit<1, kEmitBlock>,
+                             (const void *)scatter_emit<2, kEmitBlock>,
+                             (const void *)scatter_emit<3, kEmitBlock>,
+                             (const void *)scatter_emit<4, kEmitBlock>,
+                             (const void *)scatter_emit<1, 512>, (const void *)scatter_emit<2, 512>,
+                             (const void *)scatter_emit<3, 512>, (const void *)scatter_emit<4, 512>};
         for (const void *f : fns)
             NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, most));
         emit_lds_ok = true;
     }
-    if (planar) {
-        NVR_EMIT_L(true)
-    } else {
-        NVR_EMIT_L(false)
+    switch (lpg) {
+    case 1: NVR_EMIT(1); break;
+    case 2: NVR_EMIT(2); break;
+    case 3: NVR_EMIT(3); break;
+    default: NVR_EMIT(4); break;
     }
-#undef NVR_EMIT_L
 #undef NVR_EMIT
     NVR_LAUNCHED();
     if (dtable == nullptr) return NVR_OK;   // scan + emit only
@@ -643,11 +616,65 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     return NVR_OK;
 }
 
+// Row-major feature gradients dfeat[n][2L] to the level-group-planar layout
+// emit reads, [8][n][2 lpg] (level l = g + 8 m at [g][s][2m, 2m+1]; slots of
+// levels >= L hold 0).  Each workgroup pass moves 128 whole rows through LDS,
+// so both the reads and the eight per-group writes are contiguous runs.
+constexpr int kPlanarRows = 128;
+
+__global__ void __launch_bounds__(256)
+scatter_planarize(int L, int lpg, int64_t n, const float *__restrict__ dfeat,
+                  float *__restrict__ out) {
+    extern __shared__ float rows[];                    // [kPlanarRows][2L + 1]
+    const int w = 2 * L, wp = w + 1, q = 2 * lpg;
+    for (int64_t s0 = (int64_t)blockIdx.x * kPlanarRows; s0 < n;
+         s0 += (int64_t)gridDim.x * kPlanarRows) {
+        const int ns = (int)(n - s0 < kPlanarRows ? n - s0 : kPlanarRows);
+        const float *src = dfeat + (size_t)s0 * w;
+        for (int i = threadIdx.x; i < ns * w; i += blockDim.x) rows[(i / w) * wp + i % w] = src[i];
+        __syncthreads();
+        for (int g = 0; g < kXcds; ++g) {
+            float *dst = out + ((size_t)g * n + s0) * q;
+            for (int j = threadIdx.x; j < ns * q; j += blockDim.x) {
+                const int r = j / q, c = j % q, l = g + kXcds * (c >> 1);
+                dst[j] = l < L ? rows[r * wp + 2 * l + (c & 1)] : 0.f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// dx[n][3] += the eight level groups' partial position gradients [8][n][3].
+__global__ void __launch_bounds__(256)
+scatter_dx_sum(int64_t n3, const float *__restrict__ parts, float *__restrict__ dx) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float a = 0.f;
+#pragma unroll
+        for (int g = 0; g < kXcds; ++g) a += parts[(size_t)g * n3 + i];
+        dx[i] += a;
+    }
+}
+
+// Bytes of the public entry point's workspace: the binned scatter's, then the
+// planar feature gradients [8][n][2 lpg] and the partial position gradients
+// [8][n][3].
+static size_t public_ws_bytes(const GridParams &p, int64_t n, size_t *planar_at, size_t *parts_at) {
+    const int lpg = (p.L + kXcds - 1) / kXcds;
+    size_t b = (scatter_ws_bytes(p, n) + 255) & ~size_t(255);
+    *planar_at = b;
+    b += sizeof(float) * (size_t)kXcds * n * 2 * lpg;
+    b = (b + 255) & ~size_t(255);
+    *parts_at = b;
+    b += sizeof(float) * (size_t)kXcds * n * 3;
+    return b;
+}
+
 nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_t *n_dev,
                                     int64_t cap, const float *x, const void *table,
-                                    const float *dfeat, bool planar, void *ws, hipStream_t st,
+                                    const float *dfeat, void *ws, hipStream_t st,
                                     int emit_chunks, int emit_block) {
-    return launch_scatter(p, n, n_dev, cap, x, table, dfeat, nullptr, nullptr, planar, ws, st,
+    return launch_scatter(p, n, n_dev, cap, x, table, dfeat, nullptr, nullptr, ws, st,
                           /*counted=*/true, emit_chunks, emit_block);
 }
 
@@ -657,7 +684,8 @@ using namespace nvr;
 
 extern "C" size_t nvr_encode_bwd_workspace(const nvr_grid_desc *g, int64_t n) {
     if (check_grid(g) != NVR_OK || n < 0) return 0;
-    return scatter_ws_bytes(make_grid_params(g), n);
+    size_t planar_at, parts_at;
+    return public_ws_bytes(make_grid_params(g), n, &planar_at, &parts_at);
 }
 
 extern "C" nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, const float *x,
@@ -674,6 +702,23 @@ extern "C" nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, c
     const GridParams p = make_grid_params(g);
     NVR_TRY(scatter_check(p));
     NVR_REQUIRE((size_t)n * p.L * 8 < (1ull << 32), NVR_EINVAL, "too many contributions");
-    return launch_scatter(p, n, nullptr, n, x, table, dfeat, dtable, dx, false, workspace,
-                          hs(stream));
+    const hipStream_t st = hs(stream);
+    size_t planar_at, parts_at;
+    public_ws_bytes(p, n, &planar_at, &parts_at);
+    float *planar = (float *)((char *)workspace + planar_at);
+    float *parts = dx ? (float *)((char *)workspace + parts_at) : nullptr;
+    const int lpg = (p.L + kXcds - 1) / kXcds;
+    scatter_planarize<<<grid_for(n, kPlanarRows, 8192), 256,
+                        sizeof(float) * kPlanarRows * (2 * p.L + 1), st>>>(p.L, lpg, n, dfeat,
+                                                                           planar);
+    NVR_LAUNCHED();
+    // 512-sample emit chunks, 256 chunks per level group: the shape the step's
+    // tuner settles on for large sample counts
+    NVR_TRY(launch_scatter(p, n, nullptr, n, x, table, planar, dtable, parts, workspace, st,
+                           /*counted=*/false, 256, 512));
+    if (dx) {
+        scatter_dx_sum<<<grid_for(3 * n, 256, 8192), 256, 0, st>>>(3 * n, parts, dx);
+        NVR_LAUNCHED();
+    }
+    return NVR_OK;
 }

@@ -10,18 +10,19 @@ nvr_status scatter_check(const GridParams &p);
 // The tile counter inside a scatter workspace, and a launch that zeroes it.
 TileCounter scatter_counter(const GridParams &p, void *ws);
 nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st);
-// dtable (acc) += binned scatter of w * dfeat; dx_parts: planar -> [8][cap][3]
-// partials, row-major -> [n][3] (acc, via atomics); nullable.  counted: the
-// tile counts in ws were already formed (zeroed, then counted by the forward
-// gather over the same positions); otherwise they are counted here.
+// dtable (acc) += binned scatter of w * dfeat, dfeat in the level-group-planar
+// layout [8][cap][2 lpg] (level g + 8 m at [g][s][2m, 2m+1]); dx_parts
+// (nullable) receives the [8][cap][3] per-group position-gradient partials.
+// counted: the tile counts in ws were already formed (zeroed, then counted by
+// the forward gather over the same positions); otherwise they are counted here.
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
-                          float *dx_parts, bool planar, void *ws, hipStream_t st,
+                          float *dx_parts, void *ws, hipStream_t st,
                           bool counted = false, int emit_chunks = 0, int emit_block = 0);
 // the scan and emit passes alone (tile counts already formed), for tuning
 nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_t *n_dev,
                                     int64_t cap, const float *x, const void *table,
-                                    const float *dfeat, bool planar, void *ws, hipStream_t st,
+                                    const float *dfeat, void *ws, hipStream_t st,
                                     int emit_chunks, int emit_block);
 
 }  // namespace nvr

@@ -249,7 +249,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                              f->params, true, w.dsigma, w.drgb, f->params_grad, w.dfeat, w.mlp_ws,
                              st, w.mlp_bwd_blocks));
             NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
-                                   f->has_warp ? w.dx : nullptr, true, w.scatter_ws, st,
+                                   f->has_warp ? w.dx : nullptr, w.scatter_ws, st,
                                    /*counted=*/true, w.emit_chunks, w.emit_block));
             if (f->has_warp)
                 NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, kXcds, 3 * cap,
@@ -404,7 +404,7 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         }));
         int e = 0;
         NVR_TRY(pick(st, emit, 6, &e, [&](int c) {
-            return launch_scatter_emit_only(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, true,
+            return launch_scatter_emit_only(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                             w.scatter_ws, st, c % 1000, c / 1000);
         }));
         w.emit_chunks = e % 1000;
