@@ -187,10 +187,14 @@ encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
 #pragma unroll
                     for (int k = 0; k < 8; ++k) v[k] = table[e[k]];
                 }
-                if (COUNT) {
+                if (COUNT) {   // the two corners of an x edge share a tile but rarely
                     uint32_t *h = hist + m * cnt.level_tiles - (int)((uint32_t)p.off[l] >> cnt.tb);
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) atomicAdd(&h[e[k] >> cnt.tb], 1u);
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t t0 = e[2 * j] >> cnt.tb, t1 = e[2 * j + 1] >> cnt.tb;
+                        atomicAdd(&h[t0], t0 == t1 ? 2u : 1u);
+                        if (t0 != t1) atomicAdd(&h[t1], 1u);
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {

@@ -133,9 +133,11 @@ scatter_count(GridParams p, int tb, int n_tiles, int64_t n, const int32_t *__res
                 if (l >= p.L) break;
                 const LevelPos lp = level_pos(p, l, px, py, pz);
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t e = p.off[l] + corner_index(p, l, lp, k);
-                    atomicAdd(&hist[e >> tb], 1u);
+                for (int j = 0; j < 4; ++j) {   // an x edge's two corners: one tile but rarely
+                    const uint32_t t0 = (p.off[l] + corner_index(p, l, lp, 2 * j)) >> tb;
+                    const uint32_t t1 = (p.off[l] + corner_index(p, l, lp, 2 * j + 1)) >> tb;
+                    atomicAdd(&hist[t0], t0 == t1 ? 2u : 1u);
+                    if (t0 != t1) atomicAdd(&hist[t1], 1u);
                 }
             }
         }
@@ -291,7 +293,6 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                     ent[k] = e;
                     v0[k] = w * g0;
                     v1[k] = w * g1;
-                    rank[k] = atomicAdd(&hist[(int)(e >> tb) - t_lo], 1u);
                     if (dx_parts != nullptr) {
                         const uint32_t v = table[e];
                         const float tg = f16_bits_to_f32((uint16_t)(v & 0xffffu)) * g0 +
@@ -301,6 +302,16 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                         e1 += dw.y * tg;
                         e2 += dw.z * tg;
                     }
+                }
+                // ranks inside the tiles; the two corners of an x edge (2j, 2j + 1)
+                // fall into one tile but rarely, and then take one counter update
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t0 = (int)(ent[2 * j] >> tb) - t_lo;
+                    const int t1 = (int)(ent[2 * j + 1] >> tb) - t_lo;
+                    const uint32_t r = atomicAdd(&hist[t0], t0 == t1 ? 2u : 1u);
+                    rank[2 * j] = r;
+                    rank[2 * j + 1] = t0 == t1 ? r + 1u : atomicAdd(&hist[t1], 1u);
                 }
                 if (dx_parts != nullptr) {
                     const float N = (float)p.res[l];
