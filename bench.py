@@ -158,9 +158,38 @@ def main():
                        "speedup_bf16_over_fp32": dt_32 / dt_bf, "loss": loss_32},
         "render": render,
         "roofline": roof,
+        "step_roofline": step_roofline(f, R, n_samp, n_entries,
+                                       sum(a * b for a, b in f.layer_shapes()), dt_bf),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+MFMA_PEAK_FLOPS = 2.5e15    # dense fp16 / bf16 MFMA
+
+
+def step_roofline(f, R, n, n_entries, n_params, t_step):
+    """Step time if every stage ran at its own bound (HBM bytes at 8 TB/s or
+    MFMA flops at 2.5 PFLOP/s, whichever is longer), from per-unit algorithmic
+    figures; the measured step is reported as a fraction of it."""
+    L_ = f.n_levels
+    fwd_flop = sum(2 * a * b for a, b in f.layer_shapes())   # one forward, unpadded
+    stages = {   # name: (bytes, flops)
+        "march": (24 * n + 28 * R, 0),                        # t, dt, x, ray id; rays in
+        "gather": ((12 + L_ * 8 * 4 + 2 * 2 * L_) * n, 0),    # 588 B / sample at L = 16
+        "mlp_fwd": ((4 * L_ + 16) * n, fwd_flop * n),         # fp16 features in, sigma + rgb out
+        "composite_loss": (40 * n + 40 * R, 10 * n),
+        "mlp_bwd": ((4 * L_ + 16 + 8 * L_) * n, 3 * fwd_flop * n),  # recompute + dX + dW
+        "scatter": ((12 + 8 * L_ + L_ * 8 * 2 * 4) * n, 0),   # 1164 B / sample at L = 16
+        "adam": (34 * (2 * n_entries + n_params), 0),
+    }
+    out, total = {}, 0.0
+    for k, (by, fl) in stages.items():
+        t = max(by / (HBM_PEAK_GBS * 1e9), fl / MFMA_PEAK_FLOPS)
+        out[k] = {"bytes": by, "flops": fl, "ms": t * 1e3}
+        total += t
+    return {"rays_per_s": R / total, "ms_per_step": total * 1e3,
+            "measured_frac": total / t_step, "stages": out}
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -199,29 +228,52 @@ def calibrate_copy(torch, gib=1):
 
 
 def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
-    """Times the hash-grid backward (the binned table-gradient scatter: regroup
-    by level group, count, scan, tile-bucketed append, per-tile LDS sum,
-    split-tile reduce) alone with
-    HIP events on the current stream, on this workload's own samples; the
-    forward gather is timed beside it."""
+    """Times the hash-grid kernels alone with HIP events on the current stream,
+    on this workload's own samples.  The roofline entry is the binned
+    table-gradient scatter with feature gradients in the level-group layout the
+    step keeps them in (count, scan, tile-bucketed append, per-tile LDS sum,
+    split-tile reduce; in the step the gather forms the counts instead).  Beside
+    it: the same call on row-major gradients (regrouped first), the level-split
+    gather in both layouts, and the random-gather probe at the table's own
+    footprint, the practical ceiling of the gather."""
+    import ctypes as C
     md = O.march_desc_of(w, f)
     m = O.march(md, o_d, d_d, fld.occ, capacity=cap)
     n = m["n"]
     x = m["x"].contiguous()
     g = fld.grid
+    L_ = f.n_levels
+    lpg = (L_ + 7) // 8
     rng = np.random.default_rng(5)
-    dfeat = torch.from_numpy(rng.normal(size=(n, 32)).astype(np.float32) * 1e-3).cuda()
+    dfeat = torch.from_numpy(rng.normal(size=(n, 2 * L_)).astype(np.float32) * 1e-3).cuda()
+    dgrp = torch.zeros((8, n, 2 * lpg), dtype=torch.float32, device="cuda")
+    for l in range(L_):
+        dgrp[l % 8, :, 2 * (l // 8):2 * (l // 8) + 2] = dfeat[:, 2 * l:2 * l + 2]
     dtab = torch.zeros_like(fld.table)
-    nb = L.lib().nvr_encode_bwd_workspace(__import__("ctypes").byref(g), n)
+    nb = L.lib().nvr_encode_bwd_workspace(C.byref(g), n)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    import ctypes as C
+    feat_g = torch.empty((8, n, 2 * lpg), dtype=torch.float16, device="cuda")
+    probe_out = torch.empty((8, n), dtype=torch.int32, device="cuda")
+    th = fld.table_half
 
-    def bwd():
-        L.call("nvr_encode_bwd_binned", C.byref(g), n, O._p(x), O._p(fld.table_half), O._p(dfeat),
+    def bwd_grouped():
+        L.call("nvr_encode_bwd_binned_grouped", C.byref(g), n, O._p(x), O._p(th), O._p(dgrp),
                O._p(dtab), None, O._p(ws), O._stream())
 
-    def fwd():
-        O.encode_fwd(g, x, fld.table_half, torch.float16)
+    def bwd_rowmajor():
+        L.call("nvr_encode_bwd_binned", C.byref(g), n, O._p(x), O._p(th), O._p(dfeat),
+               O._p(dtab), None, O._p(ws), O._stream())
+
+    def fwd_grouped():
+        L.call("nvr_encode_fwd_grouped", C.byref(g), n, O._p(x), O._p(th), O._p(feat_g),
+               O._stream())
+
+    def fwd_rowmajor():
+        O.encode_fwd(g, x, th, torch.float16)
+
+    def probe():
+        L.call("nvr_probe_gather", O._p(th), th.numel() * th.element_size(), n, 4 * lpg, 1,
+               O._p(probe_out), O._stream())
 
     def timed(fn, reps=10):
         for _ in range(3):
@@ -235,29 +287,48 @@ def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
-    t_bwd = timed(bwd)
-    t_fwd = timed(fwd)
-    L_ = f.n_levels
+    t_bwd = timed(bwd_grouped)
+    t_bwd_rm = timed(bwd_rowmajor)
+    t_fwd = timed(fwd_grouped)
+    t_fwd_rm = timed(fwd_rowmajor)
+    t_probe = timed(probe)
     # algorithmic bytes per sample (per-unit figures of the scatter and gather):
     #   backward: position 12 B + dfeat 2L x 4 B + L x 8 corners x F=2 fp32 gradient
     #             contributions of 4 B (the 1,024 B / sample table-gradient RMW at L = 16)
     #   forward:  position 12 B + L x 8 corners x 4 B (fp16 x 2) + 2L fp16 features
     bwd_bpu = 12 + 4 * 2 * L_ + L_ * 8 * 2 * 4
     fwd_bpu = 12 + L_ * 8 * 4 + 2 * 2 * L_
-    log(f"[bench] hash-grid backward (binned) {t_bwd * 1e3:.3f} ms, forward gather "
-        f"{t_fwd * 1e3:.3f} ms over {n} samples")
+    log(f"[bench] binned scatter {t_bwd * 1e3:.3f} ms (row-major gradients "
+        f"{t_bwd_rm * 1e3:.3f} ms), gather {t_fwd * 1e3:.3f} ms (row-major "
+        f"{t_fwd_rm * 1e3:.3f} ms), random-gather probe {t_probe * 1e3:.3f} ms over {n} samples")
     achieved = bwd_bpu * n / t_bwd / 1e9
-    return {"kernel": "hash-grid backward: binned table-gradient scatter (scatter_planarize + "
-                      "scatter_count + scatter_scan + scatter_emit + scatter_accum + scatter_reduce)",
+    loads = 8 * n * 4 * lpg   # 16-byte probe loads: 4 per level, every level group
+    return {"kernel": "hash-grid backward: binned table-gradient scatter, gradients in the "
+                      "level-group layout (nvr_encode_bwd_binned_grouped: zero_u32 + "
+                      "scatter_count + scatter_scan + scatter_emit + scatter_accum + "
+                      "scatter_reduce)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "samples_per_launch": n, "bytes_per_sample": bwd_bpu,
             "avg_launch_ms": t_bwd * 1e3,
+            "row_major_call": {"entry": "nvr_encode_bwd_binned (adds scatter_planarize)",
+                               "avg_launch_ms": t_bwd_rm * 1e3,
+                               "achieved_GBs": bwd_bpu * n / t_bwd_rm / 1e9},
             "encode_fwd": {"kernel": "encode_fwd_split (level-split gather, fp16 table, fp16 "
-                                     "features)",
+                                     "features in the level-group layout; "
+                                     "nvr_encode_fwd_grouped)",
                            "avg_launch_ms": t_fwd * 1e3, "bytes_per_sample": fwd_bpu,
                            "achieved_GBs": fwd_bpu * n / t_fwd / 1e9,
-                           "frac": fwd_bpu * n / t_fwd / 1e9 / HBM_PEAK_GBS}}
+                           "frac": fwd_bpu * n / t_fwd / 1e9 / HBM_PEAK_GBS,
+                           "row_major_ms": t_fwd_rm * 1e3,
+                           "gather_probe": {
+                               "what": "random aligned 16-byte loads over the same fp16 table "
+                                       "split into 8 XCD slices, as many as the gather's "
+                                       "x-edge loads (4 per level per sample)",
+                               "avg_launch_ms": t_probe * 1e3,
+                               "loads_per_s": loads / t_probe,
+                               "GBs_16B": loads * 16 / t_probe / 1e9,
+                               "gather_frac_of_probe": t_probe / t_fwd}}}
 
 
 def time_render(O, L, F, torch, w, f, table, params, occ, dev):

@@ -115,6 +115,21 @@ nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, const float 
                                  const void *table, const float *dfeat, float *dtable,
                                  float *dx, void *workspace, nvr_stream stream);
 
+/* The level-group ("grouped") layout the fused step keeps features and their
+ * gradients in: [8][n][2 lpg] with lpg = ceil(L / 8), level l = g + 8 m at
+ * [g][s][2m, 2m+1] (slots of levels >= L are written as 0 / ignored); F = 2
+ * only.  Each XCD serves one plane, so neither call regroups anything.
+ * nvr_encode_fwd_grouped: fp16 table, fp16 features (same values as
+ * nvr_encode_fwd with table_dtype = feat_dtype = NVR_F16).
+ * nvr_encode_bwd_binned_grouped: nvr_encode_bwd_binned with dfeat (float32)
+ * in the grouped layout; same workspace and errors. */
+nvr_status nvr_encode_fwd_grouped(const nvr_grid_desc *g, int64_t n, const float *x,
+                                  const void *table, void *feat, nvr_stream stream);
+nvr_status nvr_encode_bwd_binned_grouped(const nvr_grid_desc *g, int64_t n, const float *x,
+                                         const void *table, const float *dfeat,
+                                         float *dtable, float *dx, void *workspace,
+                                         nvr_stream stream);
+
 /* ------------------------------------------------------------------------
  * Ray marching with occupancy skipping (the back-end is built on Instant-NGP,
  * Sec. 4.3; its marcher is not described in the paper).  Per ray: clip
@@ -384,7 +399,6 @@ nvr_status nvr_train_step_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
 nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
                           const nvr_batch *b, nvr_train_state *state_dev, float *loss_dev,
                           nvr_stream stream);
-/* Total kept samples of field f in the last forward (synchronises `stream`). */
 /* Launch shapes in use for `field` (0 or 1): shape[0] gather chunks per level
  * group, [1] network forward workgroups, [2] network backward workgroups,
  * [3] emit chunks per level group, [4] compositing workgroups, [5] 1 if
@@ -392,6 +406,8 @@ nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const
  * shape is a host array of 7. */
 nvr_status nvr_launch_shape(const nvr_ctx *ctx, int32_t field, int32_t *shape);
 
+/* Total kept samples of field `field` in the last forward (synchronises
+ * `stream`); count is a host pointer. */
 nvr_status nvr_last_sample_count(nvr_ctx *ctx, int32_t field, int64_t *count,
                                  nvr_stream stream);
 
@@ -402,6 +418,20 @@ nvr_status nvr_last_sample_count(nvr_ctx *ctx, int32_t field, int64_t *count,
 nvr_status nvr_render(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
                       int64_t n_rays, const float *o, const float *d, float t_stop,
                       float *rgb, float *depth, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Measurement probe (not part of the method): the random-gather ceiling the
+ * hash-grid gather of Sec. 4.3's back-end is measured against.  The table
+ * (device, 16-byte aligned, `bytes` long) is split into eight equal slices;
+ * workgroup b serves slice b % 8 (one per XCD, as the level-split gather
+ * serves level groups).  For each of the n items of each slice, `loads`
+ * (a positive multiple of 4, <= 1024) independent 16-byte loads at uniformly
+ * random aligned offsets of the slice are issued, and the xor of the loaded
+ * words is stored to out[slice][n] (device, caller-owned, 8 n words).
+ * Errors: NVR_EINVAL for n outside [0, 2^31), bad `loads`, a table under
+ * 128 bytes or over 2^39 bytes, NULL or misaligned arrays. */
+nvr_status nvr_probe_gather(const void *table, size_t bytes, int64_t n, int32_t loads,
+                            uint32_t seed, uint32_t *out, nvr_stream stream);
 
 #ifdef __cplusplus
 }

@@ -439,6 +439,21 @@ extern "C" nvr_status nvr_encode_fwd(const nvr_grid_desc *g, int64_t n, const fl
                              feat_dtype, false, hs(stream));
 }
 
+extern "C" nvr_status nvr_encode_fwd_grouped(const nvr_grid_desc *g, int64_t n, const float *x,
+                                             const void *table, void *feat, nvr_stream stream) {
+    clear_error();
+    NVR_TRY(check_grid(g));
+    NVR_REQUIRE(n >= 0 && n < (1ll << 31), NVR_EINVAL, "n out of range");
+    if (n == 0) return NVR_OK;
+    NVR_REQUIRE(x && table && feat, NVR_EINVAL, "NULL array");
+    NVR_REQUIRE(aligned(x, 4) && aligned(table, 4) && aligned(feat, 4), NVR_EINVAL,
+                "misaligned array");
+    // 2048 chunks per level group: the shape the step's tuner settles on for
+    // large sample counts
+    return launch_encode_fwd(make_grid_params(g), n, nullptr, n, x, table, NVR_F16, feat, NVR_F16,
+                             true, hs(stream), nullptr, 2048);
+}
+
 extern "C" nvr_status nvr_encode_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
                                      const void *table, nvr_dtype table_dtype,
                                      const float *dfeat, float *dtable, float *dx,

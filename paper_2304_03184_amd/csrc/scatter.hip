@@ -699,9 +699,11 @@ extern "C" size_t nvr_encode_bwd_workspace(const nvr_grid_desc *g, int64_t n) {
     return public_ws_bytes(make_grid_params(g), n, &planar_at, &parts_at);
 }
 
-extern "C" nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, const float *x,
-                                            const void *table, const float *dfeat, float *dtable,
-                                            float *dx, void *workspace, nvr_stream stream) {
+// Both public binned entry points: dfeat row-major [n][2L] (regrouped first)
+// or already level-group planar [8][n][2 lpg].
+static nvr_status binned_public(const nvr_grid_desc *g, int64_t n, const float *x,
+                                const void *table, const float *dfeat, bool grouped,
+                                float *dtable, float *dx, void *workspace, nvr_stream stream) {
     clear_error();
     NVR_TRY(check_grid(g));
     NVR_REQUIRE(n >= 0 && n < (1ll << 31), NVR_EINVAL, "n out of range");
@@ -716,13 +718,17 @@ extern "C" nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, c
     const hipStream_t st = hs(stream);
     size_t planar_at, parts_at;
     public_ws_bytes(p, n, &planar_at, &parts_at);
-    float *planar = (float *)((char *)workspace + planar_at);
+    const float *planar = dfeat;
     float *parts = dx ? (float *)((char *)workspace + parts_at) : nullptr;
-    const int lpg = (p.L + kXcds - 1) / kXcds;
-    scatter_planarize<<<grid_for(n, kPlanarRows, 8192), 256,
-                        sizeof(float) * kPlanarRows * (2 * p.L + 1), st>>>(p.L, lpg, n, dfeat,
-                                                                           planar);
-    NVR_LAUNCHED();
+    if (!grouped) {
+        float *buf = (float *)((char *)workspace + planar_at);
+        const int lpg = (p.L + kXcds - 1) / kXcds;
+        scatter_planarize<<<grid_for(n, kPlanarRows, 8192), 256,
+                            sizeof(float) * kPlanarRows * (2 * p.L + 1), st>>>(p.L, lpg, n, dfeat,
+                                                                               buf);
+        NVR_LAUNCHED();
+        planar = buf;
+    }
     // 512-sample emit chunks, 256 chunks per level group: the shape the step's
     // tuner settles on for large sample counts
     NVR_TRY(launch_scatter(p, n, nullptr, n, x, table, planar, dtable, parts, workspace, st,
@@ -732,4 +738,17 @@ extern "C" nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, c
         NVR_LAUNCHED();
     }
     return NVR_OK;
+}
+
+extern "C" nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, const float *x,
+                                            const void *table, const float *dfeat, float *dtable,
+                                            float *dx, void *workspace, nvr_stream stream) {
+    return binned_public(g, n, x, table, dfeat, false, dtable, dx, workspace, stream);
+}
+
+extern "C" nvr_status nvr_encode_bwd_binned_grouped(const nvr_grid_desc *g, int64_t n,
+                                                    const float *x, const void *table,
+                                                    const float *dfeat, float *dtable, float *dx,
+                                                    void *workspace, nvr_stream stream) {
+    return binned_public(g, n, x, table, dfeat, true, dtable, dx, workspace, stream);
 }

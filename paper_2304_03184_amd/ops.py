@@ -132,6 +132,39 @@ def encode_bwd_binned(g, x, table, dfeat, dtable, dx=None):
          _p(dx), _p(ws), _stream())
 
 
+def grouped_width(g):
+    """Features per sample in one level-group plane (2 x ceil(L / 8))."""
+    return 2 * ((g.n_levels + 7) // 8)
+
+
+def encode_fwd_grouped(g, x, table):
+    """fp16 features in the level-group layout [8][n][2 lpg] from an fp16 table."""
+    n = x.shape[0]
+    feat = torch.empty((8, n, grouped_width(g)), dtype=torch.float16, device=x.device)
+    call("nvr_encode_fwd_grouped", C.byref(g), n, _p(x), _p(table), _p(feat), _stream())
+    return feat
+
+
+def encode_bwd_binned_grouped(g, x, table, dfeat, dtable, dx=None):
+    """Binned backward with float32 feature gradients in the level-group layout."""
+    _dev(dfeat, torch.float32)
+    _dev(dtable, torch.float32)
+    n = x.shape[0]
+    nb = L.lib().nvr_encode_bwd_workspace(C.byref(g), n)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=x.device)
+    call("nvr_encode_bwd_binned_grouped", C.byref(g), n, _p(x), _p(table), _p(dfeat),
+         _p(dtable), _p(dx), _p(ws), _stream())
+
+
+def probe_gather(table, n, loads, seed=1):
+    """Random 16-byte gathers over `table`'s bytes split into eight slices
+    (measurement probe, not part of the method); returns the [8][n] xors."""
+    out = torch.empty((8, n), dtype=torch.int32, device=table.device)
+    call("nvr_probe_gather", _p(table), table.numel() * table.element_size(), n, loads, seed,
+         _p(out), _stream())
+    return out
+
+
 class EncodeFn(torch.autograd.Function):
     """feat = encode(x, table); backward scatters into the table gradient and
     (when x requires grad) accumulates the position gradient."""

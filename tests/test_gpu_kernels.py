@@ -129,6 +129,41 @@ def test_encode_split_fp16_table():
     assert rel_err(host(dtab2), 2 * rt) < 1e-5
 
 
+def _to_grouped(a, L):
+    """[n][2L] -> level-group layout [8][n][2 ceil(L/8)] (level g + 8m at 2m, 2m+1)."""
+    lpg = (L + 7) // 8
+    out = np.zeros((8, a.shape[0], 2 * lpg), a.dtype)
+    for l in range(L):
+        g, m = l % 8, l // 8
+        out[g, :, 2 * m:2 * m + 2] = a[:, 2 * l:2 * l + 2]
+    return out
+
+
+@pytest.mark.parametrize("k,n", [(1, 3001), (2, 20000)])
+def test_encode_grouped_layout(k, n):
+    I = field_inputs(k, 8)
+    f, lay = I["fcfg"], I["lay"]
+    O = ops()
+    g = O.grid_desc_of(f)
+    rng = synth.rng_for(18)
+    lo, hi = (-1.5, 1.5) if k == 1 else (-1.0, 1.0)
+    x = _positions(rng, n, lo, hi)
+    t16 = I["table"].astype(np.float16)
+    ref = ogrid.encode(x, t16.astype(np.float64), lay)
+    L = f.n_levels
+    feat = O.encode_fwd_grouped(g, dev(x), dev(t16))
+    assert tuple(feat.shape) == (8, n, 2 * ((L + 7) // 8))
+    np.testing.assert_allclose(host(feat.float()), _to_grouped(ref, L), rtol=1e-3, atol=1e-7)
+    dfeat = rng.normal(size=ref.shape).astype(np.float32)
+    rt, rdx = ogrid.encode_backward(x, t16.astype(np.float64), dfeat, lay)
+    dtab = torch.zeros((lay.n_entries, 2), device="cuda")
+    dx = torch.zeros((n, 3), device="cuda")
+    O.encode_bwd_binned_grouped(g, dev(x), dev(t16), dev(_to_grouped(dfeat, L)), dtab, dx)
+    assert rel_err(host(dtab), rt) < 1e-5
+    np.testing.assert_allclose(host(dtab), rt, rtol=0, atol=1e-5 * np.abs(rt).max())
+    assert rel_err(host(dx), rdx) < 1e-4
+
+
 def test_encode_binned_heavy_tiles_and_empty():
     # 300k samples in a small region: the coarse tiles are split over many work
     # items (partial slabs summed by a last pass), the rest owned by single items
