@@ -94,23 +94,46 @@ __device__ __forceinline__ f4 relu4(f4 a) {
     for (int i = 0; i < 4; ++i) r[i] = fmaxf(a[i], 0.f);
     return r;
 }
-__device__ __forceinline__ f4 mask4(f4 g, f4 act) {
-    f4 r;
-    for (int i = 0; i < 4; ++i) r[i] = act[i] > 0.f ? g[i] : 0.f;
-    return r;
-}
 __device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
 
 // Per-wave staging tiles of the backward: 16 units x 16 samples, bf16 bits,
 // unit-major.  A lane of orientation A (sample c, rows 4g..4g+3) writes its
 // four values; a lane reading operand rows (unit u, samples 4g..4g+3) gets
-// 8 contiguous bytes.
-constexpr int kTiles = 30;
-constexpr int TX = 0, THD = 2, TCI = 6, TH1 = 8, TH2 = 12;          // activations
-constexpr int TDHD = 16, TDO = 20, TDH1 = 21, TDH2 = 25, TDZ = 29;  // gradients
+// 8 contiguous bytes.  The forward's activations take 16 tiles; each layer's
+// weight gradient is formed as soon as its output gradient is staged, after
+// which the gradient of the layer below takes the place of the activations
+// just consumed, so 17 tiles per wave suffice.
+constexpr int kTiles = 17;
+constexpr int TX = 0, THD = 2, TCI = 6, TH1 = 8, TH2 = 12, TDZ = 16;
 __device__ __forceinline__ void stage4(uint16_t *tile, int g, int c, f4 v) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) tile[(4 * g + j) * 16 + c] = (uint16_t)bfs(v[j]);
+}
+// four activations as bf16 bits, two per word (element 2i in the low half)
+struct P4 {
+    uint32_t lo, hi;
+};
+typedef __attribute__((ext_vector_type(2))) __bf16 bf2;
+__device__ __forceinline__ P4 pk4(f4 v) {
+    return P4{__builtin_bit_cast(uint32_t, bf2{(__bf16)v[0], (__bf16)v[1]}),
+              __builtin_bit_cast(uint32_t, bf2{(__bf16)v[2], (__bf16)v[3]})};
+}
+__device__ __forceinline__ void stagep(uint16_t *tile, int g, int c, P4 p) {
+    tile[(4 * g + 0) * 16 + c] = (uint16_t)(p.lo & 0xffffu);
+    tile[(4 * g + 1) * 16 + c] = (uint16_t)(p.lo >> 16);
+    tile[(4 * g + 2) * 16 + c] = (uint16_t)(p.hi & 0xffffu);
+    tile[(4 * g + 3) * 16 + c] = (uint16_t)(p.hi >> 16);
+}
+// gradient through a ReLU whose output was rounded to bf16: passes where the
+// output is nonzero (a positive output below bf16's smallest subnormal counts
+// as zero)
+__device__ __forceinline__ f4 maskp(f4 gr, P4 p) {
+    f4 r;
+    r[0] = (p.lo & 0x7fffu) ? gr[0] : 0.f;
+    r[1] = (p.lo & 0x7fff0000u) ? gr[1] : 0.f;
+    r[2] = (p.hi & 0x7fffu) ? gr[2] : 0.f;
+    r[3] = (p.hi & 0x7fff0000u) ? gr[3] : 0.f;
+    return r;
 }
 __device__ __forceinline__ s4 unstage(const uint16_t *tile, int u, int g) {
     return *reinterpret_cast<const s4 *>(tile + u * 16 + 4 * g);
@@ -372,8 +395,10 @@ struct DW {
     f4 c3[4];
 };
 
+// two waves per SIMD: at most 256 registers per lane (weight-gradient
+// accumulators take 160 of them) and 72 KiB of LDS per workgroup
 template <int NCH, bool PLANAR, typename FT>
-__global__ void __launch_bounds__(kMfmaBlock)
+__global__ void __launch_bounds__(kMfmaBlock) __attribute__((amdgpu_waves_per_eu(2)))
 mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const uint16_t *__restrict__ feat, const float *__restrict__ dirs,
              const int32_t *__restrict__ ray_id, const void *__restrict__ params,
@@ -421,20 +446,31 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
         }
         FwdA<NCH, FT> a;
         forward_a<NCH, FT>(F, l, g, xf, dir, nsh, a);
-        // activations of this block -> staging tiles (features at their index)
+        // activations of this block -> staging tiles (features at their index);
+        // from here on the hidden activations are only needed as ReLU masks,
+        // which their bf16 bits serve
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = kin<PLANAR>(g, j);
             if (k < net.n_in) tw[TX + (k >> 4)][(k & 15) * 16 + c] = (uint16_t)bfs((float)xf[j]);
         }
+        P4 phd[4], ph1[4], ph2[4];
         for (int m = 0; m < 4; ++m) {
-            stage4(tw[THD + m], g, c, a.hd[m]);
-            stage4(tw[TH1 + m], g, c, a.h1[m]);
-            if (NCH == 2) stage4(tw[TH2 + m], g, c, a.h2[m]);
+            phd[m] = pk4(a.hd[m]);
+            ph1[m] = pk4(a.h1[m]);
+            stagep(tw[THD + m], g, c, phd[m]);
+            stagep(tw[TH1 + m], g, c, ph1[m]);
+            if (NCH == 2) {
+                ph2[m] = pk4(a.h2[m]);
+                stagep(tw[TH2 + m], g, c, ph2[m]);
+            }
         }
         stage4(tw[TCI], g, c, a.o);
         stage4(tw[TCI + 1], g, c, a.sh4);
-        // ------------------------------------------------ orientation A backward
+        // ------------------------------------------------ orientation A backward,
+        // each layer's weight gradient (K = 16 samples) as soon as its operands
+        // are staged; a wave's LDS operations complete in order, so its reads
+        // see its writes and a tile is rewritten only after it was read
         f4 dz = zero4();
         if (g == 0) {
             for (int i = 0; i < 3; ++i) {
@@ -443,28 +479,64 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
             }
         }
         const s4 dzq = quad(dz);
-        f4 dh2[4], dh1[4];
-        bf8 dh2b[2], dh1b[2];
+        stage4(tw[TDZ], g, c, dz);
+        {   // last colour layer: dz x (h2 or h1)
+            const s4 gq = unstage(tw[TDZ], c, g);
+            const int th = NCH == 2 ? TH2 : TH1;
+            for (int ti = 0; ti < 4; ++ti) acc.c3[ti] = mfma16(gq, unstage(tw[th + ti], c, g), acc.c3[ti]);
+        }
+        f4 dh1[4];
         if (NCH == 2) {
-            for (int m = 0; m < 4; ++m) dh2[m] = mask4(mfma16(F.c3t[m][l], dzq, zero4()), a.h2[m]);
-            dh2b[0] = pair8(dh2[0], dh2[1]);
-            dh2b[1] = pair8(dh2[2], dh2[3]);
+            f4 dh2[4];
+            for (int m = 0; m < 4; ++m) dh2[m] = maskp(mfma16(F.c3t[m][l], dzq, zero4()), ph2[m]);
+            const bf8 dh2b0 = pair8(dh2[0], dh2[1]), dh2b1 = pair8(dh2[2], dh2[3]);
+            for (int m = 0; m < 4; ++m) stage4(tw[TH2 + m], g, c, dh2[m]);   // over h2
+            {   // second colour layer: dh2 x h1
+                s4 hq[4];
+                for (int ti = 0; ti < 4; ++ti) hq[ti] = unstage(tw[TH1 + ti], c, g);
+                for (int mo = 0; mo < 4; ++mo) {
+                    const s4 gq = unstage(tw[TH2 + mo], c, g);
+                    for (int ti = 0; ti < 4; ++ti) acc.c2[mo][ti] = mfma16(gq, hq[ti], acc.c2[mo][ti]);
+                }
+            }
             for (int m = 0; m < 4; ++m) {
-                f4 t = mfma32(F.c2t[m][0][l], dh2b[0], zero4());
-                dh1[m] = mask4(mfma32(F.c2t[m][1][l], dh2b[1], t), a.h1[m]);
+                f4 t = mfma32(F.c2t[m][0][l], dh2b0, zero4());
+                dh1[m] = maskp(mfma32(F.c2t[m][1][l], dh2b1, t), ph1[m]);
             }
         } else {
-            for (int m = 0; m < 4; ++m) dh1[m] = mask4(mfma16(F.c3t[m][l], dzq, zero4()), a.h1[m]);
+            for (int m = 0; m < 4; ++m) dh1[m] = maskp(mfma16(F.c3t[m][l], dzq, zero4()), ph1[m]);
         }
-        dh1b[0] = pair8(dh1[0], dh1[1]);
-        dh1b[1] = pair8(dh1[2], dh1[3]);
-        f4 dO = mfma32(F.c1t[0][l], dh1b[0], zero4());
-        dO = mfma32(F.c1t[1][l], dh1b[1], dO);
+        const bf8 dh1b0 = pair8(dh1[0], dh1[1]), dh1b1 = pair8(dh1[2], dh1[3]);
+        for (int m = 0; m < 4; ++m) stage4(tw[TH1 + m], g, c, dh1[m]);   // over h1
+        {   // first colour layer: dh1 x [o, sh]
+            const s4 c0 = unstage(tw[TCI], c, g), c1v = unstage(tw[TCI + 1], c, g);
+            for (int mo = 0; mo < 4; ++mo) {
+                const s4 gq = unstage(tw[TH1 + mo], c, g);
+                acc.c1[mo][0] = mfma16(gq, c0, acc.c1[mo][0]);
+                acc.c1[mo][1] = mfma16(gq, c1v, acc.c1[mo][1]);
+            }
+        }
+        f4 dO = mfma32(F.c1t[0][l], dh1b0, zero4());
+        dO = mfma32(F.c1t[1][l], dh1b1, dO);
         if (g == 0 && fabsf(a.o[0]) < kSigmaClamp) dO[0] += ds * expf(a.o[0]);
         const s4 dOq = quad(dO);
+        stage4(tw[TCI], g, c, dO);   // over [o, sh]
+        {   // density output layer: dO x hd
+            const s4 gq = unstage(tw[TCI], c, g);
+            for (int ti = 0; ti < 4; ++ti) acc.d2[ti] = mfma16(gq, unstage(tw[THD + ti], c, g), acc.d2[ti]);
+        }
         f4 dhd[4];
-        for (int m = 0; m < 4; ++m) dhd[m] = mask4(mfma16(F.d2t[m][l], dOq, zero4()), a.hd[m]);
+        for (int m = 0; m < 4; ++m) dhd[m] = maskp(mfma16(F.d2t[m][l], dOq, zero4()), phd[m]);
         const bf8 dhdb0 = pair8(dhd[0], dhd[1]), dhdb1 = pair8(dhd[2], dhd[3]);
+        for (int m = 0; m < 4; ++m) stage4(tw[THD + m], g, c, dhd[m]);   // over hd
+        {   // density hidden layer: dhd x features
+            const s4 x0 = unstage(tw[TX], c, g), x1 = unstage(tw[TX + 1], c, g);
+            for (int mo = 0; mo < 4; ++mo) {
+                const s4 gq = unstage(tw[THD + mo], c, g);
+                acc.d1[mo][0] = mfma16(gq, x0, acc.d1[mo][0]);
+                acc.d1[mo][1] = mfma16(gq, x1, acc.d1[mo][1]);
+            }
+        }
         if (dfeat != nullptr) {
             for (int m = 0; m < 2; ++m) {
                 f4 df = mfma32(F.d1t[m][0][l], dhdb0, zero4());
@@ -482,49 +554,6 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
                     }
                 }
             }
-        }
-        // gradients of this block -> staging tiles
-        stage4(tw[TDZ], g, c, dz);
-        stage4(tw[TDO], g, c, dO);
-        for (int m = 0; m < 4; ++m) {
-            stage4(tw[TDHD + m], g, c, dhd[m]);
-            stage4(tw[TDH1 + m], g, c, dh1[m]);
-            if (NCH == 2) stage4(tw[TDH2 + m], g, c, dh2[m]);
-        }
-        // ------------------------------------------------ weight gradients (K = 16 samples)
-        // a wave's LDS operations complete in order, so its reads see its writes
-        {
-            const s4 x0 = unstage(tw[TX], c, g), x1 = unstage(tw[TX + 1], c, g);
-            for (int mo = 0; mo < 4; ++mo) {
-                const s4 gq = unstage(tw[TDHD + mo], c, g);
-                acc.d1[mo][0] = mfma16(gq, x0, acc.d1[mo][0]);
-                acc.d1[mo][1] = mfma16(gq, x1, acc.d1[mo][1]);
-            }
-        }
-        {
-            const s4 gq = unstage(tw[TDO], c, g);
-            for (int ti = 0; ti < 4; ++ti) acc.d2[ti] = mfma16(gq, unstage(tw[THD + ti], c, g), acc.d2[ti]);
-        }
-        {
-            const s4 c0 = unstage(tw[TCI], c, g), c1v = unstage(tw[TCI + 1], c, g);
-            for (int mo = 0; mo < 4; ++mo) {
-                const s4 gq = unstage(tw[TDH1 + mo], c, g);
-                acc.c1[mo][0] = mfma16(gq, c0, acc.c1[mo][0]);
-                acc.c1[mo][1] = mfma16(gq, c1v, acc.c1[mo][1]);
-            }
-        }
-        if (NCH == 2) {
-            s4 hq[4];
-            for (int ti = 0; ti < 4; ++ti) hq[ti] = unstage(tw[TH1 + ti], c, g);
-            for (int mo = 0; mo < 4; ++mo) {
-                const s4 gq = unstage(tw[TDH2 + mo], c, g);
-                for (int ti = 0; ti < 4; ++ti) acc.c2[mo][ti] = mfma16(gq, hq[ti], acc.c2[mo][ti]);
-            }
-        }
-        {
-            const s4 gq = unstage(tw[TDZ], c, g);
-            const int th = NCH == 2 ? TH2 : TH1;
-            for (int ti = 0; ti < 4; ++ti) acc.c3[ti] = mfma16(gq, unstage(tw[th + ti], c, g), acc.c3[ti]);
         }
     }
     // ---------------------------------------------------- workgroup reduction
