@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--rays", type=int, default=1 << 18)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-render", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=8192)
+    ap.add_argument("--cpu-rays", type=int, default=32768)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -383,7 +383,21 @@ def cpu_baseline(n_rays):
     log(f"[bench] oracle step on {n_rays} rays: {dt:.2f} s")
     return {"value": n_rays / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
             "sample": f"one FP64 training step (fwd+bwd+Adam) over {n_rays} rays of the same "
-                      f"workload (full-size tables and networks), single thread"}
+                      f"workload (full-size tables and networks), single thread, "
+                      f"{dt:.1f} s",
+            "host": {"cpu": host_cpu(), "nproc": os.cpu_count(), "blas_threads": 1}}
+
+
+def host_cpu():
+    """CPU model name of this host (from /proc/cpuinfo), or the platform string."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
 if __name__ == "__main__":
