@@ -588,12 +588,26 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
     for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = red[i];
 }
 
-__global__ void reduce_partials(int nblocks, int np, const float *__restrict__ partial,
-                                float *__restrict__ dparams) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
-        float acc = 0.f;
-        for (int b = 0; b < nblocks; ++b) acc += partial[(int64_t)b * np + i];
-        dparams[i] += acc;
+// dparams[i] += sum over workgroups b of partial[b][i]: 64 parameters per
+// workgroup, the 16 rows of threads each summing every 16th partial
+// (coalesced along i), then the rows are added in LDS.
+constexpr int kRedCols = 64, kRedRows = 16;
+__global__ void __launch_bounds__(kRedCols * kRedRows)
+reduce_partials(int nblocks, int np, const float *__restrict__ partial,
+                float *__restrict__ dparams) {
+    __shared__ float part[kRedRows][kRedCols];
+    const int col = threadIdx.x % kRedCols, row = threadIdx.x / kRedCols;
+    const int i = blockIdx.x * kRedCols + col;
+    float acc = 0.f;
+    if (i < np)
+        for (int b = row; b < nblocks; b += kRedRows) acc += partial[(int64_t)b * np + i];
+    part[row][col] = acc;
+    __syncthreads();
+    if (row == 0 && i < np) {
+        float t = 0.f;
+#pragma unroll
+        for (int r = 0; r < kRedRows; ++r) t += part[r][col];
+        dparams[i] += t;
     }
 }
 
@@ -685,7 +699,8 @@ nvr_status mfma_backward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int6
 #undef NVR_BWD
     NVR_LAUNCHED();
     if (dparams == nullptr) return NVR_OK;
-    reduce_partials<<<grid_for(m.n_params, 256, 64), 256, 0, st>>>((int)gr, (int)m.n_params, partial,
+    reduce_partials<<<(unsigned)((m.n_params + kRedCols - 1) / kRedCols), kRedCols * kRedRows, 0, st>>>(
+        (int)gr, (int)m.n_params, partial,
                                                                    dparams);
     NVR_LAUNCHED();
     return NVR_OK;
