@@ -6,8 +6,11 @@
 //                      block totals;
 //   2. scan_blocks  -- one workgroup scans the block totals, writes the total
 //                      sample count to n_dev and off[R];
-//   3. march_write  -- one thread per ray: walk again and write t, dt, x and
-//                      the ray id at its global offset (capacity-bounded).
+//   3. march_write  -- a group of 16 lanes per ray walks again, 16 steps at a
+//                      time, and writes t, dt, x and the ray id of the kept
+//                      samples at the ray's global offset (capacity-bounded);
+//                      the kept samples of a 16-step chunk are numbered by a
+//                      group ballot, so they are stored as one contiguous run.
 // The walk's integer decisions use IEEE float32 with one rounding per
 // operation (floating-point contraction is switched off in those functions,
 // so no multiply-add is fused), in the order fixed by the documented reading.
@@ -144,31 +147,59 @@ scan_blocks(int64_t nb, int32_t *__restrict__ block_sums, int64_t n_rays, int64_
     }
 }
 
+constexpr int kRayGroup = 16;   // lanes per ray in march_write
+
 __global__ void __launch_bounds__(kMarchBlock)
 march_write(MarchParams p, int64_t n_rays, const float *__restrict__ o,
             const float *__restrict__ d, const uint32_t *__restrict__ occ,
             const int32_t *__restrict__ block_sums, int64_t capacity, int32_t *__restrict__ off,
             int32_t *__restrict__ ray_id, float *__restrict__ t_out, float *__restrict__ dt_out,
             float *__restrict__ x_out) {
-    const int64_t r = blockIdx.x * (int64_t)kMarchBlock + threadIdx.x;
-    if (r >= n_rays) return;
-    const int64_t base = (int64_t)off[r] + block_sums[blockIdx.x];
-    off[r] = (int32_t)(base < capacity ? base : capacity);
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x % kRayGroup;
+    const int64_t r = (blockIdx.x * (int64_t)kMarchBlock + threadIdx.x) / kRayGroup;
+    if (r >= n_rays) return;                       // the same for the whole group
+    // every lane of the group reads off[r] before lane 0 rewrites it (one
+    // wavefront, program order)
+    const int64_t base = (int64_t)off[r] + block_sums[r / kMarchBlock];
+    if (lane == 0) off[r] = (int32_t)(base < capacity ? base : capacity);
     if (r < p.begin || r >= p.end) return;
-    float oo[3] = {o[3 * r], o[3 * r + 1], o[3 * r + 2]};
-    float dd[3] = {d[3 * r], d[3 * r + 1], d[3 * r + 2]};
-    const float step = p.step;
-    walk(p, occ, oo, dd, [&](int k, float t, const float *x) {
-        const int64_t j = base + k;
-        if (j < capacity) {
-            ray_id[j] = (int32_t)r;
-            t_out[j] = t;
-            dt_out[j] = step;
-            x_out[3 * j] = x[0];
-            x_out[3 * j + 1] = x[1];
-            x_out[3 * j + 2] = x[2];
+    const float oo[3] = {o[3 * r], o[3 * r + 1], o[3 * r + 2]};
+    const float dd[3] = {d[3 * r], d[3 * r + 1], d[3 * r + 2]};
+    const RaySeg sg = clip_ray(p, oo, dd);
+    if (!(sg.tf > sg.tn)) return;
+    const int first = (threadIdx.x % 64) & ~(kRayGroup - 1);   // group's first lane in the wave
+    int64_t kept = 0;
+    for (int i0 = 0; i0 < p.max_steps; i0 += kRayGroup) {
+        // step i = i0 + lane, with the same arithmetic as the sequential walk
+        const int i = i0 + lane;
+        bool live = false, keep = false;
+        float t = 0.f, x[3] = {0.f, 0.f, 0.f};
+        if (i < p.max_steps) {
+            t = sg.tn + ((float)i + 0.5f) * p.step;
+            if (t < sg.tf) {
+                live = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) x[a] = oo[a] + t * dd[a];
+                keep = occupied(p, occ, x);
+            }
         }
-    });
+        const uint32_t gk = (uint32_t)(__ballot(keep) >> first) & 0xffffu;
+        const uint32_t gl = (uint32_t)(__ballot(live) >> first) & 0xffffu;
+        if (keep) {
+            const int64_t j = base + kept + __popc(gk & ((1u << lane) - 1u));
+            if (j < capacity) {
+                ray_id[j] = (int32_t)r;
+                t_out[j] = t;
+                dt_out[j] = p.step;
+                x_out[3 * j] = x[0];
+                x_out[3 * j + 1] = x[1];
+                x_out[3 * j + 2] = x[2];
+            }
+        }
+        kept += __popc(gk);
+        if (gl != 0xffffu) break;                  // the walk ended inside this chunk
+    }
 }
 
 nvr_status make_march_params(const nvr_march_desc *m, int64_t begin, int64_t end,
@@ -209,7 +240,8 @@ nvr_status launch_march(const MarchParams &p, int64_t n_rays, const float *o, co
     scan_blocks<<<1, 1024, 0, st>>>(nb, block_sums, n_rays, capacity, off, n_dev);
     NVR_LAUNCHED();
     if (nb > 0) {
-        march_write<<<(unsigned)nb, kMarchBlock, 0, st>>>(p, n_rays, o, d, occ, block_sums,
+        const int64_t nw = (n_rays * kRayGroup + kMarchBlock - 1) / kMarchBlock;
+        march_write<<<(unsigned)nw, kMarchBlock, 0, st>>>(p, n_rays, o, d, occ, block_sums,
                                                           capacity, off, ray_id, t, dt, x);
         NVR_LAUNCHED();
     }
