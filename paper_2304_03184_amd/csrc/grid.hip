@@ -310,7 +310,7 @@ nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_de
             encode_fwd_plain<f16_t><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x, (const float2 *)table,
                                                         (f16_t *)feat);
     } else {
-        unsigned chunks = grid_for(cap, 256, chunks_cap > 0 ? chunks_cap : 1024);
+        unsigned chunks = grid_for(cap, 256, chunks_cap > 0 ? chunks_cap : 2048);
         unsigned gr = chunks * kXcds;
         const uint32_t *tb = (const uint32_t *)table;
         const TileCounter none{nullptr, 0, 0};

@@ -651,7 +651,9 @@ nvr_status mfma_forward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64
                         const int32_t *ray_id, const void *params, bool f16, float *sigma,
                         float *rgb, hipStream_t st, int blocks = 0) {
     if (cap <= 0) return NVR_OK;
-    const unsigned gr = blocks > 0 ? (unsigned)blocks : mfma_blocks(cap);
+    // the forward keeps no per-workgroup partials: by default one 16-sample block
+    // per wave, at most 2048 workgroups (the tuned shape at millions of samples)
+    const unsigned gr = blocks > 0 ? (unsigned)blocks : grid_for((cap + 15) / 16, 4, 2048);
 #define NVR_FWD(NCH, PL, FT)                                                                   \
     mlp_fwd_mfma<NCH, PL, FT><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id, \
                                                          params, sigma, rgb)
