@@ -48,13 +48,20 @@ size_t mfma_ws_bytes(const Net &net, int64_t cap);
 // reduction of the per-workgroup weight-gradient partials.
 // f16: fp16 forward (feat fp16, params the fp32 masters); otherwise bf16
 // forward (feat bf16, params the bf16 copy).  Backward products are bf16.
+// sh_rays: the per-ray SH coefficients of launch_sh_rays for the same rays as
+// dirs (ray_id indexes both), or nullptr to evaluate them per sample.
 nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
                     const void *params, bool f16, float *sigma, float *rgb, hipStream_t st,
-                    int blocks = 0);
+                    int blocks = 0, const float *sh_rays = nullptr);
 nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
                     const void *params, bool f16, const float *dsigma, const float *drgb,
-                    float *dparams, float *dfeat, void *ws, hipStream_t st, int blocks = 0);
+                    float *dparams, float *dfeat, void *ws, hipStream_t st, int blocks = 0,
+                    const float *sh_rays = nullptr);
+// out[n_rays][16] = SH coefficients of each ray's direction (0 past the
+// network's coefficient count), 16-byte aligned.
+nvr_status launch_sh_rays(const Net &net, int64_t n_rays, const float *dirs, float *out,
+                          hipStream_t st);
 
 }  // namespace nvr

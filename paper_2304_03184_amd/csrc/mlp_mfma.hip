@@ -179,6 +179,7 @@ struct MfmaNet {
     int n_in, nsh, nch;
     int64_t off_d1, off_d2, off_c1, off_c2, off_c3;
     int64_t n_params;
+    const float *sh;   // per-ray SH coefficients [rays][16] (zero past nsh), or nullptr
 };
 
 // Builds the LDS weight fragments from the flat parameters: fp32 masters for
@@ -307,23 +308,33 @@ struct FwdA {
     f4 sh4;    // SH coefficients 4g..4g+3 of this lane's sample
 };
 
+// SH coefficients 4g..4g+3 of a sample's ray: from the per-ray table when
+// there is one, else evaluated from the direction
+template <bool SHT>
+__device__ __forceinline__ f4 sh4_lane(const MfmaNet &net, int64_t r, const float *dirs, int g) {
+    if (SHT) return *reinterpret_cast<const f4 *>(net.sh + 16 * r + 4 * g);
+    const int nsh = net.nsh;
+    float sh[16];
+    for (int k = 0; k < 16; ++k) sh[k] = 0.f;
+    sh_eval(dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2],
+            nsh == 1 ? 1 : (nsh == 4 ? 2 : (nsh == 9 ? 3 : 4)), sh);
+    f4 v;
+    for (int j = 0; j < 4; ++j) {
+        const int k = 4 * g + j;
+        v[j] = k < nsh ? pick16(sh, k) : 0.f;
+    }
+    return v;
+}
+
 template <int NCH, typename FT>
 __device__ __forceinline__ void forward_a(const Frags<FT> &F, int l, int g,
-                                         typename Vec8<FT>::type xf, const float *dir, int nsh,
+                                         typename Vec8<FT>::type xf, f4 s4v,
                                          FwdA<NCH, FT> &a) {
     for (int m = 0; m < 4; ++m) a.hd[m] = relu4(mfma32(F.d1[m][l], xf, zero4()));
     a.hdb[0] = packf<FT>(a.hd[0], a.hd[1]);
     a.hdb[1] = packf<FT>(a.hd[2], a.hd[3]);
     a.o = mfma32(F.d2[0][l], a.hdb[0], zero4());
     a.o = mfma32(F.d2[1][l], a.hdb[1], a.o);
-    float sh[16];
-    for (int k = 0; k < 16; ++k) sh[k] = 0.f;
-    sh_eval(dir[0], dir[1], dir[2], nsh == 1 ? 1 : (nsh == 4 ? 2 : (nsh == 9 ? 3 : 4)), sh);
-    f4 s4v;
-    for (int j = 0; j < 4; ++j) {
-        const int k = 4 * g + j;
-        s4v[j] = k < nsh ? pick16(sh, k) : 0.f;
-    }
     a.sh4 = s4v;
     a.cin = packf<FT>(a.o, s4v);
     for (int m = 0; m < 4; ++m) a.h1[m] = relu4(mfma32(F.c1[m][l], a.cin, zero4()));
@@ -349,7 +360,8 @@ __device__ __forceinline__ float clamp_sigma(float o) {
     return fminf(fmaxf(o, -kSigmaClamp), kSigmaClamp);
 }
 
-template <int NCH, bool PLANAR, typename FT>
+// SHT: the colour network's SH inputs come from the per-ray table net.sh
+template <int NCH, bool PLANAR, typename FT, bool SHT>
 __global__ void __launch_bounds__(kMfmaBlock)
 mlp_fwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const uint16_t *__restrict__ feat, const float *__restrict__ dirs,
@@ -366,15 +378,10 @@ mlp_fwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
         const int64_t s = cb * 16 + c;
         const bool valid = s < count;
         const typename Vec8<FT>::type xf = load_feat_a<PLANAR, FT>(feat, s, cap, net.n_in, g, valid);
-        float dir[3] = {0.f, 0.f, 1.f};
-        if (valid) {
-            const int64_t r = ray_id ? ray_id[s] : s;
-            dir[0] = dirs[3 * r];
-            dir[1] = dirs[3 * r + 1];
-            dir[2] = dirs[3 * r + 2];
-        }
+        f4 s4v = zero4();
+        if (valid) s4v = sh4_lane<SHT>(net, ray_id ? ray_id[s] : s, dirs, g);
         FwdA<NCH, FT> a;
-        forward_a<NCH, FT>(F, l, g, xf, dir, net.nsh, a);
+        forward_a<NCH, FT>(F, l, g, xf, s4v, a);
         if (valid && g == 0) {
             sigma[s] = expf(clamp_sigma(a.o[0]));
             rgb[3 * s] = sigmoidf_(a.z[0]);
@@ -397,7 +404,7 @@ struct DW {
 
 // two waves per SIMD: at most 256 registers per lane (weight-gradient
 // accumulators take 160 of them) and 72 KiB of LDS per workgroup
-template <int NCH, bool PLANAR, typename FT>
+template <int NCH, bool PLANAR, typename FT, bool SHT>
 __global__ void __launch_bounds__(kMfmaBlock) __attribute__((amdgpu_waves_per_eu(2)))
 mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
              const uint16_t *__restrict__ feat, const float *__restrict__ dirs,
@@ -425,27 +432,23 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
         for (int b = 0; b < 4; ++b) acc.c2[a][b] = zero4();
     }
     const int nsh = net.nsh;
-    const int deg = nsh == 1 ? 1 : (nsh == 4 ? 2 : (nsh == 9 ? 3 : 4));
     for (int64_t cb = wave; cb * 16 < count; cb += nwaves) {
         const int64_t base = cb * 16;
         const int64_t s = base + c;
         const bool valid = s < count;
         // ------------------------------------------------ orientation A forward
         const typename Vec8<FT>::type xf = load_feat_a<PLANAR, FT>(feat, s, cap, net.n_in, g, valid);
-        float dir[3] = {0.f, 0.f, 1.f};
+        f4 s4v = zero4();
         float ds = 0.f, dr[3] = {0.f, 0.f, 0.f};
         if (valid) {
-            const int64_t r = ray_id ? ray_id[s] : s;
-            dir[0] = dirs[3 * r];
-            dir[1] = dirs[3 * r + 1];
-            dir[2] = dirs[3 * r + 2];
+            s4v = sh4_lane<SHT>(net, ray_id ? ray_id[s] : s, dirs, g);
             ds = dsigma[s];
             dr[0] = drgb[3 * s];
             dr[1] = drgb[3 * s + 1];
             dr[2] = drgb[3 * s + 2];
         }
         FwdA<NCH, FT> a;
-        forward_a<NCH, FT>(F, l, g, xf, dir, nsh, a);
+        forward_a<NCH, FT>(F, l, g, xf, s4v, a);
         // activations of this block -> staging tiles (features at their index);
         // from here on the hidden activations are only needed as ReLU masks,
         // which their bf16 bits serve
@@ -588,6 +591,25 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
     for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = red[i];
 }
 
+// Per-ray SH coefficients of the colour network's direction input: [n][16],
+// coefficients past nsh are 0.  The samples of a ray share its direction, so
+// the networks read these instead of evaluating the basis per sample.
+__global__ void __launch_bounds__(256)
+sh_rays_kernel(int64_t n, const float *__restrict__ dirs, int nsh, float *__restrict__ out) {
+    const int deg = nsh == 1 ? 1 : (nsh == 4 ? 2 : (nsh == 9 ? 3 : 4));
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        float sh[16];
+        for (int k = 0; k < 16; ++k) sh[k] = 0.f;
+        sh_eval(dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2], deg, sh);
+        f4 *o = reinterpret_cast<f4 *>(out + 16 * r);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            o[q] = f4{4 * q < nsh ? sh[4 * q] : 0.f, 4 * q + 1 < nsh ? sh[4 * q + 1] : 0.f,
+                      4 * q + 2 < nsh ? sh[4 * q + 2] : 0.f, 4 * q + 3 < nsh ? sh[4 * q + 3] : 0.f};
+    }
+}
+
 // dparams[i] += sum over workgroups b of partial[b][i]: 64 parameters per
 // workgroup, the 16 rows of threads each summing every 16th partial
 // (coalesced along i), then the rows are added in LDS.
@@ -630,6 +652,7 @@ nvr_status make_mfma_net(const Net &net, MfmaNet *m) {
     m->off_c2 = nch == 2 ? net.woff[3] : 0;
     m->off_c3 = net.woff[2 + nch];
     m->n_params = net.woff[net.n_layers];
+    m->sh = nullptr;
     NVR_REQUIRE(m->n_params * 4 <= (int64_t)sizeof(Frags<__bf16>), NVR_EUNSUPPORTED, "too many parameters");
     return NVR_OK;
 }
@@ -655,8 +678,14 @@ nvr_status mfma_forward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int64
     // per wave, at most 2048 workgroups (the tuned shape at millions of samples)
     const unsigned gr = blocks > 0 ? (unsigned)blocks : grid_for((cap + 15) / 16, 4, 2048);
 #define NVR_FWD(NCH, PL, FT)                                                                   \
-    mlp_fwd_mfma<NCH, PL, FT><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id, \
-                                                         params, sigma, rgb)
+    do {                                                                                       \
+        if (m.sh)                                                                              \
+            mlp_fwd_mfma<NCH, PL, FT, true><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, \
+                dirs, ray_id, params, sigma, rgb);                                             \
+        else                                                                                   \
+            mlp_fwd_mfma<NCH, PL, FT, false><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat,\
+                dirs, ray_id, params, sigma, rgb);                                             \
+    } while (0)
 #define NVR_FWD_T(FT)                                                                          \
     if (m.nch == 2) {                                                                          \
         if (planar) NVR_FWD(2, true, FT); else NVR_FWD(2, false, FT);                          \
@@ -684,8 +713,14 @@ nvr_status mfma_backward(const MfmaNet &m, int64_t n, const int32_t *n_dev, int6
     const unsigned gr = blocks > 0 && (unsigned)blocks < mfma_blocks(cap) ? (unsigned)blocks
                                                                           : mfma_blocks(cap);
 #define NVR_BWD(NCH, PL, FT)                                                                   \
-    mlp_bwd_mfma<NCH, PL, FT><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, dirs, ray_id, \
-                                                         params, dsigma, drgb, dfeat, partial)
+    do {                                                                                       \
+        if (m.sh)                                                                              \
+            mlp_bwd_mfma<NCH, PL, FT, true><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat, \
+                dirs, ray_id, params, dsigma, drgb, dfeat, partial);                           \
+        else                                                                                   \
+            mlp_bwd_mfma<NCH, PL, FT, false><<<gr, kMfmaBlock, 0, st>>>(m, n, n_dev, cap, feat,\
+                dirs, ray_id, params, dsigma, drgb, dfeat, partial);                           \
+    } while (0)
 #define NVR_BWD_T(FT)                                                                          \
     if (m.nch == 2) {                                                                          \
         if (planar) NVR_BWD(2, true, FT); else NVR_BWD(2, false, FT);                          \
@@ -725,12 +760,21 @@ size_t mfma_ws_bytes(const Net &net, int64_t cap) {
     return mfma_workspace(m, cap);
 }
 
+nvr_status launch_sh_rays(const Net &net, int64_t n_rays, const float *dirs, float *out,
+                          hipStream_t st) {
+    if (n_rays <= 0) return NVR_OK;
+    sh_rays_kernel<<<grid_for(n_rays, 256, 4096), 256, 0, st>>>(n_rays, dirs, net.n_sh, out);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
 nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
                     const void *params, bool f16, float *sigma, float *rgb, hipStream_t st,
-                    int blocks) {
+                    int blocks, const float *sh_rays) {
     MfmaNet m;
     NVR_TRY(make_mfma_net(net, &m));
+    m.sh = sh_rays;
     return mfma_forward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, f16, sigma, rgb, st,
                         blocks);
 }
@@ -738,9 +782,11 @@ nvr_status mfma_fwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap
 nvr_status mfma_bwd(const Net &net, int64_t n, const int32_t *n_dev, int64_t cap,
                     const uint16_t *feat, bool planar, const float *dirs, const int32_t *ray_id,
                     const void *params, bool f16, const float *dsigma, const float *drgb,
-                    float *dparams, float *dfeat, void *ws, hipStream_t st, int blocks) {
+                    float *dparams, float *dfeat, void *ws, hipStream_t st, int blocks,
+                    const float *sh_rays) {
     MfmaNet m;
     NVR_TRY(make_mfma_net(net, &m));
+    m.sh = sh_rays;
     return mfma_backward(m, n, n_dev, cap, feat, planar, dirs, ray_id, params, f16, dsigma, drgb,
                          dparams, dfeat, (float *)ws, st, blocks);
 }

@@ -26,6 +26,7 @@ struct FieldWs {
     float *dx;                      // [8][cap][3] (split) | [cap][3] (plain)
     void *mlp_ws;
     void *scatter_ws;               // binned table-gradient scatter (bf16 training)
+    float *sh;                      // bf16 path: per-ray SH coefficients [n_rays][16]
     // launch shapes of the BF16 step's kernels (0: built-in default), set by
     // the autotuner for this capacity
     int enc_chunks = 0, mlp_fwd_blocks = 0, mlp_bwd_blocks = 0, emit_chunks = 0, emit_block = 0;
@@ -101,7 +102,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     }
     const bool bf = precision == NVR_BF16;
     const int nin = net.n_in;
-    size_t sz[17] = {
+    size_t sz[18] = {
         sizeof(int32_t) * (size_t)(n_rays + 1),             // off
         sizeof(int32_t) * (size_t)cap,                      // ray_id
         sizeof(int32_t) * 4,                                // n_dev
@@ -119,6 +120,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         f->has_warp ? sizeof(float) * 3 * (bf ? kXcds : 1) * (size_t)cap : 0,  // dx
         mlp_bytes,                                                             // mlp
         scatter_bytes,                                                         // scatter
+        bf ? sizeof(float) * 16 * (size_t)n_rays : 0,                          // sh
     };
     size_t total = 0;
     for (size_t s : sz) total += up(s);
@@ -130,8 +132,8 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         return NVR_ENOMEM;
     }
     char *p = (char *)blk;
-    void *ptr[17];
-    for (int i = 0; i < 17; ++i) {
+    void *ptr[18];
+    for (int i = 0; i < 18; ++i) {
         ptr[i] = sz[i] ? p : nullptr;
         p += up(sz[i]);
     }
@@ -160,6 +162,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.dx = (float *)ptr[14];
     w.mlp_ws = ptr[15];
     w.scatter_ws = ptr[16];
+    w.sh = (float *)ptr[17];
     w.enc_chunks = w.mlp_fwd_blocks = w.mlp_bwd_blocks = w.emit_chunks = w.emit_block = 0;
     w.tuned = false;
     return NVR_OK;
@@ -190,8 +193,10 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
         // fp16 features and fp16 forward; the networks' backward products run in bf16
         NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat, NVR_F16,
                                   true, st, count ? &counter : nullptr, w.enc_chunks));
+        // the colour network's direction encoding, once per ray
+        NVR_TRY(launch_sh_rays(net, n_rays, d, w.sh, st));
         NVR_TRY(mfma_fwd(net, 0, w.n_dev, cap, (const uint16_t *)w.feat, true, d, w.ray_id,
-                         f->params, true, w.sigma, w.rgb, st, w.mlp_fwd_blocks));
+                         f->params, true, w.sigma, w.rgb, st, w.mlp_fwd_blocks, w.sh));
     } else {
         NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table, NVR_F32, w.feat, NVR_F32, false,
                                   st));
@@ -247,7 +252,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
         if (s->precision == NVR_BF16) {
             NVR_TRY(mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
                              f->params, true, w.dsigma, w.drgb, f->params_grad, w.dfeat, w.mlp_ws,
-                             st, w.mlp_bwd_blocks));
+                             st, w.mlp_bwd_blocks, w.sh));
             NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
                                    f->has_warp ? w.dx : nullptr, w.scatter_ws, st,
                                    /*counted=*/true, w.emit_chunks, w.emit_block));
@@ -379,7 +384,7 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         }));
         NVR_TRY(pick(st, mlp_f, 4, &w.mlp_fwd_blocks, [&](int c) {
             return mfma_fwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d,
-                            w.ray_id, f->params, true, w.sigma, w.rgb, st, c);
+                            w.ray_id, f->params, true, w.sigma, w.rgb, st, c, w.sh);
         }));
     }
     const nvr_samples sa = samples_of(ctx->ws[0]);
@@ -400,7 +405,8 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         const GridParams gp = make_grid_params(&f->grid);
         NVR_TRY(pick(st, mlp_b, 3, &w.mlp_bwd_blocks, [&](int c) {
             return mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
-                            f->params, true, w.dsigma, w.drgb, nullptr, w.dfeat, w.mlp_ws, st, c);
+                            f->params, true, w.dsigma, w.drgb, nullptr, w.dfeat, w.mlp_ws, st, c,
+                            w.sh);
         }));
         int e = 0;
         NVR_TRY(pick(st, emit, 6, &e, [&](int c) {
