@@ -37,6 +37,8 @@
 #include "grid_dev.hpp"
 #include "scatter_dev.hpp"
 
+#include <atomic>
+
 namespace nvr {
 
 constexpr int kMinTileBits = 10;   // 8 KiB of float2 sums + 1 KiB of tags per wave
@@ -584,8 +586,12 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
             scatter_emit<LP, kEmitBlock><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n, n_dev,   \
                 cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts); \
     } while (0)
-    static bool emit_lds_ok = false;   // opt in to more than 64 KiB of dynamic LDS
-    if (!emit_lds_ok) {
+    // opt in to more than 64 KiB of dynamic LDS, once per device
+    int dev = 0;
+    NVR_HIP(hipGetDevice(&dev));
+    static std::atomic<uint64_t> emit_lds_ok{0}, accum_lds_ok{0};
+    const uint64_t dev_bit = 1ull << (dev & 63);
+    if (!(emit_lds_ok.load() & dev_bit)) {
         const int most = (int)emit_lds_bytes(kEmitBlock, kMaxLevelTiles);
         const void *fns[] = {(const void *)scatter_emit<1, kEmitBlock>,
                              (const void *)scatter_emit<2, kEmitBlock>,
@@ -595,7 +601,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
                              (const void *)scatter_emit<3, 512>, (const void *)scatter_emit<4, 512>};
         for (const void *f : fns)
             NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, most));
-        emit_lds_ok = true;
+        emit_lds_ok.fetch_or(dev_bit);
     }
     switch (lpg) {
     case 1: NVR_EMIT(1); break;
@@ -609,14 +615,11 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     const int64_t max_items = max_items_of(cap, p.L, nt);
     const unsigned ga = (unsigned)(max_items < 65535 ? max_items : 65535);
     const size_t acc_lds = accum_lds_bytes(tb);
-    if (acc_lds > 65536) {   // opt in to more than 64 KiB of dynamic LDS
-        static bool lds_ok = false;
-        if (!lds_ok) {
-            NVR_HIP(hipFuncSetAttribute((const void *)scatter_accum,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)accum_lds_bytes(kMaxTileBits)));
-            lds_ok = true;
-        }
+    if (acc_lds > 65536 && !(accum_lds_ok.load() & dev_bit)) {
+        NVR_HIP(hipFuncSetAttribute((const void *)scatter_accum,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)accum_lds_bytes(kMaxTileBits)));
+        accum_lds_ok.fetch_or(dev_bit);
     }
     scatter_accum<<<ga, 64, acc_lds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
                                            w.rec, (float2 *)dtable, w.partial);
