@@ -420,6 +420,33 @@ nvr_status nvr_render(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fi
                       float *rgb, float *depth, nvr_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Occupancy-grid upkeep.  The fields' back-end (Instant-NGP's, Sec. 4.3)
+ * keeps the marcher's bitfield current from a decayed density grid; the paper
+ * states none of its steps, and the reading is Instant-NGP's published grid at
+ * one scale.  One update, all on `stream`:
+ *   grid <- decay * grid (every cell; decay in [0, 1], 0.95 in that method);
+ *   grid[cells[i]] <- max(grid[cells[i]], sigma(points[i])) for i < m, sigma
+ *     being the field's density from the training step's encode and density
+ *     network (NVR_F32: fp32 table and kernels; NVR_BF16: fp16 table copy,
+ *     fp16 network forward from the fp32 masters); cells outside the grid are
+ *     ignored, repeated cells take the largest density;
+ *   *tau <- min(tau_max, mean(grid)) (tau_max = 0.01 * 1024 / sqrt(3) in that
+ *     method), the mean formed in float64 in a fixed order;
+ *   bits[c >> 5] bit (c & 31) <- grid[c] > *tau for c < res^3.
+ * The grid is field->march.occ_res cubed, indexed vx + res * (vy + res * vz)
+ * like the bitfield; its values must be finite and non-negative.  cells [m]
+ * int32, points [m][3] float32 world positions (each inside its cell; drawn
+ * by the caller), grid [res^3] float32, bits [ceil(res^3 / 32)] uint32, tau one
+ * float32: all device, caller-owned.  workspace: device, 256-byte aligned, of
+ * nvr_occupancy_workspace(f, precision, m) bytes.  Fields with a warp return
+ * NVR_EUNSUPPORTED (their occupancy lives in the live space). */
+size_t nvr_occupancy_workspace(const nvr_field *f, int32_t precision, int64_t m);
+nvr_status nvr_occupancy_update(const nvr_field *f, int32_t precision, int64_t m,
+                                const int32_t *cells, const float *points, float decay,
+                                float tau_max, float *grid, uint32_t *bits, float *tau,
+                                void *workspace, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
  * Measurement probe (not part of the method): the random-gather ceiling the
  * hash-grid gather of Sec. 4.3's back-end is measured against.  The table
  * (device, 16-byte aligned, `bytes` long) is split into eight equal slices;

@@ -94,6 +94,8 @@ _SIGS = {
     "nvr_encode_bwd_binned": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_encode_fwd_grouped": (i32, [P(GridDesc), i64, vp, vp, vp, vp]),
     "nvr_encode_bwd_binned_grouped": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
+    "nvr_occupancy_workspace": (C.c_size_t, [P(Field), i32, i64]),
+    "nvr_occupancy_update": (i32, [P(Field), i32, i64, vp, vp, f32, f32, vp, vp, vp, vp, vp]),
     "nvr_probe_gather": (i32, [vp, C.c_size_t, i64, i32, C.c_uint32, vp, vp]),
     "nvr_march_workspace": (C.c_size_t, [i64]),
     "nvr_march": (i32, [P(MarchDesc), i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp,

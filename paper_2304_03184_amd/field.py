@@ -69,6 +69,26 @@ class Field:
         return f
 
 
+def occupancy_update(field, precision, cells, points, grid, bits, decay=0.95,
+                     tau_max=0.01 * 1024 / 3 ** 0.5):
+    """One occupancy-grid update of `field` (a Field without warp): decays the
+    density grid, takes the maximum with the field's density at the probes
+    (cells [m] int32, points [m][3] float32), and rebuilds the bitfield
+    `bits` from tau = min(tau_max, mean).  Returns tau (a 1-element tensor)."""
+    m = int(cells.shape[0])
+    cf = field.c(0)
+    nb = L.lib().nvr_occupancy_workspace(C.byref(cf), precision, m)
+    if nb == 0:
+        call("nvr_occupancy_update", C.byref(cf), precision, m, None, None, 0.0, 0.0, None, None,
+             None, None, None)   # raises with the library's reason
+    ws = torch.empty(nb, dtype=torch.uint8, device=grid.device)
+    tau = torch.empty(1, dtype=torch.float32, device=grid.device)
+    p = lambda t: None if t is None or t.numel() == 0 else t.data_ptr()  # noqa: E731
+    call("nvr_occupancy_update", C.byref(cf), precision, m, p(cells), p(points), decay, tau_max,
+         grid.data_ptr(), bits.data_ptr(), tau.data_ptr(), ws.data_ptr(), ops._stream())
+    return tau
+
+
 class Trainer:
     """Owns an nvr context; runs training steps and renders."""
 
