@@ -120,6 +120,13 @@ def main():
     except Exception as e:  # measurement is reported as missing, never invented
         log(f"[bench] roofline measurement failed: {e}")
 
+    # ---------------------------------------------------------------- occupancy upkeep
+    occupancy = None
+    try:
+        occupancy = time_occupancy(L, F, torch, w, f, table, params)
+    except Exception as e:  # measurement is reported as missing, never invented
+        log(f"[bench] occupancy update measurement failed: {e}")
+
     # ---------------------------------------------------------------- render
     render = None
     if not args.no_render:
@@ -157,6 +164,7 @@ def main():
         "fp32_plain": {"rays_per_s": R / dt_32, "ms_per_step": dt_32 * 1e3,
                        "speedup_bf16_over_fp32": dt_32 / dt_bf, "loss": loss_32},
         "render": render,
+        "occupancy_update": occupancy,
         "roofline": roof,
         "step_roofline": step_roofline(f, R, n_samp, n_entries,
                                        sum(a * b for a, b in f.layer_shapes()), dt_bf),
@@ -329,6 +337,41 @@ def time_encode_kernels(O, L, torch, fld, w, f, o_d, d_d, occ, cap):
                                "loads_per_s": loads / t_probe,
                                "GBs_16B": loads * 16 / t_probe / 1e9,
                                "gather_frac_of_probe": t_probe / t_fwd}}}
+
+
+def time_occupancy(L, F, torch, w, f, table, params, m=1 << 19):
+    """One occupancy-grid update of the field (128^3 density grid, m probes at
+    random cells, BF16 path), timed with HIP events on the current stream."""
+    res = f.occ_res
+    n = res ** 3
+    rng = np.random.default_rng(31)
+    cells = rng.integers(0, n, size=m).astype(np.int32)
+    v = np.stack([cells % res, (cells // res) % res, cells // (res * res)], 1)
+    lo, hi = np.asarray(f.aabb_min, np.float64), np.asarray(f.aabb_max, np.float64)
+    pts = (lo + (v + rng.uniform(size=(m, 3))) * (hi - lo) / res).astype(np.float32)
+    fld = F.Field(w, f, table, params)
+    grid = torch.from_numpy(rng.uniform(0, 2, size=n).astype(np.float32)).cuda()
+    bits = torch.zeros((n + 31) // 32, dtype=torch.int32, device="cuda")
+    c_d, p_d = torch.from_numpy(cells).cuda(), torch.from_numpy(pts).cuda()
+    for _ in range(3):
+        F.occupancy_update(fld, L.NVR_BF16, c_d, p_d, grid, bits)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        F.occupancy_update(fld, L.NVR_BF16, c_d, p_d, grid, bits)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    # algorithmic bytes: the grid read and written once and the bitfield written
+    # (8 B + 1/8 B per cell); per probe its cell and position (16 B), the
+    # gather's 16 levels x 8 corners x 4 B and the grid update (8 B)
+    by = n * (8 + 1 / 8) + m * (16 + f.n_levels * 8 * 4 + 8)
+    log(f"[bench] occupancy update: {t * 1e3:.3f} ms ({m} probes, {n} cells)")
+    return {"cells": n, "probes": m, "precision": "bf16", "ms": t * 1e3,
+            "bytes_per_update": by, "achieved_GBs": by / t / 1e9,
+            "ms_per_step_if_every_16_steps": t * 1e3 / 16}
 
 
 def time_render(O, L, F, torch, w, f, table, params, occ, dev):
