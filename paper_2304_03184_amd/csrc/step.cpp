@@ -313,7 +313,7 @@ static nvr_status prepare(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const
 // ---------------------------------------------------------------- autotuner
 // Best of `reps` timed launches (after one untimed) on stream st.
 template <class F>
-static nvr_status time_best(hipStream_t st, F &&launch, float *best_ms, int reps = 3) {
+static nvr_status time_best(hipStream_t st, F &&launch, float *best_ms, int reps = 5) {
     hipEvent_t e0, e1;
     NVR_HIP(hipEventCreate(&e0));
     NVR_HIP(hipEventCreate(&e1));
@@ -334,7 +334,9 @@ static nvr_status time_best(hipStream_t st, F &&launch, float *best_ms, int reps
     return r;
 }
 
-// Picks the candidate of `cands` (n of them) with the shortest launch.
+// Picks the candidate of `cands` (n of them) with the shortest launch; a later
+// candidate must beat the one held by more than 1% (timing noise between
+// near-equal shapes would otherwise decide).
 template <class F>
 static nvr_status pick(hipStream_t st, const int *cands, int n, int *out, F &&launch_with) {
     float best = 1e30f;
@@ -342,7 +344,7 @@ static nvr_status pick(hipStream_t st, const int *cands, int n, int *out, F &&la
     for (int i = 0; i < n; ++i) {
         float ms = 0.f;
         NVR_TRY(time_best(st, [&] { return launch_with(cands[i]); }, &ms));
-        if (ms < best) {
+        if (ms < 0.99f * best) {
             best = ms;
             arg = cands[i];
         }
@@ -363,12 +365,17 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
                            const nvr_batch *b, const Net *nets, nvr_train_state *state,
                            float *loss, hipStream_t st) {
     NVR_TRY(enqueue_fwd(ctx, s, fields, b, nets, state, loss, nullptr, nullptr, st));
-    static const int enc[] = {256, 512, 1024, 2048};
-    static const int mlp_f[] = {256, 512, 1024, 2048};
-    static const int mlp_b[] = {128, 256, 512};
-    // emit: (samples per chunk, chunks per level group)
-    static const int emit[] = {1024 * 1000 + 32, 1024 * 1000 + 64, 1024 * 1000 + 128,
-                               512 * 1000 + 64, 512 * 1000 + 128, 512 * 1000 + 256};
+    // candidates in order of preference: the first is kept unless another is
+    // more than 1% faster (the first ones are best inside the whole step at
+    // millions of samples)
+    static const int enc[] = {2048, 1024, 512, 256};
+    static const int mlp_f[] = {2048, 1024, 512, 256};
+    static const int mlp_b[] = {512, 256, 128};
+    // emit: samples per chunk * kShape + chunks per level group
+    constexpr int kShape = 100000;
+    static const int emit[] = {512 * kShape + 512, 512 * kShape + 256, 512 * kShape + 1024,
+                               512 * kShape + 128, 512 * kShape + 64, 1024 * kShape + 128,
+                               1024 * kShape + 64, 1024 * kShape + 32};
     static const int comp[] = {4096, 16384, 65536};
     for (int k = 0; k < s->n_fields; ++k) {
         const nvr_field *f = fields[k];
@@ -409,12 +416,12 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
                             w.sh);
         }));
         int e = 0;
-        NVR_TRY(pick(st, emit, 6, &e, [&](int c) {
+        NVR_TRY(pick(st, emit, 8, &e, [&](int c) {
             return launch_scatter_emit_only(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
-                                            w.scatter_ws, st, c % 1000, c / 1000);
+                                            w.scatter_ws, st, c % kShape, c / kShape);
         }));
-        w.emit_chunks = e % 1000;
-        w.emit_block = e / 1000;
+        w.emit_chunks = e % kShape;
+        w.emit_block = e / kShape;
         w.tuned = true;
     }
     return NVR_OK;
