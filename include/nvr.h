@@ -402,7 +402,7 @@ nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const
 /* Launch shapes in use for `field` (0 or 1): shape[0] gather chunks per level
  * group, [1] network forward workgroups, [2] network backward workgroups,
  * [3] emit chunks per level group, [4] compositing workgroups, [5] 1 if
- * tuned, [6] emit samples per chunk (512 or 1024); 0 = built-in default.
+ * tuned, [6] emit samples per chunk (256, 512 or 1024); 0 = built-in default.
  * shape is a host array of 7. */
 nvr_status nvr_launch_shape(const nvr_ctx *ctx, int32_t field, int32_t *shape);
 

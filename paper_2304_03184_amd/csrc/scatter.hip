@@ -46,7 +46,7 @@ constexpr int kMaxTileBits = 14;
 constexpr int kMaxTiles = 8192;
 constexpr uint32_t kItemRecords = 1u << 17;
 constexpr int kBinBlock = 256;     // count
-constexpr int kEmitBlock = 1024;   // emit: samples per chunk (default; 512 also built)
+constexpr int kEmitBlock = 1024;   // emit: samples per chunk (default; 512 and 256 also built)
 constexpr int kMaxLpg = 4;   // levels per group (L <= 32)
 constexpr int kMaxLevelTiles = 2048;   // tiles one level may span
 // emit LDS: per-level tile counts / offsets and deltas (lt each), one partial
@@ -562,7 +562,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     ScatterWs w = carve_scatter(p, ws, cap);
     const uint32_t n_records = (uint32_t)((uint64_t)cap * p.L * 8 < 0xffffffffull
                                               ? (uint64_t)cap * p.L * 8 : 0xffffffffull);
-    const int eb = emit_block == 512 ? 512 : kEmitBlock;
+    const int eb = emit_block == 512 || emit_block == 256 ? emit_block : kEmitBlock;
     const unsigned gre = grid_for(cap, eb, emit_chunks > 0 ? emit_chunks : 64) * kXcds;
     const int lt = level_tiles(p, tb);
     const size_t elds = emit_lds_bytes(eb, lt);
@@ -582,6 +582,9 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
         if (eb == 512)                                                                         \
             scatter_emit<LP, 512><<<gre, 512, elds, st>>>(p, tb, lt, n, n_dev, cap, x,         \
                 (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts);         \
+        else if (eb == 256)                                                                    \
+            scatter_emit<LP, 256><<<gre, 256, elds, st>>>(p, tb, lt, n, n_dev, cap, x,         \
+                (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts);         \
         else                                                                                   \
             scatter_emit<LP, kEmitBlock><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n, n_dev,   \
                 cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts); \
@@ -598,7 +601,9 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
                              (const void *)scatter_emit<3, kEmitBlock>,
                              (const void *)scatter_emit<4, kEmitBlock>,
                              (const void *)scatter_emit<1, 512>, (const void *)scatter_emit<2, 512>,
-                             (const void *)scatter_emit<3, 512>, (const void *)scatter_emit<4, 512>};
+                             (const void *)scatter_emit<3, 512>, (const void *)scatter_emit<4, 512>,
+                             (const void *)scatter_emit<1, 256>, (const void *)scatter_emit<2, 256>,
+                             (const void *)scatter_emit<3, 256>, (const void *)scatter_emit<4, 256>};
         for (const void *f : fns)
             NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, most));
         emit_lds_ok.fetch_or(dev_bit);

@@ -373,9 +373,10 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
     static const int mlp_b[] = {512, 256, 128};
     // emit: samples per chunk * kShape + chunks per level group
     constexpr int kShape = 100000;
-    static const int emit[] = {512 * kShape + 512, 512 * kShape + 256, 512 * kShape + 1024,
+    static const int emit[] = {512 * kShape + 1024, 512 * kShape + 512, 512 * kShape + 256,
                                512 * kShape + 128, 512 * kShape + 64, 1024 * kShape + 128,
-                               1024 * kShape + 64, 1024 * kShape + 32};
+                               1024 * kShape + 64, 1024 * kShape + 32, 256 * kShape + 1024,
+                               256 * kShape + 2048};
     static const int comp[] = {4096, 16384, 65536};
     for (int k = 0; k < s->n_fields; ++k) {
         const nvr_field *f = fields[k];
@@ -416,7 +417,7 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
                             w.sh);
         }));
         int e = 0;
-        NVR_TRY(pick(st, emit, 8, &e, [&](int c) {
+        NVR_TRY(pick(st, emit, 10, &e, [&](int c) {
             return launch_scatter_emit_only(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                             w.scatter_ws, st, c % kShape, c / kShape);
         }));
