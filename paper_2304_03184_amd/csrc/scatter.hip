@@ -737,10 +737,10 @@ static nvr_status binned_public(const nvr_grid_desc *g, int64_t n, const float *
         NVR_LAUNCHED();
         planar = buf;
     }
-    // 512-sample emit chunks, 256 chunks per level group: the shape the step's
-    // tuner settles on for large sample counts
+    // 512-sample emit chunks, 1024 chunks per level group: the shape the step's
+    // tuner settles on for millions of samples
     NVR_TRY(launch_scatter(p, n, nullptr, n, x, table, planar, dtable, parts, workspace, st,
-                           /*counted=*/false, 256, 512));
+                           /*counted=*/false, 1024, 512));
     if (dx) {
         scatter_dx_sum<<<grid_for(3 * n, 256, 8192), 256, 0, st>>>(3 * n, parts, dx);
         NVR_LAUNCHED();
