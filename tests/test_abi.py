@@ -124,3 +124,59 @@ def test_invalid_arguments_rejected_before_launch(L):
     ad = L.AdamDesc(-1.0, 0.9, 0.99, 1e-15)
     assert lib.nvr_adam(C.byref(ad), 4, None, None, None, None, 0, C.c_void_p(8), None, 0,
                         None) == L.NVR_EINVAL
+
+
+def test_new_entry_points_reject_before_launch(L):
+    # host-side validation of the grouped-layout encode calls, the binned
+    # scatter's size limits, the random-gather probe and the occupancy upkeep:
+    # each returns its status before any device work (fake pointers are never
+    # touched)
+    lib = L.lib()
+    fake = C.c_void_p(4096)
+    lo = (C.c_float * 3)(-1, -1, -1)
+    hi = (C.c_float * 3)(1, 1, 1)
+    g = L.GridDesc()
+    L.call("nvr_grid_init", C.byref(g), 16, 2, 19, 16, 2048, lo, hi)
+    assert lib.nvr_encode_fwd_grouped(C.byref(g), 10, None, fake, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_encode_fwd_grouped(C.byref(g), -1, fake, fake, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_encode_fwd_grouped(C.byref(g), 0, None, None, None, None) == L.NVR_OK
+    assert lib.nvr_encode_bwd_binned_grouped(C.byref(g), 10, fake, fake, None, fake, None, fake,
+                                             None) == L.NVR_EINVAL
+    assert lib.nvr_encode_bwd_binned(C.byref(g), 10, fake, fake, fake, fake, None,
+                                     C.c_void_p(4096 + 8), None) == L.NVR_EINVAL   # workspace alignment
+    # 32 levels of 2^24 entries: more table tiles than the binned scatter holds
+    big = L.GridDesc()
+    L.call("nvr_grid_init", C.byref(big), 32, 2, 24, 16, 65536, lo, hi)
+    assert lib.nvr_encode_bwd_binned(C.byref(big), 10, fake, fake, fake, fake, None, fake,
+                                     None) == L.NVR_EUNSUPPORTED
+    assert b"8192 tiles" in lib.nvr_last_error()
+    assert lib.nvr_encode_bwd_binned_grouped(C.byref(big), 10, fake, fake, fake, fake, None,
+                                             fake, None) == L.NVR_EUNSUPPORTED
+    assert lib.nvr_encode_bwd_workspace(C.byref(g), -1) == 0
+    # random-gather probe: loads a multiple of 4, a table of at least 8 words
+    assert lib.nvr_probe_gather(fake, 4096, 10, 6, 1, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_probe_gather(fake, 64, 10, 8, 1, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_probe_gather(None, 4096, 10, 8, 1, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_probe_gather(None, 4096, 0, 8, 1, None, None) == L.NVR_OK
+    # occupancy upkeep: a warped field, no occupancy grid, bad decay / tau_max
+    import synth
+    from paper_2304_03184_amd import ops as O
+    w = synth.config(2)
+    fc = w.fields[0]
+    f = L.Field()
+    f.grid, f.mlp, f.march = O.grid_desc_of(fc), O.mlp_desc_of(fc), O.march_desc_of(w, fc)
+    f.table, f.params, f.table_half = fake, fake, fake
+    assert lib.nvr_occupancy_workspace(C.byref(f), L.NVR_F32, 100) > 0
+    args = (10, fake, fake, 0.95, 5.9, fake, fake, fake, fake, None)
+    assert lib.nvr_occupancy_update(C.byref(f), L.NVR_F32, 10, fake, fake, 1.5, 5.9, fake, fake,
+                                    fake, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_occupancy_update(C.byref(f), L.NVR_F32, 10, fake, fake, 0.95, 0.0, fake, fake,
+                                    fake, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_occupancy_update(C.byref(f), L.NVR_F32, 10, None, fake, 0.95, 5.9, fake, fake,
+                                    fake, fake, None) == L.NVR_EINVAL
+    f.has_warp = 1
+    assert lib.nvr_occupancy_update(C.byref(f), L.NVR_F32, *args) == L.NVR_EUNSUPPORTED
+    assert lib.nvr_occupancy_workspace(C.byref(f), L.NVR_F32, 100) == 0
+    f.has_warp = 0
+    f.march.occ_res = 0
+    assert lib.nvr_occupancy_update(C.byref(f), L.NVR_F32, *args) == L.NVR_EINVAL
