@@ -18,11 +18,18 @@
 // l%16, which is the operand layout of the weight-gradient contraction over
 // samples.  The backward computes every layer once in orientation A; each
 // wave stages its activation and gradient tiles (bf16, unit-major 16 x 16) in
-// its own 15 KiB of LDS and reads them back as "4 samples of one unit"
-// operands for dW = dY X^T (one 8-byte read per tile and lane).
+// its own LDS and reads them back as "4 samples of one unit" operands for
+// dW = dY X^T (one 8-byte read per tile and lane).  Each layer's dW is formed
+// as soon as its output gradient is staged, which then takes the place of the
+// activations just consumed: 17 tiles (8.5 KiB) per wave, so that with the
+// ReLU masks kept as the packed bf16 activations two waves share a SIMD.
+//
+// The colour network's SH inputs come from a per-ray table in the step and
+// the renderer (rays share their direction), else they are evaluated per
+// sample.
 //
 // Weight fragments (forward W and backward W^T, 38 KiB) are built in LDS once
-// per workgroup from the flat bf16 parameters; the per-wave weight gradients
+// per workgroup from the flat parameters; the per-wave weight gradients
 // stay in accumulation registers for the whole persistent loop, are summed
 // over the workgroup in LDS and written as one partial per workgroup, which a
 // final launch adds into dparams (no global atomics, deterministic order).
