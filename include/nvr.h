@@ -447,6 +447,39 @@ nvr_status nvr_occupancy_update(const nvr_field *f, int32_t precision, int64_t m
                                 void *workspace, nvr_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Live look-up table of the fast neighbour search (Sec. 4.2, "On-the-fly
+ * Radiance Fields").  A canonical KNN field lists the nearest graph nodes of
+ * every canonical voxel; per frame, each canonical voxel centre
+ * v_k = canon_min + (i + 1/2) (canon_max - canon_min) / canon_res per axis
+ * (k = ix + canon_res (iy + canon_res iz)) is carried to the live space by the
+ * node blend of Eq. 2, and the live voxel it lands in records k:
+ *   w_j = exp(-(|v_k - x_j|^2 - d_min^2) / r_ed^2) over the listed nodes
+ *     (d_min the nearest listed one: a common scale the normalised blend
+ *     ignores), sign-aligned to the first listed node's rotation part,
+ *   c = sum_j w_j dq_j / |real part|, v~ = R(c_r) v_k + 2 vec(c_d conj(c_r)),
+ *   live voxel floor((v~ - live_min) live_res / (live_max - live_min));
+ * points outside the live box are dropped, and a live voxel reached by several
+ * canonical voxels keeps the largest k, one reached by none holds -1.  The
+ * arithmetic is float32; the result does not depend on the launch order.
+ * knn [canon_res^3][k_nodes] uint16 node ids, nearest first (an id >= n_nodes,
+ * e.g. 0xFFFF, marks "none"; a voxel whose first id is none is not carried);
+ * node_canon [n_nodes][3] canonical node positions; node_dq [n_nodes][8] the
+ * frame's unit node dual quaternions (w, x, y, z real part, then dual part);
+ * lut [live_res^3] int32 output (overwritten): all device, caller-owned.
+ * Errors: NVR_EINVAL for resolutions outside 1..1024, k_nodes outside 1..8,
+ * n_nodes outside 1..65535, r_ed <= 0, an empty box, NULL or misaligned
+ * arrays. */
+typedef struct {
+    float canon_min[3], canon_max[3];
+    float live_min[3], live_max[3];
+    int32_t canon_res, live_res;
+    int32_t k_nodes, n_nodes;
+    float r_ed;                   /* node influence radius r (0.1 in Sec. 4.1) */
+} nvr_lut_desc;
+nvr_status nvr_live_lut(const nvr_lut_desc *d, const uint16_t *knn, const float *node_canon,
+                        const float *node_dq, int32_t *lut, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
  * Measurement probe (not part of the method): the random-gather ceiling the
  * hash-grid gather of Sec. 4.3's back-end is measured against.  The table
  * (device, 16-byte aligned, `bytes` long) is split into eight equal slices;

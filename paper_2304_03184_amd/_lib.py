@@ -47,6 +47,12 @@ class WarpRig(C.Structure):
     _fields_ = [("joints", vp), ("bones", vp), ("node_dq", vp), ("node_pos", vp), ("lut", vp)]
 
 
+class LutDesc(C.Structure):
+    _fields_ = [("canon_min", f32 * 3), ("canon_max", f32 * 3), ("live_min", f32 * 3),
+                ("live_max", f32 * 3), ("canon_res", i32), ("live_res", i32), ("k_nodes", i32),
+                ("n_nodes", i32), ("r_ed", f32)]
+
+
 class MlpDesc(C.Structure):
     _fields_ = [("n_in", i32), ("n_density_hidden", i32), ("density_hidden", i32 * 4),
                 ("density_out", i32), ("sh_degree", i32), ("n_colour_hidden", i32),
@@ -96,6 +102,7 @@ _SIGS = {
     "nvr_encode_bwd_binned_grouped": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_occupancy_workspace": (C.c_size_t, [P(Field), i32, i64]),
     "nvr_occupancy_update": (i32, [P(Field), i32, i64, vp, vp, f32, f32, vp, vp, vp, vp, vp]),
+    "nvr_live_lut": (i32, [P(LutDesc), vp, vp, vp, vp, vp]),
     "nvr_probe_gather": (i32, [vp, C.c_size_t, i64, i32, C.c_uint32, vp, vp]),
     "nvr_march_workspace": (C.c_size_t, [i64]),
     "nvr_march": (i32, [P(MarchDesc), i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp,

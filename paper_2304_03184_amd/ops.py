@@ -156,6 +156,25 @@ def encode_bwd_binned_grouped(g, x, table, dfeat, dtable, dx=None):
          _p(dtable), _p(dx), _p(ws), _stream())
 
 
+def live_lut(knn, node_canon, node_dq, canon_box, canon_res, live_box, live_res, r_ed=0.1):
+    """Live look-up table of the fast neighbour search (Sec. 4.2, Eq. 2): the
+    canonical voxel index per live voxel, -1 for holes.  knn [canon_res^3][K]
+    uint16 (int16 storage) node ids, node_canon [n][3], node_dq [n][8]; the boxes
+    are (min xyz, max xyz) pairs."""
+    assert knn.dtype == torch.int16 and knn.dim() == 2 and knn.shape[0] == canon_res ** 3
+    assert node_canon.dtype == torch.float32 and node_dq.dtype == torch.float32
+    assert node_canon.shape[0] == node_dq.shape[0]
+    d = L.LutDesc()
+    d.canon_min[:], d.canon_max[:] = canon_box[0], canon_box[1]
+    d.live_min[:], d.live_max[:] = live_box[0], live_box[1]
+    d.canon_res, d.live_res, d.k_nodes = canon_res, live_res, knn.shape[1]
+    d.n_nodes, d.r_ed = node_canon.shape[0], r_ed
+    knn, node_canon, node_dq = knn.contiguous(), node_canon.contiguous(), node_dq.contiguous()
+    lut = torch.empty(live_res ** 3, dtype=torch.int32, device=knn.device)
+    call("nvr_live_lut", C.byref(d), _p(knn), _p(node_canon), _p(node_dq), _p(lut), _stream())
+    return lut
+
+
 def probe_gather(table, n, loads, seed=1):
     """Random 16-byte gathers over `table`'s bytes split into eight slices
     (measurement probe, not part of the method); returns the [8][n] xors."""

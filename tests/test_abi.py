@@ -180,3 +180,20 @@ def test_new_entry_points_reject_before_launch(L):
     f.has_warp = 0
     f.march.occ_res = 0
     assert lib.nvr_occupancy_update(C.byref(f), L.NVR_F32, *args) == L.NVR_EINVAL
+    # live look-up table: resolutions, node counts, radius, boxes, pointers
+    d = L.LutDesc()
+    d.canon_min[:], d.canon_max[:] = (-1, -1, -1), (1, 1, 1)
+    d.live_min[:], d.live_max[:] = (-1, -1, -1), (1, 1, 1)
+    d.canon_res, d.live_res, d.k_nodes, d.n_nodes, d.r_ed = 16, 16, 4, 64, 0.1
+    for field, bad in (("canon_res", 0), ("live_res", 1025), ("k_nodes", 9), ("n_nodes", 0),
+                       ("n_nodes", 65536), ("r_ed", 0.0)):
+        old = getattr(d, field)
+        setattr(d, field, bad)
+        assert lib.nvr_live_lut(C.byref(d), fake, fake, fake, fake, None) == L.NVR_EINVAL
+        setattr(d, field, old)
+    d.live_max[1] = -1.0
+    assert lib.nvr_live_lut(C.byref(d), fake, fake, fake, fake, None) == L.NVR_EINVAL
+    d.live_max[1] = 1.0
+    assert lib.nvr_live_lut(C.byref(d), None, fake, fake, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_live_lut(C.byref(d), fake, fake, fake, C.c_void_p(4098), None) == L.NVR_EINVAL
+    assert lib.nvr_live_lut(None, fake, fake, fake, fake, None) == L.NVR_EINVAL
