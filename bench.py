@@ -130,7 +130,7 @@ def main():
     # ---------------------------------------------------------------- live look-up table
     live_lut = None
     try:
-        live_lut = time_live_lut(O, torch)
+        live_lut = [time_live_lut(O, torch), time_live_lut(O, torch, res=512, k=4)]
     except Exception as e:  # measurement is reported as missing, never invented
         log(f"[bench] live look-up table measurement failed: {e}")
 
@@ -382,26 +382,32 @@ def time_occupancy(L, F, torch, w, f, table, params, m=1 << 19):
             "ms_per_step_if_every_16_steps": t * 1e3 / 16}
 
 
-def time_live_lut(O, torch, res=128, k=8):
-    """Live look-up table of the human field's neighbour search at the rig's
-    size (res^3 canonical and live voxels, k of 1024 nodes listed per voxel),
-    timed with HIP events on the current stream."""
+def time_live_lut(O, torch, res=128, k=8, knn_res=128):
+    """Live look-up table of the human field's neighbour search: res^3 canonical
+    and live voxels, k of the rig's 1024 nodes listed per voxel, timed with HIP
+    events on the current stream.  The canonical KNN field is computed at
+    knn_res^3 (the k nodes nearest each voxel centre) and, for a finer res,
+    repeated over the res / knn_res finer voxels of each cell."""
     import synth
     from scipy.spatial import cKDTree
     rig = synth.human_rig(np.random.default_rng(33), knn_res=8)
     canon, dq = rig["node_canon"], rig["node_dq"][0]
-    g = (np.arange(res) + 0.5) / res * 2.0 - 1.0
+    g = (np.arange(knn_res) + 0.5) / knn_res * 2.0 - 1.0
     zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
     centres = np.stack([xx, yy, zz], -1).reshape(-1, 3)
     _, ids = cKDTree(canon.astype(np.float64)).query(centres, k=k)
     knn = torch.from_numpy(ids.astype(np.uint16).view(np.int16)).cuda()
+    if res != knn_res:
+        s = res // knn_res
+        knn = knn.view(knn_res, 1, knn_res, 1, knn_res, 1, k).expand(
+            knn_res, s, knn_res, s, knn_res, s, k).reshape(res ** 3, k)
     c_d, q_d = torch.from_numpy(canon).cuda(), torch.from_numpy(dq).cuda()
     box = ((-1.0,) * 3, (1.0,) * 3)
     for _ in range(3):
         lut = O.live_lut(knn, c_d, q_d, box, res, box, res)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    reps = 20
+    reps = 20 if res <= 128 else 5
     e0.record()
     for _ in range(reps):
         lut = O.live_lut(knn, c_d, q_d, box, res, box, res)
@@ -410,14 +416,15 @@ def time_live_lut(O, torch, res=128, k=8):
     t = e0.elapsed_time(e1) / reps * 1e-3
     n = res ** 3
     filled = float((lut >= 0).float().mean().item())
+    del knn, lut
     # algorithmic bytes: the KNN field read once (2 k B per canonical voxel), the
     # table filled and then updated once per carried voxel (8 B per voxel); the
     # node data (1024 x 44 B) stays in cache
     by = n * (2 * k + 8)
-    log(f"[bench] live look-up table {res}^3: {t * 1e6:.1f} us ({filled:.2f} filled)")
+    log(f"[bench] live look-up table {res}^3, {k} nodes: {t * 1e6:.1f} us ({filled:.2f} filled)")
     return {"canon_res": res, "live_res": res, "k_nodes": k, "n_nodes": len(canon),
-            "us": t * 1e6, "filled": filled, "bytes": by, "achieved_GBs": by / t / 1e9,
-            "voxels_per_s": n / t}
+            "knn_res": knn_res, "us": t * 1e6, "filled": filled, "bytes": by,
+            "achieved_GBs": by / t / 1e9, "voxels_per_s": n / t}
 
 
 def time_render(O, L, F, torch, w, f, table, params, occ, dev):

@@ -460,7 +460,10 @@ nvr_status nvr_occupancy_update(const nvr_field *f, int32_t precision, int64_t m
  *   live voxel floor((v~ - live_min) live_res / (live_max - live_min));
  * points outside the live box are dropped, and a live voxel reached by several
  * canonical voxels keeps the largest k, one reached by none holds -1.  The
- * arithmetic is float32; the result does not depend on the launch order.
+ * arithmetic is float32 (fused multiply-adds, the hardware exponential and
+ * reciprocal square root; the antipodal sign is taken without fusion), so a
+ * voxel whose live position lies within rounding distance of a live-voxel face
+ * may land on either side; the result does not depend on the launch order.
  * knn [canon_res^3][k_nodes] uint16 node ids, nearest first (an id >= n_nodes,
  * e.g. 0xFFFF, marks "none"; a voxel whose first id is none is not carried);
  * node_canon [n_nodes][3] canonical node positions; node_dq [n_nodes][8] the

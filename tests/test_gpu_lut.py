@@ -162,3 +162,49 @@ def test_live_lut_full_size_properties():
     u2 = olut.live_coords(live2, box[0], box[1], res)
     cell = np.stack([f2 % res, (f2 // res) % res, f2 // (res * res)], 1)
     assert (np.abs(u2 - (cell + 0.5)) <= 0.5 + TOL).all()
+
+
+@pytest.mark.parametrize("k", [8, 4])
+def test_live_lut_load_paths_agree(k):
+    # eight (four) ids per voxel in 16-byte-aligned arrays take the vector-load
+    # path; the same data 2 and 4 bytes off that alignment take the element-load
+    # path: the tables are identical
+    O = _ops()
+    node_canon, node_dq = _rig(7)
+    box = ((-1.0,) * 3, (1.0,) * 3)
+    res = 32
+    knn = _knn(node_canon, *box, res, k)
+    ids = knn.astype(np.uint16).view(np.int16)
+    a = O.live_lut(dev(ids), dev(node_canon), dev(node_dq), box, res, box, res)
+    kbuf = torch.zeros(ids.size + 1, dtype=torch.int16, device="cuda")
+    kbuf[1:] = dev(ids.reshape(-1))
+    qbuf = torch.zeros(node_dq.size + 1, dtype=torch.float32, device="cuda")
+    qbuf[1:] = dev(node_dq.reshape(-1))
+    b = O.live_lut(kbuf[1:].view(-1, k), dev(node_canon), qbuf[1:].view(-1, 8), box, res, box,
+                   res)
+    torch.cuda.synchronize()
+    assert kbuf[1:].data_ptr() % 16 != 0 and qbuf[1:].data_ptr() % 16 != 0
+    np.testing.assert_array_equal(host(a), host(b))
+
+
+def test_live_lut_large_node_set():
+    # 4000 nodes with random small motions (a node table of 176 KB, larger
+    # than one workgroup's local memory)
+    O = _ops()
+    from scipy.spatial.transform import Rotation
+    from oracle import warp as owarp
+    rng = np.random.default_rng(8)
+    m = 4000
+    node_canon = rng.uniform(-0.9, 0.9, size=(m, 3))
+    rot = Rotation.from_rotvec(rng.normal(size=(m, 3)) * 0.05).as_quat()     # x, y, z, w
+    q = np.concatenate([rot[:, 3:], rot[:, :3]], 1)
+    t = rng.normal(size=(m, 3)) * 0.02
+    dq = np.concatenate([q, 0.5 * owarp.qmul(np.concatenate([np.zeros((m, 1)), t], 1), q)], 1)
+    dq[rng.uniform(size=m) < 0.5] *= -1.0                                    # antipodal copies
+    box = ((-1.0,) * 3, (1.0,) * 3)
+    res = 40
+    knn = _knn(node_canon, *box, res, 8)
+    node_canon, dq = node_canon.astype(np.float32), dq.astype(np.float32)
+    table = _compare(_run(O, knn, node_canon, dq, box, res, box, res),
+                     knn, node_canon, dq, box, res, box, res)
+    assert (table >= 0).mean() > 0.5
