@@ -134,6 +134,13 @@ def main():
     except Exception as e:  # measurement is reported as missing, never invented
         log(f"[bench] live look-up table measurement failed: {e}")
 
+    # ---------------------------------------------------------------- key-frame selection
+    keyframe = None
+    try:
+        keyframe = time_keyframe(O, torch)
+    except Exception as e:  # measurement is reported as missing, never invented
+        log(f"[bench] key-frame measurement failed: {e}")
+
     # ---------------------------------------------------------------- render
     render = None
     if not args.no_render:
@@ -173,6 +180,7 @@ def main():
         "render": render,
         "occupancy_update": occupancy,
         "live_lut": live_lut,
+        "keyframe": keyframe,
         "roofline": roof,
         "step_roofline": step_roofline(f, R, n_samp, n_entries,
                                        sum(a * b for a, b in f.layer_shapes()), dt_bf),
@@ -425,6 +433,60 @@ def time_live_lut(O, torch, res=128, k=8, knn_res=128):
     return {"canon_res": res, "live_res": res, "k_nodes": k, "n_nodes": len(canon),
             "knn_res": knn_res, "us": t * 1e6, "filled": filled, "bytes": by,
             "achieved_GBs": by / t / 1e9, "voxels_per_s": n / t}
+
+
+def time_keyframe(O, torch):
+    """Key-frame selection kernels and the depth-test assembly, timed with HIP
+    events on the current stream: Eq. 5 visibility of 1024 nodes against a
+    640x576 depth map for one frame and for a full pool of 100 frames, Eq. 6
+    of a query against 100 pooled frames, the assembly of two 1920x1080
+    renderings."""
+    import synth
+    rng = np.random.default_rng(35)
+    F, M, H, W, fl = 100, 1024, 576, 640, 500.0
+    P = []
+    for R, c in synth.look_at_cameras(F, radius=2.0, arc_deg=180.0):
+        K = np.array([[fl, 0.0, W / 2], [0.0, -fl, H / 2], [0.0, 0.0, 1.0]])
+        P.append(K @ np.concatenate([R.T, (-R.T @ c)[:, None]], 1))
+    P = torch.from_numpy(np.stack(P).astype(np.float32)).cuda()
+    X = torch.from_numpy(rng.uniform(-0.8, 0.8, size=(F, M, 3)).astype(np.float32)).cuda()
+    D = torch.from_numpy(rng.uniform(1.0, 3.0, size=(F, H, W)).astype(np.float32)).cuda()
+    theta = torch.randn((F, 72), device="cuda") * 0.3
+    beta = torch.full((72,), 0.02, device="cuda")
+    t = torch.arange(F, dtype=torch.int32, device="cuda")
+    bits = O.visibility(X, P, D)
+    n_pix = 1920 * 1080
+    g = torch.Generator(device="cuda").manual_seed(36)
+    ca, cb = (torch.rand((n_pix, 3), device="cuda", generator=g) for _ in range(2))
+    aa, ab = (torch.rand(n_pix, device="cuda", generator=g) for _ in range(2))
+    da, db = aa * 2.0, ab * 1.5
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    out = {
+        "visibility_1_frame_us": timed(lambda: O.visibility(X[:1], P[:1], D[:1])),
+        "visibility_100_frames_us": timed(lambda: O.visibility(X, P, D)),
+        "human_distance_pool_100_us": timed(
+            lambda: O.human_distance(theta, bits, t, theta[0], bits[0], 7, beta)),
+        "assemble_1080p_us": timed(lambda: O.depth_assemble(ca, da, aa, cb, db, ab)),
+        "nodes": M, "depth_map": [W, H], "pool": F,
+    }
+    # the assembly reads 2 x 20 B and writes 16 B per pixel
+    out["assemble_GBs"] = n_pix * 56 / (out["assemble_1080p_us"] * 1e-6) / 1e9
+    log(f"[bench] key-frame: visibility {out['visibility_1_frame_us']:.1f} us (1 frame), "
+        f"{out['visibility_100_frames_us']:.1f} us (100), distances "
+        f"{out['human_distance_pool_100_us']:.1f} us, assembly {out['assemble_1080p_us']:.1f} us")
+    return out
 
 
 def time_render(O, L, F, torch, w, f, table, params, occ, dev):

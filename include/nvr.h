@@ -483,6 +483,82 @@ nvr_status nvr_live_lut(const nvr_lut_desc *d, const uint16_t *knn, const float 
                         const float *node_dq, int32_t *lut, nvr_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Key-frame selection (Sec. 4.3, "Online key frame selection"; weights in
+ * Sec. 4.4) and the per-pixel depth-test assembly of the two fields.
+ *
+ * nvr_visibility -- Eq. 5 for every node of every frame: with
+ * (u', v', w') = P_f (x, 1) (P_f the frame's 3 x 4 world-to-pixel projection,
+ * row-major; w' the camera depth), node i of frame f is visible when w' > 0,
+ * the pixel (floor(u'/w'), floor(v'/w')) lies in the width x height map and
+ * |w' - depth_f[v][u]| < eps (0.01 in Sec. 4.4).  Float32, one rounding per
+ * operation, no fused multiply-add, sums in the order ((P0 x + P1 y) + P2 z)
+ * + P3, correctly rounded divisions.  nodes [n_frames][n_nodes][3] world
+ * positions, proj [n_frames][12], depth [n_frames][height][width] (row-major,
+ * camera depth), bits [n_frames][ceil(n_nodes / 32)] uint32 output (node i at
+ * word i >> 5, bit i & 31; bits past n_nodes are 0): all device,
+ * caller-owned.  Errors: NVR_EINVAL for n_frames outside 0..65535, n_nodes
+ * outside 0..2^24, an empty or oversized map (more than 2^28 pixels), eps < 0,
+ * NULL or misaligned arrays.
+ *
+ * nvr_human_distance -- Eq. 6 between a query frame and n pooled frames:
+ * E[j] = sum_k beta[k] (pool_theta[j][k] - q_theta[k])^2
+ *        + beta_vis popcount(pool_bits[j] xor q_bits) + beta_h (pool_t[j] - q_t)^2
+ * (Sec. 4.4: beta 0.1 on torso joints and 0.02 on limbs, per axis-angle
+ * component; beta_vis 0.01; beta_h 0.02), float32 with the popcount exact;
+ * xor_count[j] (nullable) receives the popcount.  pool_theta [n][n_pose],
+ * pool_bits [n][n_words] uint32, pool_t [n] frame indices, q_theta [n_pose],
+ * q_bits [n_words], beta [n_pose], E [n]: all device.  Errors: NVR_EINVAL for
+ * n outside 0..2^24, n_pose outside 0..4096, n_words outside 0..2^20, NULL
+ * arrays.
+ *
+ * nvr_object_distance -- Eq. 7: E[j] = beta_d |pool_d[j] - q_d|^2
+ * + beta_o (pool_t[j] - q_t)^2 (beta_d 1, beta_o 0.02), float32; pool_d
+ * [n][3] object translations, pool_t [n], q_d [3], E [n]: all device.
+ *
+ * nvr_pool_step -- one spatial-pool decision, host only (pool, n_pool, dist,
+ * action and slot are host memory): an empty pool takes the frame
+ * (NVR_POOL_FIRST); otherwise the frame enters only if dist[j] (its E to
+ * pooled frame j, j < *n_pool) exceeds gamma (2.5) for every j, appended while
+ * *n_pool < cap (100 in Sec. 4.4; NVR_POOL_APPEND) and otherwise replacing the
+ * pooled frame with the smallest E, the lowest slot on ties
+ * (NVR_POOL_REPLACE); else NVR_POOL_REJECT (slot -1).  E is a distance
+ * (frames enter when it is large), so "most similar" is read as smallest E.
+ *
+ * nvr_pool_select -- the spatial half of the spatial-temporal pool, host
+ * only: the slots of the min(m, n_pool) smallest dist (m = 10 in Sec. 4.4),
+ * ascending, ties by slot, into slots[]; *n_out their number.
+ *
+ * nvr_depth_assemble -- the per-pixel combination of two renderings by depth:
+ * a field covers a pixel when its opacity alpha = 1 - T_N is >= 1/2, its
+ * surface depth being depth / alpha; the pixel takes the colour and surface
+ * depth of the nearer covering field (the first on ties); with none covering,
+ * the colours add (both over black) and the depth is the more opaque field's
+ * depth / alpha (the first's on ties; 0 when its alpha is 0).  rgb_* [n][3],
+ * depth_* [n] (un-normalised, as nvr_render writes them), alpha_* [n],
+ * rgb [n][3], depth [n] outputs: all device.  Errors: NVR_EINVAL for n
+ * outside 0..2^31, NULL arrays. */
+enum { NVR_POOL_REJECT = 0, NVR_POOL_FIRST = 1, NVR_POOL_APPEND = 2, NVR_POOL_REPLACE = 3 };
+nvr_status nvr_visibility(int32_t n_frames, int32_t n_nodes, const float *nodes,
+                          const float *proj, const float *depth, int32_t height, int32_t width,
+                          float eps, uint32_t *bits, nvr_stream stream);
+nvr_status nvr_human_distance(int32_t n, int32_t n_pose, int32_t n_words,
+                              const float *pool_theta, const uint32_t *pool_bits,
+                              const int32_t *pool_t, const float *q_theta, const uint32_t *q_bits,
+                              int32_t q_t, const float *beta, float beta_vis, float beta_h,
+                              float *E, int32_t *xor_count, nvr_stream stream);
+nvr_status nvr_object_distance(int32_t n, const float *pool_d, const int32_t *pool_t,
+                               const float *q_d, int32_t q_t, float beta_d, float beta_o,
+                               float *E, nvr_stream stream);
+nvr_status nvr_pool_step(int32_t *pool, int32_t *n_pool, int32_t cap, const float *dist,
+                         int32_t frame, float gamma, int32_t *action, int32_t *slot);
+nvr_status nvr_pool_select(int32_t n_pool, const float *dist, int32_t m, int32_t *slots,
+                           int32_t *n_out);
+nvr_status nvr_depth_assemble(int64_t n, const float *rgb_a, const float *depth_a,
+                              const float *alpha_a, const float *rgb_b, const float *depth_b,
+                              const float *alpha_b, float *rgb, float *depth,
+                              nvr_stream stream);
+
+/* ------------------------------------------------------------------------
  * Measurement probe (not part of the method): the random-gather ceiling the
  * hash-grid gather of Sec. 4.3's back-end is measured against.  The table
  * (device, 16-byte aligned, `bytes` long) is split into eight equal slices;

@@ -53,6 +53,9 @@ class LutDesc(C.Structure):
                 ("n_nodes", i32), ("r_ed", f32)]
 
 
+NVR_POOL_REJECT, NVR_POOL_FIRST, NVR_POOL_APPEND, NVR_POOL_REPLACE = 0, 1, 2, 3
+
+
 class MlpDesc(C.Structure):
     _fields_ = [("n_in", i32), ("n_density_hidden", i32), ("density_hidden", i32 * 4),
                 ("density_out", i32), ("sh_degree", i32), ("n_colour_hidden", i32),
@@ -103,6 +106,13 @@ _SIGS = {
     "nvr_occupancy_workspace": (C.c_size_t, [P(Field), i32, i64]),
     "nvr_occupancy_update": (i32, [P(Field), i32, i64, vp, vp, f32, f32, vp, vp, vp, vp, vp]),
     "nvr_live_lut": (i32, [P(LutDesc), vp, vp, vp, vp, vp]),
+    "nvr_visibility": (i32, [i32, i32, vp, vp, vp, i32, i32, f32, vp, vp]),
+    "nvr_human_distance": (i32, [i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, f32, f32, vp, vp,
+                                 vp]),
+    "nvr_object_distance": (i32, [i32, vp, vp, vp, i32, f32, f32, vp, vp]),
+    "nvr_pool_step": (i32, [P(i32), P(i32), i32, P(f32), i32, f32, P(i32), P(i32)]),
+    "nvr_pool_select": (i32, [i32, P(f32), i32, P(i32), P(i32)]),
+    "nvr_depth_assemble": (i32, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_probe_gather": (i32, [vp, C.c_size_t, i64, i32, C.c_uint32, vp, vp]),
     "nvr_march_workspace": (C.c_size_t, [i64]),
     "nvr_march": (i32, [P(MarchDesc), i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp,

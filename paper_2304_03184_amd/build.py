@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["abi.cpp", "grid.hip", "march.hip", "warp.hip", "mlp.cpp", "mlp_plain.hip",
            "mlp_mfma.hip", "scatter.hip", "composite.hip", "optim.hip", "step.cpp",
-           "occupancy.hip", "lut.hip", "probe.hip"]
+           "occupancy.hip", "lut.hip", "keyframe.hip", "probe.hip"]
 
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
          # no packed-fp32 instructions anywhere in the device code

@@ -175,6 +175,76 @@ def live_lut(knn, node_canon, node_dq, canon_box, canon_res, live_box, live_res,
     return lut
 
 
+def visibility(nodes, proj, depth, eps=0.01):
+    """Eq. 5 visibility bits: nodes [F][M][3], proj [F][3][4], depth [F][H][W]
+    (float32, device) -> int32 [F][ceil(M / 32)] words (uint32 bit patterns)."""
+    F, M = nodes.shape[0], nodes.shape[1]
+    H, W = depth.shape[1], depth.shape[2]
+    assert nodes.dtype == proj.dtype == depth.dtype == torch.float32
+    assert proj.shape == (F, 3, 4) and depth.shape[0] == F
+    nodes, proj, depth = nodes.contiguous(), proj.contiguous(), depth.contiguous()
+    bits = torch.empty((F, (M + 31) // 32), dtype=torch.int32, device=nodes.device)
+    call("nvr_visibility", F, M, _p(nodes), _p(proj), _p(depth), H, W, eps, _p(bits), _stream())
+    return bits
+
+
+def human_distance(pool_theta, pool_bits, pool_t, q_theta, q_bits, q_t, beta, beta_vis=0.01,
+                   beta_h=0.02):
+    """Eq. 6 of a query frame against every pooled frame: (E [n] float32,
+    xor counts [n] int32)."""
+    n, n_pose = pool_theta.shape
+    n_words = pool_bits.shape[1]
+    args = [t.contiguous() for t in (pool_theta, pool_bits, pool_t, q_theta, q_bits, beta)]
+    E = torch.empty(n, dtype=torch.float32, device=pool_theta.device)
+    cnt = torch.empty(n, dtype=torch.int32, device=pool_theta.device)
+    call("nvr_human_distance", n, n_pose, n_words, _p(args[0]), _p(args[1]), _p(args[2]),
+         _p(args[3]), _p(args[4]), int(q_t), _p(args[5]), beta_vis, beta_h, _p(E), _p(cnt),
+         _stream())
+    return E, cnt
+
+
+def object_distance(pool_d, pool_t, q_d, q_t, beta_d=1.0, beta_o=0.02):
+    """Eq. 7 of a query frame against every pooled frame: E [n] float32."""
+    n = pool_d.shape[0]
+    a, b, c = pool_d.contiguous(), pool_t.contiguous(), q_d.contiguous()
+    E = torch.empty(n, dtype=torch.float32, device=pool_d.device)
+    call("nvr_object_distance", n, _p(a), _p(b), _p(c), int(q_t), beta_d, beta_o, _p(E),
+         _stream())
+    return E
+
+
+def pool_step(pool, dist, frame, cap=100, gamma=2.5):
+    """One spatial-pool decision on the host: pool (list of frame ids) is
+    updated in place; returns (action, slot)."""
+    buf = (C.c_int32 * cap)(*pool)
+    n = C.c_int32(len(pool))
+    d = (C.c_float * max(len(pool), 1))(*[float(x) for x in dist])
+    act, slot = C.c_int32(), C.c_int32()
+    call("nvr_pool_step", buf, C.byref(n), cap, d, frame, gamma, C.byref(act), C.byref(slot))
+    pool[:] = list(buf[:n.value])
+    return act.value, slot.value
+
+
+def pool_select(dist, m=10):
+    """Slots of the m smallest distances (ties by slot), host side."""
+    n = len(dist)
+    d = (C.c_float * max(n, 1))(*[float(x) for x in dist])
+    out = (C.c_int32 * max(min(m, n), 1))()
+    k = C.c_int32()
+    call("nvr_pool_select", n, d, m, out, C.byref(k))
+    return list(out[:k.value])
+
+
+def depth_assemble(rgb_a, depth_a, alpha_a, rgb_b, depth_b, alpha_b):
+    """Per-pixel depth test of two renderings: (rgb [n][3], depth [n])."""
+    n = depth_a.shape[0]
+    ins = [t.contiguous().float() for t in (rgb_a, depth_a, alpha_a, rgb_b, depth_b, alpha_b)]
+    rgb = torch.empty((n, 3), dtype=torch.float32, device=depth_a.device)
+    depth = torch.empty(n, dtype=torch.float32, device=depth_a.device)
+    call("nvr_depth_assemble", n, *[_p(t) for t in ins], _p(rgb), _p(depth), _stream())
+    return rgb, depth
+
+
 def probe_gather(table, n, loads, seed=1):
     """Random 16-byte gathers over `table`'s bytes split into eight slices
     (measurement probe, not part of the method); returns the [8][n] xors."""
