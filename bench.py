@@ -134,6 +134,13 @@ def main():
     except Exception as e:  # measurement is reported as missing, never invented
         log(f"[bench] live look-up table measurement failed: {e}")
 
+    # ---------------------------------------------------------------- deformation network
+    deform = None
+    try:
+        deform = time_deform(O, L, torch)
+    except Exception as e:  # measurement is reported as missing, never invented
+        log(f"[bench] deformation network measurement failed: {e}")
+
     # ---------------------------------------------------------------- key-frame selection
     keyframe = None
     try:
@@ -181,6 +188,7 @@ def main():
         "occupancy_update": occupancy,
         "live_lut": live_lut,
         "keyframe": keyframe,
+        "deform": deform,
         "roofline": roof,
         "step_roofline": step_roofline(f, R, n_samp, n_entries,
                                        sum(a * b for a, b in f.layer_shapes()), dt_bf),
@@ -433,6 +441,46 @@ def time_live_lut(O, torch, res=128, k=8, knn_res=128):
     return {"canon_res": res, "live_res": res, "k_nodes": k, "n_nodes": len(canon),
             "knn_res": knn_res, "us": t * 1e6, "filled": filled, "bytes": by,
             "achieved_GBs": by / t / 1e9, "voxels_per_s": n / t}
+
+
+def time_deform(O, L, torch, n=1 << 18):
+    """Pose-conditioned deformation network on n points (the field's ladder for
+    its own 2^19-entry table, 104 -> 4 x 128 -> 3), forward and backward
+    (which recomputes the forward), timed with HIP events."""
+    import ctypes as C
+    rng = np.random.default_rng(37)
+    g = L.GridDesc()
+    L.call("nvr_grid_init", C.byref(g), 16, 2, 19, 16, 2048, (C.c_float * 3)(-1, -1, -1),
+           (C.c_float * 3)(1, 1, 1))
+    n_entries = int(g.offset[16])
+    table = torch.from_numpy(rng.uniform(-0.1, 0.1, size=(n_entries, 2)).astype(np.float32)).cuda()
+    n_par = int(L.lib().nvr_deform_param_count())
+    params = (torch.rand(n_par, device="cuda") * 2 - 1) * 0.1
+    x = torch.from_numpy(rng.uniform(-0.9, 0.9, size=(n, 3)).astype(np.float32)).cuda()
+    theta = torch.randn(72, device="cuda") * 0.3
+    dvc = torch.randn((n, 3), device="cuda")
+
+    def timed(fn, reps=10):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    fwd = timed(lambda: O.deform_fwd(g, x, theta, table, params))
+    bwd = timed(lambda: O.deform_bwd(g, x, theta, table, params, dvc))
+    flops_fwd = 2.0 * n * n_par
+    out = {"points": n, "fwd_ms": fwd, "bwd_ms": bwd,
+           "fwd_tflops": flops_fwd / (fwd * 1e-3) / 1e12,
+           "bwd_tflops": 3 * flops_fwd / (bwd * 1e-3) / 1e12,
+           "dtype": "f32 (sgemm)"}
+    log(f"[bench] deformation net {n} points: fwd {fwd:.3f} ms, fwd+bwd {bwd:.3f} ms")
+    return out
 
 
 def time_keyframe(O, torch):

@@ -483,6 +483,32 @@ nvr_status nvr_live_lut(const nvr_lut_desc *d, const uint16_t *knn, const float 
                         const float *node_dq, int32_t *lut, nvr_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Pose-conditioned deformation network (Sec. 4.2, hybrid deformation; widths
+ * in Sec. 4.4): x_can = x + MLP([enc(x), theta]) with enc a multiresolution
+ * hash encoding of its own (grid `g`, 32 wide: levels x features = 32, fp32
+ * table) and theta one 72-wide pose for all points; 104 -> 128 -> 128 -> 128
+ * -> 128 -> 3, bias-free, ReLU on the hidden layers, linear output, float32
+ * (each layer one sgemm).  params: nvr_deform_param_count() floats, each
+ * layer's W[out][in] row-major in order.  x [n][3], theta [72], table
+ * [n_entries][2], x_can [n][3]: device.  workspace: device, 256-byte aligned,
+ * nvr_deform_workspace(n) bytes (about 4 KB per point), overwritten.
+ * nvr_deform_bwd recomputes the forward and, for the gradient dx_can [n][3] of
+ * the output, accumulates dparams (acc), dtable (acc), dx (acc, nullable:
+ * through the encoding plus the identity of the residual) and dtheta [72]
+ * (acc, nullable, summed over the points).  Errors: NVR_EINVAL for n outside
+ * 0..2^24, NULL arrays or workspace; NVR_EUNSUPPORTED for an encoding not 32
+ * wide; NVR_EHIP when a rocBLAS call fails. */
+size_t nvr_deform_workspace(int64_t n);
+int64_t nvr_deform_param_count(void);
+nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
+                          const float *table, const float *params, float *x_can, void *workspace,
+                          nvr_stream stream);
+nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
+                          const float *table, const float *params, const float *dx_can,
+                          float *dparams, float *dtable, float *dx, float *dtheta,
+                          void *workspace, nvr_stream stream);
+
+/* ------------------------------------------------------------------------
  * Key-frame selection (Sec. 4.3, "Online key frame selection"; weights in
  * Sec. 4.4) and the per-pixel depth-test assembly of the two fields.
  *

@@ -16,7 +16,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["abi.cpp", "grid.hip", "march.hip", "warp.hip", "mlp.cpp", "mlp_plain.hip",
            "mlp_mfma.hip", "scatter.hip", "composite.hip", "optim.hip", "step.cpp",
-           "occupancy.hip", "lut.hip", "keyframe.hip", "probe.hip"]
+           "occupancy.hip", "lut.hip", "keyframe.hip", "deform.hip", "probe.hip"]
+
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
          # no packed-fp32 instructions anywhere in the device code
@@ -40,7 +42,8 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    p = subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp, *objs],
+    p = subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp, *objs,
+                        "-L" + ROCM_LIB, "-lrocblas", "-Wl,-rpath," + ROCM_LIB],
                        capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"link failed:\n{p.stderr}")

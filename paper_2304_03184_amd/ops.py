@@ -175,6 +175,36 @@ def live_lut(knn, node_canon, node_dq, canon_box, canon_res, live_box, live_res,
     return lut
 
 
+def _workspace(nbytes, device):
+    # 256-byte aligned device bytes (torch's allocations are)
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def deform_fwd(g, x, theta, table, params):
+    """Deformation network (Sec. 4.2): x + MLP([enc(x), theta]) for x [n][3]."""
+    n = x.shape[0]
+    x, theta, table, params = (t.contiguous() for t in (x, theta, table, params))
+    out = torch.empty_like(x)
+    ws = _workspace(L.lib().nvr_deform_workspace(n), x.device)
+    call("nvr_deform_fwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), _p(out),
+         _p(ws), _stream())
+    return out
+
+
+def deform_bwd(g, x, theta, table, params, dx_can, want_dx=True, want_dtheta=True):
+    """Gradients of sum(dx_can . deform_fwd(...)): (dparams, dtable, dx, dtheta)."""
+    n = x.shape[0]
+    x, theta, table, params, dx_can = (t.contiguous() for t in (x, theta, table, params, dx_can))
+    dparams = torch.zeros_like(params)
+    dtable = torch.zeros_like(table)
+    dx = torch.zeros_like(x) if want_dx else None
+    dtheta = torch.zeros_like(theta) if want_dtheta else None
+    ws = _workspace(L.lib().nvr_deform_workspace(n), x.device)
+    call("nvr_deform_bwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), _p(dx_can),
+         _p(dparams), _p(dtable), _p(dx), _p(dtheta), _p(ws), _stream())
+    return dparams, dtable, dx, dtheta
+
+
 def visibility(nodes, proj, depth, eps=0.01):
     """Eq. 5 visibility bits: nodes [F][M][3], proj [F][3][4], depth [F][H][W]
     (float32, device) -> int32 [F][ceil(M / 32)] words (uint32 bit patterns)."""
