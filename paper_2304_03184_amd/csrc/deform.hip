@@ -8,6 +8,7 @@
 // holds them); the small kernels here assemble the input, apply the ReLU and
 // its mask, add the residual and split the input gradient.  The backward
 // recomputes the forward into the workspace.
+#include <algorithm>
 #include <mutex>
 
 #include <rocblas/rocblas.h>
@@ -21,8 +22,13 @@ constexpr int kFeat = 32, kPose = 72, kIn = kFeat + kPose, kWidth = 128, kHidden
 constexpr int64_t kParams = (int64_t)kWidth * kIn + (int64_t)(kHidden - 1) * kWidth * kWidth +
                             3 * kWidth;
 
+// The weight gradients reduce over all points; rocBLAS is given the points in
+// kDwParts chunks of kDwChunk (a batched product into partials, summed by
+// dn_reduce_partials), so that the reduction spreads over many workgroups.
+constexpr int kDwChunk = 4096, kDwParts = 64;
+
 struct DeformWs {
-    float *feat, *a0, *h[kHidden], *dv, *dh0, *dh1, *da0, *dfeat;
+    float *feat, *a0, *h[kHidden], *dv, *dh0, *dh1, *da0, *dfeat, *partial;
 };
 
 size_t round_up(size_t b) { return (b + 255) / 256 * 256; }
@@ -44,6 +50,7 @@ size_t carve(int64_t n, char *base, DeformWs *w) {
     t.dh1 = take((size_t)n * kWidth);
     t.da0 = take((size_t)n * kIn);
     t.dfeat = take((size_t)n * kFeat);
+    t.partial = take((size_t)kDwParts * kWidth * kWidth);   // largest layer: 128 x 128
     if (w) *w = t;
     return off;
 }
@@ -97,20 +104,32 @@ dn_split(int64_t n, const float *__restrict__ da0, float *__restrict__ dfeat) {
     }
 }
 
-// dtheta[c] += sum over points of da0[s][32 + c]: one workgroup per component.
-__global__ void __launch_bounds__(256)
+// dtheta[c] += sum over points of da0[s][32 + c]: each workgroup sums a chunk
+// of kThetaChunk points (lanes over the 72 components, so each row is read
+// contiguously) and adds its partial with one atomic per component.
+constexpr int kThetaChunk = 256;
+
+__global__ void __launch_bounds__(128)
 dn_theta_sum(int64_t n, const float *__restrict__ da0, float *__restrict__ dtheta) {
-    __shared__ float part[256];
-    const int c = blockIdx.x;
+    const int c = threadIdx.x;
+    if (c >= kPose) return;
+    const int64_t s0 = (int64_t)blockIdx.x * kThetaChunk;
+    const int64_t s1 = s0 + kThetaChunk < n ? s0 + kThetaChunk : n;
     float acc = 0.f;
-    for (int64_t s = threadIdx.x; s < n; s += blockDim.x) acc += da0[s * kIn + kFeat + c];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
-        __syncthreads();
+    for (int64_t s = s0; s < s1; ++s) acc += da0[s * kIn + kFeat + c];
+    atomicAdd(dtheta + c, acc);
+}
+
+// dW_partial[b] = (dY rows of chunk b)^T (X rows of chunk b), then summed.
+__global__ void __launch_bounds__(256)
+dn_reduce_partials(int64_t m, int32_t parts, const float *__restrict__ partial,
+                   float *__restrict__ dW) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int b = 0; b < parts; ++b) acc += partial[(int64_t)b * m + i];
+        dW[i] += acc;
     }
-    if (threadIdx.x == 0) dtheta[c] += part[0];
 }
 
 // One rocBLAS handle per device, created on first use.
@@ -151,14 +170,32 @@ nvr_status gemm_dx(rocblas_handle h, int64_t n, int out, int in, const float *W,
     return NVR_OK;
 }
 
-// Row-major dW[out][in] += dY^T X over the n points.
-nvr_status gemm_dw(rocblas_handle h, int64_t n, int out, int in, const float *dY, const float *X,
-                   float *dW) {
-    const float one = 1.f;
-    NVR_REQUIRE(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, in, out,
-                              (int)n, &one, X, in, dY, out, &one, dW, in) ==
-                    rocblas_status_success,
-                NVR_EHIP, "rocblas_sgemm failed");
+// Row-major dW[out][in] += dY^T X over the n points: whole chunks of kDwChunk
+// points as one strided-batched product into `partial` (up to kDwParts chunks
+// per pass) summed into dW, the remaining points as one product into dW.
+nvr_status gemm_dw(rocblas_handle h, hipStream_t st, int64_t n, int out, int in, const float *dY,
+                   const float *X, float *dW, float *partial) {
+    const float one = 1.f, zero = 0.f;
+    int64_t s = 0;
+    while (n - s >= kDwChunk) {
+        const int parts = (int)std::min<int64_t>(kDwParts, (n - s) / kDwChunk);
+        NVR_REQUIRE(rocblas_sgemm_strided_batched(
+                        h, rocblas_operation_none, rocblas_operation_transpose, in, out,
+                        kDwChunk, &one, X + s * in, in, (rocblas_stride)kDwChunk * in,
+                        dY + s * out, out, (rocblas_stride)kDwChunk * out, &zero, partial, in,
+                        (rocblas_stride)in * out, parts) == rocblas_status_success,
+                    NVR_EHIP, "rocblas_sgemm_strided_batched failed");
+        const int64_t m = (int64_t)in * out;
+        dn_reduce_partials<<<grid_for(m, 256, 1024), 256, 0, st>>>(m, parts, partial, dW);
+        NVR_LAUNCHED();
+        s += (int64_t)parts * kDwChunk;
+    }
+    if (s < n) {
+        NVR_REQUIRE(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, in, out,
+                                  (int)(n - s), &one, X + s * in, in, dY + s * out, out, &one, dW,
+                                  in) == rocblas_status_success,
+                    NVR_EHIP, "rocblas_sgemm failed");
+    }
     return NVR_OK;
 }
 
@@ -247,7 +284,7 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
     NVR_TRY(forward(g, n, x, theta, table, params, w, st, h));
     // output layer: dW_out += dx_can^T h4; dh = dx_can W_out
     float *dW = dparams + (kParams - 3 * kWidth);
-    NVR_TRY(gemm_dw(h, n, 3, kWidth, dx_can, w.h[kHidden - 1], dW));
+    NVR_TRY(gemm_dw(h, st, n, 3, kWidth, dx_can, w.h[kHidden - 1], dW, w.partial));
     NVR_TRY(gemm_dx(h, n, 3, kWidth, layer_w(params, kHidden), dx_can, w.dh0));
     float *dh = w.dh0, *dh_next = w.dh1;
     for (int i = kHidden - 1; i >= 0; --i) {
@@ -256,7 +293,7 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
         const int width_in = i == 0 ? kIn : kWidth;
         const float *in = i == 0 ? w.a0 : w.h[i - 1];
         float *dWi = dparams + (layer_w(params, i) - params);
-        NVR_TRY(gemm_dw(h, n, kWidth, width_in, dh, in, dWi));
+        NVR_TRY(gemm_dw(h, st, n, kWidth, width_in, dh, in, dWi, w.partial));
         float *dst = i == 0 ? w.da0 : dh_next;
         NVR_TRY(gemm_dx(h, n, kWidth, width_in, layer_w(params, i), dh, dst));
         if (i > 0) {
@@ -267,7 +304,8 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
     dn_split<<<grid_for(n * kFeat, 256, 16384), 256, 0, st>>>(n, w.da0, w.dfeat);
     NVR_LAUNCHED();
     if (dtheta) {
-        dn_theta_sum<<<kPose, 256, 0, st>>>(n, w.da0, dtheta);
+        dn_theta_sum<<<(unsigned)((n + kThetaChunk - 1) / kThetaChunk), 128, 0, st>>>(n, w.da0,
+                                                                                  dtheta);
         NVR_LAUNCHED();
     }
     NVR_TRY(nvr_encode_bwd(g, n, x, table, NVR_F32, w.dfeat, dtable, dx, stream));
