@@ -491,14 +491,16 @@ nvr_status nvr_live_lut(const nvr_lut_desc *d, const uint16_t *knn, const float 
  * (each layer one sgemm).  params: nvr_deform_param_count() floats, each
  * layer's W[out][in] row-major in order.  x [n][3], theta [72], table
  * [n_entries][2], x_can [n][3]: device.  workspace: device, 256-byte aligned,
- * nvr_deform_workspace(n) bytes (about 4 KB per point), overwritten.
+ * nvr_deform_workspace(g, n) bytes (about 4 KB per point), overwritten.
  * nvr_deform_bwd recomputes the forward and, for the gradient dx_can [n][3] of
- * the output, accumulates dparams (acc), dtable (acc), dx (acc, nullable:
- * through the encoding plus the identity of the residual) and dtheta [72]
- * (acc, nullable, summed over the points).  Errors: NVR_EINVAL for n outside
- * 0..2^24, NULL arrays or workspace; NVR_EUNSUPPORTED for an encoding not 32
- * wide; NVR_EHIP when a rocBLAS call fails. */
-size_t nvr_deform_workspace(int64_t n);
+ * the output, accumulates dparams (acc), dtable (acc, 8-byte aligned; formed
+ * by the binned scatter of nvr_encode_bwd_binned, same rounding), dx (acc,
+ * nullable: through the encoding plus the identity of the residual) and
+ * dtheta [72] (acc, nullable, summed over the points).  Errors: NVR_EINVAL for
+ * n outside 0..2^24, NULL arrays or workspace; NVR_EUNSUPPORTED for an
+ * encoding not 32 wide or a ladder the binned scatter does not take; NVR_EHIP
+ * when a rocBLAS call fails. */
+size_t nvr_deform_workspace(const nvr_grid_desc *g, int64_t n);
 int64_t nvr_deform_param_count(void);
 nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
                           const float *table, const float *params, float *x_can, void *workspace,

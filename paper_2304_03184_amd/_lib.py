@@ -106,7 +106,7 @@ _SIGS = {
     "nvr_occupancy_workspace": (C.c_size_t, [P(Field), i32, i64]),
     "nvr_occupancy_update": (i32, [P(Field), i32, i64, vp, vp, f32, f32, vp, vp, vp, vp, vp]),
     "nvr_live_lut": (i32, [P(LutDesc), vp, vp, vp, vp, vp]),
-    "nvr_deform_workspace": (C.c_size_t, [i64]),
+    "nvr_deform_workspace": (C.c_size_t, [P(GridDesc), i64]),
     "nvr_deform_param_count": (i64, []),
     "nvr_deform_fwd": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_deform_bwd": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),

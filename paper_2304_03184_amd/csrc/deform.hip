@@ -14,6 +14,7 @@
 #include <rocblas/rocblas.h>
 
 #include "common.hpp"
+#include "grid_dev.hpp"
 
 namespace nvr {
 namespace {
@@ -22,6 +23,10 @@ constexpr int kFeat = 32, kPose = 72, kIn = kFeat + kPose, kWidth = 128, kHidden
 constexpr int64_t kParams = (int64_t)kWidth * kIn + (int64_t)(kHidden - 1) * kWidth * kWidth +
                             3 * kWidth;
 
+// The table gradient goes through the binned scatter (no float atomics; its
+// records never read the table when no position gradient is asked of it), the
+// position gradient through the plain fp32 kernel with its table-gradient
+// atomics switched off.
 // The weight gradients reduce over all points; rocBLAS is given the points in
 // kDwParts chunks of kDwChunk (a batched product into partials, summed by
 // dn_reduce_partials), so that the reduction spreads over many workgroups.
@@ -29,12 +34,13 @@ constexpr int kDwChunk = 4096, kDwParts = 64;
 
 struct DeformWs {
     float *feat, *a0, *h[kHidden], *dv, *dh0, *dh1, *da0, *dfeat, *partial;
+    void *binned;
 };
 
 size_t round_up(size_t b) { return (b + 255) / 256 * 256; }
 
 // Carves the workspace; returns its size (base may be null to only measure).
-size_t carve(int64_t n, char *base, DeformWs *w) {
+size_t carve(const nvr_grid_desc *g, int64_t n, char *base, DeformWs *w) {
     size_t off = 0;
     auto take = [&](size_t floats) {
         float *p = base ? reinterpret_cast<float *>(base + off) : nullptr;
@@ -51,6 +57,7 @@ size_t carve(int64_t n, char *base, DeformWs *w) {
     t.da0 = take((size_t)n * kIn);
     t.dfeat = take((size_t)n * kFeat);
     t.partial = take((size_t)kDwParts * kWidth * kWidth);   // largest layer: 128 x 128
+    t.binned = take((nvr_encode_bwd_workspace(g, n) + sizeof(float) - 1) / sizeof(float));
     if (w) *w = t;
     return off;
 }
@@ -239,9 +246,9 @@ nvr_status forward(const nvr_grid_desc *g, int64_t n, const float *x, const floa
 
 using namespace nvr;
 
-extern "C" size_t nvr_deform_workspace(int64_t n) {
-    if (n < 0) return 0;
-    return carve(n, nullptr, nullptr);
+extern "C" size_t nvr_deform_workspace(const nvr_grid_desc *g, int64_t n) {
+    if (g == nullptr || n < 0) return 0;
+    return carve(g, n, nullptr, nullptr);
 }
 
 extern "C" int64_t nvr_deform_param_count(void) { return kParams; }
@@ -258,7 +265,7 @@ extern "C" nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const fl
     std::lock_guard<std::mutex> lock(g_blas_mu);
     NVR_TRY(blas_for(st, &h));
     DeformWs w;
-    carve(n, static_cast<char *>(workspace), &w);
+    carve(g, n, static_cast<char *>(workspace), &w);
     NVR_TRY(forward(g, n, x, theta, table, params, w, st, h));
     dn_residual<<<grid_for(n * 3, 256, 16384), 256, 0, st>>>(n * 3, x, w.dv, x_can);
     NVR_LAUNCHED();
@@ -280,7 +287,7 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
     std::lock_guard<std::mutex> lock(g_blas_mu);
     NVR_TRY(blas_for(st, &h));
     DeformWs w;
-    carve(n, static_cast<char *>(workspace), &w);
+    carve(g, n, static_cast<char *>(workspace), &w);
     NVR_TRY(forward(g, n, x, theta, table, params, w, st, h));
     // output layer: dW_out += dx_can^T h4; dh = dx_can W_out
     float *dW = dparams + (kParams - 3 * kWidth);
@@ -308,7 +315,10 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
                                                                                   dtheta);
         NVR_LAUNCHED();
     }
-    NVR_TRY(nvr_encode_bwd(g, n, x, table, NVR_F32, w.dfeat, dtable, dx, stream));
+    NVR_TRY(nvr_encode_bwd_binned(g, n, x, table, w.dfeat, dtable, nullptr, w.binned, stream));
+    if (dx)
+        NVR_TRY(launch_encode_bwd(make_grid_params(g), n, nullptr, n, x, table, NVR_F32, w.dfeat,
+                                  nullptr, dx, false, st));
     if (dx) {
         // the residual's identity: dx += dx_can
         dn_add<<<grid_for(n * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can);

@@ -185,7 +185,7 @@ def deform_fwd(g, x, theta, table, params):
     n = x.shape[0]
     x, theta, table, params = (t.contiguous() for t in (x, theta, table, params))
     out = torch.empty_like(x)
-    ws = _workspace(L.lib().nvr_deform_workspace(n), x.device)
+    ws = _workspace(L.lib().nvr_deform_workspace(C.byref(g), n), x.device)
     call("nvr_deform_fwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), _p(out),
          _p(ws), _stream())
     return out
@@ -199,7 +199,7 @@ def deform_bwd(g, x, theta, table, params, dx_can, want_dx=True, want_dtheta=Tru
     dtable = torch.zeros_like(table)
     dx = torch.zeros_like(x) if want_dx else None
     dtheta = torch.zeros_like(theta) if want_dtheta else None
-    ws = _workspace(L.lib().nvr_deform_workspace(n), x.device)
+    ws = _workspace(L.lib().nvr_deform_workspace(C.byref(g), n), x.device)
     call("nvr_deform_bwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), _p(dx_can),
          _p(dparams), _p(dtable), _p(dx), _p(dtheta), _p(ws), _stream())
     return dparams, dtable, dx, dtheta

@@ -68,7 +68,7 @@ def test_deform_empty_and_accumulation():
     out = O.deform_fwd(g, dev(x[:0]), dev(theta), dev(table), dev(params))
     assert out.shape == (0, 3)
     # gradients accumulate into what the caller passes
-    ws = torch.empty(L.lib().nvr_deform_workspace(300), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(L.lib().nvr_deform_workspace(C.byref(g), 300), dtype=torch.uint8, device="cuda")
     dp = torch.zeros(params.size, device="cuda")
     dt = torch.zeros(table.shape, device="cuda")
     xd, thd, td, pd, dvd = dev(x), dev(theta), dev(table), dev(params), dev(dvc)
