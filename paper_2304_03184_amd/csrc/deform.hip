@@ -25,8 +25,7 @@ constexpr int64_t kParams = (int64_t)kWidth * kIn + (int64_t)(kHidden - 1) * kWi
 
 // The table gradient goes through the binned scatter (no float atomics; its
 // records never read the table when no position gradient is asked of it), the
-// position gradient through the plain fp32 kernel with its table-gradient
-// atomics switched off.
+// position gradient through dn_encode_dx (one thread per point).
 // The weight gradients reduce over all points; rocBLAS is given the points in
 // kDwParts chunks of kDwChunk (a batched product into partials, summed by
 // dn_reduce_partials), so that the reduction spreads over many workgroups.
@@ -136,6 +135,42 @@ dn_reduce_partials(int64_t m, int32_t parts, const float *__restrict__ partial,
         float acc = 0.f;
         for (int b = 0; b < parts; ++b) acc += partial[(int64_t)b * m + i];
         dW[i] += acc;
+    }
+}
+
+// Position gradient of the encoding alone (the table gradient is binned
+// separately): one thread per point over all levels, so each point's gradient
+// is summed in registers and added once, with no atomics.  dfeat is the
+// row-major [n][2 L] feature gradient; fp32 table.
+__global__ void __launch_bounds__(256)
+dn_encode_dx(GridParams p, int64_t n, const float *__restrict__ x,
+             const float2 *__restrict__ table, const float *__restrict__ dfeat,
+             float *__restrict__ dx) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const float x0 = x[3 * s], x1 = x[3 * s + 1], x2 = x[3 * s + 2];
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+        for (int l = 0; l < p.L; ++l) {
+            const LevelPos lp = level_pos(p, l, x0, x1, x2);
+            const float g0 = dfeat[(s * p.L + l) * 2], g1 = dfeat[(s * p.L + l) * 2 + 1];
+            float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float2 v = table[p.off[l] + corner_index(p, l, lp, k)];
+                const float tg = v.x * g0 + v.y * g1;
+                const float3 dw = corner_dweight(lp, k);
+                d0 += dw.x * tg;
+                d1 += dw.y * tg;
+                d2 += dw.z * tg;
+            }
+            const float N = (float)p.res[l];
+            if (lp.inside[0]) acc0 += d0 * N * (float)p.inv_side[0];
+            if (lp.inside[1]) acc1 += d1 * N * (float)p.inv_side[1];
+            if (lp.inside[2]) acc2 += d2 * N * (float)p.inv_side[2];
+        }
+        dx[3 * s] += acc0;
+        dx[3 * s + 1] += acc1;
+        dx[3 * s + 2] += acc2;
     }
 }
 
@@ -282,6 +317,8 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(x && theta && table && params && dx_can && dparams && dtable, NVR_EINVAL,
                 "NULL array");
+    NVR_REQUIRE(aligned(x, 4) && aligned(table, 8) && aligned(dtable, 8) && aligned(dx, 4),
+                NVR_EINVAL, "misaligned array");
     const hipStream_t st = hs(stream);
     rocblas_handle h;
     std::lock_guard<std::mutex> lock(g_blas_mu);
@@ -316,9 +353,11 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
         NVR_LAUNCHED();
     }
     NVR_TRY(nvr_encode_bwd_binned(g, n, x, table, w.dfeat, dtable, nullptr, w.binned, stream));
-    if (dx)
-        NVR_TRY(launch_encode_bwd(make_grid_params(g), n, nullptr, n, x, table, NVR_F32, w.dfeat,
-                                  nullptr, dx, false, st));
+    if (dx) {
+        dn_encode_dx<<<grid_for(n, 256, 16384), 256, 0, st>>>(
+            make_grid_params(g), n, x, reinterpret_cast<const float2 *>(table), w.dfeat, dx);
+        NVR_LAUNCHED();
+    }
     if (dx) {
         // the residual's identity: dx += dx_can
         dn_add<<<grid_for(n * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can);

@@ -102,10 +102,8 @@ encode_bwd_plain(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
         for (int k = 0; k < 8; ++k) {
             float w = corner_weight(lp, k);
             uint32_t e = p.off[l] + corner_index(p, l, lp, k);
-            if (dtable != nullptr) {              // null: position gradient only
-                if (g0 != 0.f) unsafeAtomicAdd(dtable + 2 * (size_t)e, w * g0);
-                if (g1 != 0.f) unsafeAtomicAdd(dtable + 2 * (size_t)e + 1, w * g1);
-            }
+            if (g0 != 0.f) unsafeAtomicAdd(dtable + 2 * (size_t)e, w * g0);
+            if (g1 != 0.f) unsafeAtomicAdd(dtable + 2 * (size_t)e + 1, w * g1);
             if (dx != nullptr) {
                 float2 v = table[e];
                 float tg = v.x * g0 + v.y * g1;
