@@ -452,7 +452,7 @@ nvr_status nvr_occupancy_update(const nvr_field *f, int32_t precision, int64_t m
  * every canonical voxel; per frame, each canonical voxel centre
  * v_k = canon_min + (i + 1/2) (canon_max - canon_min) / canon_res per axis
  * (k = ix + canon_res (iy + canon_res iz)) is carried to the live space by the
- * node blend of Eq. 2, and the live voxel it lands in records k:
+ * node blend of Eq. 1, and the live voxel it lands in records k:
  *   w_j = exp(-(|v_k - x_j|^2 - d_min^2) / r_ed^2) over the listed nodes
  *     (d_min the nearest listed one: a common scale the normalised blend
  *     ignores), sign-aligned to the first listed node's rotation part,
@@ -484,7 +484,7 @@ nvr_status nvr_live_lut(const nvr_lut_desc *d, const uint16_t *knn, const float 
 
 /* ------------------------------------------------------------------------
  * Pose-conditioned deformation network (Sec. 4.2, hybrid deformation; widths
- * in Sec. 4.4): x_can = x + MLP([enc(x), theta]) with enc a multiresolution
+ * in Sec. 4.3): x_can = x + MLP([enc(x), theta]) with enc a multiresolution
  * hash encoding of its own (grid `g`, 32 wide: levels x features = 32, fp32
  * table) and theta one 72-wide pose for all points; 104 -> 128 -> 128 -> 128
  * -> 128 -> 3, bias-free, ReLU on the hidden layers, linear output, float32
@@ -511,14 +511,14 @@ nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x, con
                           void *workspace, nvr_stream stream);
 
 /* ------------------------------------------------------------------------
- * Key-frame selection (Sec. 4.3, "Online key frame selection"; weights in
- * Sec. 4.4) and the per-pixel depth-test assembly of the two fields.
+ * Key-frame selection (Sec. 4.2, "Online key frame selection"; weights in
+ * Sec. 4.3) and the per-pixel depth-test assembly of the two fields.
  *
  * nvr_visibility -- Eq. 5 for every node of every frame: with
  * (u', v', w') = P_f (x, 1) (P_f the frame's 3 x 4 world-to-pixel projection,
  * row-major; w' the camera depth), node i of frame f is visible when w' > 0,
  * the pixel (floor(u'/w'), floor(v'/w')) lies in the width x height map and
- * |w' - depth_f[v][u]| < eps (0.01 in Sec. 4.4).  Float32, one rounding per
+ * |w' - depth_f[v][u]| < eps (0.01 in Sec. 4.3).  Float32, one rounding per
  * operation, no fused multiply-add, sums in the order ((P0 x + P1 y) + P2 z)
  * + P3, correctly rounded divisions.  nodes [n_frames][n_nodes][3] world
  * positions, proj [n_frames][12], depth [n_frames][height][width] (row-major,
@@ -531,7 +531,7 @@ nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x, con
  * nvr_human_distance -- Eq. 6 between a query frame and n pooled frames:
  * E[j] = sum_k beta[k] (pool_theta[j][k] - q_theta[k])^2
  *        + beta_vis popcount(pool_bits[j] xor q_bits) + beta_h (pool_t[j] - q_t)^2
- * (Sec. 4.4: beta 0.1 on torso joints and 0.02 on limbs, per axis-angle
+ * (Sec. 4.3: beta 0.1 on torso joints and 0.02 on limbs, per axis-angle
  * component; beta_vis 0.01; beta_h 0.02), float32 with the popcount exact;
  * xor_count[j] (nullable) receives the popcount.  pool_theta [n][n_pose],
  * pool_bits [n][n_words] uint32, pool_t [n] frame indices, q_theta [n_pose],
@@ -547,13 +547,13 @@ nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x, con
  * action and slot are host memory): an empty pool takes the frame
  * (NVR_POOL_FIRST); otherwise the frame enters only if dist[j] (its E to
  * pooled frame j, j < *n_pool) exceeds gamma (2.5) for every j, appended while
- * *n_pool < cap (100 in Sec. 4.4; NVR_POOL_APPEND) and otherwise replacing the
+ * *n_pool < cap (100 in Sec. 4.3; NVR_POOL_APPEND) and otherwise replacing the
  * pooled frame with the smallest E, the lowest slot on ties
  * (NVR_POOL_REPLACE); else NVR_POOL_REJECT (slot -1).  E is a distance
  * (frames enter when it is large), so "most similar" is read as smallest E.
  *
  * nvr_pool_select -- the spatial half of the spatial-temporal pool, host
- * only: the slots of the min(m, n_pool) smallest dist (m = 10 in Sec. 4.4),
+ * only: the slots of the min(m, n_pool) smallest dist (m = 10 in Sec. 4.3),
  * ascending, ties by slot, into slots[]; *n_out their number.
  *
  * nvr_depth_assemble -- the per-pixel combination of two renderings by depth:

@@ -1,6 +1,6 @@
 """Pose-conditioned deformation network, FP64 (test infrastructure only).
 
-Paper definitions followed (Sec. 4.2, hybrid deformation; widths in Sec. 4.4):
+Paper definitions followed (Sec. 4.2, hybrid deformation; widths in Sec. 4.3):
 
 * a residual delta_v = MLP([hash(v_t), theta]) is added to the point,
   v_c = v_t + delta_v;

@@ -1,7 +1,7 @@
 """Key-frame selection and the human/object assembly, FP64 (test infrastructure only).
 
-Paper definitions followed (Sec. 4.3, "Online key frame selection"; values
-from Sec. 4.4, implementation details):
+Paper definitions followed (Sec. 4.2, "Online key frame selection"; values
+from Sec. 4.3, implementation details):
 
 * Eq. 5: node i of frame t is visible, s_i^t = 1, when its depth z' differs
   from the depth map D^t at its projected pixel by less than eps = 0.01;

@@ -3,13 +3,13 @@
 The fast neighbour search of Sec. 4.2 ("On-the-fly Radiance Fields"): a
 canonical KNN field lists, for every canonical voxel k, its K nearest embedded-
 graph nodes (built once); at frame t every canonical voxel centre v_k is carried
-to the live space by the node blend of Eq. 2 and the live voxel f it lands in
+to the live space by the node blend of Eq. 1 and the live voxel f it lands in
 records k, so that a live sample finds its canonical voxel, and through it its
 nodes, in O(1).
 
 Paper definitions followed:
 
-* Eq. 2: DQB(v) = sum over the listed nodes i of w(x_i, v) dq_i, and
+* Eq. 1: DQB(v) = sum over the listed nodes i of w(x_i, v) dq_i, and
   v~ = SE3(DQB(v)) v, with x_i the canonical node positions and dq_i the node
   motions of frame t;
 * w(x_i, v) = exp(-|v - x_i|^2 / r^2), r = 0.1 (Sec. 4.1).
@@ -53,7 +53,7 @@ def voxel_centres(lo, hi, res):
 
 
 def forward_dqb(v, ids, node_canon, node_dq, r=R_ED):
-    """Eq. 2 for points v [n][3] with listed node ids [n][K] (nearest first, -1 =
+    """Eq. 1 for points v [n][3] with listed node ids [n][K] (nearest first, -1 =
     none).  Returns (live positions [n][3], carried [n] bool)."""
     v = np.asarray(v, np.float64)
     ids = np.asarray(ids, np.int64)

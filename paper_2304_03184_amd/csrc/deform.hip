@@ -1,5 +1,5 @@
 // Pose-conditioned deformation network (Sec. 4.2, hybrid deformation; widths
-// in Sec. 4.4): v_c = v_t + MLP([hash(v_t), theta]), 104 -> 4 x 128 -> 3,
+// in Sec. 4.3): v_c = v_t + MLP([hash(v_t), theta]), 104 -> 4 x 128 -> 3,
 // bias-free, ReLU on the hidden layers, float32.
 //
 // The encoding runs on the hash-grid kernels of this library (fp32 table);

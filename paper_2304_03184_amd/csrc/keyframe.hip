@@ -1,4 +1,4 @@
-// Key-frame selection (Sec. 4.3, "Online key frame selection") and the
+// Key-frame selection (Sec. 4.2, "Online key frame selection") and the
 // human/object assembly by depth (Sec. 4.3, rendering).
 //
 //   vis_bits     Eq. 5 for every (frame, node): one wave per 64 nodes of a

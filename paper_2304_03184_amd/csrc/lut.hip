@@ -1,6 +1,6 @@
 // Live look-up table of the fast neighbour search (Sec. 4.2, "On-the-fly
 // Radiance Fields"): every canonical voxel centre is carried to the live space
-// by the node blend of Eq. 2 over the nodes its canonical KNN entry lists, and
+// by the node blend of Eq. 1 over the nodes its canonical KNN entry lists, and
 // the live voxel it lands in records the canonical index (the largest one on
 // collisions, -1 where none lands).  Two launches: lut_fill (-1 everywhere)
 // and lut_build (one thread per canonical voxel, an integer atomic max per
@@ -32,7 +32,7 @@ lut_fill(int64_t n, int32_t *__restrict__ lut) {
 // 8-byte load, knn aligned to that; KV = 0: element loads for any k), the node
 // positions and dual quaternions (STAGED: from the workgroup's copy in local
 // memory; otherwise from global memory, two 16-byte loads per node when KV != 0),
-// the blend of Eq. 2, and the atomic max of kk on the live voxel it lands in.
+// the blend of Eq. 1, and the atomic max of kk on the live voxel it lands in.
 template <int KV, bool STAGED>
 __device__ __forceinline__ void carry_voxel(const LutParams &p, uint32_t kk, uint32_t ix,
                                             uint32_t iy, uint32_t iz,

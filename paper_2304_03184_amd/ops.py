@@ -157,7 +157,7 @@ def encode_bwd_binned_grouped(g, x, table, dfeat, dtable, dx=None):
 
 
 def live_lut(knn, node_canon, node_dq, canon_box, canon_res, live_box, live_res, r_ed=0.1):
-    """Live look-up table of the fast neighbour search (Sec. 4.2, Eq. 2): the
+    """Live look-up table of the fast neighbour search (Sec. 4.2, Eq. 1): the
     canonical voxel index per live voxel, -1 for holes.  knn [canon_res^3][K]
     uint16 (int16 storage) node ids, node_canon [n][3], node_dq [n][8]; the boxes
     are (min xyz, max xyz) pairs."""

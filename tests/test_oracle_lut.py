@@ -100,3 +100,25 @@ def test_assembly_keeps_the_largest_index_and_drops_outsiders():
     carried = np.array([True, True, True, True, False, True])
     table = lut.assemble(u, carried, 2)
     np.testing.assert_array_equal(table, [2, 1, -1, -1, -1, -1, -1, 5])
+
+
+def test_forward_blend_unequal_translations_hand_worked():
+    # Eq. 1 with w(x_i, v) = exp(-|v - x_i|^2 / r^2), r = 0.1 (Sec. 4.1): the
+    # point v = (0.03, 0, 0) between two canonical nodes x_A = (0, 0, 0) and
+    # x_B = (0.1, 0, 0) that move by pure translations t_A = (0.02, 0, 0) and
+    # t_B = (0, 0.04, 0).  Weights e^-0.09 and e^-0.49, normalised
+    # 0.598687660112452 and 0.401312339887548; a blend of pure translations is
+    # the translation by their weighted mean (the real parts add to a multiple of
+    # the identity), so v~ = v + (w_A t_A + w_B t_B) / (w_A + w_B)
+    #   = (0.04197375320224904, 0.016052493595501923, 0)   (worked by hand).
+    dq = np.array([[1, 0, 0, 0, 0, 0.01, 0, 0], [1, 0, 0, 0, 0, 0, 0.02, 0]], np.float64)
+    nodes = np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0]])
+    live, carried = lut.forward_dqb(np.array([[0.03, 0.0, 0.0]]), np.array([[0, 1]]), nodes, dq)
+    assert carried[0]
+    np.testing.assert_allclose(live[0], [0.04197375320224904, 0.016052493595501923, 0.0],
+                               rtol=0, atol=1e-15)
+    # the listed order does not matter except for the sign reference
+    live2, _ = lut.forward_dqb(np.array([[0.03, 0.0, 0.0]]), np.array([[1, 0]]), nodes, dq)
+    np.testing.assert_allclose(live2, live, rtol=0, atol=1e-15)
+    # with exp(-d^2 / r) the weights would be nearly equal and v~_y about 0.0196
+    assert abs(live[0, 1] - 0.0196) > 1e-3

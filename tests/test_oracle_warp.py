@@ -163,3 +163,64 @@ def test_backward_vs_fd(rig):
                 rm["bones"][0, j, a, b] -= h
                 fd = (L(rp) - L(rm)) / (2 * h)
                 assert abs(fd - d_bones[0, j, a, b]) < 1e-6 * max(1, abs(fd)), (j, a, b)
+
+
+def _tiny_rig(joints, bones, node_pos, node_dq, knn_ids):
+    """A rig with a 1^3 look-up grid listing ``knn_ids`` for every live point."""
+    return dict(joints=np.asarray(joints, np.float64),
+                bones=np.asarray(bones, np.float64)[None],
+                node_dq=np.asarray(node_dq, np.float64)[None],
+                node_pos=np.asarray(node_pos, np.float64)[None],
+                knn=np.asarray(knn_ids, np.uint16).reshape(1, 1, -1))
+
+
+def _translation_bone(t):
+    b = np.zeros((3, 4))
+    b[0, 0] = b[1, 1] = b[2, 2] = 1.0
+    b[:, 3] = t
+    return b
+
+
+def test_skin_weights_hand_worked():
+    # Inverse skinning with the Gaussian weights over the 4 nearest joints,
+    # sigma_s = 0.1: the live point sits at the origin, joints at distances
+    # 0.1, 0.2, 0.3, 0.4 and 0.5 (the last is not among the 4 nearest), every
+    # bone a pure translation.  With d^2 = 0.01, 0.04, 0.09, 0.16 the exponents
+    # -(d^2 - d_min^2) / (2 sigma_s^2) are 0, -1.5, -4, -7.5, so the normalised
+    # weights are e^0, e^-1.5, e^-4, e^-7.5 over their sum (worked by hand):
+    #   0.8051537029216888, 0.17965407467701772,
+    #   0.014746904472640808, 0.0004453179286526382.
+    # Translations (1,0,0), (0,1,0), (0,0,1), (1,1,1) and (5,5,5) then give
+    # y = (w0 + w3, w1 + w3, w2 + w3); the single identity node leaves it.
+    joints = [[0.1, 0, 0], [0, 0.2, 0], [0, 0, -0.3], [0.4, 0, 0], [0, 0.5, 0]]
+    ts = [[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1], [5, 5, 5]]
+    rig = _tiny_rig(joints, [_translation_bone(t) for t in ts], [[0.0, 0.0, 0.0]],
+                    [[1, 0, 0, 0, 0, 0, 0, 0]], [0])
+    z = warp.warp(np.zeros((1, 3), np.float32), rig, LO, HI)
+    want = [0.8055990208503414, 0.18009939260567034, 0.015192222401293446]
+    np.testing.assert_allclose(z[0], want, rtol=0, atol=1e-15)
+    # a width of sigma_s^2 instead of 2 sigma_s^2 would give (0.950..., 0.0497..., ...)
+    assert abs(z[0, 0] - 0.95) > 0.1
+
+
+def test_inverse_node_blend_unequal_translations_hand_worked():
+    # Eq. 4 with the node weight of Sec. 4.1 (r = 0.1) at the post-skinning
+    # point y (identity bones, so y = x = (0.03, 0, 0)) against two deformed
+    # nodes g_A = (0, 0, 0) and g_B = (0.1, 0, 0) moving by pure translations
+    # t_A = (0.02, 0, 0) and t_B = (0, 0.04, 0).  The weights are
+    # exp(-|y - g|^2 / r^2) = e^-0.09 and e^-0.49, normalised 0.598687660112452
+    # and 0.401312339887548; the blend of the conjugated (inverse) motions is the
+    # inverse translation by the weighted mean, so
+    #   z = y - (w_A t_A + w_B t_B) / (w_A + w_B)
+    #     = (0.01802624679775096, -0.016052493595501923, 0)   (worked by hand).
+    eye = _translation_bone([0, 0, 0])
+    dq_a = [1, 0, 0, 0, 0, 0.01, 0, 0]           # dual part t/2 for a pure translation
+    dq_b = [1, 0, 0, 0, 0, 0, 0.02, 0]
+    rig = _tiny_rig([[0.0, 0.0, 0.0]], [eye], [[0.0, 0.0, 0.0], [0.1, 0.0, 0.0]],
+                    [dq_a, dq_b], [0, 1])
+    z = warp.warp(np.array([[0.03, 0.0, 0.0]], np.float32), rig, LO, HI, k_joints=1)
+    x0 = float(np.float32(0.03))                 # the live point as float32
+    want = [x0 - 0.03 + 0.01802624679775096, -0.016052493595501923, 0.0]
+    np.testing.assert_allclose(z[0], want, rtol=0, atol=2e-9)
+    # weights exp(-d^2 / r) (r instead of r^2) would move z[1] to about -0.0196
+    assert abs(z[0, 1] + 0.0196) > 1e-3
