@@ -164,6 +164,24 @@ nvr_status nvr_march(const nvr_march_desc *m, int64_t n_rays, int64_t ray_begin,
                      int32_t *ray_id, float *t, float *dt, float *x, int32_t *n_dev,
                      void *workspace, nvr_stream stream);
 
+/* nvr_march without a workspace argument and without any device allocation,
+ * for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, outputs
+ * and errors as nvr_march; the scan's block sums live in a fixed library array
+ * of 256 KiB per device (one int32 per 256 rays), so n_rays is limited to
+ * 2^24 (larger counts return NVR_EINVAL before any launch).  That array's
+ * device address is looked up on the first call made with a device current
+ * (the stream, if not the null stream, must belong to the current device);
+ * every call on one device shares it, so calls that overlap in time on one
+ * device (different streams, threads) race and must be serialised by the
+ * caller.  Each call rewrites every entry it reads, so nothing carries over
+ * from the previous call. */
+nvr_status nvr_march_noalloc(const nvr_march_desc *m, int64_t n_rays, int64_t ray_begin,
+                             int64_t ray_end, const float *o, const float *d,
+                             const uint32_t *occ, int64_t capacity, int32_t *off,
+                             int32_t *ray_id, float *t, float *dt, float *x, int32_t *n_dev,
+                             nvr_stream stream);
+
 /* ------------------------------------------------------------------------
  * Hybrid warp live -> canonical (Sec. 4.2, Eq. 4, with the node weight of
  * Sec. 4.1 after Eq. 1, r = 0.1, and the voxel look-up of neighbour nodes of

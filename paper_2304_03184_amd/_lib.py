@@ -121,6 +121,8 @@ _SIGS = {
     "nvr_march_workspace": (C.c_size_t, [i64]),
     "nvr_march": (i32, [P(MarchDesc), i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp,
                         vp, vp]),
+    "nvr_march_noalloc": (i32, [P(MarchDesc), i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp,
+                                vp, vp, vp]),
     "nvr_warp_fwd": (i32, [P(WarpDesc), P(WarpRig), i64, vp, vp, vp, vp, vp]),
     "nvr_warp_bwd": (i32, [P(WarpDesc), P(WarpRig), i64, vp, vp, vp, vp, i32, vp, vp, vp]),
     "nvr_mlp_param_count": (i32, [P(MlpDesc), P(i64)]),

@@ -17,6 +17,7 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <mutex>
 
 namespace nvr {
 
@@ -276,6 +277,77 @@ extern "C" nvr_status nvr_march(const nvr_march_desc *m, int64_t n_rays, int64_t
     if (capacity > 0) NVR_REQUIRE(ray_id && t && dt && x, NVR_EINVAL, "NULL sample arrays");
     return launch_march(p, n_rays, o, d, occ, capacity, off, ray_id, t, dt, x, n_dev,
                         (int32_t *)workspace, hs(stream));
+}
+
+// ---------------------------------------------------------------- no-alloc entry
+// nvr_march_noalloc keeps the per-block sums of the scan in a file-scope device
+// array instead of a caller workspace.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol): the device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+namespace nvr {
+
+constexpr int64_t kNoAllocMaxRays = 1ll << 24;
+constexpr int kMaxDevices = 64;
+
+}  // namespace nvr
+
+static __device__ __align__(256) int32_t scratch[nvr::kNoAllocMaxRays / nvr::kMarchBlock + 1];
+
+namespace nvr {
+
+static std::mutex g_scratch_mu;
+static int32_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+static nvr_status scratch_on_current_device(hipStream_t st, int32_t **out) {
+    int dev = -1;
+    NVR_HIP(hipGetDevice(&dev));
+    NVR_REQUIRE(dev >= 0 && dev < kMaxDevices, NVR_EUNSUPPORTED, "device %d beyond %d", dev,
+                kMaxDevices);
+    if (st != nullptr) {
+        int sdev = -1;
+        NVR_HIP(hipStreamGetDevice(st, &sdev));
+        NVR_REQUIRE(sdev == dev, NVR_EINVAL,
+                    "stream belongs to device %d but device %d is current", sdev, dev);
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        NVR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        NVR_REQUIRE(p != nullptr, NVR_EHIP, "hipGetSymbolAddress returned NULL");
+        g_scratch_ptr[dev] = static_cast<int32_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return NVR_OK;
+}
+
+}  // namespace nvr
+
+extern "C" nvr_status nvr_march_noalloc(const nvr_march_desc *m, int64_t n_rays,
+                                        int64_t ray_begin, int64_t ray_end, const float *o,
+                                        const float *d, const uint32_t *occ, int64_t capacity,
+                                        int32_t *off, int32_t *ray_id, float *t, float *dt,
+                                        float *x, int32_t *n_dev, nvr_stream stream) {
+    clear_error();
+    MarchParams p;
+    NVR_TRY(make_march_params(m, ray_begin, ray_end, &p));
+    NVR_REQUIRE(n_rays >= 0 && n_rays <= kNoAllocMaxRays, NVR_EINVAL,
+                "n_rays %lld outside 0..%lld (the fixed scratch holds the block sums of at "
+                "most 2^24 rays)", (long long)n_rays, (long long)kNoAllocMaxRays);
+    NVR_REQUIRE(ray_begin >= 0 && ray_begin <= ray_end && ray_end <= n_rays, NVR_EINVAL,
+                "ray range [%lld, %lld) not inside [0, %lld)", (long long)ray_begin,
+                (long long)ray_end, (long long)n_rays);
+    NVR_REQUIRE(capacity >= 0 && capacity < (1ll << 31), NVR_EINVAL, "capacity out of range");
+    NVR_REQUIRE(off && n_dev, NVR_EINVAL, "NULL off / n_dev");
+    NVR_REQUIRE(m->occ_res == 0 || occ != nullptr, NVR_EINVAL, "occ is NULL but occ_res > 0");
+    if (n_rays > 0) NVR_REQUIRE(o && d, NVR_EINVAL, "NULL rays");
+    if (capacity > 0) NVR_REQUIRE(ray_id && t && dt && x, NVR_EINVAL, "NULL sample arrays");
+    int32_t *ws = nullptr;
+    NVR_TRY(scratch_on_current_device(hs(stream), &ws));
+    // every block sum the scan reads is written by the count launch of this call
+    return launch_march(p, n_rays, o, d, occ, capacity, off, ray_id, t, dt, x, n_dev, ws,
+                        hs(stream));
 }
 
 #include "launch.hpp"
