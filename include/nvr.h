@@ -115,6 +115,20 @@ nvr_status nvr_encode_bwd_binned(const nvr_grid_desc *g, int64_t n, const float 
                                  const void *table, const float *dfeat, float *dtable,
                                  float *dx, void *workspace, nvr_stream stream);
 
+/* nvr_encode_bwd_binned with every sum formed in an order fixed by the inputs
+ * alone, so repeated calls give bit-identical dtable and dx whatever the
+ * timing of the launch: each tile's records are placed by level, then by
+ * chunk of 512 samples, wavefront, corner and lane (counts per chunk and
+ * tile are formed and scanned first, instead of reserving ranges with
+ * atomics), and one lane adds all records of an entry in that order.  Same
+ * arguments, record rounding and errors as nvr_encode_bwd_binned; workspace
+ * (device, 256-byte aligned) of nvr_encode_bwd_deterministic_workspace(g, n)
+ * bytes (it adds one uint32 per chunk and tile), owned by the caller. */
+size_t nvr_encode_bwd_deterministic_workspace(const nvr_grid_desc *g, int64_t n);
+nvr_status nvr_encode_bwd_deterministic(const nvr_grid_desc *g, int64_t n, const float *x,
+                                        const void *table, const float *dfeat, float *dtable,
+                                        float *dx, void *workspace, nvr_stream stream);
+
 /* The level-group ("grouped") layout the fused step keeps features and their
  * gradients in: [8][n][2 lpg] with lpg = ceil(L / 8), level l = g + 8 m at
  * [g][s][2m, 2m+1] (slots of levels >= L are written as 0 / ignored); F = 2
@@ -221,12 +235,14 @@ nvr_status nvr_warp_fwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t
 
 /* Backward of sum(dx_can . x_can): d_node_dq[n_frames][n_nodes][8] (acc)
  * through the blend; d_bones[n_frames][n_joints][12] (acc, nullable) through
- * y including y's effect on the node weights.  dx_can may be given as
- * n_parts partial arrays of [n][3] laid out back to back, which are summed. */
+ * y including y's effect on the node weights; dx_live[n][3] (acc, nullable)
+ * through the skinning blend, its weights and the node weights (the joint and
+ * voxel choices are locally constant).  dx_can may be given as n_parts
+ * partial arrays of [n][3] laid out back to back, which are summed. */
 nvr_status nvr_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t n,
                         const int32_t *n_dev, const float *x_live, const int32_t *frame,
                         const float *dx_can, int32_t n_parts, float *d_node_dq,
-                        float *d_bones, nvr_stream stream);
+                        float *d_bones, float *dx_live, nvr_stream stream);
 
 /* ------------------------------------------------------------------------
  * Density + colour networks of a field (Sec. 4.2: geometry network E_g and
@@ -401,6 +417,17 @@ nvr_status nvr_create(nvr_ctx **out, int32_t device, uint32_t flags);
  * them.  Only shape-independent results are produced: the tuned step differs
  * from an untuned one only in the summation order of gradients. */
 #define NVR_AUTOTUNE 2u
+/* NVR_DETERMINISTIC: every sum of a training step is formed in an order fixed
+ * by the inputs, so a step repeated on the same state and batch (eagerly or
+ * from a captured graph) gives bit-identical losses, gradients and
+ * parameters: the BF16 step's table gradients go through the deterministic
+ * binned scatter (see nvr_encode_bwd_deterministic) and the autotuner is off
+ * (launch shapes change summation groupings).  The node and bone gradients of
+ * a warped field are still accumulated with float atomics (the optimiser does
+ * not read them).  The network weight gradients and the loss are summed in a
+ * fixed order with or without this flag.  The F32 step keeps its float
+ * atomics on the table gradients either way. */
+#define NVR_DETERMINISTIC 4u
 void nvr_destroy(nvr_ctx *ctx);
 
 /* Forward half: march, warp, encode, networks, composite, loss.  Writes

@@ -123,8 +123,10 @@ def warp(x, rig, grid_lo, grid_hi, frame=None, k_joints=4, r=R_ED, sigma_s=SIGMA
          want_cache=False):
     """x (n,3) live samples; rig: dict(joints (24,3), bones (F,24,3,4),
     node_dq (F,M,8), node_pos (F,M,3), knn (F,res^3,K)).  Returns z (n,3)."""
+    # joint and voxel choices are float32 decisions on the rounded position;
+    # the arithmetic runs in float64 on the position as given
     x32 = np.asarray(x, f32)
-    x = x32.astype(np.float64)
+    x = np.asarray(x, np.float64)
     n = x.shape[0]
     fr = _gather(rig, frame, n)
     J = np.asarray(rig["joints"], np.float64)
@@ -189,8 +191,11 @@ def _grad_c(c, y, gz):
 
 
 def warp_backward(x, rig, grid_lo, grid_hi, gz, frame=None, k_joints=4, r=R_ED,
-                  sigma_s=SIGMA_SKIN):
-    """Gradients of sum(gz . z): returns (d_node_dq (F,M,8), d_bones (F,24,3,4))."""
+                  sigma_s=SIGMA_SKIN, want_dx=False):
+    """Gradients of sum(gz . z): returns (d_node_dq (F,M,8), d_bones (F,24,3,4)),
+    and with ``want_dx`` also dx (n,3), the gradient with respect to the live
+    positions (through the skinning blend, its weights and the node weights;
+    the float32 joint / voxel choices are locally constant)."""
     z, C = warp(x, rig, grid_lo, grid_hi, frame, k_joints, r, sigma_s, want_cache=True)
     gz = np.asarray(gz, np.float64)
     gc, gy = _grad_c(C["c"], C["y"], gz)
@@ -212,4 +217,17 @@ def warp_backward(x, rig, grid_lo, grid_hi, gz, frame=None, k_joints=4, r=R_ED,
     gM = C["lw"][:, :, None, None] * gy[:, None, :, None] * C["xh"][:, None, None, :]
     d_bones = np.zeros_like(np.asarray(rig["bones"], np.float64))
     np.add.at(d_bones, (C["fr"][:, None].repeat(C["jsel"].shape[1], 1), C["jsel"]), gM)
-    return d_dq, d_bones
+    if not want_dx:
+        return d_dq, d_bones
+    # y = sum_j lw_j M_j xh with lw = softmax_j(-|x - J_j|^2 / (2 sigma^2)):
+    # dy/dx = sum_j lw_j R_j + sum_j (M_j xh) (a_j - a_bar)^T lw_j,
+    # a_j = -(x - J_j) / sigma^2, a_bar = sum_k lw_k a_k
+    Jsel = np.asarray(rig["joints"], np.float64)[C["jsel"]]           # (n,4,3)
+    a = -(C["x"][:, None, :] - Jsel) / sigma_s ** 2
+    a_bar = np.einsum("nk,nka->na", C["lw"], a)
+    R = C["M"][..., :3]                                                # (n,4,3,3)
+    yj = np.einsum("nkab,nb->nka", C["M"], C["xh"])
+    gx = np.einsum("nk,nkab,na->nb", C["lw"], R, gy)
+    gx += np.einsum("nk,nk,nka->na", C["lw"], np.einsum("nka,na->nk", yj, gy),
+                    a - a_bar[:, None, :])
+    return d_dq, d_bones, gx

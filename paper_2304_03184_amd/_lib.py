@@ -18,6 +18,7 @@ NVR_OK, NVR_EINVAL, NVR_EUNSUPPORTED, NVR_EHIP, NVR_ENOMEM, NVR_ENONFINITE, NVR_
 NVR_F32, NVR_F16, NVR_BF16 = 0, 1, 2
 NVR_USE_GRAPH = 1
 NVR_AUTOTUNE = 2
+NVR_DETERMINISTIC = 4
 MAX_LEVELS = 32
 
 
@@ -101,6 +102,8 @@ _SIGS = {
     "nvr_encode_bwd": (i32, [P(GridDesc), i64, vp, vp, i32, vp, vp, vp, vp]),
     "nvr_encode_bwd_workspace": (C.c_size_t, [P(GridDesc), i64]),
     "nvr_encode_bwd_binned": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
+    "nvr_encode_bwd_deterministic_workspace": (C.c_size_t, [P(GridDesc), i64]),
+    "nvr_encode_bwd_deterministic": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_encode_fwd_grouped": (i32, [P(GridDesc), i64, vp, vp, vp, vp]),
     "nvr_encode_bwd_binned_grouped": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_occupancy_workspace": (C.c_size_t, [P(Field), i32, i64]),
@@ -124,7 +127,7 @@ _SIGS = {
     "nvr_march_noalloc": (i32, [P(MarchDesc), i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp,
                                 vp, vp, vp]),
     "nvr_warp_fwd": (i32, [P(WarpDesc), P(WarpRig), i64, vp, vp, vp, vp, vp]),
-    "nvr_warp_bwd": (i32, [P(WarpDesc), P(WarpRig), i64, vp, vp, vp, vp, i32, vp, vp, vp]),
+    "nvr_warp_bwd": (i32, [P(WarpDesc), P(WarpRig), i64, vp, vp, vp, vp, i32, vp, vp, vp, vp]),
     "nvr_mlp_param_count": (i32, [P(MlpDesc), P(i64)]),
     "nvr_mlp_fwd": (i32, [P(MlpDesc), i64, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp]),
     "nvr_mlp_workspace": (C.c_size_t, [P(MlpDesc), i32, i64]),

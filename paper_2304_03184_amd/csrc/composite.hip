@@ -97,6 +97,35 @@ __device__ __forceinline__ void block_sum_atomic(float v, float *out) {
     }
 }
 
+// Block sum to partials[blockIdx.x] (plain store), summed later in a fixed order.
+__device__ __forceinline__ void block_sum_store(float v, float *partials) {
+    __shared__ float red[8];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += red[i];
+        partials[blockIdx.x] = s;
+    }
+}
+
+// out[0] = sum of partials[0, n) in a fixed order (one workgroup of 256).
+__global__ void __launch_bounds__(256)
+sum_in_order(int n, const float *__restrict__ partials, float *__restrict__ out) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) s += partials[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 __device__ __forceinline__ float ray_loss(int64_t r, const float *C, float Dv, const float *C_t,
                                           const float *D_t, const float *mask, float lambda_d,
                                           float inv_R, float S, float *gc, float *gd) {
@@ -138,7 +167,7 @@ composite_loss_fused(int64_t n_rays, nvr_samples a, nvr_samples b, bool has_b,
                      const nvr_train_state *__restrict__ state, float *__restrict__ loss,
                      float *__restrict__ C_out, float *__restrict__ D_out,
                      float *__restrict__ dsa, float *__restrict__ dra, float *__restrict__ dsb,
-                     float *__restrict__ drb) {
+                     float *__restrict__ drb, float *__restrict__ partials) {
     const int gl = threadIdx.x % kGroup;
     const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kGroup);
     float l = 0.f;
@@ -160,7 +189,8 @@ composite_loss_fused(int64_t n_rays, nvr_samples a, nvr_samples b, bool has_b,
         }
         if (dsa) group_ray_backward(a, b, has_b, r, gl, acc.c, acc.d, gc, gd, dsa, dra, dsb, drb);
     }
-    block_sum_atomic(l, loss);
+    if (partials) block_sum_store(l, partials);
+    else block_sum_atomic(l, loss);
 }
 
 nvr_status launch_fill_zero(float *p, int64_t n, hipStream_t st) {
@@ -174,14 +204,19 @@ nvr_status launch_composite_loss(int64_t n_rays, const nvr_samples &a, const nvr
                                  const float *C_t, const float *D_t, const float *mask,
                                  float lambda_d, const nvr_train_state *state, float *loss,
                                  float *C_out, float *D_out, float *dsa, float *dra, float *dsb,
-                                 float *drb, hipStream_t st, int blocks) {
-    NVR_TRY(launch_fill_zero(loss, 1, st));
+                                 float *drb, hipStream_t st, int blocks, float *partials) {
+    if (n_rays <= 0 || partials == nullptr) NVR_TRY(launch_fill_zero(loss, 1, st));
     if (n_rays <= 0) return NVR_OK;
     nvr_samples bb = b ? *b : nvr_samples{};
-    composite_loss_fused<<<grid_for(n_rays * kGroup, 256, blocks > 0 ? blocks : 65536), 256, 0, st>>>(
+    const unsigned gr = grid_for(n_rays * kGroup, 256, blocks > 0 ? blocks : kMaxLossBlocks);
+    composite_loss_fused<<<gr, 256, 0, st>>>(
         n_rays, a, bb, b != nullptr, C_t, D_t, mask, lambda_d, state, loss, C_out, D_out, dsa, dra,
-        dsb, drb);
+        dsb, drb, partials);
     NVR_LAUNCHED();
+    if (partials) {
+        sum_in_order<<<1, 256, 0, st>>>((int)gr, partials, loss);
+        NVR_LAUNCHED();
+    }
     return NVR_OK;
 }
 

@@ -227,7 +227,11 @@ nvr_status launch_composite_loss(int64_t n_rays, const nvr_samples &a, const nvr
                                  const float *C_t, const float *D_t, const float *mask,
                                  float lambda_d, const nvr_train_state *state, float *loss,
                                  float *C_out, float *D_out, float *dsa, float *dra, float *dsb,
-                                 float *drb, hipStream_t st, int blocks = 0);
+                                 float *drb, hipStream_t st, int blocks = 0,
+                                 float *partials = nullptr);
+// most workgroups launch_composite_loss uses; partials (nullable) holds one
+// float per workgroup, and makes the loss a fixed-order sum of them
+constexpr int kMaxLossBlocks = 65536;
 nvr_status launch_composite_fwd(int64_t n_rays, const nvr_samples &a, const nvr_samples *b,
                                 float t_stop, float *C, float *D, float *TN, hipStream_t st);
 

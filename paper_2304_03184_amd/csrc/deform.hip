@@ -15,6 +15,7 @@
 
 #include "common.hpp"
 #include "grid_dev.hpp"
+#include "scatter_dev.hpp"
 
 namespace nvr {
 namespace {
@@ -246,13 +247,19 @@ const float *layer_w(const float *params, int i) {
     return params + (int64_t)kWidth * kIn + (int64_t)(i - 1) * kWidth * kWidth;
 }
 
+// Every check of both entry points, including those of the encoding and the
+// binned scatter they call, so that nothing is launched before an error.
 nvr_status check(const nvr_grid_desc *g, int64_t n, const void *ws) {
     NVR_REQUIRE(g != nullptr, NVR_EINVAL, "grid descriptor is NULL");
+    NVR_TRY(check_grid(g));
     NVR_REQUIRE(g->n_levels * g->n_features == kFeat, NVR_EUNSUPPORTED,
                 "the deformation encoding must be 32 wide (levels x features)");
     NVR_REQUIRE(n >= 0 && n <= (1ll << 31) / kWidth, NVR_EINVAL, "n out of 0..2^24");
     NVR_REQUIRE(n == 0 || (ws && aligned(ws, 256)), NVR_EINVAL,
                 "workspace NULL or not 256-byte aligned");
+    const GridParams p = make_grid_params(g);
+    NVR_TRY(scatter_check(p));
+    NVR_REQUIRE((size_t)n * p.L * 8 < (1ull << 32), NVR_EINVAL, "too many contributions");
     return NVR_OK;
 }
 
@@ -317,7 +324,9 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(x && theta && table && params && dx_can && dparams && dtable, NVR_EINVAL,
                 "NULL array");
-    NVR_REQUIRE(aligned(x, 4) && aligned(table, 8) && aligned(dtable, 8) && aligned(dx, 4),
+    NVR_REQUIRE(aligned(x, 4) && aligned(theta, 4) && aligned(table, 8) && aligned(params, 4) &&
+                    aligned(dx_can, 4) && aligned(dparams, 4) && aligned(dtable, 8) &&
+                    aligned(dx, 4) && aligned(dtheta, 4),
                 NVR_EINVAL, "misaligned array");
     const hipStream_t st = hs(stream);
     rocblas_handle h;

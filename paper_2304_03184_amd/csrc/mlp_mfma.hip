@@ -573,27 +573,35 @@ mlp_bwd_mfma(MfmaNet net, int64_t n, const int32_t *__restrict__ n_dev, int64_t 
     for (int i = threadIdx.x; i < np; i += blockDim.x) red[i] = 0.f;
     __syncthreads();
     const int cin = 16 + nsh;
+    // the wavefronts add their sums one after the other (a fixed order, so the
+    // partials do not depend on timing); inside one wavefront every lane owns
+    // distinct (row, column) entries
     auto put = [&](int64_t off, int ncol, int nrow, int mo, int ti, f4 v) {
         const int col = 16 * ti + c;
         if (col >= ncol) return;
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * mo + 4 * g + r;
-            if (row < nrow) atomicAdd(red + (off - net.off_d1) + row * ncol + col, v[r]);
+            if (row < nrow) red[(off - net.off_d1) + row * ncol + col] += v[r];
         }
     };
-    for (int mo = 0; mo < 4; ++mo)
-        for (int ti = 0; ti < 2; ++ti) {
-            put(net.off_d1, net.n_in, 64, mo, ti, acc.d1[mo][ti]);
-            put(net.off_c1, cin, 64, mo, ti, acc.c1[mo][ti]);
+    const int my_wave = threadIdx.x >> 6;
+    for (int wv = 0; wv < kMfmaBlock / 64; ++wv) {
+        if (my_wave == wv) {
+            for (int mo = 0; mo < 4; ++mo)
+                for (int ti = 0; ti < 2; ++ti) {
+                    put(net.off_d1, net.n_in, 64, mo, ti, acc.d1[mo][ti]);
+                    put(net.off_c1, cin, 64, mo, ti, acc.c1[mo][ti]);
+                }
+            for (int ti = 0; ti < 4; ++ti) {
+                put(net.off_d2, 64, 16, 0, ti, acc.d2[ti]);
+                put(net.off_c3, 64, 3, 0, ti, acc.c3[ti]);
+            }
+            if (NCH == 2)
+                for (int mo = 0; mo < 4; ++mo)
+                    for (int ti = 0; ti < 4; ++ti) put(net.off_c2, 64, 64, mo, ti, acc.c2[mo][ti]);
         }
-    for (int ti = 0; ti < 4; ++ti) {
-        put(net.off_d2, 64, 16, 0, ti, acc.d2[ti]);
-        put(net.off_c3, 64, 3, 0, ti, acc.c3[ti]);
+        __syncthreads();
     }
-    if (NCH == 2)
-        for (int mo = 0; mo < 4; ++mo)
-            for (int ti = 0; ti < 4; ++ti) put(net.off_c2, 64, 64, mo, ti, acc.c2[mo][ti]);
-    __syncthreads();
     float *dst = partial + (int64_t)blockIdx.x * np;
     for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = red[i];
 }

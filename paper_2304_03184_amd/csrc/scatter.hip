@@ -635,6 +635,396 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     return NVR_OK;
 }
 
+// ---------------------------------------------------------------- deterministic variant
+// The same records and sums in an order fixed by the inputs alone.  A tile's
+// range holds its levels in increasing order; a level's records are ordered by
+// chunk (kDetBlock consecutive samples), inside a chunk by wavefront, then by
+// corner, then by lane.  Counts per (chunk, level, tile) are formed first and
+// scanned over the chunks, so no range is reserved in a race; ranks inside a
+// wavefront come from ballots; the accumulation gives every entry of a tile
+// to one lane, which adds that entry's records in range order.  Split tiles
+// are added up slab by slab in item order as before.
+constexpr int kDetBlock = 512;
+constexpr int kDetWaves = kDetBlock / 64;
+
+struct DetSeg {
+    int at[NVR_MAX_LEVELS + 1];   // first column of level l's tiles in a count row
+};
+
+static DetSeg det_segments(const GridParams &p, int tb) {
+    DetSeg sg;
+    int s = 0;
+    for (int l = 0; l < p.L; ++l) {
+        sg.at[l] = s;
+        s += (int)(((p.off[l + 1] - 1) >> tb) - (p.off[l] >> tb) + 1);
+    }
+    for (int l = p.L; l <= NVR_MAX_LEVELS; ++l) sg.at[l] = s;
+    return sg;
+}
+
+static size_t det_lds_bytes(int lt) {
+    return sizeof(uint32_t) * ((size_t)(2 + kDetWaves) * lt + 16) +
+           (sizeof(uint2) + sizeof(uint16_t)) * 8 * kDetBlock;
+}
+
+size_t scatter_det_ws_bytes(const GridParams &p, int64_t cap) {
+    const int tb = tile_bits(p);
+    const DetSeg sg = det_segments(p, tb);
+    const int64_t nc = (cap + kDetBlock - 1) / kDetBlock;
+    return ((scatter_ws_bytes(p, cap) + 255) & ~size_t(255)) +
+           sizeof(uint32_t) * (size_t)nc * sg.at[p.L];
+}
+
+// seg[c][sg.at[l] + j] = records of chunk c that level l puts into its j-th
+// tile; tile_count[t] += the same (integer sums: order-free).
+template <int LPG>
+__global__ void __launch_bounds__(kDetBlock)
+det_count(GridParams p, int tb, DetSeg sg, int64_t n, const int32_t *__restrict__ n_dev,
+          int64_t cap, const float *__restrict__ x, uint32_t *__restrict__ seg,
+          uint32_t *__restrict__ tile_count) {
+    extern __shared__ uint32_t hist[];
+    const int64_t count = count_of(n, n_dev, cap);
+    const int g = blockIdx.x % kXcds;
+    const int64_t chunks = gridDim.x / kXcds;
+    const int S = sg.at[p.L];
+    for (int64_t c = blockIdx.x / kXcds; c * kDetBlock < count; c += chunks) {
+        const int64_t s = c * kDetBlock + threadIdx.x;
+        const bool valid = s < count;
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if (valid) {
+            px = x[3 * s];
+            py = x[3 * s + 1];
+            pz = x[3 * s + 2];
+        }
+        for (int m = 0; m < LPG; ++m) {
+            const int l = g + kXcds * m;
+            if (l >= p.L) break;
+            const int t_lo = (int)(p.off[l] >> tb);
+            const int n_lt = (int)((p.off[l + 1] - 1) >> tb) - t_lo + 1;
+            for (int t = threadIdx.x; t < n_lt; t += kDetBlock) hist[t] = 0u;
+            __syncthreads();
+            if (valid) {
+                const LevelPos lp = level_pos(p, l, px, py, pz);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    atomicAdd(&hist[(int)((p.off[l] + corner_index(p, l, lp, k)) >> tb) - t_lo], 1u);
+            }
+            __syncthreads();
+            uint32_t *row = seg + (size_t)c * S + sg.at[l];
+            for (int t = threadIdx.x; t < n_lt; t += kDetBlock) {
+                const uint32_t h = hist[t];
+                row[t] = h;
+                if (h) atomicAdd(&tile_count[t_lo + t], h);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// One thread per tile: the running position through the tile's levels (in
+// increasing order) and, inside each, its chunks; seg becomes the first
+// position of every (chunk, level, tile) run.
+__global__ void __launch_bounds__(256)
+det_seg_scan(GridParams p, int tb, DetSeg sg, int n_tiles, int64_t n,
+             const int32_t *__restrict__ n_dev, int64_t cap, const uint32_t *__restrict__ start,
+             uint32_t *__restrict__ seg) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t count = count_of(n, n_dev, cap);
+    const int64_t nc = (count + kDetBlock - 1) / kDetBlock;
+    const size_t S = (size_t)sg.at[p.L];
+    uint32_t run = start[t];
+    for (int l = 0; l < p.L; ++l) {
+        const int t_lo = (int)(p.off[l] >> tb), t_hi = (int)((p.off[l + 1] - 1) >> tb);
+        if (t < t_lo || t > t_hi) continue;
+        uint32_t *col = seg + sg.at[l] + (t - t_lo);
+        int64_t c = 0;
+        for (; c + 4 <= nc; c += 4) {
+            const uint32_t v0 = col[c * S], v1 = col[(c + 1) * S], v2 = col[(c + 2) * S],
+                           v3 = col[(c + 3) * S];
+            col[c * S] = run;
+            col[(c + 1) * S] = run + v0;
+            col[(c + 2) * S] = run + v0 + v1;
+            col[(c + 3) * S] = run + v0 + v1 + v2;
+            run += v0 + v1 + v2 + v3;
+        }
+        for (; c < nc; ++c) {
+            const uint32_t v = col[c * S];
+            col[c * S] = run;
+            run += v;
+        }
+    }
+}
+
+template <int LPG>
+__global__ void __launch_bounds__(kDetBlock)
+det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__restrict__ n_dev,
+         int64_t cap, const float *__restrict__ x, const uint32_t *__restrict__ table,
+         const float *__restrict__ dfeat, uint32_t n_records, const uint32_t *__restrict__ seg,
+         uint2 *__restrict__ recs, float *__restrict__ dx_parts) {
+    extern __shared__ uint32_t lds[];
+    uint32_t *hist = lds;                               // [lt] chunk totals, then bases
+    uint32_t *delta = hist + lt;                        // [lt] global - local position
+    uint32_t *wc = delta + lt;                          // [waves][lt] counts, then prefixes
+    uint32_t *part = wc + kDetWaves * lt;               // [16]
+    uint2 *srec = reinterpret_cast<uint2 *>(part + 16);                   // [8 * block]
+    uint16_t *stile = reinterpret_cast<uint16_t *>(srec + 8 * kDetBlock);  // their tiles - t_lo
+    const int64_t count = count_of(n, n_dev, cap);
+    const int g = blockIdx.x % kXcds;
+    const int64_t chunks = gridDim.x / kXcds;
+    const int kb = (tb + 1) >> 1;
+    const int S = sg.at[p.L];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int64_t c = blockIdx.x / kXcds; c * kDetBlock < count; c += chunks) {
+        const int64_t s = c * kDetBlock + threadIdx.x;
+        const bool valid = s < count;
+        const int64_t left = count - c * kDetBlock;
+        const uint32_t n_rec = 8u * (uint32_t)(left < (int64_t)kDetBlock ? left : kDetBlock);
+        float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if (valid) {
+            px = x[3 * s];
+            py = x[3 * s + 1];
+            pz = x[3 * s + 2];
+        }
+        for (int m = 0; m < LPG; ++m) {
+            const int l = g + kXcds * m;
+            if (l >= p.L) break;
+            const int t_lo = (int)(p.off[l] >> tb);
+            const int n_lt = (int)((p.off[l + 1] - 1) >> tb) - t_lo + 1;
+            for (int t = threadIdx.x; t < kDetWaves * n_lt; t += kDetBlock) wc[t] = 0u;
+            __syncthreads();
+            uint32_t ent[8], rank[8];
+            int key[8];
+            float v0[8], v1[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                key[k] = -1;
+                rank[k] = 0u;
+            }
+            if (valid) {
+                const LevelPos lp = level_pos(p, l, px, py, pz);
+                const float *src = dfeat + ((size_t)g * cap + s) * (2 * LPG) + 2 * m;
+                const float g0 = src[0], g1 = src[1];
+                float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float w = corner_weight(lp, k);
+                    const uint32_t e = p.off[l] + corner_index(p, l, lp, k);
+                    ent[k] = e;
+                    key[k] = (int)(e >> tb) - t_lo;
+                    v0[k] = w * g0;
+                    v1[k] = w * g1;
+                    if (dx_parts != nullptr) {
+                        const uint32_t v = table[e];
+                        const float tg = f16_bits_to_f32((uint16_t)(v & 0xffffu)) * g0 +
+                                         f16_bits_to_f32((uint16_t)(v >> 16)) * g1;
+                        const float3 dw = corner_dweight(lp, k);
+                        e0 += dw.x * tg;
+                        e1 += dw.y * tg;
+                        e2 += dw.z * tg;
+                    }
+                }
+                if (dx_parts != nullptr) {
+                    const float N = (float)p.res[l];
+                    if (lp.inside[0]) d0 += e0 * N * (float)p.inv_side[0];
+                    if (lp.inside[1]) d1 += e1 * N * (float)p.inv_side[1];
+                    if (lp.inside[2]) d2 += e2 * N * (float)p.inv_side[2];
+                }
+            }
+            // stable ranks inside the wavefront, corner-major then lane order;
+            // the wavefront's running count per tile lives in its own LDS row
+            uint32_t *mine = wc + wave * n_lt;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                uint64_t todo = __ballot(key[k] >= 0);
+                while (todo) {
+                    const int leader = __ffsll((unsigned long long)todo) - 1;
+                    const int K = __shfl(key[k], leader, 64);
+                    const uint64_t same = __ballot(key[k] == K);
+                    const uint32_t base = __hip_atomic_load(mine + K, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    if (key[k] == K) rank[k] = base + (uint32_t)__popcll(same & below);
+                    if (lane == leader)
+                        __hip_atomic_store(mine + K, base + (uint32_t)__popcll(same),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    todo &= ~same;
+                }
+            }
+            __syncthreads();
+            // per tile: exclusive prefix over the wavefronts (in place) and chunk total
+            for (int t = threadIdx.x; t < n_lt; t += kDetBlock) {
+                uint32_t run = 0u;
+                for (int w = 0; w < kDetWaves; ++w) {
+                    const uint32_t v = wc[w * n_lt + t];
+                    wc[w * n_lt + t] = run;
+                    run += v;
+                }
+                hist[t] = run;
+                delta[t] = seg[(size_t)c * S + sg.at[l] + t];
+            }
+            block_exclusive_scan(hist, n_lt, part);
+            for (int t = threadIdx.x; t < n_lt; t += kDetBlock) delta[t] -= hist[t];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (key[k] >= 0) {
+                    const uint32_t slot = hist[key[k]] + mine[key[k]] + rank[k];
+                    srec[slot] = pack_record(ent[k] & ((1u << tb) - 1u), kb, v0[k], v1[k]);
+                    stile[slot] = (uint16_t)key[k];
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < n_rec; i += kDetBlock) {
+                const uint32_t pos = delta[stile[i]] + i;
+                if (pos < n_records) recs[pos] = srec[i];
+            }
+            __syncthreads();
+        }
+        if (valid && dx_parts != nullptr) {
+            float *o = dx_parts + ((size_t)g * cap + s) * 3;
+            o[0] = d0;
+            o[1] = d1;
+            o[2] = d2;
+        }
+    }
+}
+
+// One wavefront per work item; lane j owns the tile entries with index j mod
+// 64 and adds their records in range order (LDS adds of one lane issue in
+// program order).  A window of 512 records is staged in LDS and read by every
+// lane.
+__global__ void __launch_bounds__(64)
+det_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
+          const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
+          const uint2 *__restrict__ recs, float2 *__restrict__ dtable,
+          float2 *__restrict__ partial) {
+    extern __shared__ float2 acc[];                                   // [te] sums
+    const uint32_t te = 1u << tb;
+    uint2 *win = reinterpret_cast<uint2 *>(acc + te);                // [512] staged records
+    const uint32_t lane = threadIdx.x;
+    const uint32_t items = *n_items;
+    const int kb = (tb + 1) >> 1;
+    const uint32_t kmask = (1u << kb) - 1u;
+    constexpr uint32_t kPer = 8, kWin = 64u * kPer;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        int lo = 0, hi = n_tiles - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_start[mid] <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const int t = lo;
+        const uint32_t first = it - item_start[t];
+        const uint32_t r0 = start[t] + first * kItemRecords;
+        const uint32_t r1e = r0 + kItemRecords;
+        const uint32_t r1 = r1e < start[t + 1] ? r1e : start[t + 1];
+        const bool owner = (item_start[t + 1] - item_start[t]) == 1u;
+        for (uint32_t i = lane; i < te; i += 64) acc[i] = make_float2(0.f, 0.f);
+        const uint32_t tbase = (uint32_t)t << tb;
+        for (uint32_t base = r0 & ~(kPer - 1u); base < r1; base += kWin) {
+            __syncthreads();
+            const uint4 *q = reinterpret_cast<const uint4 *>(recs + base + lane * kPer);
+            uint4 *wq = reinterpret_cast<uint4 *>(win + lane * kPer);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) wq[j] = q[j];
+            __syncthreads();
+            const uint32_t u0 = r0 > base ? r0 - base : 0u;
+            const uint32_t u1 = r1 - base < kWin ? r1 - base : kWin;
+            for (uint32_t u = u0; u < u1; ++u) {
+                const uint2 r = win[u];
+                const uint32_t loc = ((r.x & kmask) << kb) | (r.y & kmask);
+                if ((loc & 63u) == lane && loc < te) {
+                    atomicAdd(&acc[loc].x, __uint_as_float(r.x & ~kmask));
+                    atomicAdd(&acc[loc].y, __uint_as_float(r.y & ~kmask));
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t ne = (n_entries - tbase) < te ? (n_entries - tbase) : te;
+        if (owner) {
+            for (uint32_t i = lane; i < ne; i += 64) {
+                const float2 a = acc[i];
+                if (a.x != 0.f || a.y != 0.f) {
+                    const float2 d = dtable[tbase + i];
+                    dtable[tbase + i] = make_float2(d.x + a.x, d.y + a.y);
+                }
+            }
+        } else {
+            float2 *slab = partial + (size_t)it * te;
+            for (uint32_t i = lane; i < ne; i += 64) slab[i] = acc[i];
+        }
+        __syncthreads();
+    }
+}
+
+nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
+                              const float *x, const void *table, const float *dfeat,
+                              float *dtable, float *dx_parts, void *ws, hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    NVR_TRY(scatter_check(p));
+    const int tb = tile_bits(p);
+    const int nt = scatter_tiles(p);
+    const int lt = level_tiles(p, tb);
+    const DetSeg sg = det_segments(p, tb);
+    ScatterWs w = carve_scatter(p, ws, cap);
+    uint32_t *seg = (uint32_t *)((char *)ws + ((scatter_ws_bytes(p, cap) + 255) & ~size_t(255)));
+    const uint32_t n_records = (uint32_t)((uint64_t)cap * p.L * 8 < 0xffffffffull
+                                              ? (uint64_t)cap * p.L * 8 : 0xffffffffull);
+    const int lpg = (p.L + kXcds - 1) / kXcds;
+    const unsigned gr = grid_for(cap, kDetBlock, 512) * kXcds;
+    int dev = 0;
+    NVR_HIP(hipGetDevice(&dev));
+    static std::atomic<uint64_t> det_lds_ok{0};
+    const uint64_t dev_bit = 1ull << (dev & 63);
+    if (!(det_lds_ok.load() & dev_bit)) {
+        const int most = (int)det_lds_bytes(kMaxLevelTiles);
+        const void *fns[] = {(const void *)det_emit<1>, (const void *)det_emit<2>,
+                             (const void *)det_emit<3>, (const void *)det_emit<4>};
+        for (const void *f : fns)
+            NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, most));
+        NVR_HIP(hipFuncSetAttribute((const void *)det_accum,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)((sizeof(float2) << kMaxTileBits) + sizeof(uint2) * 512)));
+        det_lds_ok.fetch_or(dev_bit);
+    }
+    zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>(w.count, nt + 1);
+    NVR_LAUNCHED();
+    const size_t clds = sizeof(uint32_t) * lt;
+    switch (lpg) {
+    case 1: det_count<1><<<gr, kDetBlock, clds, st>>>(p, tb, sg, n, n_dev, cap, x, seg, w.count); break;
+    case 2: det_count<2><<<gr, kDetBlock, clds, st>>>(p, tb, sg, n, n_dev, cap, x, seg, w.count); break;
+    case 3: det_count<3><<<gr, kDetBlock, clds, st>>>(p, tb, sg, n, n_dev, cap, x, seg, w.count); break;
+    default: det_count<4><<<gr, kDetBlock, clds, st>>>(p, tb, sg, n, n_dev, cap, x, seg, w.count); break;
+    }
+    NVR_LAUNCHED();
+    scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items);
+    NVR_LAUNCHED();
+    det_seg_scan<<<(nt + 255) / 256, 256, 0, st>>>(p, tb, sg, nt, n, n_dev, cap, w.start, seg);
+    NVR_LAUNCHED();
+    const size_t elds = det_lds_bytes(lt);
+    const uint32_t *tab = (const uint32_t *)table;
+    switch (lpg) {
+    case 1: det_emit<1><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
+    case 2: det_emit<2><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
+    case 3: det_emit<3><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
+    default: det_emit<4><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
+    }
+    NVR_LAUNCHED();
+    if (dtable == nullptr) return NVR_OK;
+    const int64_t max_items = max_items_of(cap, p.L, nt);
+    const unsigned ga = (unsigned)(max_items < 65535 ? max_items : 65535);
+    const size_t alds = (sizeof(float2) << tb) + sizeof(uint2) * 512;
+    det_accum<<<ga, 64, alds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items, w.rec,
+                                    (float2 *)dtable, w.partial);
+    NVR_LAUNCHED();
+    scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
+        tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
 // Row-major feature gradients dfeat[n][2L] to the level-group-planar layout
 // emit reads, [8][n][2 lpg] (level l = g + 8 m at [g][s][2m, 2m+1]; slots of
 // levels >= L hold 0).  Each workgroup pass moves 128 whole rows through LDS,
@@ -678,9 +1068,10 @@ scatter_dx_sum(int64_t n3, const float *__restrict__ parts, float *__restrict__ 
 // Bytes of the public entry point's workspace: the binned scatter's, then the
 // planar feature gradients [8][n][2 lpg] and the partial position gradients
 // [8][n][3].
-static size_t public_ws_bytes(const GridParams &p, int64_t n, size_t *planar_at, size_t *parts_at) {
+static size_t public_ws_bytes(const GridParams &p, int64_t n, size_t *planar_at, size_t *parts_at,
+                              bool det = false) {
     const int lpg = (p.L + kXcds - 1) / kXcds;
-    size_t b = (scatter_ws_bytes(p, n) + 255) & ~size_t(255);
+    size_t b = ((det ? scatter_det_ws_bytes(p, n) : scatter_ws_bytes(p, n)) + 255) & ~size_t(255);
     *planar_at = b;
     b += sizeof(float) * (size_t)kXcds * n * 2 * lpg;
     b = (b + 255) & ~size_t(255);
@@ -707,11 +1098,19 @@ extern "C" size_t nvr_encode_bwd_workspace(const nvr_grid_desc *g, int64_t n) {
     return public_ws_bytes(make_grid_params(g), n, &planar_at, &parts_at);
 }
 
-// Both public binned entry points: dfeat row-major [n][2L] (regrouped first)
-// or already level-group planar [8][n][2 lpg].
+extern "C" size_t nvr_encode_bwd_deterministic_workspace(const nvr_grid_desc *g, int64_t n) {
+    if (check_grid(g) != NVR_OK || n < 0) return 0;
+    size_t planar_at, parts_at;
+    return public_ws_bytes(make_grid_params(g), n, &planar_at, &parts_at, true);
+}
+
+// The public binned entry points: dfeat row-major [n][2L] (regrouped first)
+// or already level-group planar [8][n][2 lpg]; det selects the deterministic
+// variant.
 static nvr_status binned_public(const nvr_grid_desc *g, int64_t n, const float *x,
                                 const void *table, const float *dfeat, bool grouped,
-                                float *dtable, float *dx, void *workspace, nvr_stream stream) {
+                                float *dtable, float *dx, void *workspace, nvr_stream stream,
+                                bool det = false) {
     clear_error();
     NVR_TRY(check_grid(g));
     NVR_REQUIRE(n >= 0 && n < (1ll << 31), NVR_EINVAL, "n out of range");
@@ -725,7 +1124,7 @@ static nvr_status binned_public(const nvr_grid_desc *g, int64_t n, const float *
     NVR_REQUIRE((size_t)n * p.L * 8 < (1ull << 32), NVR_EINVAL, "too many contributions");
     const hipStream_t st = hs(stream);
     size_t planar_at, parts_at;
-    public_ws_bytes(p, n, &planar_at, &parts_at);
+    public_ws_bytes(p, n, &planar_at, &parts_at, det);
     const float *planar = dfeat;
     float *parts = dx ? (float *)((char *)workspace + parts_at) : nullptr;
     if (!grouped) {
@@ -739,8 +1138,12 @@ static nvr_status binned_public(const nvr_grid_desc *g, int64_t n, const float *
     }
     // 512-sample emit chunks, 1024 chunks per level group: the shape the step's
     // tuner settles on for millions of samples
-    NVR_TRY(launch_scatter(p, n, nullptr, n, x, table, planar, dtable, parts, workspace, st,
-                           /*counted=*/false, 1024, 512));
+    if (det)
+        NVR_TRY(launch_scatter_det(p, n, nullptr, n, x, table, planar, dtable, parts, workspace,
+                                   st));
+    else
+        NVR_TRY(launch_scatter(p, n, nullptr, n, x, table, planar, dtable, parts, workspace, st,
+                               /*counted=*/false, 1024, 512));
     if (dx) {
         scatter_dx_sum<<<grid_for(3 * n, 256, 8192), 256, 0, st>>>(3 * n, parts, dx);
         NVR_LAUNCHED();
@@ -759,4 +1162,11 @@ extern "C" nvr_status nvr_encode_bwd_binned_grouped(const nvr_grid_desc *g, int6
                                                     const float *dfeat, float *dtable, float *dx,
                                                     void *workspace, nvr_stream stream) {
     return binned_public(g, n, x, table, dfeat, true, dtable, dx, workspace, stream);
+}
+
+extern "C" nvr_status nvr_encode_bwd_deterministic(const nvr_grid_desc *g, int64_t n,
+                                                   const float *x, const void *table,
+                                                   const float *dfeat, float *dtable, float *dx,
+                                                   void *workspace, nvr_stream stream) {
+    return binned_public(g, n, x, table, dfeat, false, dtable, dx, workspace, stream, true);
 }

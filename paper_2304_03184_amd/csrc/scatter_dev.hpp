@@ -19,6 +19,12 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
                           const float *x, const void *table, const float *dfeat, float *dtable,
                           float *dx_parts, void *ws, hipStream_t st,
                           bool counted = false, int emit_chunks = 0, int emit_block = 0);
+// The deterministic variant: same records, order fixed by the inputs (tile
+// counts formed by its own pass; no launch-shape choices).
+size_t scatter_det_ws_bytes(const GridParams &p, int64_t cap);
+nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
+                              const float *x, const void *table, const float *dfeat,
+                              float *dtable, float *dx_parts, void *ws, hipStream_t st);
 // the scan and emit passes alone (tile counts already formed), for tuning
 nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_t *n_dev,
                                     int64_t cap, const float *x, const void *table,

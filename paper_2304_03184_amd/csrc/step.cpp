@@ -47,6 +47,7 @@ struct nvr_ctx {
     nvr::FieldWs ws[2];
     int comp_blocks = 0;           // compositing workgroups (autotuned; 0: default)
     float *ray_buf = nullptr;      // render: C, D per ray chunk
+    float *loss_part = nullptr;    // one loss partial per compositing workgroup
     int64_t ray_buf_n = 0;
     std::map<std::string, nvr::GraphEntry> graphs;
 };
@@ -79,12 +80,17 @@ static nvr_status field_check(const nvr_field *f, const nvr_step_desc *s, Net *n
     return NVR_OK;
 }
 
+static bool deterministic(const nvr_ctx *ctx) { return (ctx->flags & NVR_DETERMINISTIC) != 0; }
+
 static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &net, int precision,
                             int64_t n_rays, int64_t cap, bool train) {
     FieldWs &w = ctx->ws[k];
     const size_t mlp_bytes = precision == NVR_BF16 ? mfma_ws_bytes(net, cap) : plain_workspace(net, cap);
-    const size_t scatter_bytes = (train && precision == NVR_BF16)
-                                     ? scatter_ws_bytes(make_grid_params(&f->grid), cap) : 0;
+    const GridParams gp = make_grid_params(&f->grid);
+    const size_t scatter_bytes =
+        (train && precision == NVR_BF16)
+            ? (deterministic(ctx) ? scatter_det_ws_bytes(gp, cap) : scatter_ws_bytes(gp, cap))
+            : 0;
     if (w.block && w.cap >= cap && w.n_rays >= n_rays && w.precision == precision &&
         w.has_warp == f->has_warp && w.n_in == net.n_in && w.mlp_bytes >= mlp_bytes &&
         w.scatter_bytes >= scatter_bytes)
@@ -184,8 +190,9 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
     const GridParams gp = make_grid_params(&f->grid);
     if (precision == NVR_BF16) {
         // a training forward also counts the table-gradient scatter's tiles
+        // (the deterministic scatter forms its own counts per chunk)
         TileCounter counter{};
-        const bool count = train && w.scatter_ws != nullptr;
+        const bool count = train && w.scatter_ws != nullptr && !deterministic(ctx);
         if (count) {
             counter = scatter_counter(gp, w.scatter_ws);
             NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
@@ -237,7 +244,8 @@ static nvr_status enqueue_fwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
     return launch_composite_loss(s->n_rays, a, s->n_fields == 2 ? &bb : nullptr, b->C_t, b->D_t, b->mask,
                                  s->lambda_depth, state, loss, C_out, D_out, ctx->ws[0].dsigma,
                                  ctx->ws[0].drgb, s->n_fields == 2 ? ctx->ws[1].dsigma : nullptr,
-                                 s->n_fields == 2 ? ctx->ws[1].drgb : nullptr, st, ctx->comp_blocks);
+                                 s->n_fields == 2 ? ctx->ws[1].drgb : nullptr, st, ctx->comp_blocks,
+                                 ctx->loss_part);
 }
 
 static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
@@ -253,9 +261,14 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
             NVR_TRY(mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
                              f->params, true, w.dsigma, w.drgb, f->params_grad, w.dfeat, w.mlp_ws,
                              st, w.mlp_bwd_blocks, w.sh));
-            NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat, f->table_grad,
-                                   f->has_warp ? w.dx : nullptr, w.scatter_ws, st,
-                                   /*counted=*/true, w.emit_chunks, w.emit_block));
+            if (deterministic(ctx))
+                NVR_TRY(launch_scatter_det(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
+                                           f->table_grad, f->has_warp ? w.dx : nullptr,
+                                           w.scatter_ws, st));
+            else
+                NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
+                                       f->table_grad, f->has_warp ? w.dx : nullptr, w.scatter_ws,
+                                       st, /*counted=*/true, w.emit_chunks, w.emit_block));
             if (f->has_warp)
                 NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, kXcds, 3 * cap,
                                      f->node_dq_grad, f->bones_grad, st));
@@ -403,7 +416,8 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
                                      b->mask, s->lambda_depth, state, loss, nullptr, nullptr,
                                      ctx->ws[0].dsigma, ctx->ws[0].drgb,
                                      s->n_fields == 2 ? ctx->ws[1].dsigma : nullptr,
-                                     s->n_fields == 2 ? ctx->ws[1].drgb : nullptr, st, c);
+                                     s->n_fields == 2 ? ctx->ws[1].drgb : nullptr, st, c,
+                                     ctx->loss_part);
     }));
     for (int k = 0; k < s->n_fields; ++k) {
         const nvr_field *f = fields[k];
@@ -453,6 +467,15 @@ extern "C" nvr_status nvr_create(nvr_ctx **out, int32_t device, uint32_t flags) 
     c->device = device;
     c->flags = flags;
     NVR_HIP(hipSetDevice(device));
+    {
+        hipError_t e = hipMalloc(&c->loss_part, sizeof(float) * kMaxLossBlocks);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete c;
+            set_error("loss partials allocation failed: %s", hipGetErrorString(e));
+            return NVR_ENOMEM;
+        }
+    }
     if (flags & NVR_USE_GRAPH) {
         hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -476,6 +499,7 @@ extern "C" void nvr_destroy(nvr_ctx *ctx) {
     for (auto &w : ctx->ws)
         if (w.block) (void)hipFree(w.block);
     if (ctx->ray_buf) (void)hipFree(ctx->ray_buf);
+    if (ctx->loss_part) (void)hipFree(ctx->loss_part);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     delete ctx;
 }
@@ -515,7 +539,7 @@ extern "C" nvr_status nvr_train_step(nvr_ctx *ctx, const nvr_step_desc *s, nvr_f
     NVR_REQUIRE(loss_dev && state_dev, NVR_EINVAL, "NULL loss or state");
     NVR_TRY(prepare(ctx, s, fields, nets));
     hipStream_t st = hs(stream);
-    if ((ctx->flags & NVR_AUTOTUNE) && s->precision == NVR_BF16) {
+    if ((ctx->flags & NVR_AUTOTUNE) && !deterministic(ctx) && s->precision == NVR_BF16) {
         bool need = false;
         for (int k = 0; k < s->n_fields; ++k) need |= !ctx->ws[k].tuned;
         if (need) {

@@ -199,7 +199,8 @@ __global__ void __launch_bounds__(kWarpBlock)
 warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__restrict__ n_dev,
                 int64_t cap, const float *__restrict__ x, const int32_t *__restrict__ frame,
                 const float *__restrict__ gz_parts, int n_parts, int64_t part_stride,
-                float *__restrict__ d_dq, float *__restrict__ d_bones) {
+                float *__restrict__ d_dq, float *__restrict__ d_bones,
+                float *__restrict__ dx_live) {
     extern __shared__ float lds[];
     float *J = lds;                                   // [3 * n_joints]
     float *acc = lds + 3 * kMaxJoints;                // [n_frames * n_nodes * 8] if LDS_ACC
@@ -286,6 +287,35 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__rest
                     for (int bb = 0; bb < 4; ++bb) unsafeAtomicAdd(dB + 4 * a + bb, lw * gys[a] * xh[bb]);
             }
         }
+        if (dx_live != nullptr) {
+            // y = sum_j lw_j M_j [x; 1], lw = softmax_j(-|x - J_j|^2 / (2 sigma^2)):
+            // dx = sum_j lw_j (R_j^T gy + (gy . M_j [x; 1]) (a_j - a_bar)),
+            // a_j = -(x - J_j) / sigma^2, a_bar = sum_k lw_k a_k
+            const float *B0 = rig.bones + (size_t)fr * p.n_joints * 12;
+            const float inv_s2 = 2.f * p.inv_two_sigma2;
+            float3 abar = make_float3(0.f, 0.f, 0.f);
+            for (int k = 0; k < p.k_joints; ++k) {
+                const float *Jk = J + 3 * f.jsel[k];
+                const float3 ak = mul3(-inv_s2, sub3(xv, make_float3(Jk[0], Jk[1], Jk[2])));
+                abar = add3(abar, mul3(f.lw[k], ak));
+            }
+            float3 gx = make_float3(0.f, 0.f, 0.f);
+            for (int k = 0; k < p.k_joints; ++k) {
+                const float *M = B0 + 12 * f.jsel[k];
+                const float *Jk = J + 3 * f.jsel[k];
+                const float3 rt = make_float3(M[0] * gy.x + M[4] * gy.y + M[8] * gy.z,
+                                              M[1] * gy.x + M[5] * gy.y + M[9] * gy.z,
+                                              M[2] * gy.x + M[6] * gy.y + M[10] * gy.z);
+                const float3 yk = make_float3(M[0] * xv.x + M[1] * xv.y + M[2] * xv.z + M[3],
+                                              M[4] * xv.x + M[5] * xv.y + M[6] * xv.z + M[7],
+                                              M[8] * xv.x + M[9] * xv.y + M[10] * xv.z + M[11]);
+                const float3 ak = mul3(-inv_s2, sub3(xv, make_float3(Jk[0], Jk[1], Jk[2])));
+                gx = add3(gx, mul3(f.lw[k], add3(rt, mul3(dot3(gy, yk), sub3(ak, abar)))));
+            }
+            dx_live[3 * i] += gx.x;
+            dx_live[3 * i + 1] += gx.y;
+            dx_live[3 * i + 2] += gx.z;
+        }
     }
     if (LDS_ACC) {
         __syncthreads();
@@ -338,16 +368,16 @@ nvr_status launch_warp_fwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t
 nvr_status launch_warp_bwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t n,
                            const int32_t *n_dev, int64_t cap, const float *x, const int32_t *frame,
                            const float *gz, int n_parts, int64_t part_stride, float *d_dq,
-                           float *d_bones, hipStream_t st) {
+                           float *d_bones, float *dx_live, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
     const size_t acc_bytes = sizeof(float) * (size_t)p.n_frames * p.n_nodes * 8;
     const size_t base = sizeof(float) * 3 * kMaxJoints;
     if (acc_bytes <= 64 * 1024) {
         warp_bwd_kernel<true><<<grid_for(cap, kWarpBlock, 512), kWarpBlock, base + acc_bytes, st>>>(
-            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones);
+            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
     } else {
         warp_bwd_kernel<false><<<grid_for(cap, kWarpBlock, 2048), kWarpBlock, base, st>>>(
-            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones);
+            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
     }
     NVR_LAUNCHED();
     return NVR_OK;
@@ -372,7 +402,7 @@ extern "C" nvr_status nvr_warp_fwd(const nvr_warp_desc *w, const nvr_warp_rig *r
 extern "C" nvr_status nvr_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t n,
                                    const int32_t *n_dev, const float *x_live, const int32_t *frame,
                                    const float *dx_can, int32_t n_parts, float *d_node_dq,
-                                   float *d_bones, nvr_stream stream) {
+                                   float *d_bones, float *dx_live, nvr_stream stream) {
     clear_error();
     WarpParams p;
     NVR_TRY(make_warp_params(w, rig, &p));
@@ -381,7 +411,7 @@ extern "C" nvr_status nvr_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *r
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(x_live && dx_can && d_node_dq, NVR_EINVAL, "NULL array");
     return launch_warp_bwd(p, *rig, n, n_dev, n, x_live, frame, dx_can, n_parts, 3 * n, d_node_dq,
-                           d_bones, hs(stream));
+                           d_bones, dx_live, hs(stream));
 }
 
 #include "launch.hpp"
@@ -401,7 +431,7 @@ nvr_status run_warp_bwd(const nvr_warp_desc *w, const nvr_warp_rig *rig, int64_t
     WarpParams p;
     NVR_TRY(make_warp_params(w, rig, &p));
     return launch_warp_bwd(p, *rig, cap, n_dev, cap, x, nullptr, gz, n_parts, part_stride, d_dq,
-                           d_bones, st);
+                           d_bones, nullptr, st);
 }
 
 }  // namespace nvr

@@ -93,11 +93,13 @@ class Trainer:
     """Owns an nvr context; runs training steps and renders."""
 
     def __init__(self, fields, n_rays, max_samples, precision=L.NVR_F32, lambda_depth=0.0,
-                 adam=None, use_graph=False, loss_scale=1.0, device_index=0, autotune=False):
+                 adam=None, use_graph=False, loss_scale=1.0, device_index=0, autotune=False,
+                 deterministic=False):
         self.fields = list(fields)
         self.n_rays = n_rays
         ctx = C.c_void_p()
-        flags = (L.NVR_USE_GRAPH if use_graph else 0) | (L.NVR_AUTOTUNE if autotune else 0)
+        flags = ((L.NVR_USE_GRAPH if use_graph else 0) | (L.NVR_AUTOTUNE if autotune else 0) |
+                 (L.NVR_DETERMINISTIC if deterministic else 0))
         call("nvr_create", C.byref(ctx), device_index, flags)
         self.ctx = ctx
         self.desc = L.StepDesc(len(self.fields), precision, n_rays, max_samples, lambda_depth,

@@ -132,6 +132,18 @@ def encode_bwd_binned(g, x, table, dfeat, dtable, dx=None):
          _p(dx), _p(ws), _stream())
 
 
+def encode_bwd_deterministic(g, x, table, dfeat, dtable, dx=None):
+    """encode_bwd_binned with every sum in an order fixed by the inputs
+    (bit-identical results call to call)."""
+    _dev(dfeat, torch.float32)
+    _dev(dtable, torch.float32)
+    n = x.shape[0]
+    nb = L.lib().nvr_encode_bwd_deterministic_workspace(C.byref(g), n)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=x.device)
+    call("nvr_encode_bwd_deterministic", C.byref(g), n, _p(x), _p(table), _p(dfeat),
+         _p(dtable), _p(dx), _p(ws), _stream())
+
+
 def grouped_width(g):
     """Features per sample in one level-group plane (2 x ceil(L / 8))."""
     return 2 * ((g.n_levels + 7) // 8)
@@ -337,27 +349,33 @@ def warp_fwd(wd, rig, x, n_dev=None):
     return xc
 
 
-def warp_bwd(wd, rig, x, dxc, d_node_dq, d_bones=None, n_parts=1):
+def warp_bwd(wd, rig, x, dxc, d_node_dq, d_bones=None, n_parts=1, dx_live=None):
     call("nvr_warp_bwd", C.byref(wd), C.byref(rig.c()), x.shape[0], None, _p(x), None,
-         _p(dxc), n_parts, _p(d_node_dq), _p(d_bones), _stream())
+         _p(dxc), n_parts, _p(d_node_dq), _p(d_bones), _p(dx_live), _stream())
 
 
 class WarpFn(torch.autograd.Function):
-    """x_can = warp(x_live); backward to node motions and bones."""
+    """x_can = warp(x_live; node_dq, bones) with the joints, node positions and
+    look-up table of `rig`; backward to the live positions, node motions and
+    bones."""
 
     @staticmethod
     def forward(ctx, x, node_dq, bones, wd, rig):
-        ctx.wd, ctx.rig = wd, rig
+        r = Rig(rig.joints, bones.contiguous(), node_dq.contiguous(), rig.node_pos, rig.lut)
+        ctx.wd, ctx.r = wd, r
+        x = x.contiguous()
         ctx.save_for_backward(x)
-        return warp_fwd(wd, rig, x.contiguous())
+        return warp_fwd(wd, r, x)
 
     @staticmethod
     def backward(ctx, dxc):
         (x,) = ctx.saved_tensors
-        d_dq = torch.zeros_like(ctx.rig.node_dq)
-        d_b = torch.zeros_like(ctx.rig.bones)
-        warp_bwd(ctx.wd, ctx.rig, x, dxc.contiguous(), d_dq, d_b)
-        return None, d_dq, d_b, None, None
+        r = ctx.r
+        d_dq = torch.zeros_like(r.node_dq)
+        d_b = torch.zeros_like(r.bones)
+        dx = torch.zeros_like(x) if ctx.needs_input_grad[0] else None
+        warp_bwd(ctx.wd, r, x, dxc.contiguous(), d_dq, d_b, dx_live=dx)
+        return dx, d_dq, d_b, None, None
 
 
 # ---------------------------------------------------------------- networks

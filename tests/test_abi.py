@@ -197,3 +197,44 @@ def test_new_entry_points_reject_before_launch(L):
     assert lib.nvr_live_lut(C.byref(d), None, fake, fake, fake, None) == L.NVR_EINVAL
     assert lib.nvr_live_lut(C.byref(d), fake, fake, fake, C.c_void_p(4098), None) == L.NVR_EINVAL
     assert lib.nvr_live_lut(None, fake, fake, fake, fake, None) == L.NVR_EINVAL
+
+
+def test_deform_and_deterministic_entry_points_reject_before_launch(L):
+    # the deformation network checks the binned scatter's limits and every
+    # array before its first launch; the deterministic scatter and the
+    # allocation-free march reject like their counterparts (fake pointers are
+    # never touched)
+    lib = L.lib()
+    fake = C.c_void_p(4096)
+    lo = (C.c_float * 3)(-1, -1, -1)
+    hi = (C.c_float * 3)(1, 1, 1)
+    # 16 levels x 2 features (32 wide) hashed at 2^24 entries: more table tiles
+    # than the binned scatter holds
+    big = L.GridDesc()
+    L.call("nvr_grid_init", C.byref(big), 16, 2, 24, 16, 65536, lo, hi)
+    args = (C.byref(big), 10, fake, fake, fake, fake, fake, fake, fake, None, None, fake, None)
+    assert lib.nvr_deform_bwd(*args) == L.NVR_EUNSUPPORTED
+    assert b"8192 tiles" in lib.nvr_last_error()
+    assert lib.nvr_deform_fwd(C.byref(big), 10, fake, fake, fake, fake, fake, fake,
+                              None) == L.NVR_EUNSUPPORTED
+    g = L.GridDesc()
+    L.call("nvr_grid_init", C.byref(g), 16, 2, 14, 16, 512, lo, hi)
+    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, fake, fake, fake, None,
+                              None, None, None) == L.NVR_EINVAL          # NULL workspace
+    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, fake, fake,
+                              C.c_void_p(4096 + 4), None, None, fake, None) == L.NVR_EINVAL
+    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, fake, None, fake, None,
+                              None, fake, None) == L.NVR_EINVAL          # NULL dtable
+    assert lib.nvr_encode_bwd_deterministic(C.byref(big), 10, fake, fake, fake, fake, None, fake,
+                                            None) == L.NVR_EUNSUPPORTED
+    assert lib.nvr_encode_bwd_deterministic(C.byref(g), 10, fake, fake, fake, fake, None,
+                                            C.c_void_p(4096 + 8), None) == L.NVR_EINVAL
+    assert lib.nvr_encode_bwd_deterministic_workspace(C.byref(g), 1000) > \
+        lib.nvr_encode_bwd_workspace(C.byref(g), 1000)
+    md = L.MarchDesc((C.c_float * 3)(-1, -1, -1), (C.c_float * 3)(1, 1, 1), 0.0, 1e30, 0.0,
+                     128, 0)
+    assert lib.nvr_march_noalloc(C.byref(md), 10, 5, 3, fake, fake, None, 100, fake, fake, fake,
+                                 fake, fake, fake, None) == L.NVR_EINVAL    # empty range
+    md.max_steps = 0
+    assert lib.nvr_march_noalloc(C.byref(md), 10, 0, 10, fake, fake, None, 100, fake, fake, fake,
+                                 fake, fake, fake, None) == L.NVR_EINVAL

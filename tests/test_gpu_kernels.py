@@ -207,10 +207,13 @@ def test_warp_fwd_bwd(small_rig):
     gz = rng.normal(size=(4000, 3)).astype(np.float32)
     d_dq = torch.zeros_like(R.node_dq)
     d_b = torch.zeros_like(R.bones)
-    O.warp_bwd(wd, R, dev(x), dev(gz), d_dq, d_b)
-    r_dq, r_b = owarp.warp_backward(x, rig, (-1.0,) * 3, (1.0,) * 3, gz)
+    dx = torch.full((4000, 3), 0.5, device="cuda")      # accumulated into
+    O.warp_bwd(wd, R, dev(x), dev(gz), d_dq, d_b, dx_live=dx)
+    r_dq, r_b, r_dx = owarp.warp_backward(x, rig, (-1.0,) * 3, (1.0,) * 3, gz, want_dx=True)
     assert rel_err(host(d_dq), r_dq) < 1e-4
     assert rel_err(host(d_b), r_b.reshape(host(d_b).shape)) < 1e-4
+    assert rel_err(host(dx) - 0.5, r_dx) < 1e-4
+    np.testing.assert_allclose(host(dx) - 0.5, r_dx, rtol=0, atol=1e-4 * np.abs(r_dx).max())
 
 
 def test_warp_identity_rig(small_rig):
@@ -408,3 +411,37 @@ def test_loss_and_adam():
     sv = O.state_values(st)
     assert sv["step"] == 3 and sv["loss_scale"] == 2.0
     np.testing.assert_array_equal(host(pg), before)
+
+
+@pytest.mark.parametrize("k,n,spread", [(1, 3001, 1.5), (2, 20000, 1.0), (2, 300000, 0.2)])
+def test_encode_deterministic_scatter(k, n, spread):
+    # the deterministic binned scatter: oracle gradients to the binned bar, and
+    # bit-identical tables and position gradients over repeated calls (the
+    # 300k clustered case splits the coarse tiles over many work items)
+    I = field_inputs(k, 8)
+    f, lay = I["fcfg"], I["lay"]
+    O = ops()
+    g = O.grid_desc_of(f)
+    rng = synth.rng_for(19)
+    x = rng.uniform(-spread, spread, size=(n, 3)).astype(np.float32)
+    t16 = I["table"].astype(np.float16)
+    dfeat = rng.normal(size=(n, 2 * f.n_levels)).astype(np.float32)
+    rt, rdx = ogrid.encode_backward(x, t16.astype(np.float64), dfeat, lay)
+    xd, td, dfd = dev(x), dev(t16), dev(dfeat)
+    outs = []
+    for rep in range(3):
+        print(f"deterministic scatter: k={k} n={n} call {rep}", flush=True)
+        dtab = torch.zeros((lay.n_entries, 2), device="cuda")
+        dx = torch.zeros((n, 3), device="cuda")
+        O.encode_bwd_deterministic(g, xd, td, dfd, dtab, dx)
+        outs.append((host(dtab), host(dx)))
+    assert rel_err(outs[0][0], rt) < 1e-5
+    np.testing.assert_allclose(outs[0][0], rt, rtol=0, atol=1e-5 * np.abs(rt).max())
+    assert rel_err(outs[0][1], rdx) < 1e-4
+    for dtab, dx in outs[1:]:
+        assert np.array_equal(dtab.view(np.uint32), outs[0][0].view(np.uint32))
+        assert np.array_equal(dx.view(np.uint32), outs[0][1].view(np.uint32))
+    # accumulation into a non-zero table
+    dtab = torch.from_numpy(outs[0][0].copy()).cuda()
+    O.encode_bwd_deterministic(g, xd, td, dfd, dtab)
+    assert rel_err(host(dtab), 2 * rt) < 1e-5

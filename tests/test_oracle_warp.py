@@ -181,6 +181,31 @@ def _translation_bone(t):
     return b
 
 
+def test_backward_position_gradient_vs_fd(rig):
+    # dL/dx through the skinning blend (bones and skin weights) and the node
+    # weights, against central differences in float64 (steps small enough that
+    # no float32 joint or voxel choice changes)
+    rng = synth.rng_for(39)
+    x = live_points(rig, rng, 30).astype(np.float64)
+    gz = rng.normal(size=(30, 3))
+    _, _, gx = warp.warp_backward(x, rig, LO, HI, gz, want_dx=True)
+    h = 1e-7
+    for a in range(3):
+        xp, xm = x.copy(), x.copy()
+        xp[:, a] += h
+        xm[:, a] -= h
+        fd = np.sum((warp.warp(xp, rig, LO, HI) - warp.warp(xm, rig, LO, HI)) * gz, 1) / (2 * h)
+        np.testing.assert_allclose(gx[:, a], fd, rtol=1e-6, atol=1e-6)
+    # identity rig: z = x, so dx = gz exactly
+    ident = dict(rig)
+    ident["bones"] = np.tile(np.eye(3, 4), (1, rig["bones"].shape[1], 1, 1))
+    dq = np.zeros_like(rig["node_dq"], dtype=np.float64)
+    dq[..., 0] = 1.0
+    ident["node_dq"] = dq
+    _, _, gx0 = warp.warp_backward(x, ident, LO, HI, gz, want_dx=True)
+    np.testing.assert_allclose(gx0, gz, rtol=0, atol=1e-12)
+
+
 def test_skin_weights_hand_worked():
     # Inverse skinning with the Gaussian weights over the 4 nearest joints,
     # sigma_s = 0.1: the live point sits at the origin, joints at distances
