@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--rays", type=int, default=1 << 18)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-render", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the human, two-field and key-frame configurations")
+    ap.add_argument("--kf-train-steps", type=int, default=600)
     ap.add_argument("--cpu-rays", type=int, default=32768)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration) and exit")
@@ -154,6 +157,20 @@ def main():
         render = time_render(O, L, F, torch, w, f, table, params, occ, dev)
 
     tr.close()
+
+    # ---------------------------------------------------------------- other configurations
+    extra = {}
+    if not args.no_extra:
+        for name, fn in (("human_warp", lambda: bench_human(O, L, F, torch, dev, 10, 3)),
+                         ("two_fields", lambda: bench_two_fields(O, L, F, torch, dev, 10, 3)),
+                         ("keyframes", lambda: bench_keyframes(O, L, F, torch, dev, 10, 3,
+                                                               args.kf_train_steps))):
+            try:
+                extra[name] = fn()
+            except Exception as e:  # reported as missing, never invented
+                log(f"[bench] {name} failed: {e}")
+                extra[name] = {"error": str(e)}
+
     log(f"[bench] fp32 plain step: {args.plain_steps} steps")
     tr32, _, dt_32, n32, loss_32 = timed_steps(L.NVR_F32, args.plain_steps, 1, False)
     tr32.close()
@@ -185,6 +202,7 @@ def main():
         "fp32_plain": {"rays_per_s": R / dt_32, "ms_per_step": dt_32 * 1e3,
                        "speedup_bf16_over_fp32": dt_32 / dt_bf, "loss": loss_32},
         "render": render,
+        "configs": extra,
         "occupancy_update": occupancy,
         "live_lut": live_lut,
         "keyframe": keyframe,
@@ -472,14 +490,17 @@ def time_deform(O, L, torch, n=1 << 18):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    fwd = timed(lambda: O.deform_fwd(g, x, theta, table, params))
-    bwd = timed(lambda: O.deform_bwd(g, x, theta, table, params, dvc))
     flops_fwd = 2.0 * n * n_par
-    out = {"points": n, "fwd_ms": fwd, "bwd_ms": bwd,
-           "fwd_tflops": flops_fwd / (fwd * 1e-3) / 1e12,
-           "bwd_tflops": 3 * flops_fwd / (bwd * 1e-3) / 1e12,
-           "dtype": "f32 (sgemm)"}
-    log(f"[bench] deformation net {n} points: fwd {fwd:.3f} ms, fwd+bwd {bwd:.3f} ms")
+    out = {"points": n}
+    for name, math in (("f32_sgemm", L.NVR_F32), ("f16_matrix_cores", L.NVR_F16)):
+        fwd = timed(lambda: O.deform_fwd(g, x, theta, table, params, math=math))
+        bwd = timed(lambda: O.deform_bwd(g, x, theta, table, params, dvc, math=math))
+        # the backward recomputes the forward: 3 x the forward's products
+        out[name] = {"fwd_ms": fwd, "bwd_ms": bwd,
+                     "fwd_tflops": flops_fwd / (fwd * 1e-3) / 1e12,
+                     "bwd_tflops": 3 * flops_fwd / (bwd * 1e-3) / 1e12}
+        log(f"[bench] deformation net {n} points ({name}): fwd {fwd:.3f} ms, "
+            f"bwd {bwd:.3f} ms")
     return out
 
 
@@ -559,6 +580,191 @@ def time_render(O, L, F, torch, w, f, table, params, occ, dev):
     log(f"[bench] render 1920x1080: {dt * 1e3:.3f} ms, {mpix:.1f} Mpix/s")
     return {"resolution": [1920, 1080], "ms_per_frame": dt * 1e3, "mpix_per_s": mpix,
             "t_stop": 1e-4, "dtype": "bf16"}
+
+
+def _f16(a):
+    return np.asarray(a, np.float32).astype(np.float16).astype(np.float64)
+
+
+def _timed(torch, tr, steps, warmup):
+    for _ in range(warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _sampled_colour_error(torch, tr, flds, w, o, d, ranges, pick, box=None):
+    """Forward colours / depths of the picked rays after training vs the FP64
+    oracle given the same fp16 tables and fp16-rounded weights."""
+    from oracle import step as ostep
+    R = o.shape[0]
+    Cg = torch.empty((R, 3), device="cuda")
+    Dg = torch.empty(R, device="cuda")
+    tr.forward(C_out=Cg, D_out=Dg)
+    torch.cuda.synchronize()
+    states = [ostep.FieldState(fl.fcfg, fl.table_half.float().cpu().numpy().astype(np.float64),
+                               _f16(fl.params.cpu().numpy()),
+                               occ_words=fl.occ.cpu().numpy().view(np.uint32)
+                               if fl.occ is not None else None,
+                               rig=getattr(fl, "rig_np", None)) for fl in flds]
+    sub = []
+    for lo, hi in ranges:   # each field's rays among the picked (sorted) ones
+        idx = np.nonzero((pick >= lo) & (pick < hi))[0]
+        sub.append((int(idx[0]), int(idx[-1]) + 1) if idx.size else (0, 0))
+    ref = ostep.forward_all(w, ostep.StepState(states), o[pick], d[pick], sub, box)
+    ec = float(np.abs(Cg.cpu().numpy()[pick] - ref["C"]).max())
+    ed = float(np.abs(Dg.cpu().numpy()[pick] - ref["D"]).max())
+    return ec, ed
+
+
+def bench_human(O, L, F, torch, dev, steps, warmup):
+    """The human field behind the hybrid warp at full size (2^18 rays, 24
+    joints, 1024 nodes listed 8 per voxel of a 128^3 look-up), fused BF16
+    step in a captured graph with tuned shapes; sampled parity after training."""
+    import synth
+    w, f, rig, o, d, Ct, occ, rng = synth.human_workload()
+    n_e = O.grid_desc_of(f).n_entries
+    table = synth.uniform_table(n_e, 2, rng)
+    params = synth.xavier_params(f.layer_shapes(), rng)
+    R, ex = w.n_rays, w.extra
+    wd = O.warp_desc(n_nodes=ex["n_nodes"], k_nodes=ex["k_nodes"], lut_res=ex["knn_res"])
+    fld = F.Field(w, f, table, params, occ_words=occ, rig=O.Rig.from_numpy(rig), warp_desc=wd)
+    fld.rig_np = rig
+    cap = R * 64
+    tr = F.Trainer([fld], R, cap, precision=L.NVR_BF16, use_graph=True, autotune=True)
+    tr.set_batch(dev(o), dev(d), dev(Ct))
+    dt = _timed(torch, tr, steps, warmup)
+    n = tr.sample_count()
+    assert n <= cap, "sample capacity overflow"
+    pick = np.sort(synth.rng_for(31).choice(R, size=64, replace=False))
+    ec, ed = _sampled_colour_error(torch, tr, [fld], w, o, d, [(0, R)], pick,
+                                   ((-1.0,) * 3, (1.0,) * 3))
+    tr.close()
+    assert ec < 2e-2 and ed < 2e-2, f"human field: sampled colour error {ec}, depth {ed}"
+    log(f"[bench] human field (warp): {dt * 1e3:.3f} ms/step, {n} samples, "
+        f"sampled C err {ec:.2e}")
+    return {"workload": w.name, "rays_per_step": R, "samples_per_step": n,
+            "ms_per_step": dt * 1e3, "rays_per_s": R / dt, "nodes": ex["n_nodes"],
+            "joints": ex["n_joints"], "lut_res": ex["knn_res"], "graph": True,
+            "sampled_parity": {"rays": int(pick.size), "colour_max_abs": ec, "depth_max_abs": ed,
+                               "bar": 2e-2}}
+
+
+def bench_two_fields(O, L, F, torch, dev, steps, warmup):
+    """Human + object fields at full size (180k / 80k rays, 20k shared rays
+    composited over the t-merged samples of both), colour + depth loss, one
+    captured BF16 graph step with tuned shapes; sampled parity after training."""
+    import synth
+    w, (fh, fo), rig, o, d, C, D, ranges, (occ_h, occ_o), rng = \
+        synth.two_field_workload(scale=1.0)
+    table_h = synth.uniform_table(O.grid_desc_of(fh).n_entries, 2, rng)
+    params_h = synth.xavier_params(fh.layer_shapes(), rng)
+    table_o = synth.uniform_table(O.grid_desc_of(fo).n_entries, 2, rng)
+    params_o = synth.xavier_params(fo.layer_shapes(), rng)
+    ex = w.extra
+    wd = O.warp_desc(n_nodes=ex["n_nodes"], k_nodes=ex["k_nodes"], lut_res=ex["knn_res"])
+    fld_h = F.Field(w, fh, table_h, params_h, occ_words=occ_h, rig=O.Rig.from_numpy(rig),
+                    warp_desc=wd, ray_range=ranges[0])
+    fld_h.rig_np = rig
+    fld_o = F.Field(w, fo, table_o, params_o, occ_words=occ_o, ray_range=ranges[1])
+    R = w.n_rays
+    cap = 180000 * 64
+    tr = F.Trainer([fld_h, fld_o], R, cap, precision=L.NVR_BF16, lambda_depth=w.lambda_depth,
+                   use_graph=True, autotune=True)
+    tr.set_batch(dev(o), dev(d), dev(C), dev(D))
+    dt = _timed(torch, tr, steps, warmup)
+    nh, no = tr.sample_count(0), tr.sample_count(1)
+    assert nh <= cap and no <= cap, "sample capacity overflow"
+    g = synth.rng_for(32)
+    pick = np.sort(np.concatenate([g.choice(ex["human_only"], 24, replace=False),
+                                   ex["human_only"] + g.choice(ex["shared"], 24, replace=False),
+                                   ranges[0][1] + g.choice(ex["object_only"], 16, replace=False)]))
+    ec, ed = _sampled_colour_error(torch, tr, [fld_h, fld_o], w, o, d, ranges, pick,
+                                   ((-1.0,) * 3, (1.0,) * 3))
+    tr.close()
+    assert ec < 2e-2 and ed < 2e-2, f"two fields: sampled colour error {ec}, depth {ed}"
+    log(f"[bench] two fields: {dt * 1e3:.3f} ms/step, {nh} + {no} samples, "
+        f"sampled C err {ec:.2e}")
+    return {"workload": w.name, "rays_per_step": R, "rays": {"human": ranges[0][1],
+            "object": R - ranges[1][0], "shared": ex["shared"]},
+            "samples_per_step": {"human": nh, "object": no}, "ms_per_step": dt * 1e3,
+            "rays_per_s": R / dt, "loss": "colour + depth (lambda_d = 1)", "graph": True,
+            "sampled_parity": {"rays": int(pick.size), "colour_max_abs": ec, "depth_max_abs": ed,
+                               "bar": 2e-2}}
+
+
+def bench_keyframes(O, L, F, torch, dev, steps, warmup, train_steps):
+    """Key-frame refinement at full size: 2^20 rays per step drawn over eight
+    1280x720 RGB-D key frames, fused BF16 step (captured graph, tuned shapes);
+    then `train_steps` steps on that batch and a forward-only 1920x1080 novel
+    view of the trained field with early termination at T < 1e-4."""
+    import synth
+    from oracle import step as ostep
+    work, f, scene, cams, occ, rng = synth.keyframe_workload()
+    table = synth.uniform_table(O.grid_desc_of(f).n_entries, 2, rng)
+    params = synth.xavier_params(f.layer_shapes(), rng)
+    box = (f.aabb_min, f.aabb_max)
+    R = work.n_rays
+    o, d, C, D, M = synth.keyframe_batch(scene, cams, R, synth.keyframe_step_rng(work, 0), box)
+    fld = F.Field(work, f, table, params, occ_words=occ)
+    cap = R * 16
+    tr = F.Trainer([fld], R, cap, precision=L.NVR_BF16, lambda_depth=work.lambda_depth,
+                   use_graph=True, autotune=True)
+    tr.set_batch(dev(o), dev(d), dev(C), dev(D), dev(M))
+    dt = _timed(torch, tr, steps, warmup)
+    n = tr.sample_count()
+    assert n <= cap, "sample capacity overflow"
+    for _ in range(train_steps):
+        tr.step()
+    loss = float(tr.loss.item())
+    # the novel view between key frames, full HD
+    W, H, fx = work.extra["render_w"], work.extra["render_h"], 1500.0
+    eo, ed_, egt, emask = synth.keyframe_eval_view(scene, box, w=W, h=H, f=fx)
+    eo_d, ed_d = dev(eo), dev(ed_)
+    rgb, depth = tr.render(eo_d, ed_d, t_stop=work.extra["t_stop"])
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tr.render(eo_d, ed_d, t_stop=work.extra["t_stop"])
+    torch.cuda.synchronize()
+    dt_r = (time.perf_counter() - t0) / reps
+    img = rgb.cpu().numpy()
+    e = (img.astype(np.float64) - egt)[emask]
+    psnr = -10.0 * math.log10(float(np.mean(e * e)))
+    # early termination: samples the marcher keeps vs samples composited
+    md = O.march_desc_of(work, f)
+    mk = O.march(md, eo_d, ed_d, fld.occ, capacity=eo.shape[0] * 48)
+    marched = mk["n"]
+    # sampled parity of the render (oracle on the same fp16 table, rounded weights)
+    pick = np.sort(synth.rng_for(33).choice(np.nonzero(emask)[0], size=64, replace=False))
+    st = ostep.StepState([ostep.FieldState(f, fld.table_half.float().cpu().numpy()
+                                           .astype(np.float64), _f16(fld.params.cpu().numpy()),
+                                           occ_words=occ)])
+    rC, rD = ostep.render(work, st, eo[pick], ed_[pick], [(0, pick.size)],
+                          t_stop=work.extra["t_stop"])
+    wts = ostep.forward_all(work, st, eo[pick], ed_[pick], [(0, pick.size)],
+                            t_stop=work.extra["t_stop"])["w"]
+    kept = int(np.count_nonzero(wts))
+    full = int(ostep.forward_all(work, st, eo[pick], ed_[pick], [(0, pick.size)])["w"].size)
+    ec = float(np.abs(img[pick] - rC).max())
+    tr.close()
+    assert ec < 2e-2, f"key-frame render: sampled colour error {ec}"
+    log(f"[bench] key frames: {dt * 1e3:.3f} ms/step ({n} samples); 1080p render "
+        f"{dt_r * 1e3:.3f} ms, PSNR {psnr:.2f} dB after {warmup + steps + train_steps} steps")
+    return {"workload": work.name, "rays_per_step": R, "samples_per_step": n,
+            "ms_per_step": dt * 1e3, "rays_per_s": R / dt, "graph": True,
+            "render": {"resolution": [W, H], "ms_per_frame": dt_r * 1e3,
+                       "mpix_per_s": W * H / dt_r / 1e6, "t_stop": work.extra["t_stop"],
+                       "trained_steps": warmup + steps + train_steps, "loss": loss,
+                       "psnr_db_in_box": psnr, "marched_samples": marched,
+                       "sampled_rays_composited_fraction": kept / max(full, 1),
+                       "sampled_parity": {"rays": int(pick.size), "colour_max_abs": ec,
+                                          "bar": 2e-2}}}
 
 
 def cpu_baseline(n_rays):

@@ -333,7 +333,8 @@ nvr_status nvr_loss(int64_t n_rays, const float *C, const float *D, const float 
 /* ------------------------------------------------------------------------
  * Adam with loss scaling (optimiser not stated in the paper; Instant-NGP's):
  * g = grad / S; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
- * p -= lr (m / (1-b1^k)) / (sqrt(v / (1-b2^k)) + eps), k = state->step + 1.
+ * p -= lr_k (m / (1-b1^k)) / (sqrt(v / (1-b2^k)) + eps), k = state->step + 1,
+ * lr_k = lr * lr_decay^(k-1).
  * skip_zero leaves entries with grad == 0 untouched.  The grad buffer is
  * zeroed after use.  If state->finite == 0 nothing but the zeroing happens.
  * copy (nullable) receives float16 / bfloat16 of the updated parameter.
@@ -345,7 +346,10 @@ typedef struct {
     float pad;
 } nvr_train_state;               /* lives in DEVICE memory */
 
-typedef struct { float lr, beta1, beta2, eps; } nvr_adam_desc;
+/* lr_decay: the learning rate of update k (1-based, k = state->step + 1) is
+ * lr * lr_decay^(k-1) (an exponential schedule, as Instant-NGP decays its
+ * rate); 0 or 1 keeps it constant. */
+typedef struct { float lr, beta1, beta2, eps, lr_decay; } nvr_adam_desc;
 
 /* state->finite = 1 (call before nvr_check_finite for a new step). */
 nvr_status nvr_state_begin(nvr_train_state *state_dev, nvr_stream stream);
@@ -532,28 +536,34 @@ nvr_status nvr_live_lut(const nvr_lut_desc *d, const uint16_t *knn, const float 
  * in Sec. 4.3): x_can = x + MLP([enc(x), theta]) with enc a multiresolution
  * hash encoding of its own (grid `g`, 32 wide: levels x features = 32, fp32
  * table) and theta one 72-wide pose for all points; 104 -> 128 -> 128 -> 128
- * -> 128 -> 3, bias-free, ReLU on the hidden layers, linear output, float32
- * (each layer one sgemm).  params: nvr_deform_param_count() floats, each
- * layer's W[out][in] row-major in order.  x [n][3], theta [72], table
- * [n_entries][2], x_can [n][3]: device.  workspace: device, 256-byte aligned,
- * nvr_deform_workspace(g, n) bytes (about 4 KB per point), overwritten.
+ * -> 128 -> 3, bias-free, ReLU on the hidden layers, linear output.
+ * math = NVR_F32: float32 throughout (each layer one rocBLAS sgemm, the plain
+ * reference path).  math = NVR_F16: the hand-written matrix-core kernels --
+ * fp16 encoding, weights and activations in the forward, bf16 products in the
+ * backward, fp32 accumulation; the pose enters as the first layer's bias
+ * W0[:, 32:] theta, weight gradients are contracted over the points in fixed
+ * order.  params: nvr_deform_param_count() floats (fp32 masters), each layer's
+ * W[out][in] row-major in order.  x [n][3], theta [72], table [n_entries][2],
+ * x_can [n][3]: device.  workspace: device, 256-byte aligned,
+ * nvr_deform_workspace(g, n) bytes (about 4 KB per point, enough for both
+ * paths), overwritten.
  * nvr_deform_bwd recomputes the forward and, for the gradient dx_can [n][3] of
  * the output, accumulates dparams (acc), dtable (acc, 8-byte aligned; formed
  * by the binned scatter of nvr_encode_bwd_binned, same rounding), dx (acc,
  * nullable: through the encoding plus the identity of the residual) and
  * dtheta [72] (acc, nullable, summed over the points).  Errors: NVR_EINVAL for
  * n outside 0..2^24, NULL arrays or workspace; NVR_EUNSUPPORTED for an
- * encoding not 32 wide or a ladder the binned scatter does not take; NVR_EHIP
- * when a rocBLAS call fails. */
+ * encoding not 32 wide or a ladder the binned scatter does not take, math
+ * other than F32 / F16 (NVR_EINVAL); NVR_EHIP when a rocBLAS call fails. */
 size_t nvr_deform_workspace(const nvr_grid_desc *g, int64_t n);
 int64_t nvr_deform_param_count(void);
 nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
-                          const float *table, const float *params, float *x_can, void *workspace,
-                          nvr_stream stream);
-nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
-                          const float *table, const float *params, const float *dx_can,
-                          float *dparams, float *dtable, float *dx, float *dtheta,
+                          const float *table, const float *params, nvr_dtype math, float *x_can,
                           void *workspace, nvr_stream stream);
+nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
+                          const float *table, const float *params, nvr_dtype math,
+                          const float *dx_can, float *dparams, float *dtable, float *dx,
+                          float *dtheta, void *workspace, nvr_stream stream);
 
 /* ------------------------------------------------------------------------
  * Key-frame selection (Sec. 4.2, "Online key frame selection"; weights in

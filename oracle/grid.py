@@ -86,14 +86,18 @@ _CORNERS = np.array([[(k >> 0) & 1, (k >> 1) & 1, (k >> 2) & 1] for k in range(8
 
 
 def _normalise(x, lay):
-    u = (np.asarray(x, np.float64) - lay.lo) / lay.side
-    inside = (u >= 0.0) & (u <= 1.0)
-    return np.clip(u, 0.0, 1.0), inside
+    """x - lo (float64) and whether x lies in the box (gradients flow)."""
+    t = np.asarray(x, np.float64) - lay.lo
+    inside = (t >= 0.0) & (t <= lay.side)
+    return t, inside
 
 
-def _level_terms(u, level, lay):
+def _level_terms(t, level, lay):
+    # x_l = x_hat * N_l with x_hat = clamp((x - lo) / side, 0, 1), evaluated as
+    # (x - lo) * N_l / side: the product is exact for float32 positions, so a
+    # position exactly on a cell face gets the exact floor
     n = lay.res[level]
-    xl = u * n
+    xl = np.clip(t * n / lay.side, 0.0, n)
     c = np.minimum(np.floor(xl), n - 1).astype(np.int64)
     f = xl - c
     corners = c[:, None, :] + _CORNERS[None, :, :]                   # (n,8,3)

@@ -48,8 +48,12 @@ def eq8_loss(C, D, C_t, D_t, mask=None):
 
 
 class Adam:
-    def __init__(self, lr=1e-2, b1=0.9, b2=0.99, eps=1e-15):
+    """``lr_decay``: update k (1-based) uses lr * lr_decay^(k-1), the exponential
+    schedule Instant-NGP applies to its rate; 1 keeps it constant."""
+
+    def __init__(self, lr=1e-2, b1=0.9, b2=0.99, eps=1e-15, lr_decay=1.0):
         self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.lr_decay = lr_decay
 
     def update(self, p, g, m, v, step, skip_zero=False):
         """One update in place on float64 arrays; ``step`` is the 1-based count."""
@@ -58,7 +62,8 @@ class Adam:
         v[live] = self.b2 * v[live] + (1.0 - self.b2) * g[live] * g[live]
         mh = m[live] / (1.0 - self.b1 ** step)
         vh = v[live] / (1.0 - self.b2 ** step)
-        p[live] -= self.lr * mh / (np.sqrt(vh) + self.eps)
+        lr = self.lr * self.lr_decay ** (step - 1)
+        p[live] -= lr * mh / (np.sqrt(vh) + self.eps)
 
 
 def unscale_and_check(grads, loss_scale):

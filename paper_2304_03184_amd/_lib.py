@@ -72,7 +72,7 @@ class TrainState(C.Structure):
 
 
 class AdamDesc(C.Structure):
-    _fields_ = [("lr", f32), ("beta1", f32), ("beta2", f32), ("eps", f32)]
+    _fields_ = [("lr", f32), ("beta1", f32), ("beta2", f32), ("eps", f32), ("lr_decay", f32)]
 
 
 class Field(C.Structure):
@@ -111,8 +111,8 @@ _SIGS = {
     "nvr_live_lut": (i32, [P(LutDesc), vp, vp, vp, vp, vp]),
     "nvr_deform_workspace": (C.c_size_t, [P(GridDesc), i64]),
     "nvr_deform_param_count": (i64, []),
-    "nvr_deform_fwd": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp]),
-    "nvr_deform_bwd": (i32, [P(GridDesc), i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+    "nvr_deform_fwd": (i32, [P(GridDesc), i64, vp, vp, vp, vp, i32, vp, vp, vp]),
+    "nvr_deform_bwd": (i32, [P(GridDesc), i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
     "nvr_visibility": (i32, [i32, i32, vp, vp, vp, i32, i32, f32, vp, vp]),
     "nvr_human_distance": (i32, [i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, f32, f32, vp, vp,
                                  vp]),

@@ -9,6 +9,7 @@
 // its mask, add the residual and split the input gradient.  The backward
 // recomputes the forward into the workspace.
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 #include <rocblas/rocblas.h>
@@ -38,6 +39,20 @@ struct DeformWs {
 };
 
 size_t round_up(size_t b) { return (b + 255) / 256 * 256; }
+
+// Workspace of the matrix-core path (carved like the float32 one).
+struct DeformMfmaWs {
+    uint16_t *feat;      // [n][32] fp16 encoding
+    float *bias;         // [128] pose term
+    uint4 *fwd, *bwd;    // weight fragments
+    uint16_t *hbuf, *zbuf;
+    float *dfeat;        // [n][32]
+    float *partial;      // [kDwGrid][128][144] weight-gradient partials
+    void *binned;
+};
+constexpr int kDwGrid = 256;
+
+size_t carve_mfma(const nvr_grid_desc *g, int64_t n, char *base, DeformMfmaWs *w);
 
 // Carves the workspace; returns its size (base may be null to only measure).
 size_t carve(const nvr_grid_desc *g, int64_t n, char *base, DeformWs *w) {
@@ -164,10 +179,9 @@ dn_encode_dx(GridParams p, int64_t n, const float *__restrict__ x,
                 d1 += dw.y * tg;
                 d2 += dw.z * tg;
             }
-            const float N = (float)p.res[l];
-            if (lp.inside[0]) acc0 += d0 * N * (float)p.inv_side[0];
-            if (lp.inside[1]) acc1 += d1 * N * (float)p.inv_side[1];
-            if (lp.inside[2]) acc2 += d2 * N * (float)p.inv_side[2];
+            if (lp.inside[0]) acc0 += d0 * p.s_hi[l][0];
+            if (lp.inside[1]) acc1 += d1 * p.s_hi[l][1];
+            if (lp.inside[2]) acc2 += d2 * p.s_hi[l][2];
         }
         dx[3 * s] += acc0;
         dx[3 * s + 1] += acc1;
@@ -242,7 +256,7 @@ nvr_status gemm_dw(rocblas_handle h, hipStream_t st, int64_t n, int out, int in,
     return NVR_OK;
 }
 
-const float *layer_w(const float *params, int i) {
+__host__ __device__ const float *layer_w(const float *params, int i) {
     if (i == 0) return params;
     return params + (int64_t)kWidth * kIn + (int64_t)(i - 1) * kWidth * kWidth;
 }
@@ -260,6 +274,492 @@ nvr_status check(const nvr_grid_desc *g, int64_t n, const void *ws) {
     const GridParams p = make_grid_params(g);
     NVR_TRY(scatter_check(p));
     NVR_REQUIRE((size_t)n * p.L * 8 < (1ull << 32), NVR_EINVAL, "too many contributions");
+    return NVR_OK;
+}
+
+// ---------------------------------------------------------------- matrix-core path
+// fp16 forward (features, weights, activations), bf16 backward products, fp32
+// accumulation, as the field networks.  A wave works on blocks of 16 points in
+// the orientation of the field networks: a layer computes D = W X (rows =
+// units, columns = points); lane l holds units 16m + 4g..4g+3 (g = l / 16) of
+// point l % 16, and pairing row tiles 2q and 2q+1 gives the operand of the
+// next layer's K-step q once its contraction index is permuted to match (the
+// weight fragments carry the same permutation), so activations stay in
+// registers.  The pose enters the first layer as a bias shared by every point,
+// W0[:, 32:] theta, formed once per call.
+//
+// Fragments (16 bytes per lane and tile) are built once per call into the
+// workspace: the forward kernel copies its set into LDS, the backward kernel
+// copies the transposed set and reads the forward set (L2-resident) to
+// recompute each block.  The backward writes, per block of 16 points, the
+// bf16 activations and output gradients of every layer unit-major ([units][16]);
+// the weight gradients are then contracted over the points on the matrix
+// cores by workgroups over point chunks (partials summed in a fixed order).
+typedef __attribute__((ext_vector_type(8))) __bf16 dbf8;
+typedef __attribute__((ext_vector_type(8))) _Float16 dh8;
+typedef __attribute__((ext_vector_type(4))) short ds4;
+typedef __attribute__((ext_vector_type(4))) float df4;
+
+__device__ __forceinline__ df4 dmfma(dh8 a, dh8 b, df4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ df4 dmfma(dbf8 a, dbf8 b, df4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ df4 dmfma16(ds4 a, ds4 b, df4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ df4 dzero() { return df4{0.f, 0.f, 0.f, 0.f}; }
+__device__ __forceinline__ df4 drelu(df4 a) {
+    return df4{fmaxf(a[0], 0.f), fmaxf(a[1], 0.f), fmaxf(a[2], 0.f), fmaxf(a[3], 0.f)};
+}
+__device__ __forceinline__ dh8 dpackh(df4 a, df4 b) {
+    dh8 r;
+    r[0] = (_Float16)a[0]; r[1] = (_Float16)a[1]; r[2] = (_Float16)a[2]; r[3] = (_Float16)a[3];
+    r[4] = (_Float16)b[0]; r[5] = (_Float16)b[1]; r[6] = (_Float16)b[2]; r[7] = (_Float16)b[3];
+    return r;
+}
+__device__ __forceinline__ dbf8 dpackb(df4 a, df4 b) {
+    dbf8 r;
+    r[0] = (__bf16)a[0]; r[1] = (__bf16)a[1]; r[2] = (__bf16)a[2]; r[3] = (__bf16)a[3];
+    r[4] = (__bf16)b[0]; r[5] = (__bf16)b[1]; r[6] = (__bf16)b[2]; r[7] = (__bf16)b[3];
+    return r;
+}
+// contraction index of a 128-wide layer input: K-step q, lane group g, slot j
+__host__ __device__ __forceinline__ int dkh(int q, int g, int j) {
+    return j < 4 ? 32 * q + 4 * g + j : 32 * q + 16 + 4 * g + (j - 4);
+}
+
+// fragment offsets, in 16-byte units (one per lane and tile)
+constexpr int kFw0 = 0;                       // W0 (feature part): 8 row tiles
+constexpr int kFw1 = kFw0 + 8 * 64;           // W1..W3: 8 row tiles x 4 K-steps each
+constexpr int kFw4 = kFw1 + 3 * 32 * 64;      // W4 (3 rows of 16): 4 K-steps
+constexpr int kFwd = kFw4 + 4 * 64;           // forward set: 6912 (108 KiB)
+constexpr int kBw1 = 0;                       // W1^T..W3^T: 8 row tiles x 4 K-steps each
+constexpr int kBw0 = kBw1 + 3 * 32 * 64;      // W0f^T: 2 row tiles (features) x 4 K-steps
+constexpr int kBw4 = kBw0 + 8 * 64;           // W4^T: 8 row tiles, 8-byte operands (half units)
+constexpr int kBwd = kBw4 + 8 * 64 / 2;       // backward set: 6912 (108 KiB)
+constexpr int kDnBlock = 512;                 // 8 waves: two per SIMD around one fragment copy
+
+// One lane-tile fragment per thread of the grid: forward (fp16, W rows) and
+// backward (bf16, W^T rows) sets, both with the chained contraction order.
+__global__ void __launch_bounds__(256)
+dn_frags(const float *__restrict__ params, uint4 *__restrict__ fwd, uint4 *__restrict__ bwd) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    auto W = [&](int layer, int row, int col) -> float {
+        const int in = layer == 0 ? kIn : kWidth;
+        return layer_w(params, layer)[(int64_t)row * in + col];
+    };
+    if (e < kFwd) {
+        const int l = e % 64, r = l % 16, g = l / 16, t = e / 64;
+        dh8 v;
+        if (e < kFw1) {                                     // W0 feature part
+            const int m = t;
+            for (int j = 0; j < 8; ++j) v[j] = (_Float16)W(0, 16 * m + r, 8 * g + j);
+        } else if (e < kFw4) {
+            const int u = t - kFw1 / 64, layer = 1 + u / 32, m = (u % 32) / 4, q = u % 4;
+            for (int j = 0; j < 8; ++j) v[j] = (_Float16)W(layer, 16 * m + r, dkh(q, g, j));
+        } else {
+            const int q = t - kFw4 / 64;
+            for (int j = 0; j < 8; ++j) v[j] = (_Float16)(r < 3 ? W(4, r, dkh(q, g, j)) : 0.f);
+        }
+        fwd[e] = __builtin_bit_cast(uint4, v);
+        return;
+    }
+    const int b = e - kFwd;
+    if (b < kBw4) {
+        const int l = b % 64, r = l % 16, g = l / 16, t = b / 64;
+        dbf8 v;
+        if (b < kBw0) {                                     // W_L^T, L = 1..3
+            const int layer = 1 + t / 32, m = (t % 32) / 4, q = t % 4;
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(layer, dkh(q, g, j), 16 * m + r);
+        } else {                                            // W0f^T: rows = features
+            const int u = t - kBw0 / 64, m = u / 4, q = u % 4;
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)W(0, dkh(q, g, j), 16 * m + r);
+        }
+        bwd[b] = __builtin_bit_cast(uint4, v);
+    } else if (b < kBw4 + 8 * 64) {                         // W4^T, 16x16x16 operands
+        const int i = b - kBw4, l = i % 64, r = l % 16, g = l / 16, m = i / 64;
+        ds4 v;
+        for (int j = 0; j < 4; ++j)
+            v[j] = __builtin_bit_cast(short, (__bf16)(4 * g + j < 3 ? W(4, 4 * g + j, 16 * m + r)
+                                                                   : 0.f));
+        reinterpret_cast<uint2 *>(bwd + kBw4)[i] = __builtin_bit_cast(uint2, v);
+    }
+}
+
+// bias[u] = sum_c W0[u][32 + c] theta[c]: the pose term of the first layer
+__global__ void __launch_bounds__(kWidth)
+dn_pose_bias(const float *__restrict__ params, const float *__restrict__ theta,
+             float *__restrict__ bias) {
+    const int u = threadIdx.x;
+    const float *w = params + (int64_t)u * kIn + kFeat;
+    float a = 0.f;
+    for (int c = 0; c < kPose; ++c) a += w[c] * theta[c];
+    bias[u] = a;
+}
+
+// Forward of one block of 16 points: acc[m] are the output row tiles of the
+// last hidden layer; hid[l][q] the packed (fp16) activations of hidden layer l.
+struct DnFwd {
+    df4 acc[8];
+    dh8 hid[4][4];
+    df4 out;
+};
+
+// bias4: the pose bias at rows 16m + 4g.. of this lane (read per block)
+__device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
+                                             const float *__restrict__ bias4, dh8 x0, DnFwd &s) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        s.acc[m] = dmfma(__builtin_bit_cast(dh8, F[kFw0 + m * 64]), x0,
+                         *reinterpret_cast<const df4 *>(bias4 + 16 * m));
+#pragma unroll
+    for (int layer = 1; layer <= 3; ++layer) {
+        asm volatile("" ::: "memory");   // load each layer's fragments when it runs
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            s.hid[layer - 1][q] = dpackh(drelu(s.acc[2 * q]), drelu(s.acc[2 * q + 1]));
+        const int base = kFw1 + (layer - 1) * 32 * 64;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (m == 4) asm volatile("" ::: "memory");   // half a layer of fragments at a time
+            df4 a = dzero();
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a = dmfma(__builtin_bit_cast(dh8, F[base + (m * 4 + q) * 64]), s.hid[layer - 1][q],
+                          a);
+            s.acc[m] = a;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s.hid[3][q] = dpackh(drelu(s.acc[2 * q]), drelu(s.acc[2 * q + 1]));
+    df4 o = dzero();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o = dmfma(__builtin_bit_cast(dh8, F[kFw4 + q * 64]), s.hid[3][q], o);
+    s.out = o;
+}
+
+// Forward: x_can = x + W4 relu(W3 relu(W2 relu(W1 relu(W0f feat + bias)))).
+// feat: fp16 encoding [n][32]; bias: the pose term [128].
+__global__ void __launch_bounds__(kDnBlock)
+dn_fwd_mfma(int64_t n, const uint16_t *__restrict__ feat, const float *__restrict__ bias,
+            const uint4 *__restrict__ gfwd, const float *__restrict__ x,
+            float *__restrict__ x_can) {
+    extern __shared__ uint4 F[];
+    for (int i = threadIdx.x; i < kFwd; i += kDnBlock) F[i] = gfwd[i];
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const float *bias4 = bias + 4 * g;
+    __syncthreads();
+    const int64_t waves = (int64_t)gridDim.x * (kDnBlock / 64);
+    for (int64_t blk = blockIdx.x * (int64_t)(kDnBlock / 64) + (threadIdx.x >> 6); blk * 16 < n;
+         blk += waves) {
+        // the fragments are re-read from LDS each block: keeps the compiler
+        // from hoisting all 108 of them into registers across the loop
+        asm volatile("" ::: "memory");
+        const int64_t p = blk * 16 + c;
+        const bool valid = p < n;
+        dh8 x0 = {};
+        if (valid) x0 = __builtin_bit_cast(dh8, *reinterpret_cast<const uint4 *>(feat + p * kFeat + 8 * g));
+        DnFwd s;
+        dn_block_fwd(F + lane, bias4, x0, s);
+        if (g == 0 && valid) {
+            x_can[3 * p] = x[3 * p] + s.out[0];
+            x_can[3 * p + 1] = x[3 * p + 1] + s.out[1];
+            x_can[3 * p + 2] = x[3 * p + 2] + s.out[2];
+        }
+    }
+}
+
+// Per-block activation / gradient tiles of the backward, bf16, unit-major
+// [block][units][16 points]: H holds the encoding (32 units) then the four
+// hidden layers' outputs (4 x 128); Z the output gradients of W0..W3 (4 x 128)
+// then of W4 (16 units, 3 used).
+constexpr int kHUnits = kFeat + 4 * kWidth;   // 544
+constexpr int kZUnits = 4 * kWidth + 16;      // 528
+__device__ __forceinline__ uint16_t bfbits(float v) {
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+__global__ void __launch_bounds__(kDnBlock)
+dn_bwd_mfma(int64_t n, const uint16_t *__restrict__ feat, const float *__restrict__ bias,
+            const uint4 *__restrict__ gfwd, const uint4 *__restrict__ gbwd,
+            const float *__restrict__ dxc, float *__restrict__ dfeat,
+            uint16_t *__restrict__ hbuf, uint16_t *__restrict__ zbuf) {
+    extern __shared__ uint4 Bt[];
+    for (int i = threadIdx.x; i < kBwd; i += kDnBlock) Bt[i] = gbwd[i];
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const float *bias4 = bias + 4 * g;
+    __syncthreads();
+    const uint4 *Ff = gfwd + lane;
+    const uint4 *Bl = Bt + lane;
+    const uint2 *B4 = reinterpret_cast<const uint2 *>(Bt + kBw4) + lane;
+    const int64_t waves = (int64_t)gridDim.x * (kDnBlock / 64);
+    for (int64_t blk = blockIdx.x * (int64_t)(kDnBlock / 64) + (threadIdx.x >> 6); blk * 16 < n;
+         blk += waves) {
+        asm volatile("" ::: "memory");   // fragments are re-read each block (see the forward)
+        // the global fragment pointer is made opaque per block: read-only
+        // loads would otherwise be hoisted out of the loop into registers
+        const uint4 *Fb = Ff;
+        asm volatile("" : "+v"(Fb));
+        const int64_t p = blk * 16 + c;
+        const bool valid = p < n;
+        dh8 x0 = {};
+        if (valid) x0 = __builtin_bit_cast(dh8, *reinterpret_cast<const uint4 *>(feat + p * kFeat + 8 * g));
+        DnFwd s;
+        dn_block_fwd(Fb, bias4, x0, s);
+        uint16_t *H = hbuf + blk * (int64_t)kHUnits * 16;
+        uint16_t *Z = zbuf + blk * (int64_t)kZUnits * 16;
+        // activations: encoding (slot j = feature 8g + j), hidden layers (slot
+        // j of K-step q = unit dkh(q, g, j)); zero for points past n
+#pragma unroll
+        for (int j = 0; j < 8; ++j) H[(8 * g + j) * 16 + c] = bfbits((float)x0[j]);
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    H[(kFeat + l * kWidth + dkh(q, g, j)) * 16 + c] =
+                        valid ? bfbits((float)s.hid[l][q][j]) : (uint16_t)0;
+        // output layer: dZ4 = dx_can (rows 0..2 of a 16-row operand)
+        ds4 z4 = {};
+        if (g == 0 && valid) {
+            z4[0] = __builtin_bit_cast(short, (__bf16)dxc[3 * p]);
+            z4[1] = __builtin_bit_cast(short, (__bf16)dxc[3 * p + 1]);
+            z4[2] = __builtin_bit_cast(short, (__bf16)dxc[3 * p + 2]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Z[(4 * kWidth + 4 * g + j) * 16 + c] = (uint16_t)z4[j];
+        df4 d[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            d[m] = dmfma16(__builtin_bit_cast(ds4, B4[m * 64]), z4, dzero());
+        dbf8 zb[4];
+#pragma unroll
+        for (int layer = 3; layer >= 0; --layer) {
+            asm volatile("" ::: "memory");   // load each layer's fragments when it runs
+            // dZ = dH through the ReLU of hidden layer `layer` (its fp16 output
+            // is the mask), staged, then paired into the next operands
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (!((float)s.hid[layer][q][i] > 0.f)) d[2 * q][i] = 0.f;
+                    if (!((float)s.hid[layer][q][4 + i] > 0.f)) d[2 * q + 1][i] = 0.f;
+                }
+                zb[q] = dpackb(d[2 * q], d[2 * q + 1]);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    Z[(layer * kWidth + dkh(q, g, j)) * 16 + c] =
+                        valid ? bfbits(j < 4 ? d[2 * q][j] : d[2 * q + 1][j - 4]) : (uint16_t)0;
+            }
+            if (layer > 0) {
+                const int base = kBw1 + (layer - 1) * 32 * 64;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    if (m == 4) asm volatile("" ::: "memory");
+                    df4 a = dzero();
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        a = dmfma(__builtin_bit_cast(dbf8, Bl[base + (m * 4 + q) * 64]), zb[q], a);
+                    d[m] = a;
+                }
+            }
+        }
+        // encoding gradient: dfeat = W0f^T dZ0, rows = features 16m + 4g + i
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            df4 a = dzero();
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a = dmfma(__builtin_bit_cast(dbf8, Bl[kBw0 + (m * 4 + q) * 64]), zb[q], a);
+            if (valid) *reinterpret_cast<df4 *>(dfeat + p * kFeat + 16 * m + 4 * g) = a;
+        }
+    }
+}
+
+// Weight gradients dW = dZ H^T over the points: workgroup b contracts K-steps
+// of 32 points (two blocks) b, b + grid, ... for out tiles w and w + 4 of its
+// wave w and every in tile; `ones` adds an in tile of ones (the sums over the
+// points of dZ, for the pose gradient).  Writes its [16 TO][16 (TI + ones)]
+// partial.
+template <int TO, int TI, bool ONES>
+__global__ void __launch_bounds__(256)
+dn_dw(int64_t nblk, const uint16_t *__restrict__ zbuf, int z_off,
+      const uint16_t *__restrict__ hbuf, int h_off, float *__restrict__ partial) {
+    constexpr int TIN = TI + (ONES ? 1 : 0);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15, w = threadIdx.x >> 6;
+    df4 acc[2][TIN];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < TIN; ++t) acc[a][t] = dzero();
+    const int64_t nstep = (nblk + 1) / 2;
+    dbf8 ones;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.f;
+    for (int64_t st = blockIdx.x; st < nstep; st += gridDim.x) {
+        const int64_t blk = 2 * st + (g >> 1);
+        const int pt = 8 * (g & 1);
+        const bool in_range = blk < nblk;
+        dbf8 A[2], B[TI];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int mo = w + 4 * a;
+            A[a] = {};
+            if (mo < TO && in_range)
+                A[a] = __builtin_bit_cast(dbf8, *reinterpret_cast<const uint4 *>(
+                    zbuf + (blk * kZUnits + z_off + 16 * mo + r) * 16 + pt));
+        }
+#pragma unroll
+        for (int t = 0; t < TI; ++t) {
+            B[t] = {};
+            if (in_range)
+                B[t] = __builtin_bit_cast(dbf8, *reinterpret_cast<const uint4 *>(
+                    hbuf + (blk * kHUnits + h_off + 16 * t + r) * 16 + pt));
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (w + 4 * a >= TO) continue;
+#pragma unroll
+            for (int t = 0; t < TI; ++t) acc[a][t] = dmfma(A[a], B[t], acc[a][t]);
+            if (ONES) acc[a][TI] = dmfma(A[a], ones, acc[a][TI]);
+        }
+    }
+    // partial[b][row 16 mo + 4g + i][col 16 t + r]
+    const int ncol = 16 * TIN;
+    float *out = partial + (int64_t)blockIdx.x * (16 * TO) * ncol;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int mo = w + 4 * a;
+        if (mo >= TO) continue;
+#pragma unroll
+        for (int t = 0; t < TIN; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[(16 * mo + 4 * g + i) * ncol + 16 * t + r] = acc[a][t][i];
+    }
+}
+
+// dW[row][col] (acc, rows < out_rows, cols < in_cols of the weight, stride
+// w_ld) += sum over the workgroups' partials in order; with `pose`, the extra
+// column block (sums of dZ0 over the points) is contracted with W0's pose
+// columns into dtheta instead.
+__global__ void __launch_bounds__(256)
+dn_dw_reduce(int parts, int rows, int ncol, int out_rows, int in_cols,
+             const float *__restrict__ partial, float *__restrict__ dW, int w_ld) {
+    const int64_t total = (int64_t)out_rows * in_cols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int row = (int)(i / in_cols), col = (int)(i % in_cols);
+        float a = 0.f;
+        for (int b = 0; b < parts; ++b) a += partial[((int64_t)b * rows + row) * ncol + col];
+        dW[(int64_t)row * w_ld + col] += a;
+    }
+}
+
+// The pose part of the first layer, from s[u] = sum over the points of dZ0[u]
+// (the ones column, column `col` of the layer-0 partials, summed in order):
+// dW0[u][32 + c] += s[u] theta[c] and (nullable) dtheta[c] += sum_u W0[u][32 + c] s[u].
+__global__ void __launch_bounds__(kWidth)
+dn_pose_grad(int parts, int ncol, int col, const float *__restrict__ partial,
+             const float *__restrict__ params, const float *__restrict__ theta,
+             float *__restrict__ dparams, float *__restrict__ dtheta) {
+    __shared__ float su[kWidth];
+    const int u = threadIdx.x;
+    float a = 0.f;
+    for (int b = 0; b < parts; ++b) a += partial[((int64_t)b * kWidth + u) * ncol + col];
+    su[u] = a;
+    for (int c = 0; c < kPose; ++c) dparams[(int64_t)u * kIn + kFeat + c] += a * theta[c];
+    __syncthreads();
+    if (dtheta != nullptr && u < kPose) {
+        float t = 0.f;
+        for (int v = 0; v < kWidth; ++v) t += params[(int64_t)v * kIn + kFeat + u] * su[v];
+        dtheta[u] += t;
+    }
+}
+
+size_t carve_mfma(const nvr_grid_desc *g, int64_t n, char *base, DeformMfmaWs *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += round_up(bytes);
+        return p;
+    };
+    const int64_t nblk = (n + 15) / 16 + 1;   // one spare block: K-steps pair blocks
+    DeformMfmaWs t;
+    t.feat = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)n * kFeat));
+    t.bias = reinterpret_cast<float *>(take(sizeof(float) * kWidth));
+    t.fwd = reinterpret_cast<uint4 *>(take(sizeof(uint4) * kFwd));
+    t.bwd = reinterpret_cast<uint4 *>(take(sizeof(uint4) * kBwd));
+    t.hbuf = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)nblk * kHUnits * 16));
+    t.zbuf = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)nblk * kZUnits * 16));
+    t.dfeat = reinterpret_cast<float *>(take(sizeof(float) * (size_t)n * kFeat));
+    t.partial = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kDwGrid * kWidth * 144));
+    t.binned = take(nvr_encode_bwd_workspace(g, n));
+    if (w) *w = t;
+    return off;
+}
+
+// opt in to the fragment copies' LDS, once per device
+nvr_status dn_lds_opt_in() {
+    static std::atomic<uint64_t> done{0};
+    int dev = 0;
+    NVR_HIP(hipGetDevice(&dev));
+    const uint64_t bit = 1ull << (dev & 63);
+    if (done.load() & bit) return NVR_OK;
+    NVR_HIP(hipFuncSetAttribute((const void *)dn_fwd_mfma,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(uint4) * kFwd)));
+    NVR_HIP(hipFuncSetAttribute((const void *)dn_bwd_mfma,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(uint4) * kBwd)));
+    done.fetch_or(bit);
+    return NVR_OK;
+}
+
+// encoding (fp16 features from the fp32 table), fragments and pose bias
+nvr_status mfma_prologue(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
+                         const float *table, const float *params, const DeformMfmaWs &w,
+                         hipStream_t st) {
+    NVR_TRY(dn_lds_opt_in());
+    NVR_TRY(nvr_encode_fwd(g, n, x, table, NVR_F32, w.feat, NVR_F16,
+                           reinterpret_cast<nvr_stream>(st)));
+    dn_frags<<<(kFwd + kBw4 + 8 * 64 + 255) / 256, 256, 0, st>>>(params, w.fwd, w.bwd);
+    NVR_LAUNCHED();
+    dn_pose_bias<<<1, kWidth, 0, st>>>(params, theta, w.bias);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
+unsigned dn_grid(int64_t n) {
+    const int64_t nblk = (n + 15) / 16;
+    const int64_t wg = (nblk + kDnBlock / 64 - 1) / (kDnBlock / 64);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg, kCus));
+}
+
+nvr_status mfma_forward(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
+                        const float *table, const float *params, float *x_can,
+                        const DeformMfmaWs &w, hipStream_t st) {
+    NVR_TRY(mfma_prologue(g, n, x, theta, table, params, w, st));
+    dn_fwd_mfma<<<dn_grid(n), kDnBlock, sizeof(uint4) * kFwd, st>>>(n, w.feat, w.bias, w.fwd, x,
+                                                                    x_can);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
+// dW (acc) of one layer: dZ rows at z_off (TO tiles) against H rows at h_off (TI tiles)
+template <int TO, int TI, bool ONES>
+nvr_status mfma_dw(int64_t nblk, const DeformMfmaWs &w, int z_off, int h_off, float *dW,
+                   int out_rows, int in_cols, int w_ld, hipStream_t st) {
+    const int64_t nstep = (nblk + 1) / 2;
+    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(nstep, kDwGrid));
+    dn_dw<TO, TI, ONES><<<parts, 256, 0, st>>>(nblk, w.zbuf, z_off, w.hbuf, h_off, w.partial);
+    NVR_LAUNCHED();
+    const int ncol = 16 * (TI + (ONES ? 1 : 0));
+    dn_dw_reduce<<<grid_for((int64_t)out_rows * in_cols, 256, 256), 256, 0, st>>>(
+        parts, 16 * TO, ncol, out_rows, in_cols, w.partial, dW, w_ld);
+    NVR_LAUNCHED();
     return NVR_OK;
 }
 
@@ -290,19 +790,29 @@ using namespace nvr;
 
 extern "C" size_t nvr_deform_workspace(const nvr_grid_desc *g, int64_t n) {
     if (g == nullptr || n < 0) return 0;
-    return carve(g, n, nullptr, nullptr);
+    return std::max(carve(g, n, nullptr, nullptr), carve_mfma(g, n, nullptr, nullptr));
 }
 
 extern "C" int64_t nvr_deform_param_count(void) { return kParams; }
 
 extern "C" nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const float *x,
                                      const float *theta, const float *table, const float *params,
-                                     float *x_can, void *workspace, nvr_stream stream) {
+                                     nvr_dtype math, float *x_can, void *workspace,
+                                     nvr_stream stream) {
     clear_error();
     NVR_TRY(check(g, n, workspace));
+    NVR_REQUIRE(math == NVR_F32 || math == NVR_F16, NVR_EINVAL, "math must be F32 or F16");
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(x && theta && table && params && x_can, NVR_EINVAL, "NULL array");
+    NVR_REQUIRE(aligned(x, 4) && aligned(theta, 4) && aligned(table, 8) && aligned(params, 4) &&
+                    aligned(x_can, 4),
+                NVR_EINVAL, "misaligned array");
     const hipStream_t st = hs(stream);
+    if (math == NVR_F16) {
+        DeformMfmaWs w;
+        carve_mfma(g, n, static_cast<char *>(workspace), &w);
+        return mfma_forward(g, n, x, theta, table, params, x_can, w, st);
+    }
     rocblas_handle h;
     std::lock_guard<std::mutex> lock(g_blas_mu);
     NVR_TRY(blas_for(st, &h));
@@ -314,13 +824,51 @@ extern "C" nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const fl
     return NVR_OK;
 }
 
+// Matrix-core backward: recompute + chain per block, weight gradients over
+// the points, pose terms, then the encoding's table and position gradients.
+static nvr_status mfma_backward(const nvr_grid_desc *g, int64_t n, const float *x,
+                                const float *theta, const float *table, const float *params,
+                                const float *dx_can, float *dparams, float *dtable, float *dx,
+                                float *dtheta, const DeformMfmaWs &w, hipStream_t st) {
+    NVR_TRY(mfma_prologue(g, n, x, theta, table, params, w, st));
+    dn_bwd_mfma<<<dn_grid(n), kDnBlock, sizeof(uint4) * kBwd, st>>>(
+        n, w.feat, w.bias, w.fwd, w.bwd, dx_can, w.dfeat, w.hbuf, w.zbuf);
+    NVR_LAUNCHED();
+    const int64_t nblk = (n + 15) / 16;
+    // W4 [3][128]: dZ4 rows at 512 (one tile) x H3 at 416
+    NVR_TRY((mfma_dw<1, 8, false>(nblk, w, 4 * kWidth, kFeat + 3 * kWidth,
+                                  dparams + (layer_w(params, 4) - params), 3, kWidth, kWidth, st)));
+    for (int layer = 3; layer >= 1; --layer)   // W_L [128][128]: dZ_L x H_{L-1}
+        NVR_TRY((mfma_dw<8, 8, false>(nblk, w, layer * kWidth, kFeat + (layer - 1) * kWidth,
+                                      dparams + (layer_w(params, layer) - params), kWidth, kWidth,
+                                      kWidth, st)));
+    // W0's feature columns: dZ0 x encoding, plus the sums of dZ0 for the pose
+    NVR_TRY((mfma_dw<8, 2, true>(nblk, w, 0, 0, dparams, kWidth, kFeat, kIn, st)));
+    const int64_t nstep = (nblk + 1) / 2;
+    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(nstep, kDwGrid));
+    dn_pose_grad<<<1, kWidth, 0, st>>>(parts, 16 * 3, 16 * 2, w.partial, params, theta, dparams,
+                                       dtheta);
+    NVR_LAUNCHED();
+    NVR_TRY(nvr_encode_bwd_binned(g, n, x, table, w.dfeat, dtable, nullptr, w.binned,
+                                  reinterpret_cast<nvr_stream>(st)));
+    if (dx) {
+        dn_encode_dx<<<grid_for(n, 256, 16384), 256, 0, st>>>(
+            make_grid_params(g), n, x, reinterpret_cast<const float2 *>(table), w.dfeat, dx);
+        NVR_LAUNCHED();
+        dn_add<<<grid_for(n * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can);
+        NVR_LAUNCHED();
+    }
+    return NVR_OK;
+}
+
 extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
                                      const float *theta, const float *table, const float *params,
-                                     const float *dx_can, float *dparams, float *dtable,
-                                     float *dx, float *dtheta, void *workspace,
+                                     nvr_dtype math, const float *dx_can, float *dparams,
+                                     float *dtable, float *dx, float *dtheta, void *workspace,
                                      nvr_stream stream) {
     clear_error();
     NVR_TRY(check(g, n, workspace));
+    NVR_REQUIRE(math == NVR_F32 || math == NVR_F16, NVR_EINVAL, "math must be F32 or F16");
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(x && theta && table && params && dx_can && dparams && dtable, NVR_EINVAL,
                 "NULL array");
@@ -329,6 +877,12 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
                     aligned(dx, 4) && aligned(dtheta, 4),
                 NVR_EINVAL, "misaligned array");
     const hipStream_t st = hs(stream);
+    if (math == NVR_F16) {
+        DeformMfmaWs w;
+        carve_mfma(g, n, static_cast<char *>(workspace), &w);
+        return mfma_backward(g, n, x, theta, table, params, dx_can, dparams, dtable, dx, dtheta,
+                             w, st);
+    }
     rocblas_handle h;
     std::lock_guard<std::mutex> lock(g_blas_mu);
     NVR_TRY(blas_for(st, &h));

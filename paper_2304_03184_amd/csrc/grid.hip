@@ -10,10 +10,10 @@
 //                gradient atomics stay L2-resident.  Workgroups are dispatched
 //                round-robin over the XCDs; the mapping only affects locality.
 //
-// Coordinate transform (both): x_l = clamp((x - lo) / side, 0, 1) * N_l in
-// float64, so the fractional position keeps float32 accuracy at N_l = 2048
-// (in float32 alone x_l carries an error of ~1e-4 of a cell at the finest
-// level).
+// Coordinate transform (both): x_l = clamp((x - lo) N_l / side, 0, N_l) carried
+// as a float32 pair (level_pos), so the fractional position keeps float32
+// accuracy at N_l = 2048 (one float32 product carries an error of ~1e-4 of a
+// cell at the finest level) and the cell is the floor of the exact x_l.
 #include "common.hpp"
 #include "grid_dev.hpp"
 
@@ -33,7 +33,13 @@ GridParams make_grid_params(const nvr_grid_desc *g) {
     p.off[g->n_levels] = (uint32_t)g->offset[g->n_levels];
     for (int a = 0; a < 3; ++a) {
         p.lo[a] = g->aabb_min[a];
-        p.inv_side[a] = 1.0 / ((double)g->aabb_max[a] - (double)g->aabb_min[a]);
+        const double side = (double)g->aabb_max[a] - (double)g->aabb_min[a];
+        p.side[a] = (float)side;
+        for (int l = 0; l < g->n_levels; ++l) {
+            const double s = (double)g->res[l] / side;
+            p.s_hi[l][a] = (float)s;
+            p.s_lo[l][a] = (float)(s - (double)p.s_hi[l][a]);
+        }
     }
     return p;
 }
@@ -114,10 +120,9 @@ encode_bwd_plain(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
             }
         }
         if (dx != nullptr) {
-            const float N = (float)p.res[l];
-            if (lp.inside[0]) unsafeAtomicAdd(dx + 3 * s + 0, d0 * N * (float)p.inv_side[0]);
-            if (lp.inside[1]) unsafeAtomicAdd(dx + 3 * s + 1, d1 * N * (float)p.inv_side[1]);
-            if (lp.inside[2]) unsafeAtomicAdd(dx + 3 * s + 2, d2 * N * (float)p.inv_side[2]);
+            if (lp.inside[0]) unsafeAtomicAdd(dx + 3 * s + 0, d0 * p.s_hi[l][0]);
+            if (lp.inside[1]) unsafeAtomicAdd(dx + 3 * s + 1, d1 * p.s_hi[l][1]);
+            if (lp.inside[2]) unsafeAtomicAdd(dx + 3 * s + 2, d2 * p.s_hi[l][2]);
         }
     }
 }
@@ -270,10 +275,9 @@ encode_bwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
                     e2 += dw.z * tg;
                 }
             }
-            const float N = (float)p.res[l];
-            if (lp.inside[0]) d0 += e0 * N * (float)p.inv_side[0];
-            if (lp.inside[1]) d1 += e1 * N * (float)p.inv_side[1];
-            if (lp.inside[2]) d2 += e2 * N * (float)p.inv_side[2];
+            if (lp.inside[0]) d0 += e0 * p.s_hi[l][0];
+            if (lp.inside[1]) d1 += e1 * p.s_hi[l][1];
+            if (lp.inside[2]) d2 += e2 * p.s_hi[l][2];
         }
         if (dx_parts != nullptr) {
             if (PLANAR) {  // per-group partials, summed by the consumer

@@ -4,6 +4,8 @@
 // the step is skipped), nvr_state_end advances the step count or halves the
 // loss scale.
 #include "common.hpp"
+
+#include <cmath>
 #include "optim_dev.hpp"
 
 namespace nvr {
@@ -34,6 +36,7 @@ adam_kernel(AdamParams a, int64_t n, float *__restrict__ p, float *__restrict__ 
     const int k = st->step + 1;
     const float bc1 = 1.f - powf(a.b1, (float)k);
     const float bc2 = 1.f - powf(a.b2, (float)k);
+    const float lr = a.lr * exp2f(a.log2_decay * (float)(k - 1));   // lr decay^(k-1)
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float g = grad[i] * inv_s;
@@ -44,7 +47,7 @@ adam_kernel(AdamParams a, int64_t n, float *__restrict__ p, float *__restrict__ 
         const float vi = a.b2 * v[i] + (1.f - a.b2) * g * g;
         m[i] = mi;
         v[i] = vi;
-        const float pi = p[i] - a.lr * (mi / bc1) / (sqrtf(vi / bc2) + a.eps);
+        const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + a.eps);
         p[i] = pi;
         if (COPY == 1) copy[i] = f32_to_f16_bits(pi);
         if (COPY == 2) copy[i] = f32_to_bf16_bits(pi);
@@ -74,6 +77,12 @@ nvr_status launch_check_finite(int64_t n, const float *g, nvr_train_state *s, hi
     NVR_LAUNCHED();
     return NVR_OK;
 }
+AdamParams adam_params(const nvr_adam_desc &a) {
+    const bool decays = a.lr_decay > 0.f && a.lr_decay < 1.f;
+    return AdamParams{a.lr, a.beta1, a.beta2, a.eps,
+                      decays ? (float)std::log2((double)a.lr_decay) : 0.f};
+}
+
 nvr_status launch_adam(const AdamParams &a, int64_t n, float *p, float *m, float *v, float *grad,
                        int skip_zero, const nvr_train_state *s, void *copy, nvr_dtype copy_dtype,
                        hipStream_t st) {
@@ -119,13 +128,13 @@ extern "C" nvr_status nvr_adam(const nvr_adam_desc *a, int64_t n, float *param, 
     NVR_REQUIRE(a && state_dev, NVR_EINVAL, "NULL descriptor or state");
     NVR_REQUIRE(n >= 0, NVR_EINVAL, "n < 0");
     NVR_REQUIRE(a->lr > 0.f && a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f &&
-                    a->beta2 < 1.f && a->eps >= 0.f,
+                    a->beta2 < 1.f && a->eps >= 0.f && a->lr_decay >= 0.f && a->lr_decay <= 1.f,
                 NVR_EINVAL, "bad Adam hyper-parameters");
     NVR_REQUIRE(copy == nullptr || copy_dtype == NVR_F16 || copy_dtype == NVR_BF16, NVR_EINVAL,
                 "copy dtype must be F16 or BF16");
     if (n == 0) return NVR_OK;
     NVR_REQUIRE(param && m && v && grad, NVR_EINVAL, "NULL array");
-    AdamParams ap{a->lr, a->beta1, a->beta2, a->eps};
+    const AdamParams ap = adam_params(*a);
     return launch_adam(ap, n, param, m, v, grad, skip_zero, state_dev, copy, copy_dtype, hs(stream));
 }
 

@@ -6,7 +6,10 @@ namespace nvr {
 
 struct AdamParams {
     float lr, b1, b2, eps;
+    float log2_decay;   // log2 of the per-update learning-rate factor (0: constant)
 };
+// AdamParams of a descriptor (lr_decay <= 0 or 1: constant learning rate)
+AdamParams adam_params(const nvr_adam_desc &a);
 
 nvr_status launch_state_begin(nvr_train_state *s, hipStream_t st);
 nvr_status launch_state_end(nvr_train_state *s, hipStream_t st);

@@ -316,10 +316,9 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                     rank[2 * j + 1] = t0 == t1 ? r + 1u : atomicAdd(&hist[t1], 1u);
                 }
                 if (dx_parts != nullptr) {
-                    const float N = (float)p.res[l];
-                    if (lp.inside[0]) d0 += e0 * N * (float)p.inv_side[0];
-                    if (lp.inside[1]) d1 += e1 * N * (float)p.inv_side[1];
-                    if (lp.inside[2]) d2 += e2 * N * (float)p.inv_side[2];
+                    if (lp.inside[0]) d0 += e0 * p.s_hi[l][0];
+                    if (lp.inside[1]) d1 += e1 * p.s_hi[l][1];
+                    if (lp.inside[2]) d2 += e2 * p.s_hi[l][2];
                 }
             }
             __syncthreads();
@@ -827,10 +826,9 @@ det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__re
                     }
                 }
                 if (dx_parts != nullptr) {
-                    const float N = (float)p.res[l];
-                    if (lp.inside[0]) d0 += e0 * N * (float)p.inv_side[0];
-                    if (lp.inside[1]) d1 += e1 * N * (float)p.inv_side[1];
-                    if (lp.inside[2]) d2 += e2 * N * (float)p.inv_side[2];
+                    if (lp.inside[0]) d0 += e0 * p.s_hi[l][0];
+                    if (lp.inside[1]) d1 += e1 * p.s_hi[l][1];
+                    if (lp.inside[2]) d2 += e2 * p.s_hi[l][2];
                 }
             }
             // stable ranks inside the wavefront, corner-major then lane order;

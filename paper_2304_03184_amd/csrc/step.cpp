@@ -228,6 +228,10 @@ static nvr_status step_check(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *co
     NVR_REQUIRE(s->max_samples >= 1 && s->max_samples < (1ll << 31), NVR_EINVAL,
                 "max_samples out of range");
     NVR_REQUIRE(b->o && b->d && b->C_t, NVR_EINVAL, "NULL batch array");
+    const nvr_adam_desc &a = s->adam;
+    NVR_REQUIRE(a.lr > 0.f && a.beta1 >= 0.f && a.beta1 < 1.f && a.beta2 >= 0.f &&
+                    a.beta2 < 1.f && a.eps >= 0.f && a.lr_decay >= 0.f && a.lr_decay <= 1.f,
+                NVR_EINVAL, "bad Adam hyper-parameters");
     for (int k = 0; k < s->n_fields; ++k) NVR_TRY(field_check(fields[k], s, &nets[k]));
     return NVR_OK;
 }
@@ -292,7 +296,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
         NVR_TRY(launch_check_finite(f->grid.offset[f->grid.n_levels] * 2, f->table_grad, state, st));
         NVR_TRY(launch_check_finite(nets[k].woff[nets[k].n_layers], f->params_grad, state, st));
     }
-    const AdamParams ap{s->adam.lr, s->adam.beta1, s->adam.beta2, s->adam.eps};
+    const AdamParams ap = adam_params(s->adam);
     const bool bf = s->precision == NVR_BF16;
     for (int k = 0; k < s->n_fields; ++k) {
         const nvr_field *f = fields[k];

@@ -194,7 +194,10 @@ warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__rest
     }
 }
 
-template <bool LDS_ACC>
+// LDS_ACC: node-motion gradients summed per workgroup in LDS; LDS_BONES: bone
+// gradients likewise (every sample touches the same few joints, so global
+// atomics per sample would serialise on them).
+template <bool LDS_ACC, bool LDS_BONES>
 __global__ void __launch_bounds__(kWarpBlock)
 warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__restrict__ n_dev,
                 int64_t cap, const float *__restrict__ x, const int32_t *__restrict__ frame,
@@ -203,11 +206,15 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__rest
                 float *__restrict__ dx_live) {
     extern __shared__ float lds[];
     float *J = lds;                                   // [3 * n_joints]
-    float *acc = lds + 3 * kMaxJoints;                // [n_frames * n_nodes * 8] if LDS_ACC
+    const int n_bacc = p.n_frames * p.n_joints * 12;
+    float *bacc = lds + 3 * kMaxJoints;               // [n_frames * n_joints * 12] if LDS_BONES
+    float *acc = bacc + (LDS_BONES ? n_bacc : 0);     // [n_frames * n_nodes * 8] if LDS_ACC
     for (int i = threadIdx.x; i < 3 * p.n_joints; i += blockDim.x) J[i] = rig.joints[i];
     const int n_acc = p.n_frames * p.n_nodes * 8;
     if (LDS_ACC)
         for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0.f;
+    if (LDS_BONES && d_bones != nullptr)
+        for (int i = threadIdx.x; i < n_bacc; i += blockDim.x) bacc[i] = 0.f;
     __syncthreads();
     const int64_t count = count_of(n, n_dev, cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
@@ -277,14 +284,18 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__rest
         }
         if (d_bones != nullptr) {
             for (int k = 0; k < p.k_joints; ++k) {
-                float *dB = d_bones + ((size_t)fr * p.n_joints + f.jsel[k]) * 12;
+                const size_t jb = ((size_t)fr * p.n_joints + f.jsel[k]) * 12;
                 const float lw = f.lw[k];
                 const float gys[3] = {gy.x, gy.y, gy.z};
                 const float xh[4] = {xv.x, xv.y, xv.z, 1.f};
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int bb = 0; bb < 4; ++bb) unsafeAtomicAdd(dB + 4 * a + bb, lw * gys[a] * xh[bb]);
+                    for (int bb = 0; bb < 4; ++bb) {
+                        const float v = lw * gys[a] * xh[bb];
+                        if (LDS_BONES) atomicAdd(bacc + jb + 4 * a + bb, v);
+                        else unsafeAtomicAdd(d_bones + jb + 4 * a + bb, v);
+                    }
             }
         }
         if (dx_live != nullptr) {
@@ -317,11 +328,17 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__rest
             dx_live[3 * i + 2] += gx.z;
         }
     }
+    if (LDS_ACC || LDS_BONES) __syncthreads();
     if (LDS_ACC) {
-        __syncthreads();
         for (int i = threadIdx.x; i < n_acc; i += blockDim.x) {
             const float v = acc[i];
             if (v != 0.f) unsafeAtomicAdd(d_dq + i, v);
+        }
+    }
+    if (LDS_BONES && d_bones != nullptr) {
+        for (int i = threadIdx.x; i < n_bacc; i += blockDim.x) {
+            const float v = bacc[i];
+            if (v != 0.f) unsafeAtomicAdd(d_bones + i, v);
         }
     }
 }
@@ -371,13 +388,26 @@ nvr_status launch_warp_bwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t
                            float *d_bones, float *dx_live, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
     const size_t acc_bytes = sizeof(float) * (size_t)p.n_frames * p.n_nodes * 8;
+    const size_t bone_bytes = sizeof(float) * (size_t)p.n_frames * p.n_joints * 12;
     const size_t base = sizeof(float) * 3 * kMaxJoints;
-    if (acc_bytes <= 64 * 1024) {
-        warp_bwd_kernel<true><<<grid_for(cap, kWarpBlock, 512), kWarpBlock, base + acc_bytes, st>>>(
-            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+    const bool lds_bones = bone_bytes <= 16 * 1024;
+    const size_t lb = lds_bones ? bone_bytes : 0;
+    if (acc_bytes + lb <= 64 * 1024) {
+        const unsigned gr = grid_for(cap, kWarpBlock, 512);
+        if (lds_bones)
+            warp_bwd_kernel<true, true><<<gr, kWarpBlock, base + lb + acc_bytes, st>>>(
+                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+        else
+            warp_bwd_kernel<true, false><<<gr, kWarpBlock, base + acc_bytes, st>>>(
+                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
     } else {
-        warp_bwd_kernel<false><<<grid_for(cap, kWarpBlock, 2048), kWarpBlock, base, st>>>(
-            p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+        const unsigned gr = grid_for(cap, kWarpBlock, 2048);
+        if (lds_bones)
+            warp_bwd_kernel<false, true><<<gr, kWarpBlock, base + lb, st>>>(
+                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+        else
+            warp_bwd_kernel<false, false><<<gr, kWarpBlock, base, st>>>(
+                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
     }
     NVR_LAUNCHED();
     return NVR_OK;

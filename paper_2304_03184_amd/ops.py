@@ -192,18 +192,19 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def deform_fwd(g, x, theta, table, params):
-    """Deformation network (Sec. 4.2): x + MLP([enc(x), theta]) for x [n][3]."""
+def deform_fwd(g, x, theta, table, params, math=F32):
+    """Deformation network (Sec. 4.2): x + MLP([enc(x), theta]) for x [n][3];
+    math F32 (float32 layers) or F16 (matrix-core kernels)."""
     n = x.shape[0]
     x, theta, table, params = (t.contiguous() for t in (x, theta, table, params))
     out = torch.empty_like(x)
     ws = _workspace(L.lib().nvr_deform_workspace(C.byref(g), n), x.device)
-    call("nvr_deform_fwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), _p(out),
-         _p(ws), _stream())
+    call("nvr_deform_fwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), math,
+         _p(out), _p(ws), _stream())
     return out
 
 
-def deform_bwd(g, x, theta, table, params, dx_can, want_dx=True, want_dtheta=True):
+def deform_bwd(g, x, theta, table, params, dx_can, want_dx=True, want_dtheta=True, math=F32):
     """Gradients of sum(dx_can . deform_fwd(...)): (dparams, dtable, dx, dtheta)."""
     n = x.shape[0]
     x, theta, table, params, dx_can = (t.contiguous() for t in (x, theta, table, params, dx_can))
@@ -212,8 +213,8 @@ def deform_bwd(g, x, theta, table, params, dx_can, want_dx=True, want_dtheta=Tru
     dx = torch.zeros_like(x) if want_dx else None
     dtheta = torch.zeros_like(theta) if want_dtheta else None
     ws = _workspace(L.lib().nvr_deform_workspace(C.byref(g), n), x.device)
-    call("nvr_deform_bwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), _p(dx_can),
-         _p(dparams), _p(dtable), _p(dx), _p(dtheta), _p(ws), _stream())
+    call("nvr_deform_bwd", C.byref(g), n, _p(x), _p(theta), _p(table), _p(params), math,
+         _p(dx_can), _p(dparams), _p(dtable), _p(dx), _p(dtheta), _p(ws), _stream())
     return dparams, dtable, dx, dtheta
 
 
@@ -477,8 +478,8 @@ def loss(C_, D, C_t, D_t=None, mask=None, lambda_d=0.0, loss_scale=None):
     return out, dC, dD
 
 
-def adam_desc(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15):
-    return L.AdamDesc(lr, beta1, beta2, eps)
+def adam_desc(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, lr_decay=1.0):
+    return L.AdamDesc(lr, beta1, beta2, eps, lr_decay)
 
 
 def new_state(loss_scale=1.0, device="cuda"):

@@ -35,7 +35,8 @@ __all__ = [
     "FieldCfg", "WorkCfg", "config", "rng_for",
     "sphere_rays", "noise_occupancy", "occupancy_from_points", "pack_bits",
     "uniform_table", "xavier_params", "smooth_colour_targets", "uniform_targets",
-    "human_rig", "object_points", "keyframe_scene",
+    "human_rig", "object_points", "keyframe_scene", "human_workload", "two_field_workload",
+    "keyframe_workload",
 ]
 
 
@@ -528,6 +529,21 @@ def keyframe_workload(seed_offset=0):
 
 def keyframe_step_rng(work, step):
     return rng_for(work.seed * 1000 + 7 + step)
+
+
+def human_workload(scale=1.0, seed_offset=0):
+    """The human field behind the hybrid warp at ``scale`` of its ray count:
+    (work, field cfg, rig, rays o, d, smooth colour targets, packed live-space
+    occupancy, rng).  The caller draws the table and weights from ``rng`` next."""
+    work = config(3, scale)
+    f = work.fields[0]
+    ex = work.extra
+    rng = rng_for(work.seed + seed_offset)
+    rig = human_rig(rng, n_nodes=ex["n_nodes"], k_nodes=ex["k_nodes"], knn_res=ex["knn_res"])
+    o, d = sphere_rays(work.n_rays, rng, aim_lo=(-0.3, -0.8, -0.2), aim_hi=(0.3, 0.8, 0.2))
+    _, occ = occupancy_from_points(rig["node_live"][0], 0.12, f.occ_res, f.aabb_min, f.aabb_max)
+    C = smooth_colour_targets(o, d, rng)
+    return work, f, rig, o, d, C, occ, rng
 
 
 def two_field_workload(scale=1.0 / 64, seed_offset=0):

@@ -28,7 +28,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth  # noqa: E402
-from oracle import grid as ogrid, step as ostep  # noqa: E402
+from oracle import optim, grid as ogrid, step as ostep  # noqa: E402
 
 
 def human_object_state():
@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--rays", type=int, default=4096)
     ap.add_argument("--eval-every", type=int, default=250)
+    ap.add_argument("--lr-decay", type=float, default=1.0,
+                    help="update k uses lr * decay^(k-1); the key-frame curve file name "
+                         "gets a _decay suffix when < 1")
     args = ap.parse_args()
     t0 = time.time()
     if args.which == "human_object":
@@ -84,12 +87,15 @@ def main():
         work, f, scene, cams, st = keyframe_state()
         box = (f.aabb_min, f.aabb_max)
         eo, ed, egt, emask = synth.keyframe_eval_view(scene, box)
-        path = os.path.join(HERE, f"curve_keyframes_{args.rays}.txt")
+        decay = args.lr_decay < 1.0
+        path = os.path.join(HERE, f"curve_keyframes_{args.rays}{'_decay' if decay else ''}.txt")
+        adam = optim.Adam(lr_decay=args.lr_decay)
         rows = []
         for i in range(args.steps):
             o, d, C, D, M = synth.keyframe_batch(scene, cams, args.rays,
                                                  synth.keyframe_step_rng(work, i), box)
-            r = ostep.train_step(work, st, o, d, C, D, [(0, args.rays)], apply=True, mask=M)
+            r = ostep.train_step(work, st, o, d, C, D, [(0, args.rays)], adam=adam, apply=True,
+                                 mask=M)
             p = float("nan")
             if (i + 1) % args.eval_every == 0:
                 rc, _ = ostep.render(work, st, eo, ed, [(0, eo.shape[0])], t_stop=1e-4)
@@ -100,11 +106,13 @@ def main():
         with open(path, "w") as fh:
             fh.write("# FP64 oracle: key-frame refinement, rays drawn per step from eight\n"
                      f"# 1280x720 key frames of the analytic scene, {args.rays} rays per step,\n"
-                     "# Adam lr 1e-2, masked colour + depth loss (Eq. 8, lambda_d = 1); PSNR\n"
-                     "# over the in-box pixels of a 160x90 novel view (t_stop 1e-4) every "
+                     f"# Adam lr 1e-2 (times {args.lr_decay:.9g}^(k-1) at update k), masked colour\n"
+                     "# + depth loss (Eq. 8, lambda_d = 1); PSNR over the in-box pixels of a\n"
+                     "# 160x90 novel view (t_stop 1e-4) every "
                      f"{args.eval_every} steps (nan elsewhere).\n"
                      f"# written by: python tests/golden/make_curves.py keyframes --steps {args.steps} "
-                     f"--rays {args.rays} --eval-every {args.eval_every}\n"
+                     f"--rays {args.rays} --eval-every {args.eval_every}"
+                     f"{f' --lr-decay {args.lr_decay!r}' if decay else ''}\n"
                      "# columns: step loss psnr_db\n")
             for i, l, p in rows:
                 fh.write(f"{i} {l:.10e} {p:.6f}\n")

@@ -212,19 +212,23 @@ def test_deform_and_deterministic_entry_points_reject_before_launch(L):
     # than the binned scatter holds
     big = L.GridDesc()
     L.call("nvr_grid_init", C.byref(big), 16, 2, 24, 16, 65536, lo, hi)
-    args = (C.byref(big), 10, fake, fake, fake, fake, fake, fake, fake, None, None, fake, None)
+    F32, F16 = L.NVR_F32, L.NVR_F16
+    args = (C.byref(big), 10, fake, fake, fake, fake, F16, fake, fake, fake, None, None, fake,
+            None)
     assert lib.nvr_deform_bwd(*args) == L.NVR_EUNSUPPORTED
     assert b"8192 tiles" in lib.nvr_last_error()
-    assert lib.nvr_deform_fwd(C.byref(big), 10, fake, fake, fake, fake, fake, fake,
+    assert lib.nvr_deform_fwd(C.byref(big), 10, fake, fake, fake, fake, F32, fake, fake,
                               None) == L.NVR_EUNSUPPORTED
     g = L.GridDesc()
     L.call("nvr_grid_init", C.byref(g), 16, 2, 14, 16, 512, lo, hi)
-    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, fake, fake, fake, None,
-                              None, None, None) == L.NVR_EINVAL          # NULL workspace
-    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, fake, fake,
+    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, F32, fake, fake, fake,
+                              None, None, None, None) == L.NVR_EINVAL    # NULL workspace
+    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, F16, fake, fake,
                               C.c_void_p(4096 + 4), None, None, fake, None) == L.NVR_EINVAL
-    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, fake, None, fake, None,
-                              None, fake, None) == L.NVR_EINVAL          # NULL dtable
+    assert lib.nvr_deform_bwd(C.byref(g), 10, fake, fake, fake, fake, F16, fake, fake, None,
+                              None, None, fake, None) == L.NVR_EINVAL    # NULL dtable
+    assert lib.nvr_deform_fwd(C.byref(g), 10, fake, fake, fake, fake, L.NVR_BF16, fake, fake,
+                              None) == L.NVR_EINVAL                      # math type
     assert lib.nvr_encode_bwd_deterministic(C.byref(big), 10, fake, fake, fake, fake, None, fake,
                                             None) == L.NVR_EUNSUPPORTED
     assert lib.nvr_encode_bwd_deterministic(C.byref(g), 10, fake, fake, fake, fake, None,

@@ -411,6 +411,18 @@ def test_loss_and_adam():
     sv = O.state_values(st)
     assert sv["step"] == 3 and sv["loss_scale"] == 2.0
     np.testing.assert_array_equal(host(pg), before)
+    # exponential rate decay: update k uses lr * 0.5^(k-1), k from the device step
+    st2 = O.new_state(1.0)
+    pg2, mg2, vg2 = dev(p), torch.zeros(4096, device="cuda"), torch.zeros(4096, device="cuda")
+    pr2, mr2, vr2 = p.astype(np.float64), np.zeros(4096), np.zeros(4096)
+    ad2 = ooptim.Adam(lr_decay=0.5)
+    for s in range(1, 5):
+        g = rng.normal(size=4096).astype(np.float32)
+        O.state_begin(st2)
+        O.adam(O.adam_desc(lr_decay=0.5), pg2, mg2, vg2, dev(g), st2)
+        O.state_end(st2)
+        ad2.update(pr2, g.astype(np.float64), mr2, vr2, s)
+    np.testing.assert_allclose(host(pg2), pr2, rtol=0, atol=2e-6)
 
 
 @pytest.mark.parametrize("k,n,spread", [(1, 3001, 1.5), (2, 20000, 1.0), (2, 300000, 0.2)])

@@ -233,6 +233,36 @@ def test_adam_matches_torch_float64():
     np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-13, atol=1e-15)
 
 
+def test_adam_decay_matches_torch_exponential_schedule():
+    # update k uses lr * decay^(k-1): torch's ExponentialLR multiplies the rate
+    # by gamma after every step
+    import torch
+    rng = synth.rng_for(30)
+    p0 = rng.normal(size=40)
+    p = p0.copy()
+    m = np.zeros(40)
+    v = np.zeros(40)
+    tp = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.99), eps=1e-15)
+    sched = torch.optim.lr_scheduler.ExponentialLR(opt, gamma=0.5)
+    ad = optim.Adam(lr_decay=0.5)
+    for s in range(1, 7):
+        g = rng.normal(size=40)
+        ad.update(p, g, m, v, s)
+        opt.zero_grad()
+        tp.grad = torch.tensor(g)
+        opt.step()
+        sched.step()
+    np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-13, atol=1e-15)
+    # a single update of a unit gradient moves by the decayed rate exactly
+    q = np.zeros(1)
+    mm, vv = np.zeros(1), np.zeros(1)
+    for k in range(1, 4):
+        before = q.copy()
+        optim.Adam(lr_decay=0.5).update(q, np.ones(1), mm, vv, k)
+        assert abs((before - q)[0] - 1e-2 * 0.5 ** (k - 1)) < 1e-15
+
+
 def test_adam_skips_zero_gradient_entries():
     p = np.ones(4)
     m = np.zeros(4)
