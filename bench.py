@@ -597,6 +597,16 @@ def _timed(torch, tr, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def _deform_state(fl):
+    """The oracle's copy of a field's deformation network (fp32 masters)."""
+    from oracle import grid as ogrid, step as ostep
+    D = fl.deform
+    if D is None:
+        return None
+    return ostep.DeformState(ogrid.Layout.from_field(fl.fcfg), D.theta.cpu().numpy(),
+                             D.table.cpu().numpy(), D.params.cpu().numpy())
+
+
 def _sampled_colour_error(torch, tr, flds, w, o, d, ranges, pick, box=None):
     """Forward colours / depths of the picked rays after training vs the FP64
     oracle given the same fp16 tables and fp16-rounded weights."""
@@ -610,7 +620,8 @@ def _sampled_colour_error(torch, tr, flds, w, o, d, ranges, pick, box=None):
                                _f16(fl.params.cpu().numpy()),
                                occ_words=fl.occ.cpu().numpy().view(np.uint32)
                                if fl.occ is not None else None,
-                               rig=getattr(fl, "rig_np", None)) for fl in flds]
+                               rig=getattr(fl, "rig_np", None),
+                               deform=_deform_state(fl)) for fl in flds]
     sub = []
     for lo, hi in ranges:   # each field's rays among the picked (sorted) ones
         idx = np.nonzero((pick >= lo) & (pick < hi))[0]
@@ -621,18 +632,21 @@ def _sampled_colour_error(torch, tr, flds, w, o, d, ranges, pick, box=None):
     return ec, ed
 
 
-def bench_human(O, L, F, torch, dev, steps, warmup):
-    """The human field behind the hybrid warp at full size (2^18 rays, 24
-    joints, 1024 nodes listed 8 per voxel of a 128^3 look-up), fused BF16
-    step in a captured graph with tuned shapes; sampled parity after training."""
+def _human_step(O, L, F, torch, dev, steps, warmup, with_deform):
     import synth
     w, f, rig, o, d, Ct, occ, rng = synth.human_workload()
-    n_e = O.grid_desc_of(f).n_entries
-    table = synth.uniform_table(n_e, 2, rng)
+    g = O.grid_desc_of(f)
+    table = synth.uniform_table(g.n_entries, 2, rng)
     params = synth.xavier_params(f.layer_shapes(), rng)
+    D = None
+    if with_deform:
+        # the deformation network's own encoding on the field's ladder
+        theta, dtab, dpar = synth.deform_inputs(g.n_entries, synth.rng_for(w.seed + 90))
+        D = F.Deform(O.grid_desc_of(f), theta, dtab, dpar)
     R, ex = w.n_rays, w.extra
     wd = O.warp_desc(n_nodes=ex["n_nodes"], k_nodes=ex["k_nodes"], lut_res=ex["knn_res"])
-    fld = F.Field(w, f, table, params, occ_words=occ, rig=O.Rig.from_numpy(rig), warp_desc=wd)
+    fld = F.Field(w, f, table, params, occ_words=occ, rig=O.Rig.from_numpy(rig), warp_desc=wd,
+                  deform=D)
     fld.rig_np = rig
     cap = R * 64
     tr = F.Trainer([fld], R, cap, precision=L.NVR_BF16, use_graph=True, autotune=True)
@@ -645,11 +659,26 @@ def bench_human(O, L, F, torch, dev, steps, warmup):
                                    ((-1.0,) * 3, (1.0,) * 3))
     tr.close()
     assert ec < 2e-2 and ed < 2e-2, f"human field: sampled colour error {ec}, depth {ed}"
-    log(f"[bench] human field (warp): {dt * 1e3:.3f} ms/step, {n} samples, "
-        f"sampled C err {ec:.2e}")
+    return w, dt, n, ec, ed, pick
+
+
+def bench_human(O, L, F, torch, dev, steps, warmup):
+    """The human field behind the hybrid deformation at full size (2^18 rays,
+    24 joints, 1024 nodes listed 8 per voxel of a 128^3 look-up, then the
+    pose-conditioned deformation network on its own hash grid), fused BF16 step
+    in a captured graph with tuned shapes; the same step without the network
+    beside it; sampled parity after training."""
+    w, dt, n, ec, ed, pick = _human_step(O, L, F, torch, dev, steps, warmup, True)
+    _, dt0, n0, ec0, ed0, _ = _human_step(O, L, F, torch, dev, steps, warmup, False)
+    R, ex = w.n_rays, w.extra
+    log(f"[bench] human field (warp + deformation network): {dt * 1e3:.3f} ms/step, {n} samples, "
+        f"sampled C err {ec:.2e}; warp only {dt0 * 1e3:.3f} ms/step")
     return {"workload": w.name, "rays_per_step": R, "samples_per_step": n,
             "ms_per_step": dt * 1e3, "rays_per_s": R / dt, "nodes": ex["n_nodes"],
             "joints": ex["n_joints"], "lut_res": ex["knn_res"], "graph": True,
+            "deformation_network": "104 -> 4 x 128 -> 3, matrix cores, own 16-level grid",
+            "warp_only": {"ms_per_step": dt0 * 1e3, "rays_per_s": R / dt0,
+                          "samples_per_step": n0, "colour_max_abs": ec0},
             "sampled_parity": {"rays": int(pick.size), "colour_max_abs": ec, "depth_max_abs": ed,
                                "bar": 2e-2}}
 

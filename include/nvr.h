@@ -375,6 +375,26 @@ nvr_status nvr_state_end(nvr_train_state *state_dev, nvr_stream stream);
  * ---------------------------------------------------------------------- */
 typedef struct nvr_ctx nvr_ctx;
 
+/* Residual deformation network of a warped field in the step (Sec. 4.2,
+ * hybrid deformation): the warped sample x_t moves to
+ * x_c = x_t + MLP([enc_d(x_t), theta]) before the field's encoding, with the
+ * network of nvr_deform_fwd (its own 32-wide grid, 104 -> 4 x 128 -> 3).
+ * NVR_F32 steps run its float32 kernels, NVR_BF16 steps its matrix-core
+ * kernels (math = NVR_F16 of nvr_deform_fwd); the backward chains the field
+ * encoding's position gradient through it into the warp.  Its table and
+ * parameters are trained with the field (same Adam, tables skip zero-gradient
+ * entries, fp32 masters only); the pose's gradient is left scaled by the loss
+ * scale, like the node and bone gradients.  Host struct, device arrays. */
+typedef struct {
+    nvr_grid_desc grid;          /* its encoding: levels x features = 32 */
+    const float *theta;          /* [72] pose of the batch's frame */
+    float *table;                /* [n_entries][2] fp32 */
+    float *params;               /* nvr_deform_param_count() fp32 */
+    float *table_grad, *params_grad;          /* zero on entry, zeroed by the step */
+    float *table_m, *table_v, *params_m, *params_v;
+    float *theta_grad;           /* (acc, nullable) [72] */
+} nvr_deform_state;
+
 typedef struct {
     nvr_grid_desc grid;
     nvr_mlp_desc mlp;
@@ -393,6 +413,7 @@ typedef struct {
     float *table_m, *table_v, *params_m, *params_v;
     float *node_dq_grad;         /* (acc, nullable) [n_frames][n_nodes][8] */
     float *bones_grad;           /* (acc, nullable) [n_frames][n_joints][12] */
+    const nvr_deform_state *deform;  /* nullable; only with has_warp */
 } nvr_field;
 
 typedef struct {

@@ -7,13 +7,16 @@ other oracle modules in that order for one or two fields:
 
     march (per field, over the rays the field covers)
     -> [warp]  (human field)
+    -> [deformation network: x_c = x_t + MLP([enc_d(x_t), theta])]  (human field, if given)
     -> encode -> SH(view direction) -> networks
     -> composite (two fields on a shared ray: merged by t)
     -> loss -> composite backward -> network backward -> encode backward
-    -> [warp backward] -> Adam (tables skip zero-gradient entries).
+    -> [deformation-network backward] -> [warp backward]
+    -> Adam (tables skip zero-gradient entries; the deformation network's table
+       and parameters are trained with its field).
 
-Motion priors are inputs (they come from the tracker, Sec. 4.1): their
-gradients are returned but not applied.
+Motion priors (and the pose theta) are inputs (they come from the tracker,
+Sec. 4.1): their gradients are returned but not applied.
 """
 from __future__ import annotations
 
@@ -21,7 +24,29 @@ from dataclasses import dataclass, field as dfield
 
 import numpy as np
 
-from . import composite, grid, march, network, optim, sh, warp
+from . import composite, deform, grid, march, network, optim, sh, warp
+
+
+@dataclass
+class DeformState:
+    """The deformation network of a warped field (Sec. 4.2, hybrid deformation)."""
+    lay: object                       # grid.Layout of its own 32-wide encoding
+    theta: np.ndarray                 # (72,) pose
+    table: np.ndarray                 # (n_entries, 2) float64 master
+    params: np.ndarray                # flat float64 master
+    m_t: np.ndarray = None
+    v_t: np.ndarray = None
+    m_p: np.ndarray = None
+    v_p: np.ndarray = None
+
+    def __post_init__(self):
+        self.theta = np.asarray(self.theta, np.float64).copy()
+        self.table = np.asarray(self.table, np.float64).copy()
+        self.params = np.asarray(self.params, np.float64).copy()
+        self.m_t = np.zeros_like(self.table)
+        self.v_t = np.zeros_like(self.table)
+        self.m_p = np.zeros_like(self.params)
+        self.v_p = np.zeros_like(self.params)
 
 
 @dataclass
@@ -31,6 +56,7 @@ class FieldState:
     params: np.ndarray                # flat float64 master
     occ_words: np.ndarray = None
     rig: dict = None                  # warp inputs for a human field
+    deform: DeformState = None        # its deformation network (needs rig)
     m_t: np.ndarray = None
     v_t: np.ndarray = None
     m_p: np.ndarray = None
@@ -73,12 +99,18 @@ def march_field(work, st: FieldState, o, d, ray_lo=0, ray_hi=None):
 
 
 def field_forward(st: FieldState, x, dirs, grid_box=None, frame=None):
+    """``xc`` in the cache is where the field's encoding is read: the warped
+    point, moved by the deformation network when the field has one."""
     f = st.fcfg
-    xc = x if st.rig is None else warp.warp(x, st.rig, grid_box[0], grid_box[1], frame)
+    xw = x if st.rig is None else warp.warp(x, st.rig, grid_box[0], grid_box[1], frame)
+    xc, dcache = xw, None
+    if st.deform is not None:
+        D = st.deform
+        xc, dcache = deform.forward(D.params, xw, D.theta, D.table, D.lay)
     feat = grid.encode(xc, st.table, st.lay)
     shv = sh.sh_encode(dirs, f.sh_degree)
     sigma, rgb, cache = network.forward(f, st.params, feat, shv)
-    return sigma, rgb, dict(xc=xc, net=cache, x=x, frame=frame)
+    return sigma, rgb, dict(xc=xc, xw=xw, deform=dcache, net=cache, x=x, frame=frame)
 
 
 def field_backward(st: FieldState, cache, dsigma, drgb, grid_box=None):
@@ -87,9 +119,13 @@ def field_backward(st: FieldState, cache, dsigma, drgb, grid_box=None):
     dtable, dxc = grid.encode_backward(cache["xc"], st.table, dfeat, st.lay, want_dx)
     out = dict(table=dtable, params=dparams)
     if want_dx:
+        dxw = dxc
+        if st.deform is not None:
+            dp, dt, dxw, dth = deform.backward(cache["deform"], dxc)
+            out.update(deform_params=dp, deform_table=dt, theta=dth)
         d_dq, d_bones = warp.warp_backward(cache["x"], st.rig, grid_box[0], grid_box[1],
-                                           dxc, cache["frame"])
-        out.update(node_dq=d_dq, bones=d_bones, dxc=dxc)
+                                           dxw, cache["frame"])
+        out.update(node_dq=d_dq, bones=d_bones, dxc=dxc, dxw=dxw)
     return out
 
 
@@ -143,13 +179,18 @@ def train_step(work, state: StepState, o, d, C_t, D_t, ranges, grid_box=None,
         ds[fw["idx"][sel]] = dsig[sel]
         dr[fw["idx"][sel]] = drgb[sel]
         grads.append(field_backward(st, p["cache"], ds, dr, grid_box))
-    flat = []
-    for g in grads:
-        flat += [g["table"], g["params"]]
-    unscaled, finite = optim.unscale_and_check(flat, state.loss_scale)
+    trained = ("table", "params", "deform_table", "deform_params")
+    flat, where = [], []
     for k, g in enumerate(grads):
-        g["table"], g["params"] = unscaled[2 * k], unscaled[2 * k + 1]
-        for key in ("node_dq", "bones", "dxc"):
+        for key in trained:
+            if key in g:
+                flat.append(g[key])
+                where.append((k, key))
+    unscaled, finite = optim.unscale_and_check(flat, state.loss_scale)
+    for (k, key), u in zip(where, unscaled):
+        grads[k][key] = u
+    for g in grads:
+        for key in ("node_dq", "bones", "dxc", "dxw", "theta"):
             if key in g:
                 g[key] = g[key] / state.loss_scale
     if apply:
@@ -158,6 +199,11 @@ def train_step(work, state: StepState, o, d, C_t, D_t, ranges, grid_box=None,
             for st, g in zip(state.fields, grads):
                 adam.update(st.table, g["table"], st.m_t, st.v_t, state.step, skip_zero=True)
                 adam.update(st.params, g["params"], st.m_p, st.v_p, state.step)
+                if st.deform is not None:
+                    D = st.deform
+                    adam.update(D.table, g["deform_table"], D.m_t, D.v_t, state.step,
+                                skip_zero=True)
+                    adam.update(D.params, g["deform_params"], D.m_p, D.v_p, state.step)
         else:
             state.loss_scale *= 0.5
     state.history.append(L)

@@ -75,13 +75,19 @@ class AdamDesc(C.Structure):
     _fields_ = [("lr", f32), ("beta1", f32), ("beta2", f32), ("eps", f32), ("lr_decay", f32)]
 
 
+class DeformState(C.Structure):
+    _fields_ = [("grid", GridDesc), ("theta", vp), ("table", vp), ("params", vp),
+                ("table_grad", vp), ("params_grad", vp), ("table_m", vp), ("table_v", vp),
+                ("params_m", vp), ("params_v", vp), ("theta_grad", vp)]
+
+
 class Field(C.Structure):
     _fields_ = [("grid", GridDesc), ("mlp", MlpDesc), ("march", MarchDesc), ("has_warp", i32),
                 ("warp", WarpDesc), ("rig", WarpRig), ("ray_begin", i64), ("ray_end", i64),
                 ("occ", vp), ("table", vp), ("table_half", vp), ("params", vp),
                 ("params_bf16", vp), ("table_grad", vp), ("params_grad", vp), ("table_m", vp),
                 ("table_v", vp), ("params_m", vp), ("params_v", vp), ("node_dq_grad", vp),
-                ("bones_grad", vp)]
+                ("bones_grad", vp), ("deform", C.POINTER(DeformState))]
 
 
 class StepDesc(C.Structure):

@@ -43,7 +43,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     p = subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp, *objs,
-                        "-L" + ROCM_LIB, "-lrocblas", "-Wl,-rpath," + ROCM_LIB],
+                        "-L" + ROCM_LIB, "-Wl,-rpath," + ROCM_LIB],
                        capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"link failed:\n{p.stderr}")

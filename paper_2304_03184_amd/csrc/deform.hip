@@ -1,20 +1,20 @@
 // Pose-conditioned deformation network (Sec. 4.2, hybrid deformation; widths
 // in Sec. 4.3): v_c = v_t + MLP([hash(v_t), theta]), 104 -> 4 x 128 -> 3,
-// bias-free, ReLU on the hidden layers, float32.
+// bias-free, ReLU on the hidden layers.
 //
-// The encoding runs on the hash-grid kernels of this library (fp32 table);
-// each layer is one rocBLAS sgemm over all points (row-major [n][width]
-// activations, weights W[out][in] row-major as the flat parameter vector
-// holds them); the small kernels here assemble the input, apply the ReLU and
-// its mask, add the residual and split the input gradient.  The backward
-// recomputes the forward into the workspace.
+// The encoding runs on the hash-grid kernels of this library (fp32 table).
+// Two paths share the entry points: a float32 one (each layer one tiled
+// product over the points, row-major [n][width] activations, weights W[out][in]
+// row-major as the flat parameter vector holds them; weight gradients formed
+// as per-chunk partials summed in chunk order) and the matrix-core one below.
+// Every kernel takes the point count from the host or from a device word (at
+// most a capacity), so the training step can call both without reading the
+// sample count back; the backward recomputes the forward into the workspace.
 #include <algorithm>
 #include <atomic>
-#include <mutex>
-
-#include <rocblas/rocblas.h>
 
 #include "common.hpp"
+#include "deform_dev.hpp"
 #include "grid_dev.hpp"
 #include "scatter_dev.hpp"
 
@@ -25,16 +25,15 @@ constexpr int kFeat = 32, kPose = 72, kIn = kFeat + kPose, kWidth = 128, kHidden
 constexpr int64_t kParams = (int64_t)kWidth * kIn + (int64_t)(kHidden - 1) * kWidth * kWidth +
                             3 * kWidth;
 
-// The table gradient goes through the binned scatter (no float atomics; its
-// records never read the table when no position gradient is asked of it), the
-// position gradient through dn_encode_dx (one thread per point).
-// The weight gradients reduce over all points; rocBLAS is given the points in
-// kDwParts chunks of kDwChunk (a batched product into partials, summed by
-// dn_reduce_partials), so that the reduction spreads over many workgroups.
-constexpr int kDwChunk = 4096, kDwParts = 64;
+// The table gradient goes through the binned scatter (its records never read
+// the table when no position gradient is asked of it), the position gradient
+// through dn_encode_dx (one thread per point).
+constexpr int kMmT = 64, kMmK = 16;     // product tiles: 64 x 64 outputs, 16-deep slices
+constexpr int kMmParts = 64;            // most point chunks of a weight gradient
+constexpr int kThetaChunk = 256;        // points per pose-gradient partial
 
 struct DeformWs {
-    float *feat, *a0, *h[kHidden], *dv, *dh0, *dh1, *da0, *dfeat, *partial;
+    float *feat, *a0, *h[kHidden], *dv, *dh0, *dh1, *da0, *dfeat, *partial, *theta_part;
     void *binned;
 };
 
@@ -52,10 +51,16 @@ struct DeformMfmaWs {
 };
 constexpr int kDwGrid = 256;
 
-size_t carve_mfma(const nvr_grid_desc *g, int64_t n, char *base, DeformMfmaWs *w);
+size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, DeformMfmaWs *w);
 
-// Carves the workspace; returns its size (base may be null to only measure).
-size_t carve(const nvr_grid_desc *g, int64_t n, char *base, DeformWs *w) {
+// point chunks of the float32 weight gradients at capacity cap
+int mm_parts(int64_t cap) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMmParts, cap / 2048));
+}
+
+// Carves the workspace of capacity n; returns its size (base may be null to
+// only measure).
+size_t carve(const nvr_grid_desc *g, int64_t n, bool det, char *base, DeformWs *w) {
     size_t off = 0;
     auto take = [&](size_t floats) {
         float *p = base ? reinterpret_cast<float *>(base + off) : nullptr;
@@ -71,15 +76,18 @@ size_t carve(const nvr_grid_desc *g, int64_t n, char *base, DeformWs *w) {
     t.dh1 = take((size_t)n * kWidth);
     t.da0 = take((size_t)n * kIn);
     t.dfeat = take((size_t)n * kFeat);
-    t.partial = take((size_t)kDwParts * kWidth * kWidth);   // largest layer: 128 x 128
-    t.binned = take((nvr_encode_bwd_workspace(g, n) + sizeof(float) - 1) / sizeof(float));
+    t.partial = take((size_t)mm_parts(n) * kWidth * kWidth);  // largest layer: 128 x 128
+    t.theta_part = take((size_t)((n + kThetaChunk - 1) / kThetaChunk + 1) * kPose);
+    t.binned = take((scatter_rows_ws_bytes(make_grid_params(g), n, det) + sizeof(float) - 1) /
+                    sizeof(float));
     if (w) *w = t;
     return off;
 }
 
 __global__ void __launch_bounds__(256)
-dn_concat(int64_t n, const float *__restrict__ feat, const float *__restrict__ theta,
-          float *__restrict__ a0) {
+dn_concat(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+          const float *__restrict__ feat, const float *__restrict__ theta, float *__restrict__ a0) {
+    n = count_of(n, n_dev, cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * kIn;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = i / kIn;
@@ -88,37 +96,39 @@ dn_concat(int64_t n, const float *__restrict__ feat, const float *__restrict__ t
     }
 }
 
+// dh = h > 0 ? dh : 0 over the first count rows of width w
 __global__ void __launch_bounds__(256)
-dn_relu(int64_t m, float *__restrict__ h) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x)
-        h[i] = h[i] > 0.f ? h[i] : 0.f;
-}
-
-__global__ void __launch_bounds__(256)
-dn_relu_bwd(int64_t m, float *__restrict__ dh, const float *__restrict__ h) {
+dn_relu_bwd(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap, int w,
+            float *__restrict__ dh, const float *__restrict__ h) {
+    const int64_t m = count_of(n, n_dev, cap) * w;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x)
         dh[i] = h[i] > 0.f ? dh[i] : 0.f;
 }
 
 __global__ void __launch_bounds__(256)
-dn_residual(int64_t m, const float *__restrict__ x, const float *__restrict__ dv,
-            float *__restrict__ out) {
+dn_residual(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+            const float *__restrict__ x, const float *__restrict__ dv, float *__restrict__ out) {
+    const int64_t m = 3 * count_of(n, n_dev, cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x)
         out[i] = x[i] + dv[i];
 }
 
+// acc += v over the first m values, or over 3 * (device count) when n_dev is given
 __global__ void __launch_bounds__(256)
-dn_add(int64_t m, float *__restrict__ acc, const float *__restrict__ v) {
+dn_add(int64_t m, float *__restrict__ acc, const float *__restrict__ v,
+       const int32_t *__restrict__ n_dev = nullptr, int64_t cap = 0) {
+    if (n_dev != nullptr) m = 3 * count_of(0, n_dev, cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x)
         acc[i] += v[i];
 }
 
 __global__ void __launch_bounds__(256)
-dn_split(int64_t n, const float *__restrict__ da0, float *__restrict__ dfeat) {
+dn_split(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+         const float *__restrict__ da0, float *__restrict__ dfeat) {
+    n = count_of(n, n_dev, cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * kFeat;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = i / kFeat;
@@ -126,23 +136,144 @@ dn_split(int64_t n, const float *__restrict__ da0, float *__restrict__ dfeat) {
     }
 }
 
-// dtheta[c] += sum over points of da0[s][32 + c]: each workgroup sums a chunk
-// of kThetaChunk points (lanes over the 72 components, so each row is read
-// contiguously) and adds its partial with one atomic per component.
-constexpr int kThetaChunk = 256;
-
+// Pose gradient, summed over the points in a fixed order: workgroup b sums
+// points [b kThetaChunk, (b + 1) kThetaChunk) into part[b] (lanes over the 72
+// components, each row read contiguously); dn_theta_reduce then adds the
+// partials in order.
 __global__ void __launch_bounds__(128)
-dn_theta_sum(int64_t n, const float *__restrict__ da0, float *__restrict__ dtheta) {
+dn_theta_sum(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+             const float *__restrict__ da0, float *__restrict__ part) {
+    n = count_of(n, n_dev, cap);
     const int c = threadIdx.x;
-    if (c >= kPose) return;
     const int64_t s0 = (int64_t)blockIdx.x * kThetaChunk;
+    if (c >= kPose || s0 >= n) return;
     const int64_t s1 = s0 + kThetaChunk < n ? s0 + kThetaChunk : n;
     float acc = 0.f;
     for (int64_t s = s0; s < s1; ++s) acc += da0[s * kIn + kFeat + c];
-    atomicAdd(dtheta + c, acc);
+    part[blockIdx.x * kPose + c] = acc;
 }
 
-// dW_partial[b] = (dY rows of chunk b)^T (X rows of chunk b), then summed.
+__global__ void __launch_bounds__(128)
+dn_theta_reduce(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+                const float *__restrict__ part, float *__restrict__ dtheta) {
+    n = count_of(n, n_dev, cap);
+    const int c = threadIdx.x;
+    if (c >= kPose) return;
+    const int64_t nb = (n + kThetaChunk - 1) / kThetaChunk;
+    float acc = 0.f;
+    for (int64_t b = 0; b < nb; ++b) acc += part[b * kPose + c];
+    dtheta[c] += acc;
+}
+
+// Y[s][j] = act(sum_k X[s][k] B(j, k)) for the first count points s and j < J,
+// with B(j, k) = W[j bj + k bk] (bj = K, bk = 1: Y = X W^T for W[J][K]; bj = 1,
+// bk = J: Y = X W for W[K][J]).  A workgroup forms 64 points x 64 outputs
+// (thread: 4 points x 4 outputs, outputs 16 apart so each row's stores are
+// contiguous) over 16-deep slices of X and B staged in LDS; workgroups stride
+// over the point tiles.
+template <bool RELU>
+__global__ void __launch_bounds__(256)
+dn_mm(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap, const float *__restrict__ X,
+      int ldx, int K, const float *__restrict__ W, int bj, int bk, int J, float *__restrict__ Y,
+      int ldy) {
+    n = count_of(n, n_dev, cap);
+    __shared__ __align__(16) float xs[kMmK][kMmT + 4];
+    __shared__ __align__(16) float bs[kMmK][kMmT + 4];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int j0 = blockIdx.y * kMmT;
+    for (int64_t s0 = (int64_t)blockIdx.x * kMmT; s0 < n; s0 += (int64_t)gridDim.x * kMmT) {
+        float acc[4][4] = {};
+        for (int k0 = 0; k0 < K; k0 += kMmK) {
+#pragma unroll
+            for (int e = t; e < kMmT * kMmK; e += 256) {
+                const int r = e / kMmK, c = e % kMmK;
+                const int64_t s = s0 + r;
+                const int k = k0 + c, j = j0 + r;
+                xs[c][r] = (s < n && k < K) ? X[s * ldx + k] : 0.f;
+                bs[c][r] = (j < J && k < K) ? W[(int64_t)j * bj + (int64_t)k * bk] : 0.f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < kMmK; ++c) {
+                const float4 a = *reinterpret_cast<const float4 *>(&xs[c][4 * ty]);
+                const float av[4] = {a.x, a.y, a.z, a.w};
+                float bv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bv[q] = bs[c][tx + 16 * q];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[i][q] = fmaf(av[i], bv[q], acc[i][q]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t s = s0 + 4 * ty + i;
+            if (s >= n) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + tx + 16 * q;
+                if (j < J) Y[s * ldy + j] = RELU ? fmaxf(acc[i][q], 0.f) : acc[i][q];
+            }
+        }
+    }
+}
+
+// part[p][o][i] = sum over the points s of chunk p of dY[s][o] X[s][i]: the
+// count points split into `parts` chunks of a multiple of 16 points (p =
+// blockIdx.z); a workgroup forms 64 o x 64 i over 16-point slices in LDS.
+// Empty chunks write zeros, so dn_reduce_partials can add every part in order.
+__global__ void __launch_bounds__(256)
+dn_mm_dw(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap, const float *__restrict__ dY,
+         int O, const float *__restrict__ X, int ldx, int I, int parts,
+         float *__restrict__ part) {
+    n = count_of(n, n_dev, cap);
+    __shared__ __align__(16) float ys[16][kMmT + 4];
+    __shared__ __align__(16) float xs[16][kMmT + 4];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int o0 = blockIdx.y * kMmT, i0 = blockIdx.x * kMmT;
+    const int64_t chunk = ((n + parts - 1) / parts + 15) / 16 * 16;
+    const int64_t sb = (int64_t)blockIdx.z * chunk;
+    const int64_t se = sb + chunk < n ? sb + chunk : n;
+    float acc[4][4] = {};
+    for (int64_t s0 = sb; s0 < se; s0 += 16) {
+#pragma unroll
+        for (int e = t; e < 16 * kMmT; e += 256) {
+            const int r = e / kMmT, c = e % kMmT;
+            const int64_t s = s0 + r;
+            ys[r][c] = (s < se && o0 + c < O) ? dY[s * O + o0 + c] : 0.f;
+            xs[r][c] = (s < se && i0 + c < I) ? X[s * ldx + i0 + c] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float4 a = *reinterpret_cast<const float4 *>(&ys[r][4 * ty]);
+            const float av[4] = {a.x, a.y, a.z, a.w};
+            float bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bv[q] = xs[r][tx + 16 * q];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[i][q] = fmaf(av[i], bv[q], acc[i][q]);
+        }
+        __syncthreads();
+    }
+    float *dst = part + (int64_t)blockIdx.z * O * I;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int o = o0 + 4 * ty + i;
+        if (o >= O) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = i0 + tx + 16 * q;
+            if (c < I) dst[(int64_t)o * I + c] = acc[i][q];
+        }
+    }
+}
+
+// dW[i] += sum over parts b (in order) of partial[b][i]
 __global__ void __launch_bounds__(256)
 dn_reduce_partials(int64_t m, int32_t parts, const float *__restrict__ partial,
                    float *__restrict__ dW) {
@@ -159,9 +290,11 @@ dn_reduce_partials(int64_t m, int32_t parts, const float *__restrict__ partial,
 // is summed in registers and added once, with no atomics.  dfeat is the
 // row-major [n][2 L] feature gradient; fp32 table.
 __global__ void __launch_bounds__(256)
-dn_encode_dx(GridParams p, int64_t n, const float *__restrict__ x,
+dn_encode_dx(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+             const float *__restrict__ x,
              const float2 *__restrict__ table, const float *__restrict__ dfeat,
              float *__restrict__ dx) {
+    n = count_of(n, n_dev, cap);
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
          s += (int64_t)gridDim.x * blockDim.x) {
         const float x0 = x[3 * s], x1 = x[3 * s + 1], x2 = x[3 * s + 2];
@@ -189,70 +322,31 @@ dn_encode_dx(GridParams p, int64_t n, const float *__restrict__ x,
     }
 }
 
-// One rocBLAS handle per device, created on first use.
-std::mutex g_blas_mu;
-rocblas_handle g_blas[64] = {};
+unsigned mm_grid_x(int64_t cap) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + kMmT - 1) / kMmT, 4096));
+}
 
-nvr_status blas_for(hipStream_t st, rocblas_handle *out) {
-    int dev = 0;
-    NVR_HIP(hipGetDevice(&dev));
-    NVR_REQUIRE(dev >= 0 && dev < 64, NVR_EUNSUPPORTED, "device index %d out of range", dev);
-    if (!g_blas[dev]) {
-        NVR_REQUIRE(rocblas_create_handle(&g_blas[dev]) == rocblas_status_success, NVR_EHIP,
-                    "rocblas_create_handle failed");
-    }
-    NVR_REQUIRE(rocblas_set_stream(g_blas[dev], st) == rocblas_status_success, NVR_EHIP,
-                "rocblas_set_stream failed");
-    *out = g_blas[dev];
+// Y = act(X B) as dn_mm describes, over the first count of cap points
+template <bool RELU>
+nvr_status mm(int64_t n, const int32_t *n_dev, int64_t cap, const float *X, int ldx, int K,
+              const float *W, int bj, int bk, int J, float *Y, int ldy, hipStream_t st) {
+    const dim3 grid(mm_grid_x(cap), (unsigned)((J + kMmT - 1) / kMmT));
+    dn_mm<RELU><<<grid, 256, 0, st>>>(n, n_dev, cap, X, ldx, K, W, bj, bk, J, Y, ldy);
+    NVR_LAUNCHED();
     return NVR_OK;
 }
 
-// Row-major Y[n][out] (+)= X[n][in] W^T with W[out][in] row-major.
-nvr_status gemm_fwd(rocblas_handle h, int64_t n, int out, int in, const float *W, const float *X,
-                    float *Y) {
-    const float one = 1.f, zero = 0.f;
-    NVR_REQUIRE(rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, out, (int)n,
-                              in, &one, W, in, X, in, &zero, Y, out) == rocblas_status_success,
-                NVR_EHIP, "rocblas_sgemm failed");
-    return NVR_OK;
-}
-
-// Row-major dX[n][in] = dY[n][out] W.
-nvr_status gemm_dx(rocblas_handle h, int64_t n, int out, int in, const float *W, const float *dY,
-                   float *dX) {
-    const float one = 1.f, zero = 0.f;
-    NVR_REQUIRE(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, in, (int)n, out,
-                              &one, W, in, dY, out, &zero, dX, in) == rocblas_status_success,
-                NVR_EHIP, "rocblas_sgemm failed");
-    return NVR_OK;
-}
-
-// Row-major dW[out][in] += dY^T X over the n points: whole chunks of kDwChunk
-// points as one strided-batched product into `partial` (up to kDwParts chunks
-// per pass) summed into dW, the remaining points as one product into dW.
-nvr_status gemm_dw(rocblas_handle h, hipStream_t st, int64_t n, int out, int in, const float *dY,
-                   const float *X, float *dW, float *partial) {
-    const float one = 1.f, zero = 0.f;
-    int64_t s = 0;
-    while (n - s >= kDwChunk) {
-        const int parts = (int)std::min<int64_t>(kDwParts, (n - s) / kDwChunk);
-        NVR_REQUIRE(rocblas_sgemm_strided_batched(
-                        h, rocblas_operation_none, rocblas_operation_transpose, in, out,
-                        kDwChunk, &one, X + s * in, in, (rocblas_stride)kDwChunk * in,
-                        dY + s * out, out, (rocblas_stride)kDwChunk * out, &zero, partial, in,
-                        (rocblas_stride)in * out, parts) == rocblas_status_success,
-                    NVR_EHIP, "rocblas_sgemm_strided_batched failed");
-        const int64_t m = (int64_t)in * out;
-        dn_reduce_partials<<<grid_for(m, 256, 1024), 256, 0, st>>>(m, parts, partial, dW);
-        NVR_LAUNCHED();
-        s += (int64_t)parts * kDwChunk;
-    }
-    if (s < n) {
-        NVR_REQUIRE(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, in, out,
-                                  (int)(n - s), &one, X + s * in, in, dY + s * out, out, &one, dW,
-                                  in) == rocblas_status_success,
-                    NVR_EHIP, "rocblas_sgemm failed");
-    }
+// dW[O][I] += dY^T X over the first count of cap points, chunk partials summed in order
+nvr_status mm_dw(int64_t n, const int32_t *n_dev, int64_t cap, const float *dY, int O,
+                 const float *X, int ldx, int I, float *dW, float *partial, hipStream_t st) {
+    const int parts = mm_parts(cap);
+    const dim3 grid((unsigned)((I + kMmT - 1) / kMmT), (unsigned)((O + kMmT - 1) / kMmT),
+                    (unsigned)parts);
+    dn_mm_dw<<<grid, 256, 0, st>>>(n, n_dev, cap, dY, O, X, ldx, I, parts, partial);
+    NVR_LAUNCHED();
+    const int64_t m = (int64_t)O * I;
+    dn_reduce_partials<<<grid_for(m, 256, 1024), 256, 0, st>>>(m, parts, partial, dW);
+    NVR_LAUNCHED();
     return NVR_OK;
 }
 
@@ -261,19 +355,25 @@ __host__ __device__ const float *layer_w(const float *params, int i) {
     return params + (int64_t)kWidth * kIn + (int64_t)(i - 1) * kWidth * kWidth;
 }
 
-// Every check of both entry points, including those of the encoding and the
-// binned scatter they call, so that nothing is launched before an error.
-nvr_status check(const nvr_grid_desc *g, int64_t n, const void *ws) {
+// Every check of both entry points and of the step's calls, including those of
+// the encoding and the binned scatter they call, so that nothing is launched
+// before an error.
+nvr_status check_desc(const nvr_grid_desc *g, int64_t n) {
     NVR_REQUIRE(g != nullptr, NVR_EINVAL, "grid descriptor is NULL");
     NVR_TRY(check_grid(g));
     NVR_REQUIRE(g->n_levels * g->n_features == kFeat, NVR_EUNSUPPORTED,
                 "the deformation encoding must be 32 wide (levels x features)");
     NVR_REQUIRE(n >= 0 && n <= (1ll << 31) / kWidth, NVR_EINVAL, "n out of 0..2^24");
-    NVR_REQUIRE(n == 0 || (ws && aligned(ws, 256)), NVR_EINVAL,
-                "workspace NULL or not 256-byte aligned");
     const GridParams p = make_grid_params(g);
     NVR_TRY(scatter_check(p));
     NVR_REQUIRE((size_t)n * p.L * 8 < (1ull << 32), NVR_EINVAL, "too many contributions");
+    return NVR_OK;
+}
+
+nvr_status check(const nvr_grid_desc *g, int64_t n, const void *ws) {
+    NVR_TRY(check_desc(g, n));
+    NVR_REQUIRE(n == 0 || (ws && aligned(ws, 256)), NVR_EINVAL,
+                "workspace NULL or not 256-byte aligned");
     return NVR_OK;
 }
 
@@ -443,7 +543,8 @@ __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
 // Forward: x_can = x + W4 relu(W3 relu(W2 relu(W1 relu(W0f feat + bias)))).
 // feat: fp16 encoding [n][32]; bias: the pose term [128].
 __global__ void __launch_bounds__(kDnBlock)
-dn_fwd_mfma(int64_t n, const uint16_t *__restrict__ feat, const float *__restrict__ bias,
+dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+            const uint16_t *__restrict__ feat, const float *__restrict__ bias,
             const uint4 *__restrict__ gfwd, const float *__restrict__ x,
             float *__restrict__ x_can) {
     extern __shared__ uint4 F[];
@@ -451,6 +552,7 @@ dn_fwd_mfma(int64_t n, const uint16_t *__restrict__ feat, const float *__restric
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     const float *bias4 = bias + 4 * g;
     __syncthreads();
+    n = count_of(n, n_dev, cap);
     const int64_t waves = (int64_t)gridDim.x * (kDnBlock / 64);
     for (int64_t blk = blockIdx.x * (int64_t)(kDnBlock / 64) + (threadIdx.x >> 6); blk * 16 < n;
          blk += waves) {
@@ -482,7 +584,8 @@ __device__ __forceinline__ uint16_t bfbits(float v) {
 }
 
 __global__ void __launch_bounds__(kDnBlock)
-dn_bwd_mfma(int64_t n, const uint16_t *__restrict__ feat, const float *__restrict__ bias,
+dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+            const uint16_t *__restrict__ feat, const float *__restrict__ bias,
             const uint4 *__restrict__ gfwd, const uint4 *__restrict__ gbwd,
             const float *__restrict__ dxc, float *__restrict__ dfeat,
             uint16_t *__restrict__ hbuf, uint16_t *__restrict__ zbuf) {
@@ -494,6 +597,7 @@ dn_bwd_mfma(int64_t n, const uint16_t *__restrict__ feat, const float *__restric
     const uint4 *Ff = gfwd + lane;
     const uint4 *Bl = Bt + lane;
     const uint2 *B4 = reinterpret_cast<const uint2 *>(Bt + kBw4) + lane;
+    n = count_of(n, n_dev, cap);
     const int64_t waves = (int64_t)gridDim.x * (kDnBlock / 64);
     for (int64_t blk = blockIdx.x * (int64_t)(kDnBlock / 64) + (threadIdx.x >> 6); blk * 16 < n;
          blk += waves) {
@@ -586,7 +690,8 @@ dn_bwd_mfma(int64_t n, const uint16_t *__restrict__ feat, const float *__restric
 // partial.
 template <int TO, int TI, bool ONES>
 __global__ void __launch_bounds__(256)
-dn_dw(int64_t nblk, const uint16_t *__restrict__ zbuf, int z_off,
+dn_dw(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+      const uint16_t *__restrict__ zbuf, int z_off,
       const uint16_t *__restrict__ hbuf, int h_off, float *__restrict__ partial) {
     constexpr int TIN = TI + (ONES ? 1 : 0);
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15, w = threadIdx.x >> 6;
@@ -595,6 +700,7 @@ dn_dw(int64_t nblk, const uint16_t *__restrict__ zbuf, int z_off,
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int t = 0; t < TIN; ++t) acc[a][t] = dzero();
+    const int64_t nblk = (count_of(n, n_dev, cap) + 15) / 16;
     const int64_t nstep = (nblk + 1) / 2;
     dbf8 ones;
 #pragma unroll
@@ -679,7 +785,7 @@ dn_pose_grad(int parts, int ncol, int col, const float *__restrict__ partial,
     }
 }
 
-size_t carve_mfma(const nvr_grid_desc *g, int64_t n, char *base, DeformMfmaWs *w) {
+size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, DeformMfmaWs *w) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char *p = base ? base + off : nullptr;
@@ -696,7 +802,7 @@ size_t carve_mfma(const nvr_grid_desc *g, int64_t n, char *base, DeformMfmaWs *w
     t.zbuf = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)nblk * kZUnits * 16));
     t.dfeat = reinterpret_cast<float *>(take(sizeof(float) * (size_t)n * kFeat));
     t.partial = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kDwGrid * kWidth * 144));
-    t.binned = take(nvr_encode_bwd_workspace(g, n));
+    t.binned = take(scatter_rows_ws_bytes(make_grid_params(g), n, det));
     if (w) *w = t;
     return off;
 }
@@ -718,13 +824,13 @@ nvr_status dn_lds_opt_in() {
     return NVR_OK;
 }
 
-// encoding (fp16 features from the fp32 table), fragments and pose bias
-nvr_status mfma_prologue(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
-                         const float *table, const float *params, const DeformMfmaWs &w,
-                         hipStream_t st) {
+// encoding (fp16 features from the fp32 table), fragments and pose bias; the
+// point count is n, or *n_dev (at most cap) when n_dev is given
+nvr_status mfma_prologue(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
+                         const float *x, const float *theta, const float *table,
+                         const float *params, const DeformMfmaWs &w, hipStream_t st) {
     NVR_TRY(dn_lds_opt_in());
-    NVR_TRY(nvr_encode_fwd(g, n, x, table, NVR_F32, w.feat, NVR_F16,
-                           reinterpret_cast<nvr_stream>(st)));
+    NVR_TRY(launch_encode_fwd(gp, n, n_dev, cap, x, table, NVR_F32, w.feat, NVR_F16, false, st));
     dn_frags<<<(kFwd + kBw4 + 8 * 64 + 255) / 256, 256, 0, st>>>(params, w.fwd, w.bwd);
     NVR_LAUNCHED();
     dn_pose_bias<<<1, kWidth, 0, st>>>(params, theta, w.bias);
@@ -732,29 +838,36 @@ nvr_status mfma_prologue(const nvr_grid_desc *g, int64_t n, const float *x, cons
     return NVR_OK;
 }
 
-unsigned dn_grid(int64_t n) {
-    const int64_t nblk = (n + 15) / 16;
+unsigned dn_grid(int64_t cap) {
+    const int64_t nblk = (cap + 15) / 16;
     const int64_t wg = (nblk + kDnBlock / 64 - 1) / (kDnBlock / 64);
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg, kCus));
 }
 
-nvr_status mfma_forward(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
-                        const float *table, const float *params, float *x_can,
-                        const DeformMfmaWs &w, hipStream_t st) {
-    NVR_TRY(mfma_prologue(g, n, x, theta, table, params, w, st));
-    dn_fwd_mfma<<<dn_grid(n), kDnBlock, sizeof(uint4) * kFwd, st>>>(n, w.feat, w.bias, w.fwd, x,
-                                                                    x_can);
+nvr_status mfma_forward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
+                        const float *x, const float *theta, const float *table,
+                        const float *params, float *x_can, const DeformMfmaWs &w,
+                        hipStream_t st) {
+    NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table, params, w, st));
+    dn_fwd_mfma<<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(n, n_dev, cap, w.feat,
+                                                                     w.bias, w.fwd, x, x_can);
     NVR_LAUNCHED();
     return NVR_OK;
 }
 
+int dw_parts(int64_t cap) {
+    const int64_t nstep = ((cap + 15) / 16 + 1) / 2;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nstep, kDwGrid));
+}
+
 // dW (acc) of one layer: dZ rows at z_off (TO tiles) against H rows at h_off (TI tiles)
 template <int TO, int TI, bool ONES>
-nvr_status mfma_dw(int64_t nblk, const DeformMfmaWs &w, int z_off, int h_off, float *dW,
-                   int out_rows, int in_cols, int w_ld, hipStream_t st) {
-    const int64_t nstep = (nblk + 1) / 2;
-    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(nstep, kDwGrid));
-    dn_dw<TO, TI, ONES><<<parts, 256, 0, st>>>(nblk, w.zbuf, z_off, w.hbuf, h_off, w.partial);
+nvr_status mfma_dw(int64_t n, const int32_t *n_dev, int64_t cap, const DeformMfmaWs &w,
+                   int z_off, int h_off, float *dW, int out_rows, int in_cols, int w_ld,
+                   hipStream_t st) {
+    const int parts = dw_parts(cap);
+    dn_dw<TO, TI, ONES><<<parts, 256, 0, st>>>(n, n_dev, cap, w.zbuf, z_off, w.hbuf, h_off,
+                                               w.partial);
     NVR_LAUNCHED();
     const int ncol = 16 * (TI + (ONES ? 1 : 0));
     dn_dw_reduce<<<grid_for((int64_t)out_rows * in_cols, 256, 256), 256, 0, st>>>(
@@ -763,34 +876,209 @@ nvr_status mfma_dw(int64_t nblk, const DeformMfmaWs &w, int z_off, int h_off, fl
     return NVR_OK;
 }
 
-nvr_status forward(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,
-                   const float *table, const float *params, const DeformWs &w, hipStream_t st,
-                   rocblas_handle h) {
-    NVR_TRY(nvr_encode_fwd(g, n, x, table, NVR_F32, w.feat, NVR_F32,
-                           reinterpret_cast<nvr_stream>(st)));
-    dn_concat<<<grid_for(n * kIn, 256, 16384), 256, 0, st>>>(n, w.feat, theta, w.a0);
+// Matrix-core backward: recompute + chain per block, weight gradients over
+// the points, pose terms, then the encoding's table and position gradients
+// (dx acc, nullable; it also receives dx_can, the residual's identity).
+nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
+                         const float *x, const float *theta, const float *table,
+                         const float *params, const float *dx_can, float *dparams, float *dtable,
+                         float *dx, float *dtheta, bool det, const DeformMfmaWs &w,
+                         hipStream_t st) {
+    NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table, params, w, st));
+    dn_bwd_mfma<<<dn_grid(cap), kDnBlock, sizeof(uint4) * kBwd, st>>>(
+        n, n_dev, cap, w.feat, w.bias, w.fwd, w.bwd, dx_can, w.dfeat, w.hbuf, w.zbuf);
+    NVR_LAUNCHED();
+    // W4 [3][128]: dZ4 rows at 512 (one tile) x H3 at 416
+    NVR_TRY((mfma_dw<1, 8, false>(n, n_dev, cap, w, 4 * kWidth, kFeat + 3 * kWidth,
+                                  dparams + (layer_w(params, 4) - params), 3, kWidth, kWidth,
+                                  st)));
+    for (int layer = 3; layer >= 1; --layer)   // W_L [128][128]: dZ_L x H_{L-1}
+        NVR_TRY((mfma_dw<8, 8, false>(n, n_dev, cap, w, layer * kWidth,
+                                      kFeat + (layer - 1) * kWidth,
+                                      dparams + (layer_w(params, layer) - params), kWidth,
+                                      kWidth, kWidth, st)));
+    // W0's feature columns: dZ0 x encoding, plus the sums of dZ0 for the pose
+    NVR_TRY((mfma_dw<8, 2, true>(n, n_dev, cap, w, 0, 0, dparams, kWidth, kFeat, kIn, st)));
+    dn_pose_grad<<<1, kWidth, 0, st>>>(dw_parts(cap), 16 * 3, 16 * 2, w.partial, params, theta,
+                                       dparams, dtheta);
+    NVR_LAUNCHED();
+    NVR_TRY(launch_scatter_rows(gp, n, n_dev, cap, x, w.dfeat, dtable, w.binned, st, det));
+    if (dx) {
+        dn_encode_dx<<<grid_for(cap, 256, 16384), 256, 0, st>>>(
+            gp, n, n_dev, cap, x, reinterpret_cast<const float2 *>(table), w.dfeat, dx);
+        NVR_LAUNCHED();
+        dn_add<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can, n_dev, cap);
+        NVR_LAUNCHED();
+    }
+    return NVR_OK;
+}
+
+// float32 forward into the workspace: encoding, input [enc | theta], hidden
+// layers, output dv (the residual is added by the caller)
+nvr_status f32_forward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
+                       const float *x, const float *theta, const float *table,
+                       const float *params, const DeformWs &w, hipStream_t st) {
+    NVR_TRY(launch_encode_fwd(gp, n, n_dev, cap, x, table, NVR_F32, w.feat, NVR_F32, false, st));
+    dn_concat<<<grid_for(cap * kIn, 256, 16384), 256, 0, st>>>(n, n_dev, cap, w.feat, theta, w.a0);
     NVR_LAUNCHED();
     const float *in = w.a0;
     int width_in = kIn;
     for (int i = 0; i < kHidden; ++i) {
-        NVR_TRY(gemm_fwd(h, n, kWidth, width_in, layer_w(params, i), in, w.h[i]));
-        dn_relu<<<grid_for(n * kWidth, 256, 16384), 256, 0, st>>>(n * kWidth, w.h[i]);
-        NVR_LAUNCHED();
+        NVR_TRY(mm<true>(n, n_dev, cap, in, width_in, width_in, layer_w(params, i), width_in, 1,
+                         kWidth, w.h[i], kWidth, st));
         in = w.h[i];
         width_in = kWidth;
     }
-    NVR_TRY(gemm_fwd(h, n, 3, kWidth, layer_w(params, kHidden), in, w.dv));
+    return mm<false>(n, n_dev, cap, in, kWidth, kWidth, layer_w(params, kHidden), kWidth, 1, 3,
+                     w.dv, 3, st);
+}
+
+nvr_status f32_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
+                        const float *x, const float *theta, const float *table,
+                        const float *params, const float *dx_can, float *dparams, float *dtable,
+                        float *dx, float *dtheta, bool det, const DeformWs &w, hipStream_t st) {
+    NVR_TRY(f32_forward(gp, n, n_dev, cap, x, theta, table, params, w, st));
+    // output layer: dW_out += dx_can^T h4; dh = dx_can W_out
+    float *dW = dparams + (kParams - 3 * kWidth);
+    NVR_TRY(mm_dw(n, n_dev, cap, dx_can, 3, w.h[kHidden - 1], kWidth, kWidth, dW, w.partial, st));
+    NVR_TRY(mm<false>(n, n_dev, cap, dx_can, 3, 3, layer_w(params, kHidden), 1, kWidth, kWidth,
+                      w.dh0, kWidth, st));
+    float *dh = w.dh0, *dh_next = w.dh1;
+    for (int i = kHidden - 1; i >= 0; --i) {
+        dn_relu_bwd<<<grid_for(cap * kWidth, 256, 16384), 256, 0, st>>>(n, n_dev, cap, kWidth, dh,
+                                                                        w.h[i]);
+        NVR_LAUNCHED();
+        const int width_in = i == 0 ? kIn : kWidth;
+        const float *in = i == 0 ? w.a0 : w.h[i - 1];
+        float *dWi = dparams + (layer_w(params, i) - params);
+        NVR_TRY(mm_dw(n, n_dev, cap, dh, kWidth, in, width_in, width_in, dWi, w.partial, st));
+        float *dst = i == 0 ? w.da0 : dh_next;
+        NVR_TRY(mm<false>(n, n_dev, cap, dh, kWidth, kWidth, layer_w(params, i), 1, width_in,
+                          width_in, dst, width_in, st));
+        if (i > 0) {
+            dh_next = dh;
+            dh = dst;
+        }
+    }
+    dn_split<<<grid_for(cap * kFeat, 256, 16384), 256, 0, st>>>(n, n_dev, cap, w.da0, w.dfeat);
+    NVR_LAUNCHED();
+    if (dtheta) {
+        const unsigned nb = (unsigned)std::max<int64_t>(1, (cap + kThetaChunk - 1) / kThetaChunk);
+        dn_theta_sum<<<nb, 128, 0, st>>>(n, n_dev, cap, w.da0, w.theta_part);
+        NVR_LAUNCHED();
+        dn_theta_reduce<<<1, 128, 0, st>>>(n, n_dev, cap, w.theta_part, dtheta);
+        NVR_LAUNCHED();
+    }
+    NVR_TRY(launch_scatter_rows(gp, n, n_dev, cap, x, w.dfeat, dtable, w.binned, st, det));
+    if (dx) {
+        dn_encode_dx<<<grid_for(cap, 256, 16384), 256, 0, st>>>(
+            gp, n, n_dev, cap, x, reinterpret_cast<const float2 *>(table), w.dfeat, dx);
+        NVR_LAUNCHED();
+        // the residual's identity: dx += dx_can
+        dn_add<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can, n_dev, cap);
+        NVR_LAUNCHED();
+    }
     return NVR_OK;
 }
 
+size_t ws_bytes(const nvr_grid_desc *g, int64_t cap, bool matrix_cores, bool det) {
+    return matrix_cores ? carve_mfma(g, cap, det, nullptr, nullptr)
+                        : carve(g, cap, det, nullptr, nullptr);
+}
+
+nvr_status run_fwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const int32_t *n_dev,
+                   int64_t cap, const float *x, const float *theta, const float *table,
+                   const float *params, float *x_can, void *ws, hipStream_t st) {
+    const GridParams gp = make_grid_params(g);
+    if (matrix_cores) {
+        DeformMfmaWs w;
+        carve_mfma(g, cap, false, static_cast<char *>(ws), &w);
+        return mfma_forward(gp, n, n_dev, cap, x, theta, table, params, x_can, w, st);
+    }
+    DeformWs w;
+    carve(g, cap, false, static_cast<char *>(ws), &w);
+    NVR_TRY(f32_forward(gp, n, n_dev, cap, x, theta, table, params, w, st));
+    dn_residual<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n, n_dev, cap, x, w.dv, x_can);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
+nvr_status run_bwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const int32_t *n_dev,
+                   int64_t cap, const float *x, const float *theta, const float *table,
+                   const float *params, const float *dx_can, float *dparams, float *dtable,
+                   float *dx, float *dtheta, bool det, void *ws, hipStream_t st) {
+    const GridParams gp = make_grid_params(g);
+    if (matrix_cores) {
+        DeformMfmaWs w;
+        carve_mfma(g, cap, det, static_cast<char *>(ws), &w);
+        return mfma_backward(gp, n, n_dev, cap, x, theta, table, params, dx_can, dparams, dtable,
+                             dx, dtheta, det, w, st);
+    }
+    DeformWs w;
+    carve(g, cap, det, static_cast<char *>(ws), &w);
+    return f32_backward(gp, n, n_dev, cap, x, theta, table, params, dx_can, dparams, dtable, dx,
+                        dtheta, det, w, st);
+}
+
 }  // namespace
+
+// ------------------------------------------------------- training-step calls
+nvr_status deform_check(const nvr_grid_desc *g, int64_t cap) { return check_desc(g, cap); }
+
+nvr_status deform_setup() { return dn_lds_opt_in(); }
+
+size_t deform_ws_bytes(const nvr_grid_desc *g, int64_t cap, bool matrix_cores, bool det) {
+    return ws_bytes(g, cap, matrix_cores, det);
+}
+
+nvr_status deform_fwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32_t *n_dev,
+                          int64_t cap, const float *x, const float *theta, const float *table,
+                          const float *params, float *x_can, void *ws, hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    return run_fwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, params, x_can, ws, st);
+}
+
+nvr_status deform_bwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32_t *n_dev,
+                          int64_t cap, const float *x, const float *theta, const float *table,
+                          const float *params, const float *dx_can, float *dparams,
+                          float *dtable, float *dx, float *dtheta, bool det, void *ws,
+                          hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    return run_bwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, params, dx_can, dparams,
+                   dtable, dx, dtheta, det, ws, st);
+}
+
+int64_t deform_param_count() { return kParams; }
+
+// dst[i] = sum over p < parts (in order) of src[p stride + i], i < 3 count
+__global__ void __launch_bounds__(256)
+dn_sum_parts(const int32_t *__restrict__ n_dev, int64_t cap, int parts, int64_t stride,
+             const float *__restrict__ src, float *__restrict__ dst) {
+    const int64_t m = 3 * count_of(0, n_dev, cap);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int p = 0; p < parts; ++p) acc += src[p * stride + i];
+        dst[i] = acc;
+    }
+}
+
+nvr_status launch_sum_parts(const int32_t *n_dev, int64_t cap, int parts, int64_t stride,
+                            const float *src, float *dst, hipStream_t st) {
+    if (cap <= 0) return NVR_OK;
+    dn_sum_parts<<<grid_for(3 * cap, 256, 16384), 256, 0, st>>>(n_dev, cap, parts, stride, src,
+                                                                dst);
+    NVR_LAUNCHED();
+    return NVR_OK;
+}
+
 }  // namespace nvr
 
 using namespace nvr;
 
 extern "C" size_t nvr_deform_workspace(const nvr_grid_desc *g, int64_t n) {
-    if (g == nullptr || n < 0) return 0;
-    return std::max(carve(g, n, nullptr, nullptr), carve_mfma(g, n, nullptr, nullptr));
+    if (g == nullptr || n < 0 || check_grid(g) != NVR_OK) return 0;
+    return std::max(ws_bytes(g, n, false, false), ws_bytes(g, n, true, false));
 }
 
 extern "C" int64_t nvr_deform_param_count(void) { return kParams; }
@@ -807,58 +1095,8 @@ extern "C" nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const fl
     NVR_REQUIRE(aligned(x, 4) && aligned(theta, 4) && aligned(table, 8) && aligned(params, 4) &&
                     aligned(x_can, 4),
                 NVR_EINVAL, "misaligned array");
-    const hipStream_t st = hs(stream);
-    if (math == NVR_F16) {
-        DeformMfmaWs w;
-        carve_mfma(g, n, static_cast<char *>(workspace), &w);
-        return mfma_forward(g, n, x, theta, table, params, x_can, w, st);
-    }
-    rocblas_handle h;
-    std::lock_guard<std::mutex> lock(g_blas_mu);
-    NVR_TRY(blas_for(st, &h));
-    DeformWs w;
-    carve(g, n, static_cast<char *>(workspace), &w);
-    NVR_TRY(forward(g, n, x, theta, table, params, w, st, h));
-    dn_residual<<<grid_for(n * 3, 256, 16384), 256, 0, st>>>(n * 3, x, w.dv, x_can);
-    NVR_LAUNCHED();
-    return NVR_OK;
-}
-
-// Matrix-core backward: recompute + chain per block, weight gradients over
-// the points, pose terms, then the encoding's table and position gradients.
-static nvr_status mfma_backward(const nvr_grid_desc *g, int64_t n, const float *x,
-                                const float *theta, const float *table, const float *params,
-                                const float *dx_can, float *dparams, float *dtable, float *dx,
-                                float *dtheta, const DeformMfmaWs &w, hipStream_t st) {
-    NVR_TRY(mfma_prologue(g, n, x, theta, table, params, w, st));
-    dn_bwd_mfma<<<dn_grid(n), kDnBlock, sizeof(uint4) * kBwd, st>>>(
-        n, w.feat, w.bias, w.fwd, w.bwd, dx_can, w.dfeat, w.hbuf, w.zbuf);
-    NVR_LAUNCHED();
-    const int64_t nblk = (n + 15) / 16;
-    // W4 [3][128]: dZ4 rows at 512 (one tile) x H3 at 416
-    NVR_TRY((mfma_dw<1, 8, false>(nblk, w, 4 * kWidth, kFeat + 3 * kWidth,
-                                  dparams + (layer_w(params, 4) - params), 3, kWidth, kWidth, st)));
-    for (int layer = 3; layer >= 1; --layer)   // W_L [128][128]: dZ_L x H_{L-1}
-        NVR_TRY((mfma_dw<8, 8, false>(nblk, w, layer * kWidth, kFeat + (layer - 1) * kWidth,
-                                      dparams + (layer_w(params, layer) - params), kWidth, kWidth,
-                                      kWidth, st)));
-    // W0's feature columns: dZ0 x encoding, plus the sums of dZ0 for the pose
-    NVR_TRY((mfma_dw<8, 2, true>(nblk, w, 0, 0, dparams, kWidth, kFeat, kIn, st)));
-    const int64_t nstep = (nblk + 1) / 2;
-    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(nstep, kDwGrid));
-    dn_pose_grad<<<1, kWidth, 0, st>>>(parts, 16 * 3, 16 * 2, w.partial, params, theta, dparams,
-                                       dtheta);
-    NVR_LAUNCHED();
-    NVR_TRY(nvr_encode_bwd_binned(g, n, x, table, w.dfeat, dtable, nullptr, w.binned,
-                                  reinterpret_cast<nvr_stream>(st)));
-    if (dx) {
-        dn_encode_dx<<<grid_for(n, 256, 16384), 256, 0, st>>>(
-            make_grid_params(g), n, x, reinterpret_cast<const float2 *>(table), w.dfeat, dx);
-        NVR_LAUNCHED();
-        dn_add<<<grid_for(n * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can);
-        NVR_LAUNCHED();
-    }
-    return NVR_OK;
+    return run_fwd(g, math == NVR_F16, n, nullptr, n, x, theta, table, params, x_can, workspace,
+                   hs(stream));
 }
 
 extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
@@ -876,55 +1114,6 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
                     aligned(dx_can, 4) && aligned(dparams, 4) && aligned(dtable, 8) &&
                     aligned(dx, 4) && aligned(dtheta, 4),
                 NVR_EINVAL, "misaligned array");
-    const hipStream_t st = hs(stream);
-    if (math == NVR_F16) {
-        DeformMfmaWs w;
-        carve_mfma(g, n, static_cast<char *>(workspace), &w);
-        return mfma_backward(g, n, x, theta, table, params, dx_can, dparams, dtable, dx, dtheta,
-                             w, st);
-    }
-    rocblas_handle h;
-    std::lock_guard<std::mutex> lock(g_blas_mu);
-    NVR_TRY(blas_for(st, &h));
-    DeformWs w;
-    carve(g, n, static_cast<char *>(workspace), &w);
-    NVR_TRY(forward(g, n, x, theta, table, params, w, st, h));
-    // output layer: dW_out += dx_can^T h4; dh = dx_can W_out
-    float *dW = dparams + (kParams - 3 * kWidth);
-    NVR_TRY(gemm_dw(h, st, n, 3, kWidth, dx_can, w.h[kHidden - 1], dW, w.partial));
-    NVR_TRY(gemm_dx(h, n, 3, kWidth, layer_w(params, kHidden), dx_can, w.dh0));
-    float *dh = w.dh0, *dh_next = w.dh1;
-    for (int i = kHidden - 1; i >= 0; --i) {
-        dn_relu_bwd<<<grid_for(n * kWidth, 256, 16384), 256, 0, st>>>(n * kWidth, dh, w.h[i]);
-        NVR_LAUNCHED();
-        const int width_in = i == 0 ? kIn : kWidth;
-        const float *in = i == 0 ? w.a0 : w.h[i - 1];
-        float *dWi = dparams + (layer_w(params, i) - params);
-        NVR_TRY(gemm_dw(h, st, n, kWidth, width_in, dh, in, dWi, w.partial));
-        float *dst = i == 0 ? w.da0 : dh_next;
-        NVR_TRY(gemm_dx(h, n, kWidth, width_in, layer_w(params, i), dh, dst));
-        if (i > 0) {
-            dh_next = dh;
-            dh = dst;
-        }
-    }
-    dn_split<<<grid_for(n * kFeat, 256, 16384), 256, 0, st>>>(n, w.da0, w.dfeat);
-    NVR_LAUNCHED();
-    if (dtheta) {
-        dn_theta_sum<<<(unsigned)((n + kThetaChunk - 1) / kThetaChunk), 128, 0, st>>>(n, w.da0,
-                                                                                  dtheta);
-        NVR_LAUNCHED();
-    }
-    NVR_TRY(nvr_encode_bwd_binned(g, n, x, table, w.dfeat, dtable, nullptr, w.binned, stream));
-    if (dx) {
-        dn_encode_dx<<<grid_for(n, 256, 16384), 256, 0, st>>>(
-            make_grid_params(g), n, x, reinterpret_cast<const float2 *>(table), w.dfeat, dx);
-        NVR_LAUNCHED();
-    }
-    if (dx) {
-        // the residual's identity: dx += dx_can
-        dn_add<<<grid_for(n * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can);
-        NVR_LAUNCHED();
-    }
-    return NVR_OK;
+    return run_bwd(g, math == NVR_F16, n, nullptr, n, x, theta, table, params, dx_can, dparams,
+                   dtable, dx, dtheta, false, workspace, hs(stream));
 }

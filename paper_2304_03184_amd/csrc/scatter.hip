@@ -1031,9 +1031,12 @@ constexpr int kPlanarRows = 128;
 
 __global__ void __launch_bounds__(256)
 scatter_planarize(int L, int lpg, int64_t n, const float *__restrict__ dfeat,
-                  float *__restrict__ out) {
+                  float *__restrict__ out, const int32_t *__restrict__ n_dev = nullptr,
+                  int64_t cap = 0) {
     extern __shared__ float rows[];                    // [kPlanarRows][2L + 1]
     const int w = 2 * L, wp = w + 1, q = 2 * lpg;
+    const int64_t stride = n_dev ? cap : n;           // planes are [cap][q] with a device count
+    if (n_dev) n = count_of(n, n_dev, cap);
     for (int64_t s0 = (int64_t)blockIdx.x * kPlanarRows; s0 < n;
          s0 += (int64_t)gridDim.x * kPlanarRows) {
         const int ns = (int)(n - s0 < kPlanarRows ? n - s0 : kPlanarRows);
@@ -1041,7 +1044,7 @@ scatter_planarize(int L, int lpg, int64_t n, const float *__restrict__ dfeat,
         for (int i = threadIdx.x; i < ns * w; i += blockDim.x) rows[(i / w) * wp + i % w] = src[i];
         __syncthreads();
         for (int g = 0; g < kXcds; ++g) {
-            float *dst = out + ((size_t)g * n + s0) * q;
+            float *dst = out + ((size_t)g * stride + s0) * q;
             for (int j = threadIdx.x; j < ns * q; j += blockDim.x) {
                 const int r = j / q, c = j % q, l = g + kXcds * (c >> 1);
                 dst[j] = l < L ? rows[r * wp + 2 * l + (c & 1)] : 0.f;
@@ -1084,6 +1087,33 @@ nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_
                                     int emit_chunks, int emit_block) {
     return launch_scatter(p, n, n_dev, cap, x, table, dfeat, nullptr, nullptr, ws, st,
                           /*counted=*/true, emit_chunks, emit_block);
+}
+
+// Table gradient of row-major feature gradients dfeat[cap][2L] over the first
+// count_of(n, n_dev, cap) samples: regrouped into the level-group planes, then
+// the binned scatter (det: its deterministic variant).  ws:
+// scatter_rows_ws_bytes(p, cap, det) bytes.
+size_t scatter_rows_ws_bytes(const GridParams &p, int64_t cap, bool det) {
+    const int lpg = (p.L + kXcds - 1) / kXcds;
+    const size_t sc = det ? scatter_det_ws_bytes(p, cap) : scatter_ws_bytes(p, cap);
+    return ((sc + 255) & ~size_t(255)) + sizeof(float) * (size_t)kXcds * cap * 2 * lpg;
+}
+
+nvr_status launch_scatter_rows(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
+                               const float *x, const float *dfeat, float *dtable, void *ws,
+                               hipStream_t st, bool det) {
+    if (cap <= 0) return NVR_OK;
+    const int lpg = (p.L + kXcds - 1) / kXcds;
+    const size_t sc = det ? scatter_det_ws_bytes(p, cap) : scatter_ws_bytes(p, cap);
+    float *planar = (float *)((char *)ws + ((sc + 255) & ~size_t(255)));
+    scatter_planarize<<<grid_for(cap, kPlanarRows, 8192), 256,
+                        sizeof(float) * kPlanarRows * (2 * p.L + 1), st>>>(p.L, lpg, n, dfeat,
+                                                                           planar, n_dev, cap);
+    NVR_LAUNCHED();
+    if (det)
+        return launch_scatter_det(p, n, n_dev, cap, x, nullptr, planar, dtable, nullptr, ws, st);
+    return launch_scatter(p, n, n_dev, cap, x, nullptr, planar, dtable, nullptr, ws, st,
+                          /*counted=*/false, 1024, 512);
 }
 
 }  // namespace nvr

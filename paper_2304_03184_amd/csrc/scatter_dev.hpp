@@ -25,6 +25,12 @@ size_t scatter_det_ws_bytes(const GridParams &p, int64_t cap);
 nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                               const float *x, const void *table, const float *dfeat,
                               float *dtable, float *dx_parts, void *ws, hipStream_t st);
+// Row-major feature gradients [cap][2L] (regrouped first), device-side count;
+// det selects the deterministic scatter.
+size_t scatter_rows_ws_bytes(const GridParams &p, int64_t cap, bool det);
+nvr_status launch_scatter_rows(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
+                               const float *x, const float *dfeat, float *dtable, void *ws,
+                               hipStream_t st, bool det);
 // the scan and emit passes alone (tile counts already formed), for tuning
 nvr_status launch_scatter_emit_only(const GridParams &p, int64_t n, const int32_t *n_dev,
                                     int64_t cap, const float *x, const void *table,

@@ -2,6 +2,7 @@
 // points.  The context owns per-field sample workspaces (fixed capacity, so
 // every launch is sized without reading the device-side sample count) and,
 // with NVR_USE_GRAPH, one captured HIP graph per (descriptor, fields, batch).
+#include "deform_dev.hpp"
 #include "launch.hpp"
 #include "scatter_dev.hpp"
 
@@ -15,8 +16,8 @@ namespace nvr {
 struct FieldWs {
     int64_t cap = 0, n_rays = 0;
     int precision = -1;
-    int has_warp = 0, n_in = 0;
-    size_t mlp_bytes = 0, scatter_bytes = 0;
+    int has_warp = 0, n_in = 0, has_deform = 0;
+    size_t mlp_bytes = 0, scatter_bytes = 0, deform_bytes = 0;
     void *block = nullptr;          // one allocation, carved below
     int32_t *off, *ray_id, *n_dev, *march_ws;
     float *t, *dt, *x, *xc;
@@ -27,6 +28,10 @@ struct FieldWs {
     void *mlp_ws;
     void *scatter_ws;               // binned table-gradient scatter (bf16 training)
     float *sh;                      // bf16 path: per-ray SH coefficients [n_rays][16]
+    // deformation network (warped fields with one): deformed positions, the
+    // summed gradient w.r.t. them, the gradient w.r.t. the warped positions
+    float *xd, *dxd, *dxt;
+    void *deform_ws;
     // launch shapes of the BF16 step's kernels (0: built-in default), set by
     // the autotuner for this capacity
     int enc_chunks = 0, mlp_fwd_blocks = 0, mlp_bwd_blocks = 0, emit_chunks = 0, emit_block = 0;
@@ -77,7 +82,21 @@ static nvr_status field_check(const nvr_field *f, const nvr_step_desc *s, Net *n
     if (f->has_warp) {
         NVR_REQUIRE(f->warp.n_frames >= 1, NVR_EINVAL, "warp n_frames < 1");
     }
+    if (f->deform) {
+        const nvr_deform_state *D = f->deform;
+        NVR_REQUIRE(f->has_warp, NVR_EINVAL, "a deformation network needs the warp");
+        NVR_TRY(deform_check(&D->grid, s->max_samples));
+        NVR_REQUIRE(D->theta && D->table && D->params, NVR_EINVAL,
+                    "NULL deformation pose, table or parameters");
+        NVR_REQUIRE(aligned(D->table, 8) && aligned(D->theta, 4) && aligned(D->params, 4),
+                    NVR_EINVAL, "misaligned deformation arrays");
+    }
     return NVR_OK;
+}
+
+// positions the field's encoding reads: deformed, warped or marched
+static const float *enc_pos(const nvr_field *f, const FieldWs &w) {
+    return f->deform ? w.xd : f->has_warp ? w.xc : w.x;
 }
 
 static bool deterministic(const nvr_ctx *ctx) { return (ctx->flags & NVR_DETERMINISTIC) != 0; }
@@ -91,9 +110,16 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         (train && precision == NVR_BF16)
             ? (deterministic(ctx) ? scatter_det_ws_bytes(gp, cap) : scatter_ws_bytes(gp, cap))
             : 0;
+    const int has_deform = f->deform ? 1 : 0;
+    if (has_deform) NVR_TRY(deform_setup());
+    const size_t deform_bytes =
+        has_deform ? deform_ws_bytes(&f->deform->grid, cap, precision == NVR_BF16,
+                                     deterministic(ctx))
+                   : 0;
     if (w.block && w.cap >= cap && w.n_rays >= n_rays && w.precision == precision &&
         w.has_warp == f->has_warp && w.n_in == net.n_in && w.mlp_bytes >= mlp_bytes &&
-        w.scatter_bytes >= scatter_bytes)
+        w.scatter_bytes >= scatter_bytes && w.has_deform == has_deform &&
+        w.deform_bytes >= deform_bytes)
         return NVR_OK;
     if (w.block) {
         NVR_HIP(hipDeviceSynchronize());
@@ -108,7 +134,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     }
     const bool bf = precision == NVR_BF16;
     const int nin = net.n_in;
-    size_t sz[18] = {
+    size_t sz[22] = {
         sizeof(int32_t) * (size_t)(n_rays + 1),             // off
         sizeof(int32_t) * (size_t)cap,                      // ray_id
         sizeof(int32_t) * 4,                                // n_dev
@@ -127,6 +153,10 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         mlp_bytes,                                                             // mlp
         scatter_bytes,                                                         // scatter
         bf ? sizeof(float) * 16 * (size_t)n_rays : 0,                          // sh
+        has_deform ? sizeof(float) * 3 * (size_t)cap : 0,                      // xd
+        has_deform ? sizeof(float) * 3 * (size_t)cap : 0,                      // dxd
+        has_deform ? sizeof(float) * 3 * (size_t)cap : 0,                      // dxt
+        deform_bytes,                                                          // deform
     };
     size_t total = 0;
     for (size_t s : sz) total += up(s);
@@ -138,8 +168,8 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         return NVR_ENOMEM;
     }
     char *p = (char *)blk;
-    void *ptr[18];
-    for (int i = 0; i < 18; ++i) {
+    void *ptr[22];
+    for (int i = 0; i < 22; ++i) {
         ptr[i] = sz[i] ? p : nullptr;
         p += up(sz[i]);
     }
@@ -151,6 +181,8 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.n_in = net.n_in;
     w.mlp_bytes = mlp_bytes;
     w.scatter_bytes = scatter_bytes;
+    w.has_deform = has_deform;
+    w.deform_bytes = deform_bytes;
     w.off = (int32_t *)ptr[0];
     w.ray_id = (int32_t *)ptr[1];
     w.n_dev = (int32_t *)ptr[2];
@@ -169,6 +201,10 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.mlp_ws = ptr[15];
     w.scatter_ws = ptr[16];
     w.sh = (float *)ptr[17];
+    w.xd = (float *)ptr[18];
+    w.dxd = (float *)ptr[19];
+    w.dxt = (float *)ptr[20];
+    w.deform_ws = ptr[21];
     w.enc_chunks = w.mlp_fwd_blocks = w.mlp_bwd_blocks = w.emit_chunks = w.emit_block = 0;
     w.tuned = false;
     return NVR_OK;
@@ -186,6 +222,12 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
     if (f->has_warp) {
         NVR_TRY(run_warp_fwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.xc, st));
         pos = w.xc;
+    }
+    if (f->deform) {
+        const nvr_deform_state *D = f->deform;
+        NVR_TRY(deform_fwd_dev(&D->grid, precision == NVR_BF16, w.n_dev, cap, w.xc, D->theta,
+                               D->table, D->params, w.xd, w.deform_ws, st));
+        pos = w.xd;
     }
     const GridParams gp = make_grid_params(&f->grid);
     if (precision == NVR_BF16) {
@@ -252,6 +294,28 @@ static nvr_status enqueue_fwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                                  ctx->loss_part);
 }
 
+// Position gradient of the encoding (n_parts partial arrays in w.dx) back
+// through the deformation network, if any, and the warp.
+static nvr_status warp_chain_bwd(nvr_ctx *ctx, const nvr_field *f, FieldWs &w, int n_parts,
+                                 hipStream_t st) {
+    const int64_t cap = w.cap;
+    if (!f->deform)
+        return run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, n_parts, 3 * cap,
+                            f->node_dq_grad, f->bones_grad, st);
+    const nvr_deform_state *D = f->deform;
+    const float *dxd = w.dx;
+    if (n_parts > 1) {
+        NVR_TRY(launch_sum_parts(w.n_dev, cap, n_parts, 3 * cap, w.dx, w.dxd, st));
+        dxd = w.dxd;
+    }
+    NVR_TRY(launch_fill_zero(w.dxt, 3 * cap, st));
+    NVR_TRY(deform_bwd_dev(&D->grid, w.precision == NVR_BF16, w.n_dev, cap, w.xc, D->theta,
+                           D->table, D->params, dxd, D->params_grad, D->table_grad, w.dxt,
+                           D->theta_grad, deterministic(ctx), w.deform_ws, st));
+    return run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dxt, 1, 3 * cap, f->node_dq_grad,
+                        f->bones_grad, st);
+}
+
 static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
                               const nvr_batch *b, const Net *nets, nvr_train_state *state,
                               hipStream_t st) {
@@ -259,7 +323,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
         const nvr_field *f = fields[k];
         FieldWs &w = ctx->ws[k];
         const int64_t cap = w.cap;
-        const float *pos = f->has_warp ? w.xc : w.x;
+        const float *pos = enc_pos(f, w);
         const GridParams gp = make_grid_params(&f->grid);
         if (s->precision == NVR_BF16) {
             NVR_TRY(mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
@@ -273,9 +337,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                 NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                        f->table_grad, f->has_warp ? w.dx : nullptr, w.scatter_ws,
                                        st, /*counted=*/true, w.emit_chunks, w.emit_block));
-            if (f->has_warp)
-                NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, kXcds, 3 * cap,
-                                     f->node_dq_grad, f->bones_grad, st));
+            if (f->has_warp) NVR_TRY(warp_chain_bwd(ctx, f, w, kXcds, st));
         } else {
             PlainView F{(float *)w.feat, 1, nets[k].n_in};
             PlainView dF{w.dfeat, 1, nets[k].n_in};
@@ -284,9 +346,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
             if (f->has_warp) NVR_TRY(launch_fill_zero(w.dx, 3 * cap, st));
             NVR_TRY(launch_encode_bwd(gp, 0, w.n_dev, cap, pos, f->table, NVR_F32, w.dfeat,
                                       f->table_grad, f->has_warp ? w.dx : nullptr, false, st));
-            if (f->has_warp)
-                NVR_TRY(run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, 1, 3 * cap,
-                                     f->node_dq_grad, f->bones_grad, st));
+            if (f->has_warp) NVR_TRY(warp_chain_bwd(ctx, f, w, 1, st));
         }
     }
     if (!s->apply_update) return NVR_OK;
@@ -295,6 +355,11 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
         const nvr_field *f = fields[k];
         NVR_TRY(launch_check_finite(f->grid.offset[f->grid.n_levels] * 2, f->table_grad, state, st));
         NVR_TRY(launch_check_finite(nets[k].woff[nets[k].n_layers], f->params_grad, state, st));
+        if (const nvr_deform_state *D = f->deform) {
+            NVR_TRY(launch_check_finite(D->grid.offset[D->grid.n_levels] * 2, D->table_grad,
+                                        state, st));
+            NVR_TRY(launch_check_finite(deform_param_count(), D->params_grad, state, st));
+        }
     }
     const AdamParams ap = adam_params(s->adam);
     const bool bf = s->precision == NVR_BF16;
@@ -304,6 +369,12 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                             f->table_grad, 1, state, bf ? f->table_half : nullptr, NVR_F16, st));
         NVR_TRY(launch_adam(ap, nets[k].woff[nets[k].n_layers], f->params, f->params_m, f->params_v,
                             f->params_grad, 0, state, bf ? f->params_bf16 : nullptr, NVR_BF16, st));
+        if (const nvr_deform_state *D = f->deform) {
+            NVR_TRY(launch_adam(ap, D->grid.offset[D->grid.n_levels] * 2, D->table, D->table_m,
+                                D->table_v, D->table_grad, 1, state, nullptr, NVR_F16, st));
+            NVR_TRY(launch_adam(ap, deform_param_count(), D->params, D->params_m, D->params_v,
+                                D->params_grad, 0, state, nullptr, NVR_BF16, st));
+        }
     }
     return launch_state_end(state, st);
 }
@@ -324,6 +395,14 @@ static nvr_status prepare(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const
             NVR_REQUIRE(fields[k]->params_m && fields[k]->params_v && fields[k]->table_m &&
                             fields[k]->table_v && fields[k]->table_grad && fields[k]->params_grad,
                         NVR_EINVAL, "NULL optimiser buffers");
+    for (int k = 0; k < s->n_fields; ++k)
+        if (const nvr_deform_state *D = fields[k]->deform) {
+            NVR_REQUIRE(D->table_grad && D->params_grad && aligned(D->table_grad, 8), NVR_EINVAL,
+                        "NULL or misaligned deformation gradients");
+            NVR_REQUIRE(!s->apply_update ||
+                            (D->table_m && D->table_v && D->params_m && D->params_v),
+                        NVR_EINVAL, "NULL deformation optimiser buffers");
+        }
     return NVR_OK;
 }
 
@@ -399,7 +478,7 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         const nvr_field *f = fields[k];
         FieldWs &w = ctx->ws[k];
         const int64_t cap = w.cap;
-        const float *pos = f->has_warp ? w.xc : w.x;
+        const float *pos = enc_pos(f, w);
         const GridParams gp = make_grid_params(&f->grid);
         const TileCounter counter = scatter_counter(gp, w.scatter_ws);
         NVR_TRY(pick(st, enc, 4, &w.enc_chunks, [&](int c) {
@@ -427,7 +506,7 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         const nvr_field *f = fields[k];
         FieldWs &w = ctx->ws[k];
         const int64_t cap = w.cap;
-        const float *pos = f->has_warp ? w.xc : w.x;
+        const float *pos = enc_pos(f, w);
         const GridParams gp = make_grid_params(&f->grid);
         NVR_TRY(pick(st, mlp_b, 3, &w.mlp_bwd_blocks, [&](int c) {
             return mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
@@ -450,7 +529,10 @@ static std::string graph_key(const nvr_step_desc *s, nvr_field *const *fields, c
                              const nvr_train_state *state, const float *loss) {
     std::string k;
     k.append((const char *)s, sizeof(*s));
-    for (int i = 0; i < s->n_fields; ++i) k.append((const char *)fields[i], sizeof(nvr_field));
+    for (int i = 0; i < s->n_fields; ++i) {
+        k.append((const char *)fields[i], sizeof(nvr_field));
+        if (fields[i]->deform) k.append((const char *)fields[i]->deform, sizeof(nvr_deform_state));
+    }
     k.append((const char *)b, sizeof(*b));
     k.append((const char *)&state, sizeof(state));
     k.append((const char *)&loss, sizeof(loss));

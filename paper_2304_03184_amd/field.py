@@ -17,9 +17,39 @@ from . import ops
 from ._lib import call
 
 
+class Deform:
+    """Residual deformation network of a warped field (Sec. 4.2): its grid,
+    pose, fp32 masters, gradients and Adam moments on the device."""
+
+    def __init__(self, grid, theta, table, params, device="cuda"):
+        self.grid = grid
+        n_e = grid.n_entries
+        self.theta = torch.as_tensor(np.asarray(theta, np.float32)).reshape(72).to(device)
+        self.table = torch.as_tensor(np.asarray(table, np.float32)).reshape(n_e, 2).to(device)
+        self.params = torch.as_tensor(np.asarray(params, np.float32)).reshape(-1).to(device)
+        assert self.params.numel() == L.lib().nvr_deform_param_count()
+        self.table_grad = torch.zeros_like(self.table)
+        self.params_grad = torch.zeros_like(self.params)
+        self.table_m = torch.zeros_like(self.table)
+        self.table_v = torch.zeros_like(self.table)
+        self.params_m = torch.zeros_like(self.params)
+        self.params_v = torch.zeros_like(self.params)
+        self.theta_grad = torch.zeros_like(self.theta)
+        self._c = None
+
+    def c(self):
+        d = L.DeformState()
+        d.grid = self.grid
+        for k in ("theta", "table", "params", "table_grad", "params_grad", "table_m", "table_v",
+                  "params_m", "params_v", "theta_grad"):
+            setattr(d, k, getattr(self, k).data_ptr())
+        self._c = d            # kept alive while the field struct points at it
+        return d
+
+
 class Field:
     def __init__(self, work, fcfg, table, params, occ_words=None, rig=None, warp_desc=None,
-                 ray_range=None, device="cuda"):
+                 ray_range=None, device="cuda", deform=None):
         self.work, self.fcfg = work, fcfg
         self.grid = ops.grid_desc_of(fcfg)
         self.mlp = ops.mlp_desc_of(fcfg)
@@ -48,6 +78,8 @@ class Field:
             self.node_dq_grad = torch.zeros_like(rig.node_dq)
             self.bones_grad = torch.zeros_like(rig.bones)
         self.ray_range = ray_range
+        assert deform is None or rig is not None, "the deformation network needs the warp"
+        self.deform = deform
 
     def c(self, n_rays):
         f = L.Field()
@@ -66,6 +98,8 @@ class Field:
             f.warp = self.warp
             f.rig = self.rig.c()
             f.node_dq_grad, f.bones_grad = p(self.node_dq_grad), p(self.bones_grad)
+        if self.deform is not None:
+            f.deform = C.pointer(self.deform.c())
         return f
 
 

@@ -36,7 +36,7 @@ __all__ = [
     "sphere_rays", "noise_occupancy", "occupancy_from_points", "pack_bits",
     "uniform_table", "xavier_params", "smooth_colour_targets", "uniform_targets",
     "human_rig", "object_points", "keyframe_scene", "human_workload", "two_field_workload",
-    "keyframe_workload",
+    "keyframe_workload", "deform_inputs", "DEFORM_SHAPES",
 ]
 
 
@@ -213,6 +213,11 @@ def uniform_table(n_entries: int, n_features: int, rng, lo=-0.1, hi=0.1):
     return rng.uniform(lo, hi, size=(n_entries, n_features)).astype(np.float32)
 
 
+# layer shapes (out, in) of the deformation network: [32-wide encoding, 72-wide
+# pose] -> 4 x 128 -> 3
+DEFORM_SHAPES = ((128, 104), (128, 128), (128, 128), (128, 128), (3, 128))
+
+
 def xavier_params(shapes, rng):
     """Xavier-uniform U[-a, a], a = sqrt(6/(fan_in+fan_out)), for each (out,in)
     layer; concatenated row-major into one float32 vector."""
@@ -226,6 +231,20 @@ def xavier_params(shapes, rng):
 # ----------------------------------------------------------------------------
 # targets
 # ----------------------------------------------------------------------------
+def deform_inputs(n_entries: int, rng, pose_scale=0.3, out_scale=0.05):
+    """Inputs of a deformation network (Sec. 4.2; widths in Sec. 4.3): pose
+    theta (72, normal with std pose_scale), its 2-feature table (uniform_table)
+    and Xavier weights for DEFORM_SHAPES with the output layer scaled by
+    out_scale, so the residual starts at about a centimetre.  Returns (theta,
+    table, params), float32."""
+    theta = rng.normal(scale=pose_scale, size=72).astype(np.float32)
+    table = uniform_table(n_entries, 2, rng)
+    params = xavier_params(DEFORM_SHAPES, rng)
+    n_out = DEFORM_SHAPES[-1][0] * DEFORM_SHAPES[-1][1]
+    params[-n_out:] *= np.float32(out_scale)
+    return theta, table, params
+
+
 def uniform_targets(n: int, rng):
     return rng.uniform(0.0, 1.0, size=(n, 3)).astype(np.float32)
 

@@ -61,23 +61,32 @@ def field_inputs(k, n_rays, seed_offset=0, occ_res=None):
                 lay=lay, rng=rng)
 
 
-def decided_rays(work, fcfg, rig, o, d, occ_words, grid_box, margin, want, ray_lo=0):
+def decided_rays(work, fcfg, rig, o, d, occ_words, grid_box, margin, want, ray_lo=0,
+                 deform=None):
     """Indices (first ``want``) of the rays all of whose kept samples land,
     under the oracle's float64 warp, at least ``margin`` metres from every cell
     face of every level of the field's encoding.  On such rays the float32
     canonical positions of the GPU warp (a few 1e-7 m away) pick the same cells,
     so the encoding's position gradient (discontinuous across faces) is the
-    same function on both sides.  Only synth inputs and oracle arithmetic are
-    used to choose them."""
-    from oracle import march as omarch, warp as owarp
+    same function on both sides.  With ``deform`` = (layout, theta, table,
+    params) of a deformation network, the warped points must also keep the
+    margin on its encoding's ladder, and the deformed points on the field's.
+    Only synth inputs and oracle arithmetic are used to choose them."""
+    from oracle import deform as odef, march as omarch, warp as owarp
     m = omarch.march(o, d, fcfg.aabb_min, fcfg.aabb_max, work.near, work.far,
                      omarch.step_size(work, fcfg), work.max_steps, occ_words, fcfg.occ_res)
     xc = owarp.warp(m["x"], rig, grid_box[0], grid_box[1])
     lay = ogrid.Layout.from_field(fcfg)
+    checks = [(xc, lay)]
+    if deform is not None:
+        dlay, theta, table, params = deform
+        xd, _ = odef.forward(params, xc, theta, table, dlay)
+        checks = [(xc, dlay), (xd, lay)]
     ok = np.ones(xc.shape[0], bool)
-    for N in lay.res:
-        u = np.clip((xc - lay.lo) / lay.side, 0.0, 1.0) * N
-        ok &= (np.abs(u - np.round(u)) * lay.side / N >= margin).all(axis=1)
+    for pts, ly in checks:
+        for N in ly.res:
+            u = np.clip((pts - ly.lo) / ly.side, 0.0, 1.0) * N
+            ok &= (np.abs(u - np.round(u)) * ly.side / N >= margin).all(axis=1)
     bad = np.bincount(m["ray"], weights=(~ok).astype(np.float64), minlength=o.shape[0])
     good = np.nonzero((bad == 0) & (m["count"] > 0))[0]
     assert good.size >= want, f"only {good.size} decided rays"

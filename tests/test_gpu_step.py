@@ -246,8 +246,8 @@ def test_full_size_sampled_parity():
     np.testing.assert_allclose(host(Dg)[pick], ref["D"], rtol=0, atol=2e-2)
 
 
-def _human(n_rays, knn_res=32, n_nodes=512, seed=0):
-    f = synth.FieldCfg(occ_res=64)
+def _human(n_rays, knn_res=32, n_nodes=512, seed=0, res_max=2048):
+    f = synth.FieldCfg(occ_res=64, res_max=res_max)
     w = synth.WorkCfg("h", n_rays, (f,), warp=True)
     rng = synth.rng_for(500 + seed)
     rig = synth.human_rig(rng, n_nodes=n_nodes, knn_res=knn_res)
@@ -410,3 +410,128 @@ def test_render_fp32_early_termination():
     rC, rD = ostep.render(w, st, I["o"], I["d"], [(0, w.n_rays)], t_stop=1e-4)
     np.testing.assert_allclose(host(rgb), rC, rtol=0, atol=1e-4)
     tr.close()
+
+
+# ----------------------------------------------------- deformation network
+_DEFORM_GRID = (16, 2, 14, 16, 512, (-1.0,) * 3, (1.0,) * 3)   # levels, F, log2 T, res, box
+
+
+def _deform_inputs(seed):
+    lay = ogrid.Layout(*_DEFORM_GRID)
+    theta, table, params = synth.deform_inputs(lay.n_entries, synth.rng_for(900 + seed))
+    return lay, theta, table, params
+
+
+def _decided_human_deform(n_rays, seed=0, margin=5e-6):
+    # the human field on a 16 -> 512 ladder, its deformation network on its
+    # own 16 -> 512 grid; rays decided on both encodings
+    w, f, rig, o, d, occ, table, params, Ct = _human(16 * n_rays, seed=seed, res_max=512)
+    box = ((-1.0,) * 3, (1.0,) * 3)
+    dfm = _deform_inputs(seed)
+    pick = decided_rays(w, f, rig, o, d, occ, box, margin, n_rays, deform=dfm)
+    w = synth.WorkCfg(w.name, n_rays, w.fields, warp=True)
+    return w, f, rig, o[pick], d[pick], occ, table, params, Ct[pick], box, dfm
+
+
+def _deform_field(F, O, w, f, table, params, occ, rig, dfm):
+    lay, theta, dtab, dpar = dfm
+    D = F.Deform(O.grid_desc(*_DEFORM_GRID), theta, dtab, dpar)
+    R = O.Rig.from_numpy(rig)
+    wd = O.warp_desc(n_nodes=512, lut_res=32)
+    return F.Field(w, f, table, params, occ_words=occ, rig=R, warp_desc=wd, deform=D)
+
+
+def _deform_grads(fld):
+    D = fld.deform
+    return dict(params=host(fld.params_grad), table=host(fld.table_grad),
+                node_dq=host(fld.node_dq_grad), bones=host(fld.bones_grad),
+                deform_params=host(D.params_grad), deform_table=host(D.table_grad),
+                theta=host(D.theta_grad))
+
+
+def test_cfg3_warp_deform_fp32_step():
+    # warp -> deformation network -> field (Sec. 4.2), float32 kernels, every
+    # gradient of the step against the FP64 oracle
+    L, F, O = lib()
+    w, f, rig, o, d, occ, table, params, Ct, box, dfm = _decided_human_deform(300)
+    fld = _deform_field(F, O, w, f, table, params, occ, rig, dfm)
+    tr, loss, Cg, Dg = run_step([fld], w.n_rays, w.n_rays * 128, o, d, Ct)
+
+    def oracle():
+        lay, theta, dtab, dpar = dfm
+        st = ostep.StepState([ostep.FieldState(f, table, params, occ_words=occ, rig=rig,
+                                               deform=ostep.DeformState(lay, theta, dtab,
+                                                                        dpar))])
+        return ostep.train_step(w, st, o, d, Ct, None, [(0, w.n_rays)], box, apply=False)
+
+    ref = oracle()
+    pert = _position_sensitivity(oracle)
+    g, gp = ref["grads"][0], pert["grads"][0]
+    got = _deform_grads(fld)
+    errs = {k: rel_err(v, g[k].reshape(v.shape)) for k, v in got.items()}
+    sens = {k: rel_err(gp[k], g[k]) for k in got}
+    err = np.abs(Cg - ref["C"]).max()
+    print(f"warp + deformation step: colour max abs err {err:.3e}, gradients {errs}, "
+          f"oracle sensitivity {sens}")
+    assert err < 1e-5
+    assert abs(loss - ref["loss"]) < 1e-5 * ref["loss"]
+    for k, e in errs.items():
+        assert e < max(1e-4, 4 * sens[k]), k
+    tr.close()
+
+
+def test_cfg3_warp_deform_bf16_step():
+    # the matrix-core deformation kernels inside the fused BF16 step against the
+    # oracle on the fp16 / bf16 copies of the field: colour 2e-2 absolute, the
+    # field's and the warp's gradients 5e-2 relative.  The network's own
+    # gradients (weights, table, pose) sit behind two low-precision stages in
+    # series -- their input, the encoding's position gradient, carries the
+    # BF16 step's 5e-2, and the network's bf16 backward alone carries up to
+    # 5e-2 (its large-batch test) -- so their bar is the sum, 1e-1.
+    L, F, O = lib()
+    w, f, rig, o, d, occ, table, params, Ct, box, dfm = _decided_human_deform(300, seed=1)
+    fld = _deform_field(F, O, w, f, table, params, occ, rig, dfm)
+    tr, loss, Cg, Dg = run_step([fld], w.n_rays, w.n_rays * 128, o, d, Ct, precision=L.NVR_BF16)
+    lay, theta, dtab, dpar = dfm
+    st = ostep.StepState([ostep.FieldState(f, f16_round(table), bf16_round(params),
+                                           occ_words=occ, rig=rig,
+                                           deform=ostep.DeformState(lay, theta, dtab, dpar))])
+    ref = ostep.train_step(w, st, o, d, Ct, None, [(0, w.n_rays)], box, apply=False)
+    g = ref["grads"][0]
+    got = _deform_grads(fld)
+    errs = {k: rel_err(v, g[k].reshape(v.shape)) for k, v in got.items()}
+    err = np.abs(Cg - ref["C"]).max()
+    print(f"bf16 warp + deformation step: colour max abs err {err:.3e}, gradients {errs}")
+    assert err < 2e-2
+    assert abs(loss - ref["loss"]) < 2e-2 * ref["loss"]
+    for k, e in errs.items():
+        assert e < (1e-1 if k in ("deform_params", "deform_table", "theta") else 5e-2), k
+    tr.close()
+
+
+def test_deform_step_deterministic_and_graph():
+    # NVR_DETERMINISTIC with the deformation network: three BF16 steps eagerly,
+    # again in a new context, and as replays of a captured graph give
+    # bit-identical losses and trained state (field and network)
+    L, F, O = lib()
+    w, f, rig, o, d, occ, table, params, Ct = _human(400, seed=2, res_max=512)
+    dfm = _deform_inputs(2)
+    outs = []
+    for graph in (False, False, True):
+        fld = _deform_field(F, O, w, f, table, params, occ, rig, dfm)
+        tr = F.Trainer([fld], w.n_rays, w.n_rays * 128, precision=L.NVR_BF16, use_graph=graph,
+                       deterministic=True)
+        tr.set_batch(dev(o), dev(d), dev(Ct))
+        ls = []
+        for _ in range(3):
+            ls.append(host(tr.step()).copy())        # eager sync between replays
+        torch.cuda.synchronize()
+        D = fld.deform
+        outs.append([np.concatenate(ls), host(fld.params), host(fld.table), host(D.params),
+                     host(D.table), host(D.params_m), host(D.table_v)])
+        tr.close()
+    assert np.abs(outs[0][3] - dfm[3]).max() > 0       # the network was trained
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(np.ascontiguousarray(a).view(np.uint32),
+                                  np.ascontiguousarray(b).view(np.uint32))
