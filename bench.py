@@ -598,13 +598,14 @@ def _timed(torch, tr, steps, warmup):
 
 
 def _deform_state(fl):
-    """The oracle's copy of a field's deformation network (fp32 masters)."""
+    """The oracle's copy of a field's deformation network (the fp16 table copy
+    the matrix-core kernels read, fp32 weights)."""
     from oracle import grid as ogrid, step as ostep
     D = fl.deform
     if D is None:
         return None
     return ostep.DeformState(ogrid.Layout.from_field(fl.fcfg), D.theta.cpu().numpy(),
-                             D.table.cpu().numpy(), D.params.cpu().numpy())
+                             D.table_half.float().cpu().numpy(), D.params.cpu().numpy())
 
 
 def _sampled_colour_error(torch, tr, flds, w, o, d, ranges, pick, box=None):

@@ -378,17 +378,20 @@ typedef struct nvr_ctx nvr_ctx;
 /* Residual deformation network of a warped field in the step (Sec. 4.2,
  * hybrid deformation): the warped sample x_t moves to
  * x_c = x_t + MLP([enc_d(x_t), theta]) before the field's encoding, with the
- * network of nvr_deform_fwd (its own 32-wide grid, 104 -> 4 x 128 -> 3).
- * NVR_F32 steps run its float32 kernels, NVR_BF16 steps its matrix-core
- * kernels (math = NVR_F16 of nvr_deform_fwd); the backward chains the field
- * encoding's position gradient through it into the warp.  Its table and
- * parameters are trained with the field (same Adam, tables skip zero-gradient
- * entries, fp32 masters only); the pose's gradient is left scaled by the loss
- * scale, like the node and bone gradients.  Host struct, device arrays. */
+ * network of nvr_deform_fwd (its own 16-level grid, 104 -> 4 x 128 -> 3).
+ * NVR_F32 steps run its float32 kernels on the fp32 table, NVR_BF16 steps its
+ * matrix-core kernels on the fp16 table copy (as the field's own encoding);
+ * the backward chains the field encoding's position gradient through it into
+ * the warp.  Its table and parameters are trained with the field (same Adam,
+ * tables skip zero-gradient entries); the pose's gradient is left scaled by
+ * the loss scale, like the node and bone gradients.  Host struct, device
+ * arrays. */
 typedef struct {
     nvr_grid_desc grid;          /* its encoding: levels x features = 32 */
     const float *theta;          /* [72] pose of the batch's frame */
     float *table;                /* [n_entries][2] fp32 */
+    void *table_half;            /* [n_entries][2] float16 copy, 16-byte aligned (NVR_BF16;
+                                    the step's Adam keeps it current) */
     float *params;               /* nvr_deform_param_count() fp32 */
     float *table_grad, *params_grad;          /* zero on entry, zeroed by the step */
     float *table_m, *table_v, *params_m, *params_v;
@@ -555,27 +558,31 @@ nvr_status nvr_live_lut(const nvr_lut_desc *d, const uint16_t *knn, const float 
 /* ------------------------------------------------------------------------
  * Pose-conditioned deformation network (Sec. 4.2, hybrid deformation; widths
  * in Sec. 4.3): x_can = x + MLP([enc(x), theta]) with enc a multiresolution
- * hash encoding of its own (grid `g`, 32 wide: levels x features = 32, fp32
- * table) and theta one 72-wide pose for all points; 104 -> 128 -> 128 -> 128
+ * hash encoding of its own (grid `g`, 16 levels x 2 features, fp32 table) and
+ * theta one 72-wide pose for all points; 104 -> 128 -> 128 -> 128
  * -> 128 -> 3, bias-free, ReLU on the hidden layers, linear output.
- * math = NVR_F32: float32 throughout (each layer one rocBLAS sgemm, the plain
- * reference path).  math = NVR_F16: the hand-written matrix-core kernels --
- * fp16 encoding, weights and activations in the forward, bf16 products in the
- * backward, fp32 accumulation; the pose enters as the first layer's bias
- * W0[:, 32:] theta, weight gradients are contracted over the points in fixed
- * order.  params: nvr_deform_param_count() floats (fp32 masters), each layer's
- * W[out][in] row-major in order.  x [n][3], theta [72], table [n_entries][2],
- * x_can [n][3]: device.  workspace: device, 256-byte aligned,
- * nvr_deform_workspace(g, n) bytes (about 4 KB per point, enough for both
- * paths), overwritten.
+ * math = NVR_F32: float32 throughout (each layer one tiled product over the
+ * points, weight gradients summed over point chunks in a fixed order; the
+ * plain reference path).  math = NVR_F16: the hand-written matrix-core
+ * kernels -- the encoding gathered from an fp16 copy of the table (formed in
+ * the workspace each call), fp16 weights and activations in the forward, bf16
+ * products in the backward, fp32 accumulation; the pose enters as the first
+ * layer's bias W0[:, 32:] theta, weight gradients are contracted over the
+ * points in fixed order.  params: nvr_deform_param_count() floats (fp32
+ * masters), each layer's W[out][in] row-major in order.  x [n][3], theta [72],
+ * table [n_entries][2], x_can [n][3]: device.  workspace: device, 256-byte
+ * aligned, nvr_deform_workspace(g, n) bytes (about 4 KB per point, enough for
+ * both paths), overwritten.
  * nvr_deform_bwd recomputes the forward and, for the gradient dx_can [n][3] of
  * the output, accumulates dparams (acc), dtable (acc, 8-byte aligned; formed
  * by the binned scatter of nvr_encode_bwd_binned, same rounding), dx (acc,
- * nullable: through the encoding plus the identity of the residual) and
- * dtheta [72] (acc, nullable, summed over the points).  Errors: NVR_EINVAL for
- * n outside 0..2^24, NULL arrays or workspace; NVR_EUNSUPPORTED for an
- * encoding not 32 wide or a ladder the binned scatter does not take, math
- * other than F32 / F16 (NVR_EINVAL); NVR_EHIP when a rocBLAS call fails. */
+ * nullable: through the encoding -- on the F16 path from the fp16 table copy,
+ * as the binned scatter forms it -- plus the identity of the residual) and
+ * dtheta [72] (acc, nullable, summed over the points in a fixed order).
+ * Errors: NVR_EINVAL for n outside 0..2^24, NULL arrays or workspace;
+ * NVR_EUNSUPPORTED for an encoding other than 16 levels x 2 features or a
+ * ladder the binned scatter does not take, math other than F32 / F16
+ * (NVR_EINVAL).  Every check runs before the first launch. */
 size_t nvr_deform_workspace(const nvr_grid_desc *g, int64_t n);
 int64_t nvr_deform_param_count(void);
 nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const float *x, const float *theta,

@@ -76,7 +76,7 @@ class AdamDesc(C.Structure):
 
 
 class DeformState(C.Structure):
-    _fields_ = [("grid", GridDesc), ("theta", vp), ("table", vp), ("params", vp),
+    _fields_ = [("grid", GridDesc), ("theta", vp), ("table", vp), ("table_half", vp), ("params", vp),
                 ("table_grad", vp), ("params_grad", vp), ("table_m", vp), ("table_v", vp),
                 ("params_m", vp), ("params_v", vp), ("theta_grad", vp)]
 

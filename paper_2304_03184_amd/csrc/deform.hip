@@ -41,17 +41,26 @@ size_t round_up(size_t b) { return (b + 255) / 256 * 256; }
 
 // Workspace of the matrix-core path (carved like the float32 one).
 struct DeformMfmaWs {
-    uint16_t *feat;      // [n][32] fp16 encoding
+    uint16_t *feat;      // [8][n][4] fp16 encoding, level-group layout of the split gather
     float *bias;         // [128] pose term
     uint4 *fwd, *bwd;    // weight fragments
     uint16_t *hbuf, *zbuf;
-    float *dfeat;        // [n][32]
+    float *dfeat;        // [8][n][4] encoding gradient, same layout
+    float *dx_parts;     // [8][n][3] position-gradient partials of the level groups
     float *partial;      // [kDwGrid][128][144] weight-gradient partials
-    void *binned;
+    uint32_t *half;      // fp16 copy of the table (public entry points)
+    void *binned;        // binned table-gradient scatter
 };
 constexpr int kDwGrid = 256;
 
 size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, DeformMfmaWs *w);
+
+// Matrix-core path: the encoding slot j of lane group g reads level-group
+// planes 2g and 2g+1 (levels 2g, 2g+8, then 2g+1, 2g+9, two features each),
+// which is feature dfp(g, j) of the standard [level][feature] order.
+__host__ __device__ __forceinline__ int dfp(int g, int j) {
+    return 4 * g + (j & 1) + ((j >> 1) & 1) * 16 + (j >> 2) * 2;
+}
 
 // point chunks of the float32 weight gradients at capacity cap
 int mm_parts(int64_t cap) {
@@ -361,8 +370,8 @@ __host__ __device__ const float *layer_w(const float *params, int i) {
 nvr_status check_desc(const nvr_grid_desc *g, int64_t n) {
     NVR_REQUIRE(g != nullptr, NVR_EINVAL, "grid descriptor is NULL");
     NVR_TRY(check_grid(g));
-    NVR_REQUIRE(g->n_levels * g->n_features == kFeat, NVR_EUNSUPPORTED,
-                "the deformation encoding must be 32 wide (levels x features)");
+    NVR_REQUIRE(g->n_levels == 16 && g->n_features == 2, NVR_EUNSUPPORTED,
+                "the deformation encoding must be 16 levels x 2 features");
     NVR_REQUIRE(n >= 0 && n <= (1ll << 31) / kWidth, NVR_EINVAL, "n out of 0..2^24");
     const GridParams p = make_grid_params(g);
     NVR_TRY(scatter_check(p));
@@ -455,7 +464,7 @@ dn_frags(const float *__restrict__ params, uint4 *__restrict__ fwd, uint4 *__res
         dh8 v;
         if (e < kFw1) {                                     // W0 feature part
             const int m = t;
-            for (int j = 0; j < 8; ++j) v[j] = (_Float16)W(0, 16 * m + r, 8 * g + j);
+            for (int j = 0; j < 8; ++j) v[j] = (_Float16)W(0, 16 * m + r, dfp(g, j));
         } else if (e < kFw4) {
             const int u = t - kFw1 / 64, layer = 1 + u / 32, m = (u % 32) / 4, q = u % 4;
             for (int j = 0; j < 8; ++j) v[j] = (_Float16)W(layer, 16 * m + r, dkh(q, g, j));
@@ -540,8 +549,18 @@ __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
     s.out = o;
 }
 
+// The 8 fp16 encoding values of lane group g for point p (zero past n), from
+// the level-group planes of stride cap.
+__device__ __forceinline__ dh8 dn_load_feat(const uint16_t *__restrict__ feat, int64_t cap,
+                                            int64_t p, int g, bool valid) {
+    if (!valid) return dh8{};
+    const uint2 a = *reinterpret_cast<const uint2 *>(feat + ((int64_t)(2 * g) * cap + p) * 4);
+    const uint2 b = *reinterpret_cast<const uint2 *>(feat + ((int64_t)(2 * g + 1) * cap + p) * 4);
+    return __builtin_bit_cast(dh8, uint4{a.x, a.y, b.x, b.y});
+}
+
 // Forward: x_can = x + W4 relu(W3 relu(W2 relu(W1 relu(W0f feat + bias)))).
-// feat: fp16 encoding [n][32]; bias: the pose term [128].
+// feat: fp16 encoding, level-group planes [8][cap][4]; bias: the pose term [128].
 __global__ void __launch_bounds__(kDnBlock)
 dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
             const uint16_t *__restrict__ feat, const float *__restrict__ bias,
@@ -561,8 +580,7 @@ dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
         asm volatile("" ::: "memory");
         const int64_t p = blk * 16 + c;
         const bool valid = p < n;
-        dh8 x0 = {};
-        if (valid) x0 = __builtin_bit_cast(dh8, *reinterpret_cast<const uint4 *>(feat + p * kFeat + 8 * g));
+        const dh8 x0 = dn_load_feat(feat, cap, p, g, valid);
         DnFwd s;
         dn_block_fwd(F + lane, bias4, x0, s);
         if (g == 0 && valid) {
@@ -608,16 +626,15 @@ dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
         asm volatile("" : "+v"(Fb));
         const int64_t p = blk * 16 + c;
         const bool valid = p < n;
-        dh8 x0 = {};
-        if (valid) x0 = __builtin_bit_cast(dh8, *reinterpret_cast<const uint4 *>(feat + p * kFeat + 8 * g));
+        const dh8 x0 = dn_load_feat(feat, cap, p, g, valid);
         DnFwd s;
         dn_block_fwd(Fb, bias4, x0, s);
         uint16_t *H = hbuf + blk * (int64_t)kHUnits * 16;
         uint16_t *Z = zbuf + blk * (int64_t)kZUnits * 16;
-        // activations: encoding (slot j = feature 8g + j), hidden layers (slot
-        // j of K-step q = unit dkh(q, g, j)); zero for points past n
+        // activations: encoding (slot j = feature dfp(g, j)), hidden layers
+        // (slot j of K-step q = unit dkh(q, g, j)); zero for points past n
 #pragma unroll
-        for (int j = 0; j < 8; ++j) H[(8 * g + j) * 16 + c] = bfbits((float)x0[j]);
+        for (int j = 0; j < 8; ++j) H[dfp(g, j) * 16 + c] = bfbits((float)x0[j]);
 #pragma unroll
         for (int l = 0; l < 4; ++l)
 #pragma unroll
@@ -671,14 +688,21 @@ dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
                 }
             }
         }
-        // encoding gradient: dfeat = W0f^T dZ0, rows = features 16m + 4g + i
+        // encoding gradient: dfeat = W0f^T dZ0, rows = features 16m + 4g + i,
+        // that is levels 8m + 2g (i = 0, 1) and 8m + 2g + 1 (i = 2, 3): planes
+        // 2g and 2g+1, slots 2m and 2m+1
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             df4 a = dzero();
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 a = dmfma(__builtin_bit_cast(dbf8, Bl[kBw0 + (m * 4 + q) * 64]), zb[q], a);
-            if (valid) *reinterpret_cast<df4 *>(dfeat + p * kFeat + 16 * m + 4 * g) = a;
+            if (valid) {
+                *reinterpret_cast<float2 *>(dfeat + ((int64_t)(2 * g) * cap + p) * 4 + 2 * m) =
+                    float2{a[0], a[1]};
+                *reinterpret_cast<float2 *>(dfeat + ((int64_t)(2 * g + 1) * cap + p) * 4 + 2 * m) =
+                    float2{a[2], a[3]};
+            }
         }
     }
 }
@@ -794,6 +818,7 @@ size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, Defor
     };
     const int64_t nblk = (n + 15) / 16 + 1;   // one spare block: K-steps pair blocks
     DeformMfmaWs t;
+    const GridParams gp = make_grid_params(g);
     t.feat = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)n * kFeat));
     t.bias = reinterpret_cast<float *>(take(sizeof(float) * kWidth));
     t.fwd = reinterpret_cast<uint4 *>(take(sizeof(uint4) * kFwd));
@@ -801,8 +826,10 @@ size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, Defor
     t.hbuf = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)nblk * kHUnits * 16));
     t.zbuf = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)nblk * kZUnits * 16));
     t.dfeat = reinterpret_cast<float *>(take(sizeof(float) * (size_t)n * kFeat));
+    t.dx_parts = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kXcds * n * 3));
     t.partial = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kDwGrid * kWidth * 144));
-    t.binned = take(scatter_rows_ws_bytes(make_grid_params(g), n, det));
+    t.half = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (size_t)gp.off[gp.L]));
+    t.binned = take(det ? scatter_det_ws_bytes(gp, n) : scatter_ws_bytes(gp, n));
     if (w) *w = t;
     return off;
 }
@@ -824,13 +851,45 @@ nvr_status dn_lds_opt_in() {
     return NVR_OK;
 }
 
-// encoding (fp16 features from the fp32 table), fragments and pose bias; the
-// point count is n, or *n_dev (at most cap) when n_dev is given
+// fp16 copy of an fp32 table (the public entry points' matrix-core path)
+__global__ void __launch_bounds__(256)
+dn_to_half(int64_t m, const float2 *__restrict__ t, uint32_t *__restrict__ h) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float2 v = t[i];
+        h[i] = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v.x) |
+               ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v.y) << 16);
+    }
+}
+
+// dx[i] += dx_can[i] + the eight level groups' partials, i < 3 count: the
+// position gradient through the encoding plus the residual's identity
+__global__ void __launch_bounds__(256)
+dn_dx_total(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+            const float *__restrict__ parts, const float *__restrict__ dx_can,
+            float *__restrict__ dx) {
+    const int64_t m = 3 * count_of(n, n_dev, cap);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float a = dx_can[i];
+#pragma unroll
+        for (int g = 0; g < kXcds; ++g) a += parts[(int64_t)g * 3 * cap + i];
+        dx[i] += a;
+    }
+}
+
+// Encoding (split gather of the fp16 table into level-group planes, with the
+// scatter's tile counts when `counter` is given; skipped when the features
+// are already in the workspace), fragments and pose bias.  The point count is
+// n, or *n_dev (at most cap) when n_dev is given.
 nvr_status mfma_prologue(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
-                         const float *x, const float *theta, const float *table,
-                         const float *params, const DeformMfmaWs &w, hipStream_t st) {
+                         const float *x, const float *theta, const void *table_half,
+                         const float *params, const DeformMfmaWs &w, bool encode,
+                         const TileCounter *counter, hipStream_t st) {
     NVR_TRY(dn_lds_opt_in());
-    NVR_TRY(launch_encode_fwd(gp, n, n_dev, cap, x, table, NVR_F32, w.feat, NVR_F16, false, st));
+    if (encode)
+        NVR_TRY(launch_encode_fwd(gp, n, n_dev, cap, x, table_half, NVR_F16, w.feat, NVR_F16,
+                                  true, st, counter));
     dn_frags<<<(kFwd + kBw4 + 8 * 64 + 255) / 256, 256, 0, st>>>(params, w.fwd, w.bwd);
     NVR_LAUNCHED();
     dn_pose_bias<<<1, kWidth, 0, st>>>(params, theta, w.bias);
@@ -844,11 +903,19 @@ unsigned dn_grid(int64_t cap) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg, kCus));
 }
 
+// count: form the binned scatter's tile counts during the encoding (for a
+// backward that follows with counted = true)
 nvr_status mfma_forward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
-                        const float *x, const float *theta, const float *table,
-                        const float *params, float *x_can, const DeformMfmaWs &w,
+                        const float *x, const float *theta, const void *table_half,
+                        const float *params, float *x_can, const DeformMfmaWs &w, bool count,
                         hipStream_t st) {
-    NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table, params, w, st));
+    TileCounter counter{};
+    if (count) {
+        counter = scatter_counter(gp, w.binned);
+        NVR_TRY(launch_counter_reset(gp, w.binned, st));
+    }
+    NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table_half, params, w, true,
+                          count ? &counter : nullptr, st));
     dn_fwd_mfma<<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(n, n_dev, cap, w.feat,
                                                                      w.bias, w.fwd, x, x_can);
     NVR_LAUNCHED();
@@ -877,14 +944,18 @@ nvr_status mfma_dw(int64_t n, const int32_t *n_dev, int64_t cap, const DeformMfm
 }
 
 // Matrix-core backward: recompute + chain per block, weight gradients over
-// the points, pose terms, then the encoding's table and position gradients
-// (dx acc, nullable; it also receives dx_can, the residual's identity).
+// the points, pose terms, then the encoding's table gradient (binned scatter
+// of the fp16-table encoding; deterministic variant when det) and, when dx is
+// given, its position gradient plus the residual's identity.  features_ready:
+// the forward's encoding is still in the workspace (and, with counted, so are
+// its tile counts).
 nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
-                         const float *x, const float *theta, const float *table,
+                         const float *x, const float *theta, const void *table_half,
                          const float *params, const float *dx_can, float *dparams, float *dtable,
-                         float *dx, float *dtheta, bool det, const DeformMfmaWs &w,
-                         hipStream_t st) {
-    NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table, params, w, st));
+                         float *dx, float *dtheta, bool features_ready, bool counted, bool det,
+                         const DeformMfmaWs &w, hipStream_t st) {
+    NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table_half, params, w, !features_ready,
+                          nullptr, st));
     dn_bwd_mfma<<<dn_grid(cap), kDnBlock, sizeof(uint4) * kBwd, st>>>(
         n, n_dev, cap, w.feat, w.bias, w.fwd, w.bwd, dx_can, w.dfeat, w.hbuf, w.zbuf);
     NVR_LAUNCHED();
@@ -902,12 +973,16 @@ nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, 
     dn_pose_grad<<<1, kWidth, 0, st>>>(dw_parts(cap), 16 * 3, 16 * 2, w.partial, params, theta,
                                        dparams, dtheta);
     NVR_LAUNCHED();
-    NVR_TRY(launch_scatter_rows(gp, n, n_dev, cap, x, w.dfeat, dtable, w.binned, st, det));
+    float *parts = dx ? w.dx_parts : nullptr;
+    if (det)
+        NVR_TRY(launch_scatter_det(gp, n, n_dev, cap, x, table_half, w.dfeat, dtable, parts,
+                                   w.binned, st));
+    else
+        NVR_TRY(launch_scatter(gp, n, n_dev, cap, x, table_half, w.dfeat, dtable, parts, w.binned,
+                               st, counted && features_ready, 1024, 512));
     if (dx) {
-        dn_encode_dx<<<grid_for(cap, 256, 16384), 256, 0, st>>>(
-            gp, n, n_dev, cap, x, reinterpret_cast<const float2 *>(table), w.dfeat, dx);
-        NVR_LAUNCHED();
-        dn_add<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n * 3, dx, dx_can, n_dev, cap);
+        dn_dx_total<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n, n_dev, cap, w.dx_parts,
+                                                                   dx_can, dx);
         NVR_LAUNCHED();
     }
     return NVR_OK;
@@ -986,33 +1061,52 @@ size_t ws_bytes(const nvr_grid_desc *g, int64_t cap, bool matrix_cores, bool det
                         : carve(g, cap, det, nullptr, nullptr);
 }
 
+// table_half: the fp16 copy of the table, or null to form it in the workspace
+// (matrix-core path only).  count: a training forward, whose tile counts the
+// backward will use (matrix-core path only).
 nvr_status run_fwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const int32_t *n_dev,
                    int64_t cap, const float *x, const float *theta, const float *table,
-                   const float *params, float *x_can, void *ws, hipStream_t st) {
+                   const void *table_half, const float *params, float *x_can, bool count,
+                   bool det, void *ws, hipStream_t st) {
     const GridParams gp = make_grid_params(g);
     if (matrix_cores) {
         DeformMfmaWs w;
-        carve_mfma(g, cap, false, static_cast<char *>(ws), &w);
-        return mfma_forward(gp, n, n_dev, cap, x, theta, table, params, x_can, w, st);
+        carve_mfma(g, cap, det, static_cast<char *>(ws), &w);
+        if (!table_half) {
+            dn_to_half<<<grid_for(gp.off[gp.L], 256, 16384), 256, 0, st>>>(
+                gp.off[gp.L], reinterpret_cast<const float2 *>(table), w.half);
+            NVR_LAUNCHED();
+            table_half = w.half;
+        }
+        return mfma_forward(gp, n, n_dev, cap, x, theta, table_half, params, x_can, w, count, st);
     }
     DeformWs w;
-    carve(g, cap, false, static_cast<char *>(ws), &w);
+    carve(g, cap, det, static_cast<char *>(ws), &w);
     NVR_TRY(f32_forward(gp, n, n_dev, cap, x, theta, table, params, w, st));
     dn_residual<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n, n_dev, cap, x, w.dv, x_can);
     NVR_LAUNCHED();
     return NVR_OK;
 }
 
+// after_fwd: a training forward over the same points ran on this workspace
+// (matrix-core path: its encoding, and unless det its tile counts, are reused)
 nvr_status run_bwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const int32_t *n_dev,
                    int64_t cap, const float *x, const float *theta, const float *table,
-                   const float *params, const float *dx_can, float *dparams, float *dtable,
-                   float *dx, float *dtheta, bool det, void *ws, hipStream_t st) {
+                   const void *table_half, const float *params, const float *dx_can,
+                   float *dparams, float *dtable, float *dx, float *dtheta, bool after_fwd,
+                   bool det, void *ws, hipStream_t st) {
     const GridParams gp = make_grid_params(g);
     if (matrix_cores) {
         DeformMfmaWs w;
         carve_mfma(g, cap, det, static_cast<char *>(ws), &w);
-        return mfma_backward(gp, n, n_dev, cap, x, theta, table, params, dx_can, dparams, dtable,
-                             dx, dtheta, det, w, st);
+        if (!table_half) {
+            dn_to_half<<<grid_for(gp.off[gp.L], 256, 16384), 256, 0, st>>>(
+                gp.off[gp.L], reinterpret_cast<const float2 *>(table), w.half);
+            NVR_LAUNCHED();
+            table_half = w.half;
+        }
+        return mfma_backward(gp, n, n_dev, cap, x, theta, table_half, params, dx_can, dparams,
+                             dtable, dx, dtheta, after_fwd, after_fwd && !det, det, w, st);
     }
     DeformWs w;
     carve(g, cap, det, static_cast<char *>(ws), &w);
@@ -1033,19 +1127,21 @@ size_t deform_ws_bytes(const nvr_grid_desc *g, int64_t cap, bool matrix_cores, b
 
 nvr_status deform_fwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32_t *n_dev,
                           int64_t cap, const float *x, const float *theta, const float *table,
-                          const float *params, float *x_can, void *ws, hipStream_t st) {
+                          const void *table_half, const float *params, float *x_can, bool train,
+                          bool det, void *ws, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
-    return run_fwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, params, x_can, ws, st);
+    return run_fwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, table_half, params, x_can,
+                   train && !det, det, ws, st);
 }
 
 nvr_status deform_bwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32_t *n_dev,
                           int64_t cap, const float *x, const float *theta, const float *table,
-                          const float *params, const float *dx_can, float *dparams,
-                          float *dtable, float *dx, float *dtheta, bool det, void *ws,
-                          hipStream_t st) {
+                          const void *table_half, const float *params, const float *dx_can,
+                          float *dparams, float *dtable, float *dx, float *dtheta, bool det,
+                          void *ws, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
-    return run_bwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, params, dx_can, dparams,
-                   dtable, dx, dtheta, det, ws, st);
+    return run_bwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, table_half, params, dx_can,
+                   dparams, dtable, dx, dtheta, true, det, ws, st);
 }
 
 int64_t deform_param_count() { return kParams; }
@@ -1095,8 +1191,8 @@ extern "C" nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const fl
     NVR_REQUIRE(aligned(x, 4) && aligned(theta, 4) && aligned(table, 8) && aligned(params, 4) &&
                     aligned(x_can, 4),
                 NVR_EINVAL, "misaligned array");
-    return run_fwd(g, math == NVR_F16, n, nullptr, n, x, theta, table, params, x_can, workspace,
-                   hs(stream));
+    return run_fwd(g, math == NVR_F16, n, nullptr, n, x, theta, table, nullptr, params, x_can,
+                   false, false, workspace, hs(stream));
 }
 
 extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
@@ -1114,6 +1210,6 @@ extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const fl
                     aligned(dx_can, 4) && aligned(dparams, 4) && aligned(dtable, 8) &&
                     aligned(dx, 4) && aligned(dtheta, 4),
                 NVR_EINVAL, "misaligned array");
-    return run_bwd(g, math == NVR_F16, n, nullptr, n, x, theta, table, params, dx_can, dparams,
-                   dtable, dx, dtheta, false, workspace, hs(stream));
+    return run_bwd(g, math == NVR_F16, n, nullptr, n, x, theta, table, nullptr, params, dx_can,
+                   dparams, dtable, dx, dtheta, false, false, workspace, hs(stream));
 }

@@ -88,6 +88,8 @@ static nvr_status field_check(const nvr_field *f, const nvr_step_desc *s, Net *n
         NVR_TRY(deform_check(&D->grid, s->max_samples));
         NVR_REQUIRE(D->theta && D->table && D->params, NVR_EINVAL,
                     "NULL deformation pose, table or parameters");
+        NVR_REQUIRE(s->precision != NVR_BF16 || (D->table_half && aligned(D->table_half, 16)),
+                    NVR_EINVAL, "NULL or misaligned fp16 deformation table copy");
         NVR_REQUIRE(aligned(D->table, 8) && aligned(D->theta, 4) && aligned(D->params, 4),
                     NVR_EINVAL, "misaligned deformation arrays");
     }
@@ -226,7 +228,8 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
     if (f->deform) {
         const nvr_deform_state *D = f->deform;
         NVR_TRY(deform_fwd_dev(&D->grid, precision == NVR_BF16, w.n_dev, cap, w.xc, D->theta,
-                               D->table, D->params, w.xd, w.deform_ws, st));
+                               D->table, D->table_half, D->params, w.xd, train,
+                               deterministic(ctx), w.deform_ws, st));
         pos = w.xd;
     }
     const GridParams gp = make_grid_params(&f->grid);
@@ -310,8 +313,9 @@ static nvr_status warp_chain_bwd(nvr_ctx *ctx, const nvr_field *f, FieldWs &w, i
     }
     NVR_TRY(launch_fill_zero(w.dxt, 3 * cap, st));
     NVR_TRY(deform_bwd_dev(&D->grid, w.precision == NVR_BF16, w.n_dev, cap, w.xc, D->theta,
-                           D->table, D->params, dxd, D->params_grad, D->table_grad, w.dxt,
-                           D->theta_grad, deterministic(ctx), w.deform_ws, st));
+                           D->table, D->table_half, D->params, dxd, D->params_grad,
+                           D->table_grad, w.dxt, D->theta_grad, deterministic(ctx), w.deform_ws,
+                           st));
     return run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dxt, 1, 3 * cap, f->node_dq_grad,
                         f->bones_grad, st);
 }
@@ -371,7 +375,8 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                             f->params_grad, 0, state, bf ? f->params_bf16 : nullptr, NVR_BF16, st));
         if (const nvr_deform_state *D = f->deform) {
             NVR_TRY(launch_adam(ap, D->grid.offset[D->grid.n_levels] * 2, D->table, D->table_m,
-                                D->table_v, D->table_grad, 1, state, nullptr, NVR_F16, st));
+                                D->table_v, D->table_grad, 1, state,
+                                bf ? D->table_half : nullptr, NVR_F16, st));
             NVR_TRY(launch_adam(ap, deform_param_count(), D->params, D->params_m, D->params_v,
                                 D->params_grad, 0, state, nullptr, NVR_BF16, st));
         }

@@ -26,6 +26,7 @@ class Deform:
         n_e = grid.n_entries
         self.theta = torch.as_tensor(np.asarray(theta, np.float32)).reshape(72).to(device)
         self.table = torch.as_tensor(np.asarray(table, np.float32)).reshape(n_e, 2).to(device)
+        self.table_half = self.table.to(torch.float16)
         self.params = torch.as_tensor(np.asarray(params, np.float32)).reshape(-1).to(device)
         assert self.params.numel() == L.lib().nvr_deform_param_count()
         self.table_grad = torch.zeros_like(self.table)
@@ -40,8 +41,8 @@ class Deform:
     def c(self):
         d = L.DeformState()
         d.grid = self.grid
-        for k in ("theta", "table", "params", "table_grad", "params_grad", "table_m", "table_v",
-                  "params_m", "params_v", "theta_grad"):
+        for k in ("theta", "table", "table_half", "params", "table_grad", "params_grad", "table_m",
+                  "table_v", "params_m", "params_v", "theta_grad"):
             setattr(d, k, getattr(self, k).data_ptr())
         self._c = d            # kept alive while the field struct points at it
         return d

@@ -20,7 +20,7 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def human_object_losses(precision, steps, use_graph=False):
+def human_object_losses(precision, steps, use_graph=False, deform=False):
     from paper_2304_03184_amd import field as F, ops as O
     work, (fh, fo), rig, o, d, C, D, ranges, (occ_h, occ_o), rng = synth.two_field_workload()
     table_h = synth.uniform_table(ogrid.Layout.from_field(fh).n_entries, 2, rng)
@@ -30,8 +30,13 @@ def human_object_losses(precision, steps, use_graph=False):
     ex = work.extra
     R = O.Rig.from_numpy(rig)
     wd = O.warp_desc(n_nodes=ex["n_nodes"], lut_res=ex["knn_res"])
+    dfm = None
+    if deform:
+        g = O.grid_desc_of(fh)
+        theta, dtab, dpar = synth.deform_inputs(g.n_entries, synth.rng_for(work.seed + 91))
+        dfm = F.Deform(g, theta, dtab, dpar)
     fld_h = F.Field(work, fh, table_h, params_h, occ_words=occ_h, rig=R, warp_desc=wd,
-                    ray_range=ranges[0])
+                    ray_range=ranges[0], deform=dfm)
     fld_o = F.Field(work, fo, table_o, params_o, occ_words=occ_o, ray_range=ranges[1])
     tr = F.Trainer([fld_h, fld_o], work.n_rays, work.n_rays * 128, precision=precision,
                    lambda_depth=work.lambda_depth, use_graph=use_graph)

@@ -5,6 +5,10 @@ compare against (test infrastructure; calls only ``oracle/`` and ``synth/``).
   the hybrid warp + object field, shared rays composited as one merged list,
   colour + depth loss, Eq. 8) at 1/64 of its ray counts, one fixed batch,
   Adam, loss per step.
+* ``curve_human_object_deform_r64.txt``: the same with the pose-conditioned
+  deformation network between the human field's warp and its encoding
+  (Sec. 4.2; its own 16-level grid on the human field's ladder, inputs from
+  ``synth.deform_inputs``), trained with the fields.
 * ``curve_keyframes_4096.txt``: key-frame refinement (rays drawn per step from
   eight 1280x720 key frames of the analytic scene, colour + depth loss with
   the mask M(r) of Eq. 8 set for rays whose first hit lies in the field's box,
@@ -14,6 +18,7 @@ compare against (test infrastructure; calls only ``oracle/`` and ``synth/``).
 
 Usage (from the repository root):
     python tests/golden/make_curves.py human_object --steps 500
+    python tests/golden/make_curves.py human_object_deform --steps 200
     python tests/golden/make_curves.py keyframes --steps 2000 --eval-every 250
 """
 import argparse
@@ -31,13 +36,19 @@ import synth  # noqa: E402
 from oracle import optim, grid as ogrid, step as ostep  # noqa: E402
 
 
-def human_object_state():
+def human_object_state(deform=False):
     work, (fh, fo), rig, o, d, C, D, ranges, (occ_h, occ_o), rng = synth.two_field_workload()
     table_h = synth.uniform_table(ogrid.Layout.from_field(fh).n_entries, 2, rng)
     params_h = synth.xavier_params(fh.layer_shapes(), rng)
     table_o = synth.uniform_table(ogrid.Layout.from_field(fo).n_entries, 2, rng)
     params_o = synth.xavier_params(fo.layer_shapes(), rng)
-    st = ostep.StepState([ostep.FieldState(fh, table_h, params_h, occ_words=occ_h, rig=rig),
+    dfm = None
+    if deform:
+        lay = ogrid.Layout.from_field(fh)
+        theta, table, params = synth.deform_inputs(lay.n_entries, synth.rng_for(work.seed + 91))
+        dfm = ostep.DeformState(lay, theta, table, params)
+    st = ostep.StepState([ostep.FieldState(fh, table_h, params_h, occ_words=occ_h, rig=rig,
+                                           deform=dfm),
                           ostep.FieldState(fo, table_o, params_o, occ_words=occ_o)])
     return work, st, o, d, C, D, ranges
 
@@ -57,7 +68,7 @@ def psnr(c, gt, mask):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["human_object", "keyframes"])
+    ap.add_argument("which", choices=["human_object", "human_object_deform", "keyframes"])
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--rays", type=int, default=4096)
     ap.add_argument("--eval-every", type=int, default=250)
@@ -66,10 +77,11 @@ def main():
                          "gets a _decay suffix when < 1")
     args = ap.parse_args()
     t0 = time.time()
-    if args.which == "human_object":
-        work, st, o, d, C, D, ranges = human_object_state()
+    if args.which in ("human_object", "human_object_deform"):
+        deform = args.which == "human_object_deform"
+        work, st, o, d, C, D, ranges = human_object_state(deform)
         box = ((-1.0,) * 3, (1.0,) * 3)
-        path = os.path.join(HERE, "curve_human_object_r64.txt")
+        path = os.path.join(HERE, f"curve_{args.which}_r64.txt")
         rows = []
         for i in range(args.steps):
             r = ostep.train_step(work, st, o, d, C, D, ranges, box, apply=True)
@@ -78,8 +90,9 @@ def main():
         with open(path, "w") as fh:
             fh.write("# FP64 oracle: two-field workload at 1/64 of its rays (3750 rays, human\n"
                      "# [0, 2812), object [2500, 3750)), one fixed batch, Adam lr 1e-2,\n"
-                     "# colour + depth loss (Eq. 8, lambda_d = 1).\n"
-                     f"# written by: python tests/golden/make_curves.py human_object --steps {args.steps}\n"
+                     "# colour + depth loss (Eq. 8, lambda_d = 1)"
+                     f"{'; deformation network on the human field' if deform else ''}.\n"
+                     f"# written by: python tests/golden/make_curves.py {args.which} --steps {args.steps}\n"
                      "# columns: step loss\n")
             for i, l in rows:
                 fh.write(f"{i} {l:.10e}\n")

@@ -35,6 +35,24 @@ def test_human_object_loss_curve(precision):
     assert abs(got[-1] - ref[-1, 1]) < 5e-3 * ref[-1, 1]
 
 
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_human_object_deform_loss_curve(precision):
+    # the same two-field workload with the deformation network between the
+    # human field's warp and its encoding, trained with the fields
+    L = lib()
+    ref = curves.load_curve("curve_human_object_deform_r64.txt")
+    steps = ref.shape[0]
+    prec = L.NVR_F32 if precision == "f32" else L.NVR_BF16
+    got = curves.human_object_losses(prec, steps, use_graph=precision == "bf16", deform=True)
+    rel = np.abs(got - ref[:, 1]) / ref[:, 1]
+    print(f"{precision} + deformation network: max rel {rel.max():.2e}, first 20 steps "
+          f"{rel[:20].max():.2e}, final {got[-1]:.6f} vs {ref[-1, 1]:.6f}")
+    first = 2e-5 if precision == "f32" else 3e-4
+    assert rel[:20].max() < first
+    assert rel.max() < 2e-2
+    assert abs(got[-1] - ref[-1, 1]) < 5e-3 * ref[-1, 1]
+
+
 def test_keyframe_training_psnr():
     # key-frame refinement, 4096 rays per step drawn from the eight key frames,
     # 2000 Adam steps on the fused BF16 path vs the FP64 oracle's stored curve.

@@ -94,16 +94,21 @@ def test_deform_large_batch_sampled():
     k = np.random.default_rng(10).choice(n, size=2000, replace=False)
     ref, _ = odef.forward(params, x[k], theta, table, lay)
     np.testing.assert_allclose(xc[k], ref, rtol=0, atol=2e-5)
-    dp, _, _, dth = O.deform_bwd(g, dev(x), dev(theta), dev(table), dev(params), dev(dvc),
-                                 want_dx=False)
+    dp, dt, dx, dth = O.deform_bwd(g, dev(x), dev(theta), dev(table), dev(params), dev(dvc))
     _, cache = odef.forward(params, x, theta, table, lay)
-    rp, _, _, rth = odef.backward(cache, dvc, want_dx=False)
+    rp, rt, rx, rth = odef.backward(cache, dvc)
     # over 2^18 points a few of the 2^27 hidden pre-activations lie within
     # float32 rounding of 0, where the two sides take the ReLU mask differently;
     # each such point moves the sums by about 1 / sqrt(n) of their size (bounds
-    # measured: 6.3e-4 for the parameters)
-    assert _relnorm(host(dp), rp) < 3e-3
-    assert _relnorm(host(dth), rth) < 3e-3
+    # measured: 6.3e-4 for the parameters).  The table and position gradients
+    # (every entry of the 2^19-entry ladder, split tiles and 18-bit records of
+    # the binned scatter included; cells decided in float32 on both sides)
+    # carry the same mask differences through the encoding gradient.
+    errs = dict(params=_relnorm(host(dp), rp), theta=_relnorm(host(dth), rth),
+                table=_relnorm(host(dt), rt), x=_relnorm(host(dx), rx))
+    print(f"deform float32 at 2^18 points: gradients {errs}")
+    for k, e in errs.items():
+        assert e < 3e-3, k
 
 
 def _f16(a):
@@ -112,15 +117,16 @@ def _f16(a):
 
 @pytest.mark.parametrize("n", [1, 1000, 4099])
 def test_deform_matrix_cores_match_oracle(n):
-    # the matrix-core path (fp16 encoding, weights and activations forward,
-    # bf16 products backward, fp32 accumulation) against the oracle given the
-    # fp16-rounded weights: the BF16 bars (output 1e-2 abs, gradients 3e-2 rel
-    # norm), several 16-point blocks and a ragged tail
+    # the matrix-core path (encoding from an fp16 table copy, fp16 weights and
+    # activations forward, bf16 products backward, fp32 accumulation) against
+    # the oracle given the fp16-rounded weights and table: the BF16 bars
+    # (output 1e-2 abs, gradients 3e-2 rel norm), several 16-point blocks and a
+    # ragged tail
     L, O = _ops()
     g, lay, table, params, x, theta, dvc = _setup(L, 100 + n, n)
     xd, thd, td, pd, dvd = dev(x), dev(theta), dev(table), dev(params), dev(dvc)
     xc = host(O.deform_fwd(g, xd, thd, td, pd, math=L.NVR_F16))
-    ref, cache = odef.forward(_f16(params), x, theta, table, lay)
+    ref, cache = odef.forward(_f16(params), x, theta, _f16(table), lay)
     err = np.abs(xc - ref).max()
     dp, dt, dx, dth = (host(t) for t in O.deform_bwd(g, xd, thd, td, pd, dvd, math=L.NVR_F16))
     rp, rt, rx, rth = odef.backward(cache, dvc)
@@ -148,10 +154,10 @@ def test_deform_matrix_cores_large_batch_sampled():
     xd, thd, td, pd = dev(x), dev(theta), dev(table), dev(params)
     xc = host(O.deform_fwd(g, xd, thd, td, pd, math=L.NVR_F16))
     k = np.random.default_rng(11).choice(n, size=2000, replace=False)
-    ref, _ = odef.forward(_f16(params), x[k], theta, table, lay)
+    ref, _ = odef.forward(_f16(params), x[k], theta, _f16(table), lay)
     assert np.abs(xc[k] - ref).max() < 1e-2
     dp, _, _, dth = O.deform_bwd(g, xd, thd, td, pd, dev(dvc), want_dx=False, math=L.NVR_F16)
-    _, cache = odef.forward(_f16(params), x, theta, table, lay)
+    _, cache = odef.forward(_f16(params), x, theta, _f16(table), lay)
     rp, _, _, rth = odef.backward(cache, dvc, want_dx=False)
     assert _relnorm(host(dp), rp) < 5e-2
     assert _relnorm(host(dth), rth) < 5e-2

@@ -246,6 +246,48 @@ def test_full_size_sampled_parity():
     np.testing.assert_allclose(host(Dg)[pick], ref["D"], rtol=0, atol=2e-2)
 
 
+def test_full_size_table_gradient_on_a_subset():
+    # the binned table-gradient scatter over every sample of the object
+    # workload's step (6.7 M marched samples, 16 levels, 2^19-entry tables;
+    # the six launches the benchmark's roofline line times), with feature
+    # gradients non-zero on a 10 000-sample subset: every table entry and the
+    # position gradients against the oracle's backward of that subset
+    L, F, O = lib()
+    w = synth.config(2)
+    f = w.fields[0]
+    rng = synth.rng_for(w.seed)
+    o, d = synth.sphere_rays(w.n_rays, rng)
+    _, occ = synth.noise_occupancy(f.occ_res, rng)
+    lay = ogrid.Layout.from_field(f)
+    table = synth.uniform_table(lay.n_entries, 2, rng)
+    full = omarch.march(o, d, f.aabb_min, f.aabb_max, w.near, w.far, omarch.step_size(w, f),
+                        w.max_steps, occ, f.occ_res)
+    x = full["x"]
+    n = x.shape[0]
+    sub = np.sort(synth.rng_for(98).choice(n, size=10000, replace=False))
+    g_sub = synth.rng_for(97).normal(size=(sub.size, 2 * f.n_levels)).astype(np.float32)
+    grouped = np.zeros((8, n, 4), np.float32)
+    for l in range(f.n_levels):
+        grouped[l % 8, sub, 2 * (l // 8):2 * (l // 8) + 2] = g_sub[:, 2 * l:2 * l + 2]
+    t16 = table.astype(np.float16)
+    g = O.grid_desc_of(f)
+    dtab = torch.zeros((lay.n_entries, 2), device="cuda")
+    dx = torch.zeros((n, 3), device="cuda")
+    O.encode_bwd_binned_grouped(g, dev(x), dev(t16), dev(grouped), dtab, dx)
+    torch.cuda.synchronize()
+    del grouped
+    rt, rdx = ogrid.encode_backward(x[sub], t16.astype(np.float64), g_sub, lay)
+    got = host(dtab)
+    print(f"full-size subset scatter: {n} samples, table rel err {rel_err(got, rt):.3e}")
+    assert rel_err(got, rt) < 1e-5
+    np.testing.assert_allclose(got, rt, rtol=0, atol=1e-5 * np.abs(rt).max())
+    gx = host(dx)
+    assert rel_err(gx[sub], rdx) < 1e-4
+    rest = np.ones(n, bool)
+    rest[sub] = False
+    assert not gx[rest].any()
+
+
 def _human(n_rays, knn_res=32, n_nodes=512, seed=0, res_max=2048):
     f = synth.FieldCfg(occ_res=64, res_max=res_max)
     w = synth.WorkCfg("h", n_rays, (f,), warp=True)
@@ -482,7 +524,8 @@ def test_cfg3_warp_deform_fp32_step():
 
 def test_cfg3_warp_deform_bf16_step():
     # the matrix-core deformation kernels inside the fused BF16 step against the
-    # oracle on the fp16 / bf16 copies of the field: colour 2e-2 absolute, the
+    # oracle on the fp16 / bf16 copies of the field and the fp16 copy of the
+    # network's table: colour 2e-2 absolute, the
     # field's and the warp's gradients 5e-2 relative.  The network's own
     # gradients (weights, table, pose) sit behind two low-precision stages in
     # series -- their input, the encoding's position gradient, carries the
@@ -495,7 +538,8 @@ def test_cfg3_warp_deform_bf16_step():
     lay, theta, dtab, dpar = dfm
     st = ostep.StepState([ostep.FieldState(f, f16_round(table), bf16_round(params),
                                            occ_words=occ, rig=rig,
-                                           deform=ostep.DeformState(lay, theta, dtab, dpar))])
+                                           deform=ostep.DeformState(lay, theta, f16_round(dtab),
+                                                                    dpar))])
     ref = ostep.train_step(w, st, o, d, Ct, None, [(0, w.n_rays)], box, apply=False)
     g = ref["grads"][0]
     got = _deform_grads(fld)
