@@ -45,6 +45,7 @@ struct DeformMfmaWs {
     float *bias;         // [128] pose term
     uint4 *fwd, *bwd;    // weight fragments
     uint16_t *hbuf, *zbuf;
+    uint32_t *mwords;    // [block][4][64] ReLU mask words of the training forward
     float *dfeat;        // [8][n][4] encoding gradient, same layout
     float *dx_parts;     // [8][n][3] position-gradient partials of the level groups
     float *partial;      // [kDwGrid][128][144] weight-gradient partials
@@ -449,6 +450,7 @@ constexpr int kBw0 = kBw1 + 3 * 32 * 64;      // W0f^T: 2 row tiles (features) x
 constexpr int kBw4 = kBw0 + 8 * 64;           // W4^T: 8 row tiles, 8-byte operands (half units)
 constexpr int kBwd = kBw4 + 8 * 64 / 2;       // backward set: 6912 (108 KiB)
 constexpr int kDnBlock = 512;                 // 8 waves: two per SIMD around one fragment copy
+constexpr int kDnBwdBlock = 1024;             // backward: 16 waves (<= 128 registers each)
 
 // One lane-tile fragment per thread of the grid: forward (fp16, W rows) and
 // backward (bf16, W^T rows) sets, both with the chained contraction order.
@@ -508,8 +510,38 @@ dn_pose_bias(const float *__restrict__ params, const float *__restrict__ theta,
     bias[u] = a;
 }
 
+// Per-block activation / gradient tiles of the backward, bf16, unit-major
+// [block][units][16 points]: H holds the encoding (32 units) then the four
+// hidden layers' outputs (4 x 128); Z the output gradients of W0..W3 (4 x 128)
+// then of W4 (16 units, 3 used).  The ReLU masks of the hidden layers are kept
+// as one word per lane and layer: bit 8q + j is slot j of K-step q, the
+// register layout of both the forward and the backward chain.
+constexpr int kHUnits = kFeat + 4 * kWidth;   // 544
+constexpr int kZUnits = 4 * kWidth + 16;      // 528
+__device__ __forceinline__ uint16_t bfbits(float v) {
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// Hidden layer l's activations of one block into its H tile and mask word
+// (lane g, c; zero for points past n).
+__device__ __forceinline__ void dn_store_hidden(const dh8 *hid, int l, uint16_t *H, uint32_t *mw,
+                                                int lane, int g, int c, bool valid) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float v = (float)hid[q][j];
+            H[(kFeat + l * kWidth + dkh(q, g, j)) * 16 + c] = valid ? bfbits(v) : (uint16_t)0;
+            m |= (v > 0.f ? 1u : 0u) << (8 * q + j);
+        }
+    mw[l * 64 + lane] = m;
+}
+
 // Forward of one block of 16 points: acc[m] are the output row tiles of the
 // last hidden layer; hid[l][q] the packed (fp16) activations of hidden layer l.
+// STORE: each hidden layer's tile and mask word are written as soon as the
+// layer is formed (H: the block's tile, mw: its 4 x 64 mask words).
 struct DnFwd {
     df4 acc[8];
     dh8 hid[4][4];
@@ -517,8 +549,12 @@ struct DnFwd {
 };
 
 // bias4: the pose bias at rows 16m + 4g.. of this lane (read per block)
+template <bool STORE = false>
 __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
-                                             const float *__restrict__ bias4, dh8 x0, DnFwd &s) {
+                                             const float *__restrict__ bias4, dh8 x0, DnFwd &s,
+                                             uint16_t *H = nullptr, uint32_t *mw = nullptr,
+                                             int lane = 0, bool valid = false) {
+    const int g = lane >> 4, c = lane & 15;
 #pragma unroll
     for (int m = 0; m < 8; ++m)
         s.acc[m] = dmfma(__builtin_bit_cast(dh8, F[kFw0 + m * 64]), x0,
@@ -529,6 +565,7 @@ __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             s.hid[layer - 1][q] = dpackh(drelu(s.acc[2 * q]), drelu(s.acc[2 * q + 1]));
+        if (STORE) dn_store_hidden(s.hid[layer - 1], layer - 1, H, mw, lane, g, c, valid);
         const int base = kFw1 + (layer - 1) * 32 * 64;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
@@ -543,6 +580,7 @@ __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) s.hid[3][q] = dpackh(drelu(s.acc[2 * q]), drelu(s.acc[2 * q + 1]));
+    if (STORE) dn_store_hidden(s.hid[3], 3, H, mw, lane, g, c, valid);
     df4 o = dzero();
 #pragma unroll
     for (int q = 0; q < 4; ++q) o = dmfma(__builtin_bit_cast(dh8, F[kFw4 + q * 64]), s.hid[3][q], o);
@@ -560,12 +598,17 @@ __device__ __forceinline__ dh8 dn_load_feat(const uint16_t *__restrict__ feat, i
 }
 
 // Forward: x_can = x + W4 relu(W3 relu(W2 relu(W1 relu(W0f feat + bias)))).
-// feat: fp16 encoding, level-group planes [8][cap][4]; bias: the pose term [128].
+// feat: fp16 encoding, level-group planes [8][cap][4]; bias: the pose term
+// [128]; x_can nullable.  STORE (training): each block's encoding and hidden
+// activations go to its H tile (bf16) and the ReLU masks to mwords
+// [block][4][64], for the backward, which then does not recompute the forward.
+template <bool STORE>
 __global__ void __launch_bounds__(kDnBlock)
 dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
             const uint16_t *__restrict__ feat, const float *__restrict__ bias,
             const uint4 *__restrict__ gfwd, const float *__restrict__ x,
-            float *__restrict__ x_can) {
+            float *__restrict__ x_can, uint16_t *__restrict__ hbuf,
+            uint32_t *__restrict__ mwords) {
     extern __shared__ uint4 F[];
     for (int i = threadIdx.x; i < kFwd; i += kDnBlock) F[i] = gfwd[i];
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
@@ -581,9 +624,17 @@ dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
         const int64_t p = blk * 16 + c;
         const bool valid = p < n;
         const dh8 x0 = dn_load_feat(feat, cap, p, g, valid);
+        uint16_t *H = STORE ? hbuf + blk * (int64_t)kHUnits * 16 : nullptr;
+        if (STORE) {
+            // encoding: slot j = feature dfp(g, j); the hidden layers follow
+            // in dn_block_fwd (slot j of K-step q = unit dkh(q, g, j))
+#pragma unroll
+            for (int j = 0; j < 8; ++j) H[dfp(g, j) * 16 + c] = bfbits((float)x0[j]);
+        }
         DnFwd s;
-        dn_block_fwd(F + lane, bias4, x0, s);
-        if (g == 0 && valid) {
+        dn_block_fwd<STORE>(F + lane, bias4, x0, s, H, STORE ? mwords + blk * 4 * 64 : nullptr,
+                            lane, valid);
+        if (g == 0 && valid && x_can != nullptr) {
             x_can[3 * p] = x[3 * p] + s.out[0];
             x_can[3 * p + 1] = x[3 * p + 1] + s.out[1];
             x_can[3 * p + 2] = x[3 * p + 2] + s.out[2];
@@ -591,58 +642,32 @@ dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
     }
 }
 
-// Per-block activation / gradient tiles of the backward, bf16, unit-major
-// [block][units][16 points]: H holds the encoding (32 units) then the four
-// hidden layers' outputs (4 x 128); Z the output gradients of W0..W3 (4 x 128)
-// then of W4 (16 units, 3 used).
-constexpr int kHUnits = kFeat + 4 * kWidth;   // 544
-constexpr int kZUnits = 4 * kWidth + 16;      // 528
-__device__ __forceinline__ uint16_t bfbits(float v) {
-    return __builtin_bit_cast(uint16_t, (__bf16)v);
-}
-
-__global__ void __launch_bounds__(kDnBlock)
+// Backward chain of each block from the stored masks: dZ4 = dx_can, then
+// dH3 = W4^T dZ4 (16x16x16) and dH_{l-1} = W_l^T dZ_l (bf16, masked by
+// layer l-1's ReLU), dfeat = W0f^T dZ0; each block's output gradients are
+// stored as bf16 tiles for the weight-gradient contraction.
+__global__ void __launch_bounds__(kDnBwdBlock)
 dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
-            const uint16_t *__restrict__ feat, const float *__restrict__ bias,
-            const uint4 *__restrict__ gfwd, const uint4 *__restrict__ gbwd,
+            const uint4 *__restrict__ gbwd, const uint32_t *__restrict__ mwords,
             const float *__restrict__ dxc, float *__restrict__ dfeat,
-            uint16_t *__restrict__ hbuf, uint16_t *__restrict__ zbuf) {
+            uint16_t *__restrict__ zbuf) {
     extern __shared__ uint4 Bt[];
-    for (int i = threadIdx.x; i < kBwd; i += kDnBlock) Bt[i] = gbwd[i];
+    for (int i = threadIdx.x; i < kBwd; i += kDnBwdBlock) Bt[i] = gbwd[i];
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-    const float *bias4 = bias + 4 * g;
     __syncthreads();
-    const uint4 *Ff = gfwd + lane;
     const uint4 *Bl = Bt + lane;
     const uint2 *B4 = reinterpret_cast<const uint2 *>(Bt + kBw4) + lane;
     n = count_of(n, n_dev, cap);
-    const int64_t waves = (int64_t)gridDim.x * (kDnBlock / 64);
-    for (int64_t blk = blockIdx.x * (int64_t)(kDnBlock / 64) + (threadIdx.x >> 6); blk * 16 < n;
+    const int64_t waves = (int64_t)gridDim.x * (kDnBwdBlock / 64);
+    for (int64_t blk = blockIdx.x * (int64_t)(kDnBwdBlock / 64) + (threadIdx.x >> 6); blk * 16 < n;
          blk += waves) {
         asm volatile("" ::: "memory");   // fragments are re-read each block (see the forward)
-        // the global fragment pointer is made opaque per block: read-only
-        // loads would otherwise be hoisted out of the loop into registers
-        const uint4 *Fb = Ff;
-        asm volatile("" : "+v"(Fb));
         const int64_t p = blk * 16 + c;
         const bool valid = p < n;
-        const dh8 x0 = dn_load_feat(feat, cap, p, g, valid);
-        DnFwd s;
-        dn_block_fwd(Fb, bias4, x0, s);
-        uint16_t *H = hbuf + blk * (int64_t)kHUnits * 16;
+        uint32_t mask[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) mask[l] = mwords[(blk * 4 + l) * 64 + lane];
         uint16_t *Z = zbuf + blk * (int64_t)kZUnits * 16;
-        // activations: encoding (slot j = feature dfp(g, j)), hidden layers
-        // (slot j of K-step q = unit dkh(q, g, j)); zero for points past n
-#pragma unroll
-        for (int j = 0; j < 8; ++j) H[dfp(g, j) * 16 + c] = bfbits((float)x0[j]);
-#pragma unroll
-        for (int l = 0; l < 4; ++l)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    H[(kFeat + l * kWidth + dkh(q, g, j)) * 16 + c] =
-                        valid ? bfbits((float)s.hid[l][q][j]) : (uint16_t)0;
         // output layer: dZ4 = dx_can (rows 0..2 of a 16-row operand)
         ds4 z4 = {};
         if (g == 0 && valid) {
@@ -660,14 +685,14 @@ dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
 #pragma unroll
         for (int layer = 3; layer >= 0; --layer) {
             asm volatile("" ::: "memory");   // load each layer's fragments when it runs
-            // dZ = dH through the ReLU of hidden layer `layer` (its fp16 output
-            // is the mask), staged, then paired into the next operands
+            // dZ = dH through the ReLU of hidden layer `layer`, staged, then
+            // paired into the next operands
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    if (!((float)s.hid[layer][q][i] > 0.f)) d[2 * q][i] = 0.f;
-                    if (!((float)s.hid[layer][q][4 + i] > 0.f)) d[2 * q + 1][i] = 0.f;
+                    if (!((mask[layer] >> (8 * q + i)) & 1u)) d[2 * q][i] = 0.f;
+                    if (!((mask[layer] >> (8 * q + 4 + i)) & 1u)) d[2 * q + 1][i] = 0.f;
                 }
                 zb[q] = dpackb(d[2 * q], d[2 * q + 1]);
 #pragma unroll
@@ -825,6 +850,7 @@ size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, Defor
     t.bwd = reinterpret_cast<uint4 *>(take(sizeof(uint4) * kBwd));
     t.hbuf = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)nblk * kHUnits * 16));
     t.zbuf = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * (size_t)nblk * kZUnits * 16));
+    t.mwords = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (size_t)nblk * 4 * 64));
     t.dfeat = reinterpret_cast<float *>(take(sizeof(float) * (size_t)n * kFeat));
     t.dx_parts = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kXcds * n * 3));
     t.partial = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kDwGrid * kWidth * 144));
@@ -841,7 +867,10 @@ nvr_status dn_lds_opt_in() {
     NVR_HIP(hipGetDevice(&dev));
     const uint64_t bit = 1ull << (dev & 63);
     if (done.load() & bit) return NVR_OK;
-    NVR_HIP(hipFuncSetAttribute((const void *)dn_fwd_mfma,
+    NVR_HIP(hipFuncSetAttribute((const void *)dn_fwd_mfma<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(uint4) * kFwd)));
+    NVR_HIP(hipFuncSetAttribute((const void *)dn_fwd_mfma<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(uint4) * kFwd)));
     NVR_HIP(hipFuncSetAttribute((const void *)dn_bwd_mfma,
@@ -897,18 +926,19 @@ nvr_status mfma_prologue(const GridParams &gp, int64_t n, const int32_t *n_dev, 
     return NVR_OK;
 }
 
-unsigned dn_grid(int64_t cap) {
+unsigned dn_grid(int64_t cap, int block = kDnBlock) {
     const int64_t nblk = (cap + 15) / 16;
-    const int64_t wg = (nblk + kDnBlock / 64 - 1) / (kDnBlock / 64);
+    const int64_t wg = (nblk + block / 64 - 1) / (block / 64);
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg, kCus));
 }
 
-// count: form the binned scatter's tile counts during the encoding (for a
-// backward that follows with counted = true)
+// count: form the binned scatter's tile counts during the encoding; store:
+// keep the activation tiles and ReLU masks for a backward (a training
+// forward); x_can nullable.
 nvr_status mfma_forward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
                         const float *x, const float *theta, const void *table_half,
                         const float *params, float *x_can, const DeformMfmaWs &w, bool count,
-                        hipStream_t st) {
+                        bool store, hipStream_t st) {
     TileCounter counter{};
     if (count) {
         counter = scatter_counter(gp, w.binned);
@@ -916,8 +946,12 @@ nvr_status mfma_forward(const GridParams &gp, int64_t n, const int32_t *n_dev, i
     }
     NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table_half, params, w, true,
                           count ? &counter : nullptr, st));
-    dn_fwd_mfma<<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(n, n_dev, cap, w.feat,
-                                                                     w.bias, w.fwd, x, x_can);
+    if (store)
+        dn_fwd_mfma<true><<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(
+            n, n_dev, cap, w.feat, w.bias, w.fwd, x, x_can, w.hbuf, w.mwords);
+    else
+        dn_fwd_mfma<false><<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(
+            n, n_dev, cap, w.feat, w.bias, w.fwd, x, x_can, nullptr, nullptr);
     NVR_LAUNCHED();
     return NVR_OK;
 }
@@ -943,21 +977,23 @@ nvr_status mfma_dw(int64_t n, const int32_t *n_dev, int64_t cap, const DeformMfm
     return NVR_OK;
 }
 
-// Matrix-core backward: recompute + chain per block, weight gradients over
-// the points, pose terms, then the encoding's table gradient (binned scatter
-// of the fp16-table encoding; deterministic variant when det) and, when dx is
-// given, its position gradient plus the residual's identity.  features_ready:
-// the forward's encoding is still in the workspace (and, with counted, so are
-// its tile counts).
+// Matrix-core backward: the chain per block from the training forward's
+// masks, weight gradients over the points from its activation tiles, pose
+// terms, then the encoding's table gradient (binned scatter of the fp16-table
+// encoding; deterministic variant when det) and, when dx is given, its
+// position gradient plus the residual's identity.  features_ready: a training
+// forward over the same points left its encoding, tiles and masks in the
+// workspace (and, with counted, its tile counts); otherwise one runs first.
 nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
                          const float *x, const float *theta, const void *table_half,
                          const float *params, const float *dx_can, float *dparams, float *dtable,
                          float *dx, float *dtheta, bool features_ready, bool counted, bool det,
                          const DeformMfmaWs &w, hipStream_t st) {
-    NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table_half, params, w, !features_ready,
-                          nullptr, st));
-    dn_bwd_mfma<<<dn_grid(cap), kDnBlock, sizeof(uint4) * kBwd, st>>>(
-        n, n_dev, cap, w.feat, w.bias, w.fwd, w.bwd, dx_can, w.dfeat, w.hbuf, w.zbuf);
+    if (!features_ready)
+        NVR_TRY(mfma_forward(gp, n, n_dev, cap, x, theta, table_half, params, nullptr, w, false,
+                             true, st));
+    dn_bwd_mfma<<<dn_grid(cap, kDnBwdBlock), kDnBwdBlock, sizeof(uint4) * kBwd, st>>>(
+        n, n_dev, cap, w.bwd, w.mwords, dx_can, w.dfeat, w.zbuf);
     NVR_LAUNCHED();
     // W4 [3][128]: dZ4 rows at 512 (one tile) x H3 at 416
     NVR_TRY((mfma_dw<1, 8, false>(n, n_dev, cap, w, 4 * kWidth, kFeat + 3 * kWidth,
@@ -1062,12 +1098,12 @@ size_t ws_bytes(const nvr_grid_desc *g, int64_t cap, bool matrix_cores, bool det
 }
 
 // table_half: the fp16 copy of the table, or null to form it in the workspace
-// (matrix-core path only).  count: a training forward, whose tile counts the
-// backward will use (matrix-core path only).
+// (matrix-core path only).  count, store: a training forward whose tile counts
+// and activation tiles the backward will use (matrix-core path only).
 nvr_status run_fwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const int32_t *n_dev,
                    int64_t cap, const float *x, const float *theta, const float *table,
                    const void *table_half, const float *params, float *x_can, bool count,
-                   bool det, void *ws, hipStream_t st) {
+                   bool store, bool det, void *ws, hipStream_t st) {
     const GridParams gp = make_grid_params(g);
     if (matrix_cores) {
         DeformMfmaWs w;
@@ -1078,7 +1114,8 @@ nvr_status run_fwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const i
             NVR_LAUNCHED();
             table_half = w.half;
         }
-        return mfma_forward(gp, n, n_dev, cap, x, theta, table_half, params, x_can, w, count, st);
+        return mfma_forward(gp, n, n_dev, cap, x, theta, table_half, params, x_can, w, count,
+                            store, st);
     }
     DeformWs w;
     carve(g, cap, det, static_cast<char *>(ws), &w);
@@ -1131,7 +1168,7 @@ nvr_status deform_fwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32
                           bool det, void *ws, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
     return run_fwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, table_half, params, x_can,
-                   train && !det, det, ws, st);
+                   train && !det, train, det, ws, st);
 }
 
 nvr_status deform_bwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32_t *n_dev,
@@ -1192,7 +1229,7 @@ extern "C" nvr_status nvr_deform_fwd(const nvr_grid_desc *g, int64_t n, const fl
                     aligned(x_can, 4),
                 NVR_EINVAL, "misaligned array");
     return run_fwd(g, math == NVR_F16, n, nullptr, n, x, theta, table, nullptr, params, x_can,
-                   false, false, workspace, hs(stream));
+                   false, false, false, workspace, hs(stream));
 }
 
 extern "C" nvr_status nvr_deform_bwd(const nvr_grid_desc *g, int64_t n, const float *x,
