@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the human, two-field and key-frame configurations")
     ap.add_argument("--kf-train-steps", type=int, default=600)
+    ap.add_argument("--only", choices=["human", "two_fields", "keyframes"],
+                    help="run only this configuration (for profiling) and print its record")
     ap.add_argument("--cpu-rays", type=int, default=32768)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration) and exit")
@@ -80,6 +82,13 @@ def main():
         return
     L.lib()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    if args.only:
+        fn = {"human": lambda: bench_human(O, L, F, torch, dev, args.steps, args.warmup),
+              "two_fields": lambda: bench_two_fields(O, L, F, torch, dev, args.steps, args.warmup),
+              "keyframes": lambda: bench_keyframes(O, L, F, torch, dev, args.steps, args.warmup,
+                                                   args.kf_train_steps)}[args.only]
+        print(json.dumps({"only": args.only, **fn()}), flush=True)
+        return
 
     R = args.rays
     w, f, rng, o, d, occ = make_inputs(R)
@@ -599,13 +608,13 @@ def _timed(torch, tr, steps, warmup):
 
 def _deform_state(fl):
     """The oracle's copy of a field's deformation network (the fp16 table copy
-    the matrix-core kernels read, fp32 weights)."""
+    and the fp16-rounded weights the matrix-core forward reads)."""
     from oracle import grid as ogrid, step as ostep
     D = fl.deform
     if D is None:
         return None
     return ostep.DeformState(ogrid.Layout.from_field(fl.fcfg), D.theta.cpu().numpy(),
-                             D.table_half.float().cpu().numpy(), D.params.cpu().numpy())
+                             D.table_half.float().cpu().numpy(), _f16(D.params.cpu().numpy()))
 
 
 def _sampled_colour_error(torch, tr, flds, w, o, d, ranges, pick, box=None):

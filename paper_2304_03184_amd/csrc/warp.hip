@@ -80,28 +80,35 @@ struct WarpFwd {
     float3 z;
 };
 
-// Forward of one sample; `J` is the joint table (LDS).
+// Forward of one sample; `J` is the joint table in global memory: the same
+// address for every lane, read through the scalar cache.
 __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__restrict__ J,
                                          const nvr_warp_rig &rig, float3 x, int frame,
                                          WarpFwd &f) {
     f.frame = frame;
-    // --- choose the k nearest joints by float32 squared distance (ties: lower index)
+    // --- choose the k nearest joints by float32 squared distance (ties: lower
+    // index): each joint passes down the sorted list, swapping with every entry
+    // it is strictly nearer than (selects, no divergent branches)
     float bd[kMaxKJ];
-    for (int k = 0; k < p.k_joints; ++k) {
+#pragma unroll
+    for (int k = 0; k < kMaxKJ; ++k) {
         bd[k] = INFINITY;
         f.jsel[k] = 0x7fffffff;
     }
     for (int j = 0; j < p.n_joints; ++j) {
-        const float d2 = joint_d2(x, J + 3 * j);
-        if (d2 < bd[p.k_joints - 1]) {
-            int k = p.k_joints - 1;
-            while (k > 0 && d2 < bd[k - 1]) {
-                bd[k] = bd[k - 1];
-                f.jsel[k] = f.jsel[k - 1];
-                --k;
+        float cur = joint_d2(x, J + 3 * j);
+        int cj = j;
+#pragma unroll
+        for (int k = 0; k < kMaxKJ; ++k) {
+            if (k < p.k_joints) {
+                const bool nearer = cur < bd[k];
+                const float tb = bd[k];
+                const int tj = f.jsel[k];
+                bd[k] = nearer ? cur : tb;
+                f.jsel[k] = nearer ? cj : tj;
+                cur = nearer ? tb : cur;
+                cj = nearer ? tj : cj;
             }
-            bd[k] = d2;
-            f.jsel[k] = j;
         }
     }
     // --- skinning weights and y = sum_j w_j (R_j x + t_j)
@@ -176,12 +183,9 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
 }
 
 __global__ void __launch_bounds__(kWarpBlock)
-warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__restrict__ n_dev,
-                int64_t cap, const float *__restrict__ x, const int32_t *__restrict__ frame,
-                float *__restrict__ xc) {
-    __shared__ float J[3 * kMaxJoints];
-    for (int i = threadIdx.x; i < 3 * p.n_joints; i += blockDim.x) J[i] = rig.joints[i];
-    __syncthreads();
+warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int64_t n,
+                const int32_t *__restrict__ n_dev, int64_t cap, const float *__restrict__ x,
+                const int32_t *__restrict__ frame, float *__restrict__ xc) {
     const int64_t count = count_of(n, n_dev, cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -199,17 +203,15 @@ warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__rest
 // atomics per sample would serialise on them).
 template <bool LDS_ACC, bool LDS_BONES>
 __global__ void __launch_bounds__(kWarpBlock)
-warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, int64_t n, const int32_t *__restrict__ n_dev,
-                int64_t cap, const float *__restrict__ x, const int32_t *__restrict__ frame,
-                const float *__restrict__ gz_parts, int n_parts, int64_t part_stride,
-                float *__restrict__ d_dq, float *__restrict__ d_bones,
-                float *__restrict__ dx_live) {
+warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int64_t n,
+                const int32_t *__restrict__ n_dev, int64_t cap, const float *__restrict__ x,
+                const int32_t *__restrict__ frame, const float *__restrict__ gz_parts,
+                int n_parts, int64_t part_stride, float *__restrict__ d_dq,
+                float *__restrict__ d_bones, float *__restrict__ dx_live) {
     extern __shared__ float lds[];
-    float *J = lds;                                   // [3 * n_joints]
     const int n_bacc = p.n_frames * p.n_joints * 12;
-    float *bacc = lds + 3 * kMaxJoints;               // [n_frames * n_joints * 12] if LDS_BONES
+    float *bacc = lds;                                // [n_frames * n_joints * 12] if LDS_BONES
     float *acc = bacc + (LDS_BONES ? n_bacc : 0);     // [n_frames * n_nodes * 8] if LDS_ACC
-    for (int i = threadIdx.x; i < 3 * p.n_joints; i += blockDim.x) J[i] = rig.joints[i];
     const int n_acc = p.n_frames * p.n_nodes * 8;
     if (LDS_ACC)
         for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0.f;
@@ -376,7 +378,8 @@ nvr_status launch_warp_fwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t
                            const int32_t *n_dev, int64_t cap, const float *x, const int32_t *frame,
                            float *xc, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
-    warp_fwd_kernel<<<grid_for(cap, kWarpBlock, 2048), kWarpBlock, 0, st>>>(p, rig, n, n_dev, cap, x,
+    warp_fwd_kernel<<<grid_for(cap, kWarpBlock, 2048), kWarpBlock, 0, st>>>(p, rig, rig.joints, n,
+                                                                           n_dev, cap, x,
                                                                              frame, xc);
     NVR_LAUNCHED();
     return NVR_OK;
@@ -389,25 +392,29 @@ nvr_status launch_warp_bwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t
     if (cap <= 0) return NVR_OK;
     const size_t acc_bytes = sizeof(float) * (size_t)p.n_frames * p.n_nodes * 8;
     const size_t bone_bytes = sizeof(float) * (size_t)p.n_frames * p.n_joints * 12;
-    const size_t base = sizeof(float) * 3 * kMaxJoints;
+    const size_t base = 0;
     const bool lds_bones = bone_bytes <= 16 * 1024;
     const size_t lb = lds_bones ? bone_bytes : 0;
     if (acc_bytes + lb <= 64 * 1024) {
         const unsigned gr = grid_for(cap, kWarpBlock, 512);
         if (lds_bones)
             warp_bwd_kernel<true, true><<<gr, kWarpBlock, base + lb + acc_bytes, st>>>(
-                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
+                d_bones, dx_live);
         else
             warp_bwd_kernel<true, false><<<gr, kWarpBlock, base + acc_bytes, st>>>(
-                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
+                d_bones, dx_live);
     } else {
         const unsigned gr = grid_for(cap, kWarpBlock, 2048);
         if (lds_bones)
             warp_bwd_kernel<false, true><<<gr, kWarpBlock, base + lb, st>>>(
-                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
+                d_bones, dx_live);
         else
             warp_bwd_kernel<false, false><<<gr, kWarpBlock, base, st>>>(
-                p, rig, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq, d_bones, dx_live);
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
+                d_bones, dx_live);
     }
     NVR_LAUNCHED();
     return NVR_OK;

@@ -9,6 +9,10 @@ compare against (test infrastructure; calls only ``oracle/`` and ``synth/``).
   deformation network between the human field's warp and its encoding
   (Sec. 4.2; its own 16-level grid on the human field's ladder, inputs from
   ``synth.deform_inputs``), trained with the fields.
+* ``curve_human_object_deform_r64_perturbed.txt`` (``--perturb EPS``): the
+  same oracle run with every warped position moved by U[-EPS, EPS] per
+  coordinate (EPS the size of the float32 warp's rounding), which measures how
+  fast the training trajectory itself separates under float32-sized errors.
 * ``curve_keyframes_4096.txt``: key-frame refinement (rays drawn per step from
   eight 1280x720 key frames of the analytic scene, colour + depth loss with
   the mask M(r) of Eq. 8 set for rays whose first hit lies in the field's box,
@@ -19,6 +23,7 @@ compare against (test infrastructure; calls only ``oracle/`` and ``synth/``).
 Usage (from the repository root):
     python tests/golden/make_curves.py human_object --steps 500
     python tests/golden/make_curves.py human_object_deform --steps 200
+    python tests/golden/make_curves.py human_object_deform --steps 200 --perturb 2.5e-7
     python tests/golden/make_curves.py keyframes --steps 2000 --eval-every 250
 """
 import argparse
@@ -72,6 +77,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--rays", type=int, default=4096)
     ap.add_argument("--eval-every", type=int, default=250)
+    ap.add_argument("--perturb", type=float, default=0.0,
+                    help="move every warped position by U[-eps, eps] (seeded) per coordinate; "
+                         "the curve file name gets a _perturbed suffix")
     ap.add_argument("--lr-decay", type=float, default=1.0,
                     help="update k uses lr * decay^(k-1); the key-frame curve file name "
                          "gets a _decay suffix when < 1")
@@ -81,7 +89,20 @@ def main():
         deform = args.which == "human_object_deform"
         work, st, o, d, C, D, ranges = human_object_state(deform)
         box = ((-1.0,) * 3, (1.0,) * 3)
-        path = os.path.join(HERE, f"curve_{args.which}_r64.txt")
+        suffix = "_perturbed" if args.perturb > 0 else ""
+        path = os.path.join(HERE, f"curve_{args.which}_r64{suffix}.txt")
+        if args.perturb > 0:
+            from oracle import warp as owarp
+            noise = np.random.default_rng(5)
+            orig = owarp.warp
+
+            def noisy(x, *a, **k):
+                out = orig(x, *a, **k)
+                if k.get("want_cache"):       # the backward's own recomputation
+                    return out
+                return out + noise.uniform(-args.perturb, args.perturb, size=out.shape)
+
+            owarp.warp = noisy
         rows = []
         for i in range(args.steps):
             r = ostep.train_step(work, st, o, d, C, D, ranges, box, apply=True)
@@ -91,8 +112,10 @@ def main():
             fh.write("# FP64 oracle: two-field workload at 1/64 of its rays (3750 rays, human\n"
                      "# [0, 2812), object [2500, 3750)), one fixed batch, Adam lr 1e-2,\n"
                      "# colour + depth loss (Eq. 8, lambda_d = 1)"
-                     f"{'; deformation network on the human field' if deform else ''}.\n"
-                     f"# written by: python tests/golden/make_curves.py {args.which} --steps {args.steps}\n"
+                     f"{'; deformation network on the human field' if deform else ''}"
+                     f"{f'; warped positions moved by U[-{args.perturb:g}, {args.perturb:g}]' if args.perturb > 0 else ''}.\n"
+                     f"# written by: python tests/golden/make_curves.py {args.which} --steps {args.steps}"
+                     f"{f' --perturb {args.perturb:g}' if args.perturb > 0 else ''}\n"
                      "# columns: step loss\n")
             for i, l in rows:
                 fh.write(f"{i} {l:.10e}\n")
