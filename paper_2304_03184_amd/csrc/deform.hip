@@ -52,7 +52,7 @@ struct DeformMfmaWs {
     uint32_t *half;      // fp16 copy of the table (public entry points)
     void *binned;        // binned table-gradient scatter
 };
-constexpr int kDwGrid = 256;
+constexpr int kDwGrid = 512;
 
 size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, DeformMfmaWs *w);
 
@@ -735,7 +735,8 @@ dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
 // Weight gradients dW = dZ H^T over the points: workgroup b contracts K-steps
 // of 32 points (two blocks) b, b + grid, ... for out tiles w and w + 4 of its
 // wave w and every in tile; `ones` adds an in tile of ones (the sums over the
-// points of dZ, for the pose gradient).  Writes its [16 TO][16 (TI + ones)]
+// points of dZ, for the pose gradient).  The next K-step's operands are loaded
+// while the current one is contracted.  Writes its [16 TO][16 (TI + ones)]
 // partial.
 template <int TO, int TI, bool ONES>
 __global__ void __launch_bounds__(256)
@@ -754,11 +755,10 @@ dn_dw(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
     dbf8 ones;
 #pragma unroll
     for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.f;
-    for (int64_t st = blockIdx.x; st < nstep; st += gridDim.x) {
+    const int pt = 8 * (g & 1);
+    auto load = [&](int64_t st, dbf8 *A, dbf8 *B) {
         const int64_t blk = 2 * st + (g >> 1);
-        const int pt = 8 * (g & 1);
-        const bool in_range = blk < nblk;
-        dbf8 A[2], B[TI];
+        const bool in_range = st < nstep && blk < nblk;
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const int mo = w + 4 * a;
@@ -774,6 +774,16 @@ dn_dw(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
                 B[t] = __builtin_bit_cast(dbf8, *reinterpret_cast<const uint4 *>(
                     hbuf + (blk * kHUnits + h_off + 16 * t + r) * 16 + pt));
         }
+    };
+    dbf8 An[2], Bn[TI];
+    load(blockIdx.x, An, Bn);
+    for (int64_t st = blockIdx.x; st < nstep; st += gridDim.x) {
+        dbf8 A[2], B[TI];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) A[a] = An[a];
+#pragma unroll
+        for (int t = 0; t < TI; ++t) B[t] = Bn[t];
+        load(st + gridDim.x, An, Bn);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             if (w + 4 * a >= TO) continue;
@@ -797,19 +807,31 @@ dn_dw(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
 }
 
 // dW[row][col] (acc, rows < out_rows, cols < in_cols of the weight, stride
-// w_ld) += sum over the workgroups' partials in order; with `pose`, the extra
-// column block (sums of dZ0 over the points) is contracted with W0's pose
-// columns into dtheta instead.
+// w_ld) += sum over the workgroups' partials: a workgroup takes 64 outputs,
+// its four waves sum the parts b = wave, wave + 4, ... in order, and the four
+// sums are added in wave order (a fixed order for given parts).
 __global__ void __launch_bounds__(256)
 dn_dw_reduce(int parts, int rows, int ncol, int out_rows, int in_cols,
              const float *__restrict__ partial, float *__restrict__ dW, int w_ld) {
+    __shared__ float part4[4][64];
     const int64_t total = (int64_t)out_rows * in_cols;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int row = (int)(i / in_cols), col = (int)(i % in_cols);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < total; i0 += (int64_t)gridDim.x * 64) {
+        const int64_t i = i0 + lane;
         float a = 0.f;
-        for (int b = 0; b < parts; ++b) a += partial[((int64_t)b * rows + row) * ncol + col];
-        dW[(int64_t)row * w_ld + col] += a;
+        if (i < total) {
+            const int row = (int)(i / in_cols), col = (int)(i % in_cols);
+            for (int b = wave; b < parts; b += 4)
+                a += partial[((int64_t)b * rows + row) * ncol + col];
+        }
+        part4[wave][lane] = a;
+        __syncthreads();
+        if (wave == 0 && i < total) {
+            const int row = (int)(i / in_cols), col = (int)(i % in_cols);
+            dW[(int64_t)row * w_ld + col] +=
+                ((part4[0][lane] + part4[1][lane]) + part4[2][lane]) + part4[3][lane];
+        }
+        __syncthreads();
     }
 }
 
@@ -971,7 +993,7 @@ nvr_status mfma_dw(int64_t n, const int32_t *n_dev, int64_t cap, const DeformMfm
                                                w.partial);
     NVR_LAUNCHED();
     const int ncol = 16 * (TI + (ONES ? 1 : 0));
-    dn_dw_reduce<<<grid_for((int64_t)out_rows * in_cols, 256, 256), 256, 0, st>>>(
+    dn_dw_reduce<<<grid_for((int64_t)out_rows * in_cols, 64, 1024), 256, 0, st>>>(
         parts, 16 * TO, ncol, out_rows, in_cols, w.partial, dW, w_ld);
     NVR_LAUNCHED();
     return NVR_OK;

@@ -38,19 +38,31 @@ def test_human_object_loss_curve(precision):
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 def test_human_object_deform_loss_curve(precision):
     # the same two-field workload with the deformation network between the
-    # human field's warp and its encoding, trained with the fields
+    # human field's warp and its encoding, trained with the fields.  Adam's
+    # first updates are close to lr * sign(gradient), so the network moves the
+    # warped points by centimetres per step and the trajectory is far more
+    # sensitive than without it: the oracle's own curve, rerun with its warped
+    # positions moved by float32-sized amounts (2.5e-7 m, stored beside it),
+    # separates by ~1% within five steps.  Each step's bound is the warp-free
+    # test's bar or 4x that separation so far, whichever is larger; the first
+    # loss (before any update) keeps the forward bar.
     L = lib()
     ref = curves.load_curve("curve_human_object_deform_r64.txt")
+    pert = curves.load_curve("curve_human_object_deform_r64_perturbed.txt")
     steps = ref.shape[0]
     prec = L.NVR_F32 if precision == "f32" else L.NVR_BF16
     got = curves.human_object_losses(prec, steps, use_graph=precision == "bf16", deform=True)
     rel = np.abs(got - ref[:, 1]) / ref[:, 1]
-    print(f"{precision} + deformation network: max rel {rel.max():.2e}, first 20 steps "
-          f"{rel[:20].max():.2e}, final {got[-1]:.6f} vs {ref[-1, 1]:.6f}")
+    env = np.maximum.accumulate(np.abs(pert[:, 1] - ref[:, 1]) / ref[:, 1])
+    print(f"{precision} + deformation network: step 0 {rel[0]:.2e}, step 1 {rel[1]:.2e} "
+          f"(oracle separation {env[1]:.2e}), first 20 max {rel[:20].max():.2e} (separation "
+          f"{env[19]:.2e}), all {rel.max():.2e} ({env[-1]:.2e}), final {got[-1]:.6f} vs "
+          f"{ref[-1, 1]:.6f} (perturbed oracle {pert[-1, 1]:.6f})")
+    assert rel[0] < (1e-5 if precision == "f32" else 2e-2)
     first = 2e-5 if precision == "f32" else 3e-4
-    assert rel[:20].max() < first
-    assert rel.max() < 2e-2
-    assert abs(got[-1] - ref[-1, 1]) < 5e-3 * ref[-1, 1]
+    assert np.all(rel[:20] < np.maximum(first, 4 * env[:20]))
+    assert rel.max() < max(2e-2, 4 * env[-1])
+    assert rel[-1] < max(5e-3, 4 * env[-1])
 
 
 def test_keyframe_training_psnr():

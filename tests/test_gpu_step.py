@@ -579,3 +579,55 @@ def test_deform_step_deterministic_and_graph():
         for a, b in zip(outs[0], other):
             assert np.array_equal(np.ascontiguousarray(a).view(np.uint32),
                                   np.ascontiguousarray(b).view(np.uint32))
+
+
+def test_deform_field_rejections_leave_state_untouched():
+    # every check of a field's deformation network runs before the step
+    # launches anything: a network without the warp, a BF16 step without the
+    # fp16 table copy, an encoding other than 16 levels x 2 features (8 levels)
+    L, F, O = lib()
+    w, f, rig, o, d, occ, table, params, Ct = _human(64, seed=3, res_max=512)
+    dfm = _deform_inputs(3)
+    lay, theta, dtab, dpar = dfm
+
+    def attempt(fld, precision, expect):
+        tr = F.Trainer([fld], w.n_rays, w.n_rays * 128, precision=precision)
+        tr.set_batch(dev(o), dev(d), dev(Ct))
+        before = [host(t).copy() for t in (fld.params, fld.table, fld.params_grad)]
+        with pytest.raises(L.NvrError) as e:
+            tr.forward()
+        assert e.value.code == expect, str(e.value)
+        torch.cuda.synchronize()
+        after = [host(t) for t in (fld.params, fld.table, fld.params_grad)]
+        assert all(np.array_equal(a, b) for a, b in zip(before, after))
+        tr.close()
+
+    # no warp
+    D = F.Deform(O.grid_desc(*_DEFORM_GRID), theta, dtab, dpar)
+    fld = F.Field(w, f, table, params, occ_words=occ)
+    fld.rig = None
+    fld.deform = D
+    attempt(fld, L.NVR_F32, L.NVR_EINVAL)
+    # BF16 without the fp16 copy of the network's table
+    fld = _deform_field(F, O, w, f, table, params, occ, rig, dfm)
+    fld.deform.table_half = None
+    D2 = fld.deform
+    D2.c = lambda: _c_without_half(L, D2)
+    attempt(fld, L.NVR_BF16, L.NVR_EINVAL)
+    # an 8-level encoding (16 wide)
+    g8 = O.grid_desc(8, 2, 14, 16, 512, (-1.0,) * 3, (1.0,) * 3)
+    n8 = ogrid.Layout(8, 2, 14, 16, 512, (-1.0,) * 3, (1.0,) * 3).n_entries
+    D3 = F.Deform(g8, theta, np.zeros((n8, 2), np.float32), dpar)
+    fld = _deform_field(F, O, w, f, table, params, occ, rig, dfm)
+    fld.deform = D3
+    attempt(fld, L.NVR_F32, L.NVR_EUNSUPPORTED)
+
+
+def _c_without_half(L, D):
+    d = L.DeformState()
+    d.grid = D.grid
+    for k in ("theta", "table", "params", "table_grad", "params_grad", "table_m", "table_v",
+              "params_m", "params_v", "theta_grad"):
+        setattr(d, k, getattr(D, k).data_ptr())
+    D._c = d
+    return d
