@@ -472,8 +472,9 @@ def time_live_lut(O, torch, res=128, k=8, knn_res=128):
 
 def time_deform(O, L, torch, n=1 << 18):
     """Pose-conditioned deformation network on n points (the field's ladder for
-    its own 2^19-entry table, 104 -> 4 x 128 -> 3), forward and backward
-    (which recomputes the forward), timed with HIP events."""
+    its own 2^19-entry table, 104 -> 4 x 128 -> 3) through the public entry
+    points, forward and backward (which runs the forward first), float32 tiled
+    kernels and matrix cores, timed with HIP events."""
     import ctypes as C
     rng = np.random.default_rng(37)
     g = L.GridDesc()
@@ -501,7 +502,7 @@ def time_deform(O, L, torch, n=1 << 18):
 
     flops_fwd = 2.0 * n * n_par
     out = {"points": n}
-    for name, math in (("f32_sgemm", L.NVR_F32), ("f16_matrix_cores", L.NVR_F16)):
+    for name, math in (("f32_tiled", L.NVR_F32), ("f16_matrix_cores", L.NVR_F16)):
         fwd = timed(lambda: O.deform_fwd(g, x, theta, table, params, math=math))
         bwd = timed(lambda: O.deform_bwd(g, x, theta, table, params, dvc, math=math))
         # the backward recomputes the forward: 3 x the forward's products

@@ -29,7 +29,7 @@ constexpr int64_t kParams = (int64_t)kWidth * kIn + (int64_t)(kHidden - 1) * kWi
 // the table when no position gradient is asked of it), the position gradient
 // through dn_encode_dx (one thread per point).
 constexpr int kMmT = 64, kMmK = 16;     // product tiles: 64 x 64 outputs, 16-deep slices
-constexpr int kMmParts = 64;            // most point chunks of a weight gradient
+constexpr int kMmParts = 256;           // most point chunks of a weight gradient
 constexpr int kThetaChunk = 256;        // points per pose-gradient partial
 
 struct DeformWs {
@@ -65,7 +65,7 @@ __host__ __device__ __forceinline__ int dfp(int g, int j) {
 
 // point chunks of the float32 weight gradients at capacity cap
 int mm_parts(int64_t cap) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kMmParts, cap / 2048));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMmParts, cap / 1024));
 }
 
 // Carves the workspace of capacity n; returns its size (base may be null to
@@ -163,16 +163,24 @@ dn_theta_sum(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
     part[blockIdx.x * kPose + c] = acc;
 }
 
-__global__ void __launch_bounds__(128)
+// one workgroup per pose component: thread t sums partials t, t + 256, ...,
+// then the 256 sums are added in a fixed tree order
+__global__ void __launch_bounds__(256)
 dn_theta_reduce(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
                 const float *__restrict__ part, float *__restrict__ dtheta) {
+    __shared__ float red[256];
     n = count_of(n, n_dev, cap);
-    const int c = threadIdx.x;
-    if (c >= kPose) return;
+    const int c = blockIdx.x, t = threadIdx.x;
     const int64_t nb = (n + kThetaChunk - 1) / kThetaChunk;
     float acc = 0.f;
-    for (int64_t b = 0; b < nb; ++b) acc += part[b * kPose + c];
-    dtheta[c] += acc;
+    for (int64_t b = t; b < nb; b += 256) acc += part[b * kPose + c];
+    red[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) dtheta[c] += red[0];
 }
 
 // Y[s][j] = act(sum_k X[s][k] B(j, k)) for the first count points s and j < J,
@@ -283,15 +291,24 @@ dn_mm_dw(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap, const float 
     }
 }
 
-// dW[i] += sum over parts b (in order) of partial[b][i]
+// dW[i] += sum over the parts of partial[b][i]: a workgroup takes 64 entries,
+// its four waves sum the parts b = wave, wave + 4, ... in order, and the four
+// sums are added in wave order (a fixed order for given parts)
 __global__ void __launch_bounds__(256)
 dn_reduce_partials(int64_t m, int32_t parts, const float *__restrict__ partial,
                    float *__restrict__ dW) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    __shared__ float part4[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < m; i0 += (int64_t)gridDim.x * 64) {
+        const int64_t i = i0 + lane;
         float acc = 0.f;
-        for (int b = 0; b < parts; ++b) acc += partial[(int64_t)b * m + i];
-        dW[i] += acc;
+        if (i < m)
+            for (int b = wave; b < parts; b += 4) acc += partial[(int64_t)b * m + i];
+        part4[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0 && i < m)
+            dW[i] += ((part4[0][lane] + part4[1][lane]) + part4[2][lane]) + part4[3][lane];
+        __syncthreads();
     }
 }
 
@@ -355,7 +372,7 @@ nvr_status mm_dw(int64_t n, const int32_t *n_dev, int64_t cap, const float *dY, 
     dn_mm_dw<<<grid, 256, 0, st>>>(n, n_dev, cap, dY, O, X, ldx, I, parts, partial);
     NVR_LAUNCHED();
     const int64_t m = (int64_t)O * I;
-    dn_reduce_partials<<<grid_for(m, 256, 1024), 256, 0, st>>>(m, parts, partial, dW);
+    dn_reduce_partials<<<grid_for(m, 64, 1024), 256, 0, st>>>(m, parts, partial, dW);
     NVR_LAUNCHED();
     return NVR_OK;
 }
@@ -1099,7 +1116,7 @@ nvr_status f32_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, i
         const unsigned nb = (unsigned)std::max<int64_t>(1, (cap + kThetaChunk - 1) / kThetaChunk);
         dn_theta_sum<<<nb, 128, 0, st>>>(n, n_dev, cap, w.da0, w.theta_part);
         NVR_LAUNCHED();
-        dn_theta_reduce<<<1, 128, 0, st>>>(n, n_dev, cap, w.theta_part, dtheta);
+        dn_theta_reduce<<<kPose, 256, 0, st>>>(n, n_dev, cap, w.theta_part, dtheta);
         NVR_LAUNCHED();
     }
     NVR_TRY(launch_scatter_rows(gp, n, n_dev, cap, x, w.dfeat, dtable, w.binned, st, det));
