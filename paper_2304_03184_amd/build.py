@@ -23,6 +23,9 @@ ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
          # no packed-fp32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results straight into ordinary registers (no copies out
+         # of the accumulation registers between chained layers)
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-munsafe-fp-atomics", "-Wno-unused-result"]
 
 

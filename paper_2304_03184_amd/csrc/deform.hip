@@ -438,7 +438,9 @@ __device__ __forceinline__ df4 dmfma16(ds4 a, ds4 b, df4 c) {
 }
 __device__ __forceinline__ df4 dzero() { return df4{0.f, 0.f, 0.f, 0.f}; }
 __device__ __forceinline__ df4 drelu(df4 a) {
-    return df4{fmaxf(a[0], 0.f), fmaxf(a[1], 0.f), fmaxf(a[2], 0.f), fmaxf(a[3], 0.f)};
+    // max(x, 0) as an integer max on the bits (-0 becomes +0)
+    auto r = [](float x) { return __int_as_float(max(__float_as_int(x), 0)); };
+    return df4{r(a[0]), r(a[1]), r(a[2]), r(a[3])};
 }
 __device__ __forceinline__ dh8 dpackh(df4 a, df4 b) {
     dh8 r;

@@ -96,9 +96,14 @@ __device__ __forceinline__ s4 quad(f4 a) {
     r[0] = bfs(a[0]); r[1] = bfs(a[1]); r[2] = bfs(a[2]); r[3] = bfs(a[3]);
     return r;
 }
+// max(x, 0) as one integer max on the bits (a negative float is a negative
+// int; -0 becomes +0), without the quieting that fmaxf's NaN rules add
+__device__ __forceinline__ float relu1(float x) {
+    return __int_as_float(max(__float_as_int(x), 0));
+}
 __device__ __forceinline__ f4 relu4(f4 a) {
     f4 r;
-    for (int i = 0; i < 4; ++i) r[i] = fmaxf(a[i], 0.f);
+    for (int i = 0; i < 4; ++i) r[i] = relu1(a[i]);
     return r;
 }
 __device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }

@@ -67,12 +67,15 @@ __device__ __forceinline__ float sign_dot(const float *q, const float *q0) {
     return dot >= 0.f ? 1.f : -1.f;
 }
 
+// KJ, KN: compile-time bounds of k_joints and k_nodes (4 or 8, 8 or 16), so
+// that every per-sample list is indexed by constants and lives in registers
+template <int KJ, int KN>
 struct WarpFwd {
-    int jsel[kMaxKJ];
-    float lw[kMaxKJ];
-    int nid[kMaxKN];
-    float w[kMaxKN];
-    float s[kMaxKN];
+    int jsel[KJ];
+    float lw[KJ];
+    int nid[KN];
+    float w[KN];
+    float s[KN];
     float3 y;
     float c[8];
     float nr;
@@ -82,16 +85,17 @@ struct WarpFwd {
 
 // Forward of one sample; `J` is the joint table in global memory: the same
 // address for every lane, read through the scalar cache.
+template <int KJ, int KN>
 __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__restrict__ J,
                                          const nvr_warp_rig &rig, float3 x, int frame,
-                                         WarpFwd &f) {
+                                         WarpFwd<KJ, KN> &f) {
     f.frame = frame;
     // --- choose the k nearest joints by float32 squared distance (ties: lower
     // index): each joint passes down the sorted list, swapping with every entry
     // it is strictly nearer than (selects, no divergent branches)
-    float bd[kMaxKJ];
+    float bd[KJ];
 #pragma unroll
-    for (int k = 0; k < kMaxKJ; ++k) {
+    for (int k = 0; k < KJ; ++k) {
         bd[k] = INFINITY;
         f.jsel[k] = 0x7fffffff;
     }
@@ -99,7 +103,7 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
         float cur = joint_d2(x, J + 3 * j);
         int cj = j;
 #pragma unroll
-        for (int k = 0; k < kMaxKJ; ++k) {
+        for (int k = 0; k < KJ; ++k) {
             if (k < p.k_joints) {
                 const bool nearer = cur < bd[k];
                 const float tb = bd[k];
@@ -113,14 +117,20 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
     }
     // --- skinning weights and y = sum_j w_j (R_j x + t_j)
     float wsum = 0.f;
-    for (int k = 0; k < p.k_joints; ++k) {
-        f.lw[k] = expf(-(bd[k] - bd[0]) * p.inv_two_sigma2);
-        wsum += f.lw[k];
+#pragma unroll
+    for (int k = 0; k < KJ; ++k) {
+        f.lw[k] = 0.f;
+        if (k < p.k_joints) {
+            f.lw[k] = expf(-(bd[k] - bd[0]) * p.inv_two_sigma2);
+            wsum += f.lw[k];
+        }
     }
     const float iw = 1.f / wsum;
     float3 y = make_float3(0.f, 0.f, 0.f);
     const float *B = rig.bones + (size_t)frame * p.n_joints * 12;
-    for (int k = 0; k < p.k_joints; ++k) {
+#pragma unroll
+    for (int k = 0; k < KJ; ++k) {
+        if (k >= p.k_joints) continue;
         f.lw[k] *= iw;
         const float *M = B + 12 * f.jsel[k];
         const float3 yj = make_float3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3],
@@ -138,9 +148,13 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
     const uint16_t *ids = rig.lut + ((size_t)frame * p.lut_res * p.lut_res * p.lut_res + vox) * p.k_nodes;
     const float *DQ = rig.node_dq + (size_t)frame * p.n_nodes * 8;
     const float *G = rig.node_pos + (size_t)frame * p.n_nodes * 3;
-    float e2[kMaxKN];
+    float e2[KN];
     float e2min = INFINITY;
-    for (int k = 0; k < p.k_nodes; ++k) {
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+        f.nid[k] = 0;
+        e2[k] = INFINITY;
+        if (k >= p.k_nodes) continue;
         int id = ids[k];
         id = id < p.n_nodes ? id : p.n_nodes - 1;   // ids are documented to be < n_nodes
         f.nid[k] = id;
@@ -151,7 +165,11 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
     }
     const float *q0 = DQ + 8 * f.nid[0];
     float b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < p.k_nodes; ++k) {
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+        f.s[k] = 0.f;
+        f.w[k] = 0.f;
+        if (k >= p.k_nodes) continue;
         const float *q = DQ + 8 * f.nid[k];
         float qq[8];
 #pragma unroll
@@ -182,6 +200,7 @@ __device__ __forceinline__ void warp_one(const WarpParams &p, const float *__res
     f.z = add3(qrot(wr, vr, y), tr);
 }
 
+template <int KJ, int KN>
 __global__ void __launch_bounds__(kWarpBlock)
 warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int64_t n,
                 const int32_t *__restrict__ n_dev, int64_t cap, const float *__restrict__ x,
@@ -189,9 +208,9 @@ warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
     const int64_t count = count_of(n, n_dev, cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        WarpFwd f;
+        WarpFwd<KJ, KN> f;
         const int fr = frame ? frame[i] : 0;
-        warp_one(p, J, rig, make_float3(x[3 * i], x[3 * i + 1], x[3 * i + 2]), fr, f);
+        warp_one<KJ, KN>(p, J, rig, make_float3(x[3 * i], x[3 * i + 1], x[3 * i + 2]), fr, f);
         xc[3 * i] = f.z.x;
         xc[3 * i + 1] = f.z.y;
         xc[3 * i + 2] = f.z.z;
@@ -201,7 +220,7 @@ warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
 // LDS_ACC: node-motion gradients summed per workgroup in LDS; LDS_BONES: bone
 // gradients likewise (every sample touches the same few joints, so global
 // atomics per sample would serialise on them).
-template <bool LDS_ACC, bool LDS_BONES>
+template <int KJ, int KN, bool LDS_ACC, bool LDS_BONES>
 __global__ void __launch_bounds__(kWarpBlock)
 warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int64_t n,
                 const int32_t *__restrict__ n_dev, int64_t cap, const float *__restrict__ x,
@@ -227,10 +246,10 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
             gz = add3(gz, make_float3(g[0], g[1], g[2]));
         }
         if (gz.x == 0.f && gz.y == 0.f && gz.z == 0.f) continue;
-        WarpFwd f;
+        WarpFwd<KJ, KN> f;
         const int fr = frame ? frame[i] : 0;
         const float3 xv = make_float3(x[3 * i], x[3 * i + 1], x[3 * i + 2]);
-        warp_one(p, J, rig, xv, fr, f);
+        warp_one<KJ, KN>(p, J, rig, xv, fr, f);
         const float3 y = f.y;
         const float wr = f.c[0], wd = f.c[4];
         const float3 vr = make_float3(f.c[1], f.c[2], f.c[3]);
@@ -267,7 +286,9 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
         const float cs[8] = {1.f, -1.f, -1.f, -1.f, 1.f, -1.f, -1.f, -1.f};
         const float *DQ = rig.node_dq + (size_t)fr * p.n_nodes * 8;
         const float *G = rig.node_pos + (size_t)fr * p.n_nodes * 3;
-        for (int k = 0; k < p.k_nodes; ++k) {
+#pragma unroll
+        for (int k = 0; k < KN; ++k) {
+            if (k >= p.k_nodes) continue;
             const int id = f.nid[k];
             const float sw = f.s[k] * f.w[k];
             const float *q = DQ + 8 * id;
@@ -285,7 +306,9 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
             gy = add3(gy, mul3(f.s[k] * gwk * f.w[k] * (-2.f * p.inv_r2), sub3(y, g)));
         }
         if (d_bones != nullptr) {
-            for (int k = 0; k < p.k_joints; ++k) {
+#pragma unroll
+            for (int k = 0; k < KJ; ++k) {
+                if (k >= p.k_joints) continue;
                 const size_t jb = ((size_t)fr * p.n_joints + f.jsel[k]) * 12;
                 const float lw = f.lw[k];
                 const float gys[3] = {gy.x, gy.y, gy.z};
@@ -307,13 +330,17 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
             const float *B0 = rig.bones + (size_t)fr * p.n_joints * 12;
             const float inv_s2 = 2.f * p.inv_two_sigma2;
             float3 abar = make_float3(0.f, 0.f, 0.f);
-            for (int k = 0; k < p.k_joints; ++k) {
+#pragma unroll
+            for (int k = 0; k < KJ; ++k) {
+                if (k >= p.k_joints) continue;
                 const float *Jk = J + 3 * f.jsel[k];
                 const float3 ak = mul3(-inv_s2, sub3(xv, make_float3(Jk[0], Jk[1], Jk[2])));
                 abar = add3(abar, mul3(f.lw[k], ak));
             }
             float3 gx = make_float3(0.f, 0.f, 0.f);
-            for (int k = 0; k < p.k_joints; ++k) {
+#pragma unroll
+            for (int k = 0; k < KJ; ++k) {
+                if (k >= p.k_joints) continue;
                 const float *M = B0 + 12 * f.jsel[k];
                 const float *Jk = J + 3 * f.jsel[k];
                 const float3 rt = make_float3(M[0] * gy.x + M[4] * gy.y + M[8] * gy.z,
@@ -378,9 +405,15 @@ nvr_status launch_warp_fwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t
                            const int32_t *n_dev, int64_t cap, const float *x, const int32_t *frame,
                            float *xc, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
-    warp_fwd_kernel<<<grid_for(cap, kWarpBlock, 2048), kWarpBlock, 0, st>>>(p, rig, rig.joints, n,
-                                                                           n_dev, cap, x,
-                                                                             frame, xc);
+    const unsigned gr = grid_for(cap, kWarpBlock, 2048);
+#define NVR_WARP_FWD(KJ, KN)                                                                  \
+    warp_fwd_kernel<KJ, KN><<<gr, kWarpBlock, 0, st>>>(p, rig, rig.joints, n, n_dev, cap, x, \
+                                                       frame, xc)
+    if (p.k_joints <= 4 && p.k_nodes <= 8) NVR_WARP_FWD(4, 8);
+    else if (p.k_joints <= 4) NVR_WARP_FWD(4, 16);
+    else if (p.k_nodes <= 8) NVR_WARP_FWD(8, 8);
+    else NVR_WARP_FWD(8, 16);
+#undef NVR_WARP_FWD
     NVR_LAUNCHED();
     return NVR_OK;
 }
@@ -395,27 +428,33 @@ nvr_status launch_warp_bwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t
     const size_t base = 0;
     const bool lds_bones = bone_bytes <= 16 * 1024;
     const size_t lb = lds_bones ? bone_bytes : 0;
-    if (acc_bytes + lb <= 64 * 1024) {
-        const unsigned gr = grid_for(cap, kWarpBlock, 512);
-        if (lds_bones)
-            warp_bwd_kernel<true, true><<<gr, kWarpBlock, base + lb + acc_bytes, st>>>(
-                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
-                d_bones, dx_live);
-        else
-            warp_bwd_kernel<true, false><<<gr, kWarpBlock, base + acc_bytes, st>>>(
-                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
-                d_bones, dx_live);
-    } else {
-        const unsigned gr = grid_for(cap, kWarpBlock, 2048);
-        if (lds_bones)
-            warp_bwd_kernel<false, true><<<gr, kWarpBlock, base + lb, st>>>(
-                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
-                d_bones, dx_live);
-        else
-            warp_bwd_kernel<false, false><<<gr, kWarpBlock, base, st>>>(
-                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,
-                d_bones, dx_live);
-    }
+    const bool lds_acc = acc_bytes + lb <= 64 * 1024;
+    const unsigned gr = grid_for(cap, kWarpBlock, lds_acc ? 512 : 2048);
+    const size_t lds = base + (lds_bones ? lb : 0) + (lds_acc ? acc_bytes : 0);
+#define NVR_WARP_BWD(KJ, KN)                                                                      \
+    do {                                                                                          \
+        if (lds_acc && lds_bones)                                                                 \
+            warp_bwd_kernel<KJ, KN, true, true><<<gr, kWarpBlock, lds, st>>>(                     \
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,      \
+                d_bones, dx_live);                                                                \
+        else if (lds_acc)                                                                         \
+            warp_bwd_kernel<KJ, KN, true, false><<<gr, kWarpBlock, lds, st>>>(                    \
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,      \
+                d_bones, dx_live);                                                                \
+        else if (lds_bones)                                                                       \
+            warp_bwd_kernel<KJ, KN, false, true><<<gr, kWarpBlock, lds, st>>>(                    \
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,      \
+                d_bones, dx_live);                                                                \
+        else                                                                                      \
+            warp_bwd_kernel<KJ, KN, false, false><<<gr, kWarpBlock, lds, st>>>(                   \
+                p, rig, rig.joints, n, n_dev, cap, x, frame, gz, n_parts, part_stride, d_dq,      \
+                d_bones, dx_live);                                                                \
+    } while (0)
+    if (p.k_joints <= 4 && p.k_nodes <= 8) NVR_WARP_BWD(4, 8);
+    else if (p.k_joints <= 4) NVR_WARP_BWD(4, 16);
+    else if (p.k_nodes <= 8) NVR_WARP_BWD(8, 8);
+    else NVR_WARP_BWD(8, 16);
+#undef NVR_WARP_BWD
     NVR_LAUNCHED();
     return NVR_OK;
 }
