@@ -666,12 +666,16 @@ static size_t det_lds_bytes(int lt) {
            (sizeof(uint2) + sizeof(uint16_t)) * 8 * kDetBlock;
 }
 
+// The chunk columns of the count rows are scanned in kSegParts slices of
+// consecutive chunks (slice sums, then per-slice bases, then the slices).
+constexpr int kSegParts = 64;
+
 size_t scatter_det_ws_bytes(const GridParams &p, int64_t cap) {
     const int tb = tile_bits(p);
     const DetSeg sg = det_segments(p, tb);
     const int64_t nc = (cap + kDetBlock - 1) / kDetBlock;
     return ((scatter_ws_bytes(p, cap) + 255) & ~size_t(255)) +
-           sizeof(uint32_t) * (size_t)nc * sg.at[p.L];
+           sizeof(uint32_t) * ((size_t)nc * sg.at[p.L] + 2 * (size_t)kSegParts * sg.at[p.L]);
 }
 
 // seg[c][sg.at[l] + j] = records of chunk c that level l puts into its j-th
@@ -720,38 +724,67 @@ det_count(GridParams p, int tb, DetSeg sg, int64_t n, const int32_t *__restrict_
     }
 }
 
-// One thread per tile: the running position through the tile's levels (in
-// increasing order) and, inside each, its chunks; seg becomes the first
-// position of every (chunk, level, tile) run.
+// The position of every (chunk, level, tile) run: a tile's range holds its
+// levels in increasing order and, inside each, its chunks in order, so seg
+// becomes the exclusive prefix of its column plus the tile's start.  Three
+// passes over kSegParts slices of consecutive chunks: the slice sums of every
+// column, the slices' bases (one thread per tile, through its levels), and the
+// prefixes inside the slices.  Integer sums: the result is the one serial
+// walk over the chunks would give.
+__device__ __forceinline__ void seg_slice(int64_t nc, int part, int64_t *c0, int64_t *c1) {
+    const int64_t per = (nc + kSegParts - 1) / kSegParts;
+    *c0 = per * part < nc ? per * part : nc;
+    *c1 = per * (part + 1) < nc ? per * (part + 1) : nc;
+}
+
 __global__ void __launch_bounds__(256)
-det_seg_scan(GridParams p, int tb, DetSeg sg, int n_tiles, int64_t n,
-             const int32_t *__restrict__ n_dev, int64_t cap, const uint32_t *__restrict__ start,
-             uint32_t *__restrict__ seg) {
+det_seg_sums(DetSeg sg, int L, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+             const uint32_t *__restrict__ seg, uint32_t *__restrict__ psum) {
+    const int S = sg.at[L];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)S * kSegParts) return;
+    const int j = (int)(i % S), part = (int)(i / S);
+    const int64_t nc = (count_of(n, n_dev, cap) + kDetBlock - 1) / kDetBlock;
+    int64_t c0, c1;
+    seg_slice(nc, part, &c0, &c1);
+    uint32_t a = 0u;
+    for (int64_t c = c0; c < c1; ++c) a += seg[c * S + j];
+    psum[(size_t)part * S + j] = a;
+}
+
+__global__ void __launch_bounds__(256)
+det_seg_bases(GridParams p, int tb, DetSeg sg, int n_tiles, const uint32_t *__restrict__ start,
+              const uint32_t *__restrict__ psum, uint32_t *__restrict__ pbase) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
-    const int64_t count = count_of(n, n_dev, cap);
-    const int64_t nc = (count + kDetBlock - 1) / kDetBlock;
     const size_t S = (size_t)sg.at[p.L];
     uint32_t run = start[t];
     for (int l = 0; l < p.L; ++l) {
         const int t_lo = (int)(p.off[l] >> tb), t_hi = (int)((p.off[l + 1] - 1) >> tb);
         if (t < t_lo || t > t_hi) continue;
-        uint32_t *col = seg + sg.at[l] + (t - t_lo);
-        int64_t c = 0;
-        for (; c + 4 <= nc; c += 4) {
-            const uint32_t v0 = col[c * S], v1 = col[(c + 1) * S], v2 = col[(c + 2) * S],
-                           v3 = col[(c + 3) * S];
-            col[c * S] = run;
-            col[(c + 1) * S] = run + v0;
-            col[(c + 2) * S] = run + v0 + v1;
-            col[(c + 3) * S] = run + v0 + v1 + v2;
-            run += v0 + v1 + v2 + v3;
+        const size_t j = (size_t)sg.at[l] + (t - t_lo);
+        for (int part = 0; part < kSegParts; ++part) {
+            pbase[part * S + j] = run;
+            run += psum[part * S + j];
         }
-        for (; c < nc; ++c) {
-            const uint32_t v = col[c * S];
-            col[c * S] = run;
-            run += v;
-        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+det_seg_apply(DetSeg sg, int L, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
+              const uint32_t *__restrict__ pbase, uint32_t *__restrict__ seg) {
+    const int S = sg.at[L];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)S * kSegParts) return;
+    const int j = (int)(i % S), part = (int)(i / S);
+    const int64_t nc = (count_of(n, n_dev, cap) + kDetBlock - 1) / kDetBlock;
+    int64_t c0, c1;
+    seg_slice(nc, part, &c0, &c1);
+    uint32_t run = pbase[(size_t)part * S + j];
+    for (int64_t c = c0; c < c1; ++c) {
+        const uint32_t v = seg[c * S + j];
+        seg[c * S + j] = run;
+        run += v;
     }
 }
 
@@ -832,22 +865,49 @@ det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__re
                 }
             }
             // stable ranks inside the wavefront, corner-major then lane order;
-            // the wavefront's running count per tile lives in its own LDS row
+            // the wavefront's running count per tile lives in its own LDS row.
+            // Dense levels name few tiles per instruction: one round per tile
+            // present.  Hashed levels name up to 64: each lane counts the lanes
+            // below it with its tile (and all lanes with it) by reading every
+            // lane's tile through the scalar unit, and the first lane of each
+            // tile advances the row.  Both give the same ranks.
             uint32_t *mine = wc + wave * n_lt;
+            if (p.dense[l]) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                uint64_t todo = __ballot(key[k] >= 0);
-                while (todo) {
-                    const int leader = __ffsll((unsigned long long)todo) - 1;
-                    const int K = __shfl(key[k], leader, 64);
-                    const uint64_t same = __ballot(key[k] == K);
-                    const uint32_t base = __hip_atomic_load(mine + K, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    if (key[k] == K) rank[k] = base + (uint32_t)__popcll(same & below);
-                    if (lane == leader)
-                        __hip_atomic_store(mine + K, base + (uint32_t)__popcll(same),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    todo &= ~same;
+                for (int k = 0; k < 8; ++k) {
+                    uint64_t todo = __ballot(key[k] >= 0);
+                    while (todo) {
+                        const int leader = __ffsll((unsigned long long)todo) - 1;
+                        const int K = __shfl(key[k], leader, 64);
+                        const uint64_t same = __ballot(key[k] == K);
+                        const uint32_t base = __hip_atomic_load(mine + K, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_WAVEFRONT);
+                        if (key[k] == K) rank[k] = base + (uint32_t)__popcll(same & below);
+                        if (lane == leader)
+                            __hip_atomic_store(mine + K, base + (uint32_t)__popcll(same),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                        todo &= ~same;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    uint32_t lower = 0u, total = 0u;
+                    for (int j = 0; j < 64; ++j) {
+                        const int kj = __builtin_amdgcn_readlane(key[k], j);
+                        const bool eq = kj == key[k];
+                        total += eq ? 1u : 0u;
+                        lower += (eq && j < lane) ? 1u : 0u;
+                    }
+                    const bool has = key[k] >= 0;
+                    uint32_t base = 0u;
+                    if (has)
+                        base = __hip_atomic_load(mine + key[k], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    if (has) rank[k] = base + lower;
+                    if (has && lower == 0u)
+                        __hip_atomic_store(mine + key[k], base + total, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
                 }
             }
             __syncthreads();
@@ -893,6 +953,109 @@ det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__re
 // 64 and adds their records in range order (LDS adds of one lane issue in
 // program order).  A window of 512 records is staged in LDS and read by every
 // lane.
+// The deterministic accumulate for tiles of at most kDetFastEntries entries:
+// the same windows and rounds as scatter_accum, but the lane that adds an
+// entry's record in a round is chosen by an integer minimum over the lanes
+// naming it (tags reset, then ds_min of the lane id, then read back), so the
+// order in which an entry's records are added depends only on their order in
+// the record buffer, which the deterministic emit fixes.
+constexpr uint32_t kDetFastEntries = 8192;
+__global__ void __launch_bounds__(64)
+det_accum_min(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
+              const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
+              const uint2 *__restrict__ recs, float2 *__restrict__ dtable,
+              float2 *__restrict__ partial) {
+    extern __shared__ float2 acc[];                                   // [te] sums
+    const uint32_t te = 1u << tb;
+    uint32_t *tag = reinterpret_cast<uint32_t *>(acc + te);          // [te]
+    const uint32_t lane = threadIdx.x;
+    const uint32_t items = *n_items;
+    const int kb = (tb + 1) >> 1;
+    const uint32_t kmask = (1u << kb) - 1u;
+    constexpr uint32_t kPer = 8;
+    constexpr uint32_t kWin = 64u * kPer;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        int lo = 0, hi = n_tiles - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_start[mid] <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const int t = lo;
+        const uint32_t first = it - item_start[t];
+        const uint32_t r0 = start[t] + first * kItemRecords;
+        const uint32_t r1e = r0 + kItemRecords;
+        const uint32_t r1 = r1e < start[t + 1] ? r1e : start[t + 1];
+        const bool owner = (item_start[t + 1] - item_start[t]) == 1u;
+        for (uint32_t i = lane; i < te; i += 64) acc[i] = make_float2(0.f, 0.f);
+        const uint32_t tbase = (uint32_t)t << tb;
+        const uint32_t b0 = r0 & ~(kPer - 1u);
+        for (uint32_t base = b0; base < r1; base += kWin) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(recs + base + lane * kPer);
+            const uint4 qv[4] = {q[0], q[1], q[2], q[3]};
+            const uint32_t hw[kPer] = {qv[0].x, qv[0].z, qv[1].x, qv[1].z,
+                                       qv[2].x, qv[2].z, qv[3].x, qv[3].z};
+            const uint32_t lw[kPer] = {qv[0].y, qv[0].w, qv[1].y, qv[1].w,
+                                       qv[2].y, qv[2].w, qv[3].y, qv[3].w};
+            uint32_t loc[kPer];
+            float v0[kPer], v1[kPer];
+            bool pend[kPer];
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; ++u) {
+                const uint32_t rec = base + lane * kPer + u;
+                loc[u] = ((hw[u] & kmask) << kb) | (lw[u] & kmask);
+                v0[u] = __uint_as_float(hw[u] & ~kmask);
+                v1[u] = __uint_as_float(lw[u] & ~kmask);
+                pend[u] = rec >= r0 && rec < r1 && loc[u] < te;
+            }
+            // wavefront-scope relaxed atomics: LDS accesses that complete in
+            // program order for the wave (one wave per workgroup)
+            auto round = [&](uint32_t u) {
+                if (pend[u])
+                    __hip_atomic_store(tag + loc[u], 0xffffffffu, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                if (pend[u])
+                    __hip_atomic_fetch_min(tag + loc[u], lane, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                if (pend[u] && __hip_atomic_load(tag + loc[u], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WAVEFRONT) == lane) {
+                    float2 a = acc[loc[u]];
+                    a.x += v0[u];
+                    a.y += v1[u];
+                    acc[loc[u]] = a;
+                    pend[u] = false;
+                }
+            };
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; ++u) round(u);
+            bool left = false;
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; ++u) left |= pend[u];
+            while (__ballot(left)) {
+#pragma unroll
+                for (uint32_t u = 0; u < kPer; ++u)
+                    if (__ballot(pend[u])) round(u);
+                left = false;
+#pragma unroll
+                for (uint32_t u = 0; u < kPer; ++u) left |= pend[u];
+            }
+        }
+        const uint32_t ne = (n_entries - tbase) < te ? (n_entries - tbase) : te;
+        if (owner) {
+            for (uint32_t i = lane; i < ne; i += 64) {
+                const float2 a = acc[i];
+                if (a.x != 0.f || a.y != 0.f) {
+                    const float2 d = dtable[tbase + i];
+                    dtable[tbase + i] = make_float2(d.x + a.x, d.y + a.y);
+                }
+            }
+        } else {
+            float2 *slab = partial + (size_t)it * te;
+            for (uint32_t i = lane; i < ne; i += 64) slab[i] = acc[i];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(64)
 det_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
           const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
@@ -985,6 +1148,9 @@ nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_d
         NVR_HIP(hipFuncSetAttribute((const void *)det_accum,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)((sizeof(float2) << kMaxTileBits) + sizeof(uint2) * 512)));
+        NVR_HIP(hipFuncSetAttribute((const void *)det_accum_min,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)((sizeof(float2) + sizeof(uint32_t)) * kDetFastEntries)));
         det_lds_ok.fetch_or(dev_bit);
     }
     zero_u32<<<grid_for(nt + 1, 256, 64), 256, 0, st>>>(w.count, nt + 1);
@@ -999,8 +1165,19 @@ nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_d
     NVR_LAUNCHED();
     scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items);
     NVR_LAUNCHED();
-    det_seg_scan<<<(nt + 255) / 256, 256, 0, st>>>(p, tb, sg, nt, n, n_dev, cap, w.start, seg);
-    NVR_LAUNCHED();
+    {
+        const int S = sg.at[p.L];
+        const int64_t ncap = (cap + kDetBlock - 1) / kDetBlock;
+        uint32_t *psum = seg + (size_t)ncap * S;
+        uint32_t *pbase = psum + (size_t)kSegParts * S;
+        const unsigned gs = (unsigned)(((int64_t)S * kSegParts + 255) / 256);
+        det_seg_sums<<<gs, 256, 0, st>>>(sg, p.L, n, n_dev, cap, seg, psum);
+        NVR_LAUNCHED();
+        det_seg_bases<<<(nt + 255) / 256, 256, 0, st>>>(p, tb, sg, nt, w.start, psum, pbase);
+        NVR_LAUNCHED();
+        det_seg_apply<<<gs, 256, 0, st>>>(sg, p.L, n, n_dev, cap, pbase, seg);
+        NVR_LAUNCHED();
+    }
     const size_t elds = det_lds_bytes(lt);
     const uint32_t *tab = (const uint32_t *)table;
     switch (lpg) {
@@ -1013,9 +1190,15 @@ nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_d
     if (dtable == nullptr) return NVR_OK;
     const int64_t max_items = max_items_of(cap, p.L, nt);
     const unsigned ga = (unsigned)(max_items < 65535 ? max_items : 65535);
-    const size_t alds = (sizeof(float2) << tb) + sizeof(uint2) * 512;
-    det_accum<<<ga, 64, alds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items, w.rec,
-                                    (float2 *)dtable, w.partial);
+    if ((1u << tb) <= kDetFastEntries) {
+        const size_t alds = (sizeof(float2) + sizeof(uint32_t)) << tb;
+        det_accum_min<<<ga, 64, alds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
+                                            w.rec, (float2 *)dtable, w.partial);
+    } else {
+        const size_t alds = (sizeof(float2) << tb) + sizeof(uint2) * 512;
+        det_accum<<<ga, 64, alds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
+                                        w.rec, (float2 *)dtable, w.partial);
+    }
     NVR_LAUNCHED();
     scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
         tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
