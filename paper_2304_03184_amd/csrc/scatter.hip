@@ -240,6 +240,55 @@ __device__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *part) {
     __syncthreads();
 }
 
+// Position-gradient sum of one level: each corner's table pair (fp16)
+// contracted with the feature gradient, weighted by the corner weight's
+// derivative.  With a 16-byte aligned table (level slices start at multiples of
+// 8 entries) the two corners of a cell edge along x come from one aligned
+// 16-byte load, plus a 4-byte load in the cases where the edge straddles two
+// groups of 4 entries, as in the forward gather.
+__device__ __forceinline__ uint32_t word_of(const uint4 &q, uint32_t i) {
+    const uint32_t lo = (i & 1u) ? q.y : q.x;
+    const uint32_t hi = (i & 1u) ? q.w : q.z;
+    return (i & 2u) ? hi : lo;
+}
+
+__device__ __forceinline__ float3 level_dx_sum(const uint32_t *__restrict__ table,
+                                               const uint32_t (&ent)[8], bool quad,
+                                               const LevelPos &lp, float g0, float g1) {
+    uint32_t v[8];
+    if (quad) {
+        uint4 q[4];
+        uint32_t far_v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = *reinterpret_cast<const uint4 *>(table + (ent[2 * j] & ~3u));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            far_v[j] = 0u;
+            if ((ent[2 * j] ^ ent[2 * j + 1]) > 3u) far_v[j] = table[ent[2 * j + 1]];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[2 * j] = word_of(q[j], ent[2 * j] & 3u);
+            v[2 * j + 1] = (ent[2 * j] ^ ent[2 * j + 1]) > 3u ? far_v[j]
+                                                               : word_of(q[j], ent[2 * j + 1] & 3u);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = table[ent[k]];
+    }
+    float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float tg = f16_bits_to_f32((uint16_t)(v[k] & 0xffffu)) * g0 +
+                         f16_bits_to_f32((uint16_t)(v[k] >> 16)) * g1;
+        const float3 dw = corner_dweight(lp, k);
+        e0 += dw.x * tg;
+        e1 += dw.y * tg;
+        e2 += dw.z * tg;
+    }
+    return make_float3(e0, e1, e2);
+}
+
 // One chunk of blockDim.x samples and one level at a time: the chunk's 8 records
 // per sample are ranked within their tiles (LDS counters), space is reserved
 // per tile with one global atomic, the records are staged in LDS in tile order
@@ -262,6 +311,7 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
     const int64_t chunks = gridDim.x / kXcds;
     const int lpg = LPG;
     const int kb = (tb + 1) >> 1;
+    const bool quad = ((uintptr_t)table & 15u) == 0;   // level slices are 8-entry aligned
     for (int64_t c = blockIdx.x / kXcds; c * blockDim.x < count; c += chunks) {
         const int64_t s = c * blockDim.x + threadIdx.x;
         const bool valid = s < count;
@@ -287,7 +337,6 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                 const LevelPos lp = level_pos(p, l, px, py, pz);
                 const float *src = dfeat + ((size_t)g * cap + s) * (2 * lpg) + 2 * m;
                 const float g0 = src[0], g1 = src[1];
-                float e0 = 0.f, e1 = 0.f, e2 = 0.f;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const float w = corner_weight(lp, k);
@@ -295,16 +344,9 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                     ent[k] = e;
                     v0[k] = w * g0;
                     v1[k] = w * g1;
-                    if (dx_parts != nullptr) {
-                        const uint32_t v = table[e];
-                        const float tg = f16_bits_to_f32((uint16_t)(v & 0xffffu)) * g0 +
-                                         f16_bits_to_f32((uint16_t)(v >> 16)) * g1;
-                        const float3 dw = corner_dweight(lp, k);
-                        e0 += dw.x * tg;
-                        e1 += dw.y * tg;
-                        e2 += dw.z * tg;
-                    }
                 }
+                float3 ed = make_float3(0.f, 0.f, 0.f);
+                if (dx_parts != nullptr) ed = level_dx_sum(table, ent, quad, lp, g0, g1);
                 // ranks inside the tiles; the two corners of an x edge (2j, 2j + 1)
                 // fall into one tile but rarely, and then take one counter update
 #pragma unroll
@@ -316,9 +358,9 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                     rank[2 * j + 1] = t0 == t1 ? r + 1u : atomicAdd(&hist[t1], 1u);
                 }
                 if (dx_parts != nullptr) {
-                    if (lp.inside[0]) d0 += e0 * p.s_hi[l][0];
-                    if (lp.inside[1]) d1 += e1 * p.s_hi[l][1];
-                    if (lp.inside[2]) d2 += e2 * p.s_hi[l][2];
+                    if (lp.inside[0]) d0 += ed.x * p.s_hi[l][0];
+                    if (lp.inside[1]) d1 += ed.y * p.s_hi[l][1];
+                    if (lp.inside[2]) d2 += ed.z * p.s_hi[l][2];
                 }
             }
             __syncthreads();
@@ -805,6 +847,7 @@ det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__re
     const int g = blockIdx.x % kXcds;
     const int64_t chunks = gridDim.x / kXcds;
     const int kb = (tb + 1) >> 1;
+    const bool quad = ((uintptr_t)table & 15u) == 0;   // level slices are 8-entry aligned
     const int S = sg.at[p.L];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -839,7 +882,6 @@ det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__re
                 const LevelPos lp = level_pos(p, l, px, py, pz);
                 const float *src = dfeat + ((size_t)g * cap + s) * (2 * LPG) + 2 * m;
                 const float g0 = src[0], g1 = src[1];
-                float e0 = 0.f, e1 = 0.f, e2 = 0.f;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const float w = corner_weight(lp, k);
@@ -848,20 +890,13 @@ det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__re
                     key[k] = (int)(e >> tb) - t_lo;
                     v0[k] = w * g0;
                     v1[k] = w * g1;
-                    if (dx_parts != nullptr) {
-                        const uint32_t v = table[e];
-                        const float tg = f16_bits_to_f32((uint16_t)(v & 0xffffu)) * g0 +
-                                         f16_bits_to_f32((uint16_t)(v >> 16)) * g1;
-                        const float3 dw = corner_dweight(lp, k);
-                        e0 += dw.x * tg;
-                        e1 += dw.y * tg;
-                        e2 += dw.z * tg;
-                    }
                 }
+                float3 ed = make_float3(0.f, 0.f, 0.f);
+                if (dx_parts != nullptr) ed = level_dx_sum(table, ent, quad, lp, g0, g1);
                 if (dx_parts != nullptr) {
-                    if (lp.inside[0]) d0 += e0 * p.s_hi[l][0];
-                    if (lp.inside[1]) d1 += e1 * p.s_hi[l][1];
-                    if (lp.inside[2]) d2 += e2 * p.s_hi[l][2];
+                    if (lp.inside[0]) d0 += ed.x * p.s_hi[l][0];
+                    if (lp.inside[1]) d1 += ed.y * p.s_hi[l][1];
+                    if (lp.inside[2]) d2 += ed.z * p.s_hi[l][2];
                 }
             }
             // stable ranks inside the wavefront, corner-major then lane order;
