@@ -48,6 +48,7 @@ struct DeformMfmaWs {
     uint32_t *mwords;    // [block][4][64] ReLU mask words of the training forward
     float *dfeat;        // [8][n][4] encoding gradient, same layout
     float *dx_parts;     // [8][n][3] position-gradient partials of the level groups
+    uint32_t *jac;       // [8][n][6] the training gather's spatial derivatives (fp16 pairs)
     float *partial;      // [kDwGrid][128][144] weight-gradient partials
     uint32_t *half;      // fp16 copy of the table (public entry points)
     void *binned;        // binned table-gradient scatter
@@ -894,6 +895,7 @@ size_t carve_mfma(const nvr_grid_desc *g, int64_t n, bool det, char *base, Defor
     t.mwords = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (size_t)nblk * 4 * 64));
     t.dfeat = reinterpret_cast<float *>(take(sizeof(float) * (size_t)n * kFeat));
     t.dx_parts = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kXcds * n * 3));
+    t.jac = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (size_t)3 * (kFeat / 2) * n));
     t.partial = reinterpret_cast<float *>(take(sizeof(float) * (size_t)kDwGrid * kWidth * 144));
     t.half = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (size_t)gp.off[gp.L]));
     t.binned = take(det ? scatter_det_ws_bytes(gp, n) : scatter_ws_bytes(gp, n));
@@ -955,11 +957,11 @@ dn_dx_total(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
 nvr_status mfma_prologue(const GridParams &gp, int64_t n, const int32_t *n_dev, int64_t cap,
                          const float *x, const float *theta, const void *table_half,
                          const float *params, const DeformMfmaWs &w, bool encode,
-                         const TileCounter *counter, hipStream_t st) {
+                         const TileCounter *counter, bool jac, hipStream_t st) {
     NVR_TRY(dn_lds_opt_in());
     if (encode)
         NVR_TRY(launch_encode_fwd(gp, n, n_dev, cap, x, table_half, NVR_F16, w.feat, NVR_F16,
-                                  true, st, counter));
+                                  true, st, counter, 0, jac ? w.jac : nullptr));
     dn_frags<<<(kFwd + kBw4 + 8 * 64 + 255) / 256, 256, 0, st>>>(params, w.fwd, w.bwd);
     NVR_LAUNCHED();
     dn_pose_bias<<<1, kWidth, 0, st>>>(params, theta, w.bias);
@@ -985,8 +987,10 @@ nvr_status mfma_forward(const GridParams &gp, int64_t n, const int32_t *n_dev, i
         counter = scatter_counter(gp, w.binned);
         NVR_TRY(launch_counter_reset(gp, w.binned, st));
     }
+    // a training forward also keeps the encoding's spatial derivatives for the
+    // backward's position gradient
     NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table_half, params, w, true,
-                          count ? &counter : nullptr, st));
+                          count ? &counter : nullptr, store, st));
     if (store)
         dn_fwd_mfma<true><<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(
             n, n_dev, cap, w.feat, w.bias, w.fwd, x, x_can, w.hbuf, w.mwords);
@@ -1053,10 +1057,10 @@ nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, 
     float *parts = dx ? w.dx_parts : nullptr;
     if (det)
         NVR_TRY(launch_scatter_det(gp, n, n_dev, cap, x, table_half, w.dfeat, dtable, parts,
-                                   w.binned, st));
+                                   w.binned, st, parts ? w.jac : nullptr));
     else
         NVR_TRY(launch_scatter(gp, n, n_dev, cap, x, table_half, w.dfeat, dtable, parts, w.binned,
-                               st, counted && features_ready, 1024, 512));
+                               st, counted && features_ready, 1024, 512, parts ? w.jac : nullptr));
     if (dx) {
         dn_dx_total<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n, n_dev, cap, w.dx_parts,
                                                                    dx_can, dx);

@@ -149,7 +149,7 @@ template <bool PLANAR, typename OutT, bool COUNT, bool QUAD>
 __global__ void __launch_bounds__(256)
 encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
                  const float *__restrict__ x, const uint32_t *__restrict__ table,
-                 OutT *__restrict__ feat, TileCounter cnt) {
+                 OutT *__restrict__ feat, TileCounter cnt, uint32_t *__restrict__ jac) {
     extern __shared__ uint32_t hist[];    // COUNT: [lpg][cnt.level_tiles]
     const int64_t count = count_of(n, n_dev, cap);
     const int g = blockIdx.x % kXcds;
@@ -206,6 +206,28 @@ encode_fwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
                     float w = corner_weight(lp, k);
                     a0 += w * f16_bits_to_f32((uint16_t)(v[k] & 0xffffu));
                     a1 += w * f16_bits_to_f32((uint16_t)(v[k] >> 16));
+                }
+                if (PLANAR && jac != nullptr) {
+                    // the level's spatial derivatives in cell units, d feature f / d axis a
+                    // (the trilinear weights' derivatives against the corner values), one
+                    // fp16 pair (f = 0, 1) per axis, for the backward's position gradient
+                    float j0[3] = {0.f, 0.f, 0.f}, j1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const float3 dw = corner_dweight(lp, k);
+                        const float f0 = f16_bits_to_f32((uint16_t)(v[k] & 0xffffu));
+                        const float f1 = f16_bits_to_f32((uint16_t)(v[k] >> 16));
+                        j0[0] += dw.x * f0;
+                        j0[1] += dw.y * f0;
+                        j0[2] += dw.z * f0;
+                        j1[0] += dw.x * f1;
+                        j1[1] += dw.y * f1;
+                        j1[2] += dw.z * f1;
+                    }
+                    uint32_t *o = jac + ((size_t)g * cap + s) * (3 * lpg) + 3 * m;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        o[a] = (uint32_t)f32_to_f16_bits(j0[a]) | ((uint32_t)f32_to_f16_bits(j1[a]) << 16);
                 }
             }
             if (PLANAR) {
@@ -298,10 +320,12 @@ encode_bwd_split(GridParams p, int64_t n, const int32_t *__restrict__ n_dev, int
 nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
                              void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st,
-                             const TileCounter *counter, int chunks_cap) {
+                             const TileCounter *counter, int chunks_cap, uint32_t *jac) {
     if (cap <= 0) return NVR_OK;
     NVR_REQUIRE(counter == nullptr || (table_dtype != NVR_F32 && planar && feat_dtype == NVR_F16),
                 NVR_EUNSUPPORTED, "tile counting needs the planar fp16 gather");
+    NVR_REQUIRE(jac == nullptr || (table_dtype != NVR_F32 && planar && feat_dtype == NVR_F16),
+                NVR_EUNSUPPORTED, "the stored derivatives need the planar fp16 gather");
     if (table_dtype == NVR_F32) {
         unsigned gr = grid_for(cap * p.L, 256);
         if (feat_dtype == NVR_F32)
@@ -323,20 +347,21 @@ nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_de
     do {                                                                                      \
         if (quad)                                                                             \
             encode_fwd_split<PL, T, false, true><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x, tb, \
-                                                                     (T *)feat, none);        \
+                                                                     (T *)feat, none, jac);   \
         else                                                                                  \
             encode_fwd_split<PL, T, false, false><<<gr, 256, 0, st>>>(p, n, n_dev, cap, x,    \
-                                                                      tb, (T *)feat, none);   \
+                                                                      tb, (T *)feat, none,    \
+                                                                      PL ? jac : nullptr);    \
     } while (0)
         if (counter != nullptr) {
             const int lpg = (p.L + kXcds - 1) / kXcds;
             const size_t lds = sizeof(uint32_t) * lpg * counter->level_tiles;
             if (quad)
                 encode_fwd_split<true, f16_t, true, true><<<gr, 256, lds, st>>>(
-                    p, n, n_dev, cap, x, tb, (f16_t *)feat, *counter);
+                    p, n, n_dev, cap, x, tb, (f16_t *)feat, *counter, jac);
             else
                 encode_fwd_split<true, f16_t, true, false><<<gr, 256, lds, st>>>(
-                    p, n, n_dev, cap, x, tb, (f16_t *)feat, *counter);
+                    p, n, n_dev, cap, x, tb, (f16_t *)feat, *counter, jac);
         } else if (planar) {
             if (feat_dtype == NVR_F32) NVR_SPLIT_FWD(true, float);
             else if (feat_dtype == NVR_BF16) NVR_SPLIT_FWD(true, bf16_t);

@@ -171,11 +171,16 @@ struct TileCounter {
     int level_tiles;    // most tiles one level spans
 };
 
-// launchers (grid.hip)
+// launchers (grid.hip).  jac (nullable; planar fp16 gather only) receives,
+// per sample and level, the level's spatial derivatives in cell units: three
+// fp16 pairs (d feature 0, d feature 1 along axis a), level-group-planar
+// [8][cap][3 lpg] words (level g + 8 m at [g][s][3m, 3m + 3)), which the
+// binned scatter's position gradient reads instead of the table's corners.
 nvr_status launch_encode_fwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
                              void *feat, nvr_dtype feat_dtype, bool planar, hipStream_t st,
-                             const TileCounter *counter = nullptr, int chunks = 0);
+                             const TileCounter *counter = nullptr, int chunks = 0,
+                             uint32_t *jac = nullptr);
 nvr_status launch_encode_bwd(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                              const float *x, const void *table, nvr_dtype table_dtype,
                              const float *dfeat, float *dtable, float *dx, bool planar,

@@ -289,6 +289,18 @@ __device__ __forceinline__ float3 level_dx_sum(const uint32_t *__restrict__ tabl
     return make_float3(e0, e1, e2);
 }
 
+// The same sum from the derivatives the forward gather stored (three fp16
+// pairs, one per axis: d feature 0 and d feature 1 in cell units).
+__device__ __forceinline__ float3 stored_dx_sum(const uint32_t *__restrict__ j, float g0, float g1) {
+    float e[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t v = j[a];
+        e[a] = f16_bits_to_f32((uint16_t)(v & 0xffffu)) * g0 + f16_bits_to_f32((uint16_t)(v >> 16)) * g1;
+    }
+    return make_float3(e[0], e[1], e[2]);
+}
+
 // One chunk of blockDim.x samples and one level at a time: the chunk's 8 records
 // per sample are ranked within their tiles (LDS counters), space is reserved
 // per tile with one global atomic, the records are staged in LDS in tile order
@@ -299,7 +311,8 @@ __global__ void __launch_bounds__(BLOCK)
 scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict__ n_dev,
              int64_t cap, const float *__restrict__ x, const uint32_t *__restrict__ table,
              const float *__restrict__ dfeat, uint32_t n_records, uint32_t *__restrict__ cursor,
-             uint2 *__restrict__ recs, float *__restrict__ dx_parts) {
+             uint2 *__restrict__ recs, float *__restrict__ dx_parts,
+             const uint32_t *__restrict__ jac) {
     extern __shared__ uint32_t lds[];
     uint32_t *hist = lds;                               // [lt] counts, then offsets
     uint32_t *delta = hist + lt;                        // [lt] global - local position
@@ -346,7 +359,9 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                     v1[k] = w * g1;
                 }
                 float3 ed = make_float3(0.f, 0.f, 0.f);
-                if (dx_parts != nullptr) ed = level_dx_sum(table, ent, quad, lp, g0, g1);
+                if (dx_parts != nullptr)
+                    ed = jac != nullptr ? stored_dx_sum(jac + ((size_t)g * cap + s) * (3 * LPG) + 3 * m, g0, g1)
+                                        : level_dx_sum(table, ent, quad, lp, g0, g1);
                 // ranks inside the tiles; the two corners of an x edge (2j, 2j + 1)
                 // fall into one tile but rarely, and then take one counter update
 #pragma unroll
@@ -595,7 +610,7 @@ nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st) {
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
                           float *dx_parts, void *ws, hipStream_t st, bool counted,
-                          int emit_chunks, int emit_block) {
+                          int emit_chunks, int emit_block, const uint32_t *jac) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
     const int tb = tile_bits(p);
@@ -622,13 +637,14 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     do {                                                                                       \
         if (eb == 512)                                                                         \
             scatter_emit<LP, 512><<<gre, 512, elds, st>>>(p, tb, lt, n, n_dev, cap, x,         \
-                (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts);         \
+                (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts, jac);    \
         else if (eb == 256)                                                                    \
             scatter_emit<LP, 256><<<gre, 256, elds, st>>>(p, tb, lt, n, n_dev, cap, x,         \
-                (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts);         \
+                (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts, jac);    \
         else                                                                                   \
             scatter_emit<LP, kEmitBlock><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n, n_dev,   \
-                cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts); \
+                cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts,  \
+                jac);                                                                          \
     } while (0)
     // opt in to more than 64 KiB of dynamic LDS, once per device
     int dev = 0;
@@ -835,7 +851,7 @@ __global__ void __launch_bounds__(kDetBlock)
 det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__restrict__ n_dev,
          int64_t cap, const float *__restrict__ x, const uint32_t *__restrict__ table,
          const float *__restrict__ dfeat, uint32_t n_records, const uint32_t *__restrict__ seg,
-         uint2 *__restrict__ recs, float *__restrict__ dx_parts) {
+         uint2 *__restrict__ recs, float *__restrict__ dx_parts, const uint32_t *__restrict__ jac) {
     extern __shared__ uint32_t lds[];
     uint32_t *hist = lds;                               // [lt] chunk totals, then bases
     uint32_t *delta = hist + lt;                        // [lt] global - local position
@@ -892,7 +908,9 @@ det_emit(GridParams p, int tb, int lt, DetSeg sg, int64_t n, const int32_t *__re
                     v1[k] = w * g1;
                 }
                 float3 ed = make_float3(0.f, 0.f, 0.f);
-                if (dx_parts != nullptr) ed = level_dx_sum(table, ent, quad, lp, g0, g1);
+                if (dx_parts != nullptr)
+                    ed = jac != nullptr ? stored_dx_sum(jac + ((size_t)g * cap + s) * (3 * LPG) + 3 * m, g0, g1)
+                                        : level_dx_sum(table, ent, quad, lp, g0, g1);
                 if (dx_parts != nullptr) {
                     if (lp.inside[0]) d0 += ed.x * p.s_hi[l][0];
                     if (lp.inside[1]) d1 += ed.y * p.s_hi[l][1];
@@ -1157,7 +1175,8 @@ det_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ 
 
 nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                               const float *x, const void *table, const float *dfeat,
-                              float *dtable, float *dx_parts, void *ws, hipStream_t st) {
+                              float *dtable, float *dx_parts, void *ws, hipStream_t st,
+                              const uint32_t *jac) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
     const int tb = tile_bits(p);
@@ -1216,10 +1235,10 @@ nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_d
     const size_t elds = det_lds_bytes(lt);
     const uint32_t *tab = (const uint32_t *)table;
     switch (lpg) {
-    case 1: det_emit<1><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
-    case 2: det_emit<2><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
-    case 3: det_emit<3><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
-    default: det_emit<4><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts); break;
+    case 1: det_emit<1><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts, jac); break;
+    case 2: det_emit<2><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts, jac); break;
+    case 3: det_emit<3><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts, jac); break;
+    default: det_emit<4><<<gr, kDetBlock, elds, st>>>(p, tb, lt, sg, n, n_dev, cap, x, tab, dfeat, n_records, seg, w.rec, dx_parts, jac); break;
     }
     NVR_LAUNCHED();
     if (dtable == nullptr) return NVR_OK;

@@ -15,16 +15,21 @@ nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st);
 // (nullable) receives the [8][cap][3] per-group position-gradient partials.
 // counted: the tile counts in ws were already formed (zeroed, then counted by
 // the forward gather over the same positions); otherwise they are counted here.
+// jac (nullable): the spatial derivatives the forward gather stored for these
+// positions (launch_encode_fwd); with it the position gradient reads them
+// instead of the table's corner values.
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
                           float *dx_parts, void *ws, hipStream_t st,
-                          bool counted = false, int emit_chunks = 0, int emit_block = 0);
+                          bool counted = false, int emit_chunks = 0, int emit_block = 0,
+                          const uint32_t *jac = nullptr);
 // The deterministic variant: same records, order fixed by the inputs (tile
 // counts formed by its own pass; no launch-shape choices).
 size_t scatter_det_ws_bytes(const GridParams &p, int64_t cap);
 nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                               const float *x, const void *table, const float *dfeat,
-                              float *dtable, float *dx_parts, void *ws, hipStream_t st);
+                              float *dtable, float *dx_parts, void *ws, hipStream_t st,
+                              const uint32_t *jac = nullptr);
 // Row-major feature gradients [cap][2L] (regrouped first), device-side count;
 // det selects the deterministic scatter.
 size_t scatter_rows_ws_bytes(const GridParams &p, int64_t cap, bool det);

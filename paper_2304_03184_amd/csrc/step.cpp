@@ -17,7 +17,7 @@ struct FieldWs {
     int64_t cap = 0, n_rays = 0;
     int precision = -1;
     int has_warp = 0, n_in = 0, has_deform = 0;
-    size_t mlp_bytes = 0, scatter_bytes = 0, deform_bytes = 0;
+    size_t mlp_bytes = 0, scatter_bytes = 0, deform_bytes = 0, jac_bytes = 0;
     void *block = nullptr;          // one allocation, carved below
     int32_t *off, *ray_id, *n_dev, *march_ws;
     float *t, *dt, *x, *xc;
@@ -25,6 +25,8 @@ struct FieldWs {
     float *sigma, *rgb, *dsigma, *drgb;
     float *dfeat;                   // f32 planar [8][cap][4] | f32 [cap][n_in]
     float *dx;                      // [8][cap][3] (split) | [cap][3] (plain)
+    uint32_t *jac;                  // bf16 training of a warped field: the gather's spatial
+                                    // derivatives [8][cap][3 lpg] (fp16 pairs)
     void *mlp_ws;
     void *scatter_ws;               // binned table-gradient scatter (bf16 training)
     float *sh;                      // bf16 path: per-ray SH coefficients [n_rays][16]
@@ -112,6 +114,10 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         (train && precision == NVR_BF16)
             ? (deterministic(ctx) ? scatter_det_ws_bytes(gp, cap) : scatter_ws_bytes(gp, cap))
             : 0;
+    const size_t jac_bytes =
+        (train && precision == NVR_BF16 && f->has_warp)
+            ? sizeof(uint32_t) * 3 * kXcds * (size_t)((f->grid.n_levels + kXcds - 1) / kXcds) * cap
+            : 0;
     const int has_deform = f->deform ? 1 : 0;
     if (has_deform) NVR_TRY(deform_setup());
     const size_t deform_bytes =
@@ -121,7 +127,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     if (w.block && w.cap >= cap && w.n_rays >= n_rays && w.precision == precision &&
         w.has_warp == f->has_warp && w.n_in == net.n_in && w.mlp_bytes >= mlp_bytes &&
         w.scatter_bytes >= scatter_bytes && w.has_deform == has_deform &&
-        w.deform_bytes >= deform_bytes)
+        w.deform_bytes >= deform_bytes && w.jac_bytes >= jac_bytes)
         return NVR_OK;
     if (w.block) {
         NVR_HIP(hipDeviceSynchronize());
@@ -136,7 +142,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     }
     const bool bf = precision == NVR_BF16;
     const int nin = net.n_in;
-    size_t sz[22] = {
+    size_t sz[23] = {
         sizeof(int32_t) * (size_t)(n_rays + 1),             // off
         sizeof(int32_t) * (size_t)cap,                      // ray_id
         sizeof(int32_t) * 4,                                // n_dev
@@ -159,6 +165,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         has_deform ? sizeof(float) * 3 * (size_t)cap : 0,                      // dxd
         has_deform ? sizeof(float) * 3 * (size_t)cap : 0,                      // dxt
         deform_bytes,                                                          // deform
+        jac_bytes,                                                             // jac
     };
     size_t total = 0;
     for (size_t s : sz) total += up(s);
@@ -170,8 +177,8 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
         return NVR_ENOMEM;
     }
     char *p = (char *)blk;
-    void *ptr[22];
-    for (int i = 0; i < 22; ++i) {
+    void *ptr[23];
+    for (int i = 0; i < 23; ++i) {
         ptr[i] = sz[i] ? p : nullptr;
         p += up(sz[i]);
     }
@@ -185,6 +192,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.scatter_bytes = scatter_bytes;
     w.has_deform = has_deform;
     w.deform_bytes = deform_bytes;
+    w.jac_bytes = jac_bytes;
     w.off = (int32_t *)ptr[0];
     w.ray_id = (int32_t *)ptr[1];
     w.n_dev = (int32_t *)ptr[2];
@@ -207,6 +215,7 @@ static nvr_status ensure_ws(nvr_ctx *ctx, int k, const nvr_field *f, const Net &
     w.dxd = (float *)ptr[19];
     w.dxt = (float *)ptr[20];
     w.deform_ws = ptr[21];
+    w.jac = (uint32_t *)ptr[22];
     w.enc_chunks = w.mlp_fwd_blocks = w.mlp_bwd_blocks = w.emit_chunks = w.emit_block = 0;
     w.tuned = false;
     return NVR_OK;
@@ -243,8 +252,11 @@ static nvr_status field_forward(nvr_ctx *ctx, int k, const nvr_field *f, const N
             NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
         }
         // fp16 features and fp16 forward; the networks' backward products run in bf16
+        // (and, for a warped field, stores the spatial derivatives its position
+        // gradient needs)
         NVR_TRY(launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat, NVR_F16,
-                                  true, st, count ? &counter : nullptr, w.enc_chunks));
+                                  true, st, count ? &counter : nullptr, w.enc_chunks,
+                                  train && f->has_warp ? w.jac : nullptr));
         // the colour network's direction encoding, once per ray
         NVR_TRY(launch_sh_rays(net, n_rays, d, w.sh, st));
         NVR_TRY(mfma_fwd(net, 0, w.n_dev, cap, (const uint16_t *)w.feat, true, d, w.ray_id,
@@ -336,11 +348,12 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
             if (deterministic(ctx))
                 NVR_TRY(launch_scatter_det(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                            f->table_grad, f->has_warp ? w.dx : nullptr,
-                                           w.scatter_ws, st));
+                                           w.scatter_ws, st, f->has_warp ? w.jac : nullptr));
             else
                 NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                        f->table_grad, f->has_warp ? w.dx : nullptr, w.scatter_ws,
-                                       st, /*counted=*/true, w.emit_chunks, w.emit_block));
+                                       st, /*counted=*/true, w.emit_chunks, w.emit_block,
+                                       f->has_warp ? w.jac : nullptr));
             if (f->has_warp) NVR_TRY(warp_chain_bwd(ctx, f, w, kXcds, st));
         } else {
             PlainView F{(float *)w.feat, 1, nets[k].n_in};
@@ -489,7 +502,8 @@ static nvr_status autotune(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *cons
         NVR_TRY(pick(st, enc, 4, &w.enc_chunks, [&](int c) {
             NVR_TRY(launch_counter_reset(gp, w.scatter_ws, st));
             return launch_encode_fwd(gp, 0, w.n_dev, cap, pos, f->table_half, NVR_F16, w.feat,
-                                     NVR_F16, true, st, &counter, c);
+                                     NVR_F16, true, st, &counter, c,
+                                     f->has_warp ? w.jac : nullptr);
         }));
         NVR_TRY(pick(st, mlp_f, 4, &w.mlp_fwd_blocks, [&](int c) {
             return mfma_fwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d,
