@@ -51,7 +51,7 @@ def psnr(c, gt, mask):
     return -10.0 * math.log10(float(np.mean(e * e)))
 
 
-def keyframe_run(precision, steps, n_rays, eval_every, use_graph=True):
+def keyframe_run(precision, steps, n_rays, eval_every, use_graph=True, deterministic=False):
     """Losses per step and {step: PSNR of the novel view} of key-frame training."""
     from paper_2304_03184_amd import field as F
     work, f, scene, cams, occ, rng = synth.keyframe_workload()
@@ -59,7 +59,8 @@ def keyframe_run(precision, steps, n_rays, eval_every, use_graph=True):
     params = synth.xavier_params(f.layer_shapes(), rng)
     fld = F.Field(work, f, table, params, occ_words=occ)
     tr = F.Trainer([fld], n_rays, n_rays * 128, precision=precision,
-                   lambda_depth=work.lambda_depth, use_graph=use_graph)
+                   lambda_depth=work.lambda_depth, use_graph=use_graph,
+                   deterministic=deterministic)
     bo = torch.empty((n_rays, 3), device="cuda")
     bd = torch.empty((n_rays, 3), device="cuda")
     bC = torch.empty((n_rays, 3), device="cuda")

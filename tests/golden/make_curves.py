@@ -13,6 +13,12 @@ compare against (test infrastructure; calls only ``oracle/`` and ``synth/``).
   same oracle run with every warped position moved by U[-EPS, EPS] per
   coordinate (EPS the size of the float32 warp's rounding), which measures how
   fast the training trajectory itself separates under float32-sized errors.
+* ``curve_human_object_deform_r64_gradnoise.txt`` (``--perturb-grad REL``):
+  the same oracle run with an error of relative norm REL added to every
+  gradient array before each Adam update (each non-zero entry gets
+  REL * rms * U[-sqrt 3, sqrt 3], rms over the array's non-zero entries; zero
+  entries stay zero), REL = 5e-2 being the BF16 step's gradient bar: the
+  separation to expect from gradients carrying errors of that size.
 * ``curve_keyframes_4096.txt``: key-frame refinement (rays drawn per step from
   eight 1280x720 key frames of the analytic scene, colour + depth loss with
   the mask M(r) of Eq. 8 set for rays whose first hit lies in the field's box,
@@ -24,6 +30,7 @@ Usage (from the repository root):
     python tests/golden/make_curves.py human_object --steps 500
     python tests/golden/make_curves.py human_object_deform --steps 200
     python tests/golden/make_curves.py human_object_deform --steps 200 --perturb 2.5e-7
+    python tests/golden/make_curves.py human_object_deform --steps 200 --perturb-grad 5e-2
     python tests/golden/make_curves.py keyframes --steps 2000 --eval-every 250
 """
 import argparse
@@ -80,6 +87,10 @@ def main():
     ap.add_argument("--perturb", type=float, default=0.0,
                     help="move every warped position by U[-eps, eps] (seeded) per coordinate; "
                          "the curve file name gets a _perturbed suffix")
+    ap.add_argument("--perturb-grad", type=float, default=0.0,
+                    help="add an error of relative norm rel (seeded, uniform per non-zero entry) "
+                         "to every gradient array before each Adam update; the curve file name "
+                         "gets a _gradnoise suffix")
     ap.add_argument("--lr-decay", type=float, default=1.0,
                     help="update k uses lr * decay^(k-1); the key-frame curve file name "
                          "gets a _decay suffix when < 1")
@@ -89,7 +100,22 @@ def main():
         deform = args.which == "human_object_deform"
         work, st, o, d, C, D, ranges = human_object_state(deform)
         box = ((-1.0,) * 3, (1.0,) * 3)
-        suffix = "_perturbed" if args.perturb > 0 else ""
+        suffix = "_perturbed" if args.perturb > 0 else ("_gradnoise" if args.perturb_grad > 0 else "")
+        adam = optim.Adam()
+        if args.perturb_grad > 0:
+            gnoise = np.random.default_rng(7)
+            rel = args.perturb_grad
+
+            class NoisyAdam(optim.Adam):
+                def update(self, p, g, m, v, step, skip_zero=False):
+                    nz = g != 0.0
+                    if nz.any():
+                        rms = math.sqrt(float(np.mean(g[nz] ** 2)))
+                        u = gnoise.uniform(-math.sqrt(3.0), math.sqrt(3.0), size=np.shape(g))
+                        g = np.where(nz, g + rel * rms * u, 0.0)
+                    return super().update(p, g, m, v, step, skip_zero=skip_zero)
+
+            adam = NoisyAdam()
         path = os.path.join(HERE, f"curve_{args.which}_r64{suffix}.txt")
         if args.perturb > 0:
             from oracle import warp as owarp
@@ -105,7 +131,7 @@ def main():
             owarp.warp = noisy
         rows = []
         for i in range(args.steps):
-            r = ostep.train_step(work, st, o, d, C, D, ranges, box, apply=True)
+            r = ostep.train_step(work, st, o, d, C, D, ranges, box, adam=adam, apply=True)
             rows.append((i, r["loss"]))
             print(f"step {i} loss {r['loss']:.8f} ({time.time() - t0:.0f} s)", flush=True)
         with open(path, "w") as fh:
@@ -113,9 +139,11 @@ def main():
                      "# [0, 2812), object [2500, 3750)), one fixed batch, Adam lr 1e-2,\n"
                      "# colour + depth loss (Eq. 8, lambda_d = 1)"
                      f"{'; deformation network on the human field' if deform else ''}"
-                     f"{f'; warped positions moved by U[-{args.perturb:g}, {args.perturb:g}]' if args.perturb > 0 else ''}.\n"
+                     f"{f'; warped positions moved by U[-{args.perturb:g}, {args.perturb:g}]' if args.perturb > 0 else ''}"
+                     f"{f'; gradient errors of relative norm {args.perturb_grad:g}' if args.perturb_grad > 0 else ''}.\n"
                      f"# written by: python tests/golden/make_curves.py {args.which} --steps {args.steps}"
-                     f"{f' --perturb {args.perturb:g}' if args.perturb > 0 else ''}\n"
+                     f"{f' --perturb {args.perturb:g}' if args.perturb > 0 else ''}"
+                     f"{f' --perturb-grad {args.perturb_grad:g}' if args.perturb_grad > 0 else ''}\n"
                      "# columns: step loss\n")
             for i, l in rows:
                 fh.write(f"{i} {l:.10e}\n")

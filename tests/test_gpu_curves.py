@@ -43,24 +43,36 @@ def test_human_object_deform_loss_curve(precision):
     # warped points by centimetres per step and the trajectory is far more
     # sensitive than without it: the oracle's own curve, rerun with its warped
     # positions moved by float32-sized amounts (2.5e-7 m, stored beside it),
-    # separates by ~1% within five steps.  Each step's bound is the warp-free
-    # test's bar or 4x that separation so far, whichever is larger; the first
-    # loss (before any update) keeps the forward bar.
+    # separates by ~1% within five steps.  The BF16 path's gradients carry
+    # errors up to its gradient bar (5e-2 relative norm), so for it the
+    # oracle's rerun with errors of that size added to every gradient (also
+    # stored) gives the separation as well.  Each step's bound is the warp-free
+    # test's bar or 4x the separation so far, whichever is larger; the first
+    # loss (before any update) keeps the forward bar, and the second (one
+    # update) the warp-free test's bar.
     L = lib()
     ref = curves.load_curve("curve_human_object_deform_r64.txt")
-    pert = curves.load_curve("curve_human_object_deform_r64_perturbed.txt")
+    runs = ["curve_human_object_deform_r64_perturbed.txt"]
+    if precision == "bf16":
+        runs.append("curve_human_object_deform_r64_gradnoise.txt")
+    sep = np.zeros(ref.shape[0])
+    for name in runs:
+        pert = curves.load_curve(name)
+        sep = np.maximum(sep, np.abs(pert[:, 1] - ref[:, 1]) / ref[:, 1])
+    env = np.maximum.accumulate(sep)
     steps = ref.shape[0]
     prec = L.NVR_F32 if precision == "f32" else L.NVR_BF16
     got = curves.human_object_losses(prec, steps, use_graph=precision == "bf16", deform=True)
     rel = np.abs(got - ref[:, 1]) / ref[:, 1]
-    env = np.maximum.accumulate(np.abs(pert[:, 1] - ref[:, 1]) / ref[:, 1])
-    print(f"{precision} + deformation network: step 0 {rel[0]:.2e}, step 1 {rel[1]:.2e} "
-          f"(oracle separation {env[1]:.2e}), first 20 max {rel[:20].max():.2e} (separation "
-          f"{env[19]:.2e}), all {rel.max():.2e} ({env[-1]:.2e}), final {got[-1]:.6f} vs "
-          f"{ref[-1, 1]:.6f} (perturbed oracle {pert[-1, 1]:.6f})")
-    assert rel[0] < (1e-5 if precision == "f32" else 2e-2)
     first = 2e-5 if precision == "f32" else 3e-4
-    assert np.all(rel[:20] < np.maximum(first, 4 * env[:20]))
+    bound = np.maximum(first, 4 * env)
+    worst = int(np.argmax(rel[:20] / bound[:20]))
+    print(f"{precision} + deformation network: step 0 {rel[0]:.2e}, step 1 {rel[1]:.2e}, "
+          f"first 20: worst step {worst} {rel[worst]:.2e} (bound {bound[worst]:.2e}), all "
+          f"{rel.max():.2e} (separation {env[-1]:.2e}), final {got[-1]:.6f} vs {ref[-1, 1]:.6f}")
+    assert rel[0] < (1e-5 if precision == "f32" else 2e-2)
+    assert rel[1] < first
+    assert np.all(rel[:20] < bound[:20])
     assert rel.max() < max(2e-2, 4 * env[-1])
     assert rel[-1] < max(5e-3, 4 * env[-1])
 
@@ -85,3 +97,27 @@ def test_keyframe_training_psnr():
     assert rel[:10].max() < 1e-2
     assert psnr[last] > 30.0
     assert abs(psnr[last] - evals[last]) < 4.0
+
+
+def test_keyframe_training_deterministic():
+    # the same key-frame training with NVR_DETERMINISTIC: every sum has a fixed
+    # order, so two runs give the same loss at every step bit for bit and the
+    # same novel-view PSNR, and the run fits the scene as well as the oracle
+    # within the spread that rounding alone produces (the non-deterministic
+    # test's band).  The 0.1 dB comparison with the oracle is reported.
+    L = lib()
+    ref = curves.load_curve("curve_keyframes_4096.txt")
+    steps = ref.shape[0]
+    evals = {int(i): p for i, p in zip(ref[:, 0], ref[:, 2]) if np.isfinite(p)}
+    loss_a, psnr_a = curves.keyframe_run(L.NVR_BF16, steps, 4096, 250, deterministic=True)
+    loss_b, psnr_b = curves.keyframe_run(L.NVR_BF16, steps, 4096, 250, deterministic=True)
+    last = max(evals)
+    rel = np.abs(loss_a - ref[:, 1]) / ref[:, 1]
+    print(f"keyframes, deterministic: early rel {rel[:10].max():.2e}; PSNR at {last}: "
+          f"{psnr_a[last]:.3f} / {psnr_b[last]:.3f} dB, oracle {evals[last]:.3f} dB "
+          f"(difference {psnr_a[last] - evals[last]:+.3f} dB)")
+    assert np.array_equal(loss_a, loss_b)
+    assert psnr_a == psnr_b
+    assert rel[:10].max() < 1e-2
+    assert psnr_a[last] > 30.0
+    assert abs(psnr_a[last] - evals[last]) < 4.0
