@@ -858,18 +858,30 @@ dn_dw_reduce(int parts, int rows, int ncol, int out_rows, int in_cols,
 // The pose part of the first layer, from s[u] = sum over the points of dZ0[u]
 // (the ones column, column `col` of the layer-0 partials, summed in order):
 // dW0[u][32 + c] += s[u] theta[c] and (nullable) dtheta[c] += sum_u W0[u][32 + c] s[u].
-__global__ void __launch_bounds__(kWidth)
+// One workgroup of kPoseSplit x kWidth threads: thread (k, u) sums the parts
+// k, k + kPoseSplit, ... of unit u (independent loads, several in flight), and
+// the kPoseSplit sums of a unit are added in k order: a fixed order.
+constexpr int kPoseSplit = 8;
+__global__ void __launch_bounds__(kPoseSplit * kWidth)
 dn_pose_grad(int parts, int ncol, int col, const float *__restrict__ partial,
              const float *__restrict__ params, const float *__restrict__ theta,
              float *__restrict__ dparams, float *__restrict__ dtheta) {
+    __shared__ float sk[kPoseSplit][kWidth];
     __shared__ float su[kWidth];
-    const int u = threadIdx.x;
+    const int u = threadIdx.x % kWidth, k = threadIdx.x / kWidth;
     float a = 0.f;
-    for (int b = 0; b < parts; ++b) a += partial[((int64_t)b * kWidth + u) * ncol + col];
-    su[u] = a;
-    for (int c = 0; c < kPose; ++c) dparams[(int64_t)u * kIn + kFeat + c] += a * theta[c];
+#pragma unroll 8
+    for (int b = k; b < parts; b += kPoseSplit) a += partial[((int64_t)b * kWidth + u) * ncol + col];
+    sk[k][u] = a;
     __syncthreads();
-    if (dtheta != nullptr && u < kPose) {
+    if (k == 0) {
+        a = 0.f;
+        for (int j = 0; j < kPoseSplit; ++j) a += sk[j][u];
+        su[u] = a;
+        for (int c = 0; c < kPose; ++c) dparams[(int64_t)u * kIn + kFeat + c] += a * theta[c];
+    }
+    __syncthreads();
+    if (dtheta != nullptr && k == 0 && u < kPose) {
         float t = 0.f;
         for (int v = 0; v < kWidth; ++v) t += params[(int64_t)v * kIn + kFeat + u] * su[v];
         dtheta[u] += t;
@@ -1051,8 +1063,8 @@ nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, 
                                       kWidth, kWidth, st)));
     // W0's feature columns: dZ0 x encoding, plus the sums of dZ0 for the pose
     NVR_TRY((mfma_dw<8, 2, true>(n, n_dev, cap, w, 0, 0, dparams, kWidth, kFeat, kIn, st)));
-    dn_pose_grad<<<1, kWidth, 0, st>>>(dw_parts(cap), 16 * 3, 16 * 2, w.partial, params, theta,
-                                       dparams, dtheta);
+    dn_pose_grad<<<1, kPoseSplit * kWidth, 0, st>>>(dw_parts(cap), 16 * 3, 16 * 2, w.partial,
+                                                    params, theta, dparams, dtheta);
     NVR_LAUNCHED();
     float *parts = dx ? w.dx_parts : nullptr;
     if (det)

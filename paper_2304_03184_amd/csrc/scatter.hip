@@ -10,8 +10,8 @@
 //           LDS histograms are added into per-tile counts;
 //   scan    one workgroup turns the counts into tile ranges, resets the append
 //           cursors and splits every tile into work items of <= 2^17 records
-//           (a hashed-level tile is one item; the coarse dense tiles, which
-//           every sample hits, are split);
+//           (fewer for small capacities; a hashed-level tile is one item, the
+//           coarse dense tiles, which every sample hits, are split);
 //   emit    the contributions (entry, w * dfeat_0, w * dfeat_1) are recomputed
 //           and appended to their tile's range: ranks come from LDS counters,
 //           one global atomic per (workgroup chunk, tile) reserves the space;
@@ -44,7 +44,6 @@ namespace nvr {
 constexpr int kMinTileBits = 10;   // 8 KiB of float2 sums + 1 KiB of tags per wave
 constexpr int kMaxTileBits = 14;
 constexpr int kMaxTiles = 8192;
-constexpr uint32_t kItemRecords = 1u << 17;
 constexpr int kBinBlock = 256;     // count
 constexpr int kEmitBlock = 1024;   // emit: samples per chunk (default; 512 and 256 also built)
 constexpr int kMaxLpg = 4;   // levels per group (L <= 32)
@@ -56,8 +55,18 @@ static size_t emit_lds_bytes(int block, int lt) {
 }
 constexpr size_t kRecPad = 512;   // records of padding after the record buffer (one accum window)
 
+// Records per work item of a split tile: 2^17, or fewer (down to 2^13) when the
+// capacity's records would make fewer than 2048 items, so that the coarse dense
+// tiles of a small call (every sample hits them) are not summed by a few waves.
+static uint32_t item_records(int64_t cap, int L) {
+    const int64_t want = (int64_t)cap * L * 8 / 2048;
+    uint32_t r = 1u << 13;
+    while (r < (1u << 17) && (int64_t)(r << 1) <= want) r <<= 1;
+    return r;
+}
+
 static int64_t max_items_of(int64_t cap, int L, int nt) {
-    return (int64_t)cap * L * 8 / kItemRecords + nt + 1;
+    return (int64_t)cap * L * 8 / item_records(cap, L) + nt + 1;
 }
 
 // smallest tile size (>= 2^10 entries) that keeps the tile count <= 8192
@@ -153,7 +162,7 @@ scatter_count(GridParams p, int tb, int n_tiles, int64_t n, const int32_t *__res
 __global__ void __launch_bounds__(1024)
 scatter_scan(int n_tiles, const uint32_t *__restrict__ tile_count, uint32_t *__restrict__ start,
              uint32_t *__restrict__ cursor, uint32_t *__restrict__ item_start,
-             uint32_t *__restrict__ n_items) {
+             uint32_t *__restrict__ n_items, uint32_t item) {
     __shared__ uint32_t a[1024], b[1024];
     __shared__ uint32_t carry_r, carry_i;
     if (threadIdx.x == 0) {
@@ -164,7 +173,7 @@ scatter_scan(int n_tiles, const uint32_t *__restrict__ tile_count, uint32_t *__r
     for (int base = 0; base < n_tiles; base += 1024) {
         const int t = base + threadIdx.x;
         const uint32_t c = t < n_tiles ? tile_count[t] : 0u;
-        const uint32_t it = (c + kItemRecords - 1) / kItemRecords;
+        const uint32_t it = (c + item - 1) / item;
         a[threadIdx.x] = c;
         b[threadIdx.x] = it;
         __syncthreads();
@@ -305,8 +314,10 @@ __device__ __forceinline__ float3 stored_dx_sum(const uint32_t *__restrict__ j, 
 // per sample are ranked within their tiles (LDS counters), space is reserved
 // per tile with one global atomic, the records are staged in LDS in tile order
 // and then written out by consecutive threads to consecutive positions, so
-// that each tile's run is stored contiguously.
-template <int LPG, int BLOCK>
+// that each tile's run is stored contiguously.  DX: the position gradient is
+// formed as well (its own instantiation, so that the plain one keeps fewer
+// registers).
+template <int LPG, int BLOCK, bool DX>
 __global__ void __launch_bounds__(BLOCK)
 scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict__ n_dev,
              int64_t cap, const float *__restrict__ x, const uint32_t *__restrict__ table,
@@ -359,7 +370,7 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                     v1[k] = w * g1;
                 }
                 float3 ed = make_float3(0.f, 0.f, 0.f);
-                if (dx_parts != nullptr)
+                if (DX)
                     ed = jac != nullptr ? stored_dx_sum(jac + ((size_t)g * cap + s) * (3 * LPG) + 3 * m, g0, g1)
                                         : level_dx_sum(table, ent, quad, lp, g0, g1);
                 // ranks inside the tiles; the two corners of an x edge (2j, 2j + 1)
@@ -372,7 +383,7 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
                     rank[2 * j] = r;
                     rank[2 * j + 1] = t0 == t1 ? r + 1u : atomicAdd(&hist[t1], 1u);
                 }
-                if (dx_parts != nullptr) {
+                if (DX) {
                     if (lp.inside[0]) d0 += ed.x * p.s_hi[l][0];
                     if (lp.inside[1]) d1 += ed.y * p.s_hi[l][1];
                     if (lp.inside[2]) d2 += ed.z * p.s_hi[l][2];
@@ -402,7 +413,7 @@ scatter_emit(GridParams p, int tb, int lt, int64_t n, const int32_t *__restrict_
             }
             __syncthreads();
         }
-        if (valid && dx_parts != nullptr) {   // per-group partials, summed by the consumer
+        if (valid && DX) {   // per-group partials, summed by the consumer
             float *o = dx_parts + ((size_t)g * cap + s) * 3;
             o[0] = d0;
             o[1] = d1;
@@ -417,7 +428,7 @@ __global__ void __launch_bounds__(64)
 scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
               const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
               const uint2 *__restrict__ recs, float2 *__restrict__ dtable,
-              float2 *__restrict__ partial) {
+              float2 *__restrict__ partial, uint32_t item) {
     extern __shared__ float2 acc[];                                   // [te] sums
     const uint32_t te = 1u << tb;
     uint8_t *tag = reinterpret_cast<uint8_t *>(acc + te);            // [te]
@@ -433,8 +444,8 @@ scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restric
         }
         const int t = lo;
         const uint32_t first = it - item_start[t];
-        const uint32_t r0 = start[t] + first * kItemRecords;
-        const uint32_t r1e = r0 + kItemRecords;
+        const uint32_t r0 = start[t] + first * item;
+        const uint32_t r1e = r0 + item;
         const uint32_t r1 = r1e < start[t + 1] ? r1e : start[t + 1];
         const bool owner = (item_start[t + 1] - item_start[t]) == 1u;
         for (uint32_t i = lane; i < te; i += 64) acc[i] = make_float2(0.f, 0.f);
@@ -630,21 +641,27 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
                                                                       w.count);
         NVR_LAUNCHED();
     }
-    scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items);
+    scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items,
+                                     item_records(cap, p.L));
     NVR_LAUNCHED();
     const int lpg = (p.L + kXcds - 1) / kXcds;
-#define NVR_EMIT(LP)                                                                           \
+#define NVR_EMIT_DX(LP, DXV)                                                                   \
     do {                                                                                       \
         if (eb == 512)                                                                         \
-            scatter_emit<LP, 512><<<gre, 512, elds, st>>>(p, tb, lt, n, n_dev, cap, x,         \
+            scatter_emit<LP, 512, DXV><<<gre, 512, elds, st>>>(p, tb, lt, n, n_dev, cap, x,    \
                 (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts, jac);    \
         else if (eb == 256)                                                                    \
-            scatter_emit<LP, 256><<<gre, 256, elds, st>>>(p, tb, lt, n, n_dev, cap, x,         \
+            scatter_emit<LP, 256, DXV><<<gre, 256, elds, st>>>(p, tb, lt, n, n_dev, cap, x,    \
                 (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts, jac);    \
         else                                                                                   \
-            scatter_emit<LP, kEmitBlock><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n, n_dev,   \
-                cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec, dx_parts,  \
-                jac);                                                                          \
+            scatter_emit<LP, kEmitBlock, DXV><<<gre, kEmitBlock, elds, st>>>(p, tb, lt, n,     \
+                n_dev, cap, x, (const uint32_t *)table, dfeat, n_records, w.cursor, w.rec,     \
+                dx_parts, jac);                                                                \
+    } while (0)
+#define NVR_EMIT(LP)                                                                           \
+    do {                                                                                       \
+        if (dx_parts != nullptr) NVR_EMIT_DX(LP, true);                                        \
+        else NVR_EMIT_DX(LP, false);                                                           \
     } while (0)
     // opt in to more than 64 KiB of dynamic LDS, once per device
     int dev = 0;
@@ -653,14 +670,16 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     const uint64_t dev_bit = 1ull << (dev & 63);
     if (!(emit_lds_ok.load() & dev_bit)) {
         const int most = (int)emit_lds_bytes(kEmitBlock, kMaxLevelTiles);
-        const void *fns[] = {(const void *)scatter_emit<1, kEmitBlock>,
-                             (const void *)scatter_emit<2, kEmitBlock>,
-                             (const void *)scatter_emit<3, kEmitBlock>,
-                             (const void *)scatter_emit<4, kEmitBlock>,
-                             (const void *)scatter_emit<1, 512>, (const void *)scatter_emit<2, 512>,
-                             (const void *)scatter_emit<3, 512>, (const void *)scatter_emit<4, 512>,
-                             (const void *)scatter_emit<1, 256>, (const void *)scatter_emit<2, 256>,
-                             (const void *)scatter_emit<3, 256>, (const void *)scatter_emit<4, 256>};
+#define NVR_EMIT_FNS(DXV)                                                                      \
+    (const void *)scatter_emit<1, kEmitBlock, DXV>, (const void *)scatter_emit<2, kEmitBlock, DXV>, \
+        (const void *)scatter_emit<3, kEmitBlock, DXV>,                                        \
+        (const void *)scatter_emit<4, kEmitBlock, DXV>, (const void *)scatter_emit<1, 512, DXV>, \
+        (const void *)scatter_emit<2, 512, DXV>, (const void *)scatter_emit<3, 512, DXV>,      \
+        (const void *)scatter_emit<4, 512, DXV>, (const void *)scatter_emit<1, 256, DXV>,      \
+        (const void *)scatter_emit<2, 256, DXV>, (const void *)scatter_emit<3, 256, DXV>,      \
+        (const void *)scatter_emit<4, 256, DXV>
+        const void *fns[] = {NVR_EMIT_FNS(false), NVR_EMIT_FNS(true)};
+#undef NVR_EMIT_FNS
         for (const void *f : fns)
             NVR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, most));
         emit_lds_ok.fetch_or(dev_bit);
@@ -672,6 +691,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     default: NVR_EMIT(4); break;
     }
 #undef NVR_EMIT
+#undef NVR_EMIT_DX
     NVR_LAUNCHED();
     if (dtable == nullptr) return NVR_OK;   // scan + emit only
     const int64_t max_items = max_items_of(cap, p.L, nt);
@@ -684,7 +704,8 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
         accum_lds_ok.fetch_or(dev_bit);
     }
     scatter_accum<<<ga, 64, acc_lds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
-                                           w.rec, (float2 *)dtable, w.partial);
+                                           w.rec, (float2 *)dtable, w.partial,
+                                           item_records(cap, p.L));
     NVR_LAUNCHED();
     scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
         tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
@@ -1017,7 +1038,7 @@ __global__ void __launch_bounds__(64)
 det_accum_min(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
               const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
               const uint2 *__restrict__ recs, float2 *__restrict__ dtable,
-              float2 *__restrict__ partial) {
+              float2 *__restrict__ partial, uint32_t item) {
     extern __shared__ float2 acc[];                                   // [te] sums
     const uint32_t te = 1u << tb;
     uint32_t *tag = reinterpret_cast<uint32_t *>(acc + te);          // [te]
@@ -1036,8 +1057,8 @@ det_accum_min(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restric
         }
         const int t = lo;
         const uint32_t first = it - item_start[t];
-        const uint32_t r0 = start[t] + first * kItemRecords;
-        const uint32_t r1e = r0 + kItemRecords;
+        const uint32_t r0 = start[t] + first * item;
+        const uint32_t r1e = r0 + item;
         const uint32_t r1 = r1e < start[t + 1] ? r1e : start[t + 1];
         const bool owner = (item_start[t + 1] - item_start[t]) == 1u;
         for (uint32_t i = lane; i < te; i += 64) acc[i] = make_float2(0.f, 0.f);
@@ -1113,7 +1134,7 @@ __global__ void __launch_bounds__(64)
 det_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
           const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
           const uint2 *__restrict__ recs, float2 *__restrict__ dtable,
-          float2 *__restrict__ partial) {
+          float2 *__restrict__ partial, uint32_t item) {
     extern __shared__ float2 acc[];                                   // [te] sums
     const uint32_t te = 1u << tb;
     uint2 *win = reinterpret_cast<uint2 *>(acc + te);                // [512] staged records
@@ -1131,8 +1152,8 @@ det_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ 
         }
         const int t = lo;
         const uint32_t first = it - item_start[t];
-        const uint32_t r0 = start[t] + first * kItemRecords;
-        const uint32_t r1e = r0 + kItemRecords;
+        const uint32_t r0 = start[t] + first * item;
+        const uint32_t r1e = r0 + item;
         const uint32_t r1 = r1e < start[t + 1] ? r1e : start[t + 1];
         const bool owner = (item_start[t + 1] - item_start[t]) == 1u;
         for (uint32_t i = lane; i < te; i += 64) acc[i] = make_float2(0.f, 0.f);
@@ -1217,7 +1238,8 @@ nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_d
     default: det_count<4><<<gr, kDetBlock, clds, st>>>(p, tb, sg, n, n_dev, cap, x, seg, w.count); break;
     }
     NVR_LAUNCHED();
-    scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items);
+    scatter_scan<<<1, 1024, 0, st>>>(nt, w.count, w.start, w.cursor, w.item_start, w.n_items,
+                                     item_records(cap, p.L));
     NVR_LAUNCHED();
     {
         const int S = sg.at[p.L];
@@ -1247,11 +1269,12 @@ nvr_status launch_scatter_det(const GridParams &p, int64_t n, const int32_t *n_d
     if ((1u << tb) <= kDetFastEntries) {
         const size_t alds = (sizeof(float2) + sizeof(uint32_t)) << tb;
         det_accum_min<<<ga, 64, alds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
-                                            w.rec, (float2 *)dtable, w.partial);
+                                            w.rec, (float2 *)dtable, w.partial,
+                                            item_records(cap, p.L));
     } else {
         const size_t alds = (sizeof(float2) << tb) + sizeof(uint2) * 512;
         det_accum<<<ga, 64, alds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
-                                        w.rec, (float2 *)dtable, w.partial);
+                                        w.rec, (float2 *)dtable, w.partial, item_records(cap, p.L));
     }
     NVR_LAUNCHED();
     scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
