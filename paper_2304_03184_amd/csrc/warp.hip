@@ -220,6 +220,16 @@ warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
 // LDS_ACC: node-motion gradients summed per workgroup in LDS; LDS_BONES: bone
 // gradients likewise (every sample touches the same few joints, so global
 // atomics per sample would serialise on them).
+constexpr int kRun = 8;   // consecutive samples per thread in the backward
+// adds a joint slot's register sums into the bone-gradient table
+#define NVR_FLUSH_BONE(k)                                                                      \
+    do {                                                                                       \
+        for (int e_ = 0; e_ < 12; ++e_) {                                                      \
+            if (LDS_BONES) atomicAdd(bacc + (size_t)bkey[k] * 12 + e_, bsum[k][e_]);           \
+            else unsafeAtomicAdd(d_bones + (size_t)bkey[k] * 12 + e_, bsum[k][e_]);            \
+        }                                                                                      \
+    } while (0)
+
 template <int KJ, int KN, bool LDS_ACC, bool LDS_BONES>
 __global__ void __launch_bounds__(kWarpBlock)
 warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int64_t n,
@@ -238,8 +248,24 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
         for (int i = threadIdx.x; i < n_bacc; i += blockDim.x) bacc[i] = 0.f;
     __syncthreads();
     const int64_t count = count_of(n, n_dev, cap);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    // Each thread takes runs of kRun consecutive samples, which nearly always
+    // share their nearest joints: the bone gradients of a joint slot are summed
+    // in registers while its joint stays the same and added to the table when
+    // it changes (and at the end), a small fraction of the per-sample adds.
+    int bkey[KJ];
+    float bsum[KJ][12];
+#pragma unroll
+    for (int k = 0; k < KJ; ++k) {
+        bkey[k] = -1;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) bsum[k][e] = 0.f;
+    }
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kRun; i0 < count;
+         i0 += nthreads * kRun)
+    for (int r = 0; r < kRun; ++r) {
+        const int64_t i = i0 + r;
+        if (i >= count) break;
         float3 gz = make_float3(0.f, 0.f, 0.f);
         for (int q = 0; q < n_parts; ++q) {
             const float *g = gz_parts + (size_t)q * part_stride + 3 * i;
@@ -306,21 +332,23 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
             gy = add3(gy, mul3(f.s[k] * gwk * f.w[k] * (-2.f * p.inv_r2), sub3(y, g)));
         }
         if (d_bones != nullptr) {
+            const float gys[3] = {gy.x, gy.y, gy.z};
+            const float xh[4] = {xv.x, xv.y, xv.z, 1.f};
 #pragma unroll
             for (int k = 0; k < KJ; ++k) {
                 if (k >= p.k_joints) continue;
-                const size_t jb = ((size_t)fr * p.n_joints + f.jsel[k]) * 12;
+                const int key = fr * p.n_joints + f.jsel[k];
+                if (bkey[k] != key) {
+                    if (bkey[k] >= 0) NVR_FLUSH_BONE(k);
+                    bkey[k] = key;
+#pragma unroll
+                    for (int e = 0; e < 12; ++e) bsum[k][e] = 0.f;
+                }
                 const float lw = f.lw[k];
-                const float gys[3] = {gy.x, gy.y, gy.z};
-                const float xh[4] = {xv.x, xv.y, xv.z, 1.f};
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int bb = 0; bb < 4; ++bb) {
-                        const float v = lw * gys[a] * xh[bb];
-                        if (LDS_BONES) atomicAdd(bacc + jb + 4 * a + bb, v);
-                        else unsafeAtomicAdd(d_bones + jb + 4 * a + bb, v);
-                    }
+                    for (int bb = 0; bb < 4; ++bb) bsum[k][4 * a + bb] += lw * gys[a] * xh[bb];
             }
         }
         if (dx_live != nullptr) {
@@ -357,6 +385,10 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
             dx_live[3 * i + 2] += gx.z;
         }
     }
+#pragma unroll
+    for (int k = 0; k < KJ; ++k)
+        if (bkey[k] >= 0) NVR_FLUSH_BONE(k);
+#undef NVR_FLUSH_BONE
     if (LDS_ACC || LDS_BONES) __syncthreads();
     if (LDS_ACC) {
         for (int i = threadIdx.x; i < n_acc; i += blockDim.x) {
