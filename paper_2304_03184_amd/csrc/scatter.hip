@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(64)
 scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restrict__ start,
               const uint32_t *__restrict__ item_start, const uint32_t *__restrict__ n_items,
               const uint2 *__restrict__ recs, float2 *__restrict__ dtable,
-              float2 *__restrict__ partial, uint32_t item) {
+              float2 *__restrict__ partial, uint32_t item, int dense_tiles) {
     extern __shared__ float2 acc[];                                   // [te] sums
     const uint32_t te = 1u << tb;
     uint8_t *tag = reinterpret_cast<uint8_t *>(acc + te);            // [te]
@@ -502,6 +502,25 @@ scatter_accum(int tb, int n_tiles, uint32_t n_entries, const uint32_t *__restric
                 loc[u] = key[u] - tbase;
                 // every record of the range is in the tile; the bound is a guard
                 pend[u] = rec >= r0 && rec < r1 && loc[u] < te;
+            }
+            // in the dense levels (tiles below dense_tiles) consecutive samples in
+            // one coarse cell leave a lane's window with the records of an x edge
+            // alternating (A B A B ...): the lane first sums the records of one
+            // entry that are one or two slots apart, so that the entry takes one
+            // round in this lane instead of several
+            if (t < dense_tiles)
+#pragma unroll
+            for (uint32_t u = 1; u < kPer; ++u) {
+#pragma unroll
+                for (uint32_t d = 1; d <= 2; ++d) {
+                    if (d > u) continue;
+                    const uint32_t w = u - d;
+                    if (pend[w] && pend[u] && loc[w] == loc[u]) {
+                        v0[u] += v0[w];
+                        v1[u] += v1[w];
+                        pend[w] = false;
+                    }
+                }
             }
             auto round = [&](uint32_t u) {
                 // wavefront-scope relaxed atomics: plain LDS byte accesses that
@@ -703,9 +722,12 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
                                     (int)accum_lds_bytes(kMaxTileBits)));
         accum_lds_ok.fetch_or(dev_bit);
     }
+    int dense_end = 0;   // levels are stored coarse to fine, the dense ones first
+    while (dense_end < p.L && p.dense[dense_end]) ++dense_end;
+    const int dense_tiles = (int)(((int64_t)p.off[dense_end] + (1 << tb) - 1) >> tb);
     scatter_accum<<<ga, 64, acc_lds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
                                            w.rec, (float2 *)dtable, w.partial,
-                                           item_records(cap, p.L));
+                                           item_records(cap, p.L), dense_tiles);
     NVR_LAUNCHED();
     scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
         tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
