@@ -471,6 +471,9 @@ constexpr int kBw4 = kBw0 + 8 * 64;           // W4^T: 8 row tiles, 8-byte opera
 constexpr int kBwd = kBw4 + 8 * 64 / 2;       // backward set: 6912 (108 KiB)
 constexpr int kDnBlock = 512;                 // 8 waves: two per SIMD around one fragment copy
 constexpr int kDnBwdBlock = 1024;             // backward: 16 waves (<= 128 registers each)
+// dynamic LDS: the fragment set plus a 1 KiB tile-staging area per wave
+constexpr int kFwdStoreLds = (int)(sizeof(uint4) * kFwd) + (kDnBlock / 64) * 1024;      // 116 KiB
+constexpr int kBwdLds = (int)(sizeof(uint4) * kBwd) + (kDnBwdBlock / 64) * 1024;        // 124 KiB
 
 // One lane-tile fragment per thread of the grid: forward (fp16, W rows) and
 // backward (bf16, W^T rows) sets, both with the chained contraction order.
@@ -544,17 +547,39 @@ __device__ __forceinline__ uint16_t bfbits(float v) {
 
 // Hidden layer l's activations of one block into its H tile and mask word
 // (lane g, c; zero for points past n).
+// One 32-unit slice of a block's unit-major tile ([unit][16 points], bf16)
+// stored through the wave's 1 KiB LDS staging area: every lane puts its
+// point's 8 values (slice units u[j]) there, then stores one 16-byte chunk,
+// so the slice leaves as 64 contiguous 16-byte stores instead of 512 2-byte
+// ones.  A wave's LDS operations complete in order; the empty asm statements
+// keep the compiler from moving the accesses across each other.
+__device__ __forceinline__ void dn_put_slice(uint16_t *stage, uint16_t *dst, const int (&u)[8],
+                                             const uint16_t (&v)[8], int lane, int c) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int j = 0; j < 8; ++j) stage[u[j] * 16 + c] = v[j];
+    asm volatile("" ::: "memory");
+    reinterpret_cast<uint4 *>(dst)[lane] = reinterpret_cast<const uint4 *>(stage)[lane];
+    asm volatile("" ::: "memory");
+}
+
 __device__ __forceinline__ void dn_store_hidden(const dh8 *hid, int l, uint16_t *H, uint32_t *mw,
-                                                int lane, int g, int c, bool valid) {
+                                                uint16_t *stage, int lane, int g, int c,
+                                                bool valid) {
     uint32_t m = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
+        int u[8];
+        uint16_t v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float v = (float)hid[q][j];
-            H[(kFeat + l * kWidth + dkh(q, g, j)) * 16 + c] = valid ? bfbits(v) : (uint16_t)0;
-            m |= (v > 0.f ? 1u : 0u) << (8 * q + j);
+            const float f = (float)hid[q][j];
+            u[j] = dkh(q, g, j) - 32 * q;
+            v[j] = valid ? bfbits(f) : (uint16_t)0;
+            m |= (f > 0.f ? 1u : 0u) << (8 * q + j);
         }
+        dn_put_slice(stage, H + (kFeat + l * kWidth + 32 * q) * 16, u, v, lane, c);
+    }
     mw[l * 64 + lane] = m;
 }
 
@@ -573,7 +598,8 @@ template <bool STORE = false>
 __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
                                              const float *__restrict__ bias4, dh8 x0, DnFwd &s,
                                              uint16_t *H = nullptr, uint32_t *mw = nullptr,
-                                             int lane = 0, bool valid = false) {
+                                             uint16_t *stage = nullptr, int lane = 0,
+                                             bool valid = false) {
     const int g = lane >> 4, c = lane & 15;
 #pragma unroll
     for (int m = 0; m < 8; ++m)
@@ -585,7 +611,7 @@ __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             s.hid[layer - 1][q] = dpackh(drelu(s.acc[2 * q]), drelu(s.acc[2 * q + 1]));
-        if (STORE) dn_store_hidden(s.hid[layer - 1], layer - 1, H, mw, lane, g, c, valid);
+        if (STORE) dn_store_hidden(s.hid[layer - 1], layer - 1, H, mw, stage, lane, g, c, valid);
         const int base = kFw1 + (layer - 1) * 32 * 64;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
@@ -600,7 +626,7 @@ __device__ __forceinline__ void dn_block_fwd(const uint4 *__restrict__ F,
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) s.hid[3][q] = dpackh(drelu(s.acc[2 * q]), drelu(s.acc[2 * q + 1]));
-    if (STORE) dn_store_hidden(s.hid[3], 3, H, mw, lane, g, c, valid);
+    if (STORE) dn_store_hidden(s.hid[3], 3, H, mw, stage, lane, g, c, valid);
     df4 o = dzero();
 #pragma unroll
     for (int q = 0; q < 4; ++q) o = dmfma(__builtin_bit_cast(dh8, F[kFw4 + q * 64]), s.hid[3][q], o);
@@ -629,9 +655,10 @@ dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
             const uint4 *__restrict__ gfwd, const float *__restrict__ x,
             float *__restrict__ x_can, uint16_t *__restrict__ hbuf,
             uint32_t *__restrict__ mwords) {
-    extern __shared__ uint4 F[];
+    extern __shared__ uint4 F[];   // [kFwd] fragments, then (STORE) 1 KiB staging per wave
     for (int i = threadIdx.x; i < kFwd; i += kDnBlock) F[i] = gfwd[i];
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    uint16_t *stage = reinterpret_cast<uint16_t *>(F + kFwd) + (threadIdx.x >> 6) * 512;
     const float *bias4 = bias + 4 * g;
     __syncthreads();
     n = count_of(n, n_dev, cap);
@@ -648,12 +675,18 @@ dn_fwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
         if (STORE) {
             // encoding: slot j = feature dfp(g, j); the hidden layers follow
             // in dn_block_fwd (slot j of K-step q = unit dkh(q, g, j))
+            int u[8];
+            uint16_t v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) H[dfp(g, j) * 16 + c] = bfbits((float)x0[j]);
+            for (int j = 0; j < 8; ++j) {
+                u[j] = dfp(g, j);
+                v[j] = bfbits((float)x0[j]);
+            }
+            dn_put_slice(stage, H, u, v, lane, c);
         }
         DnFwd s;
         dn_block_fwd<STORE>(F + lane, bias4, x0, s, H, STORE ? mwords + blk * 4 * 64 : nullptr,
-                            lane, valid);
+                            stage, lane, valid);
         if (g == 0 && valid && x_can != nullptr) {
             x_can[3 * p] = x[3 * p] + s.out[0];
             x_can[3 * p + 1] = x[3 * p + 1] + s.out[1];
@@ -671,9 +704,10 @@ dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
             const uint4 *__restrict__ gbwd, const uint32_t *__restrict__ mwords,
             const float *__restrict__ dxc, float *__restrict__ dfeat,
             uint16_t *__restrict__ zbuf) {
-    extern __shared__ uint4 Bt[];
+    extern __shared__ uint4 Bt[];   // [kBwd] fragments, then 1 KiB staging per wave
     for (int i = threadIdx.x; i < kBwd; i += kDnBwdBlock) Bt[i] = gbwd[i];
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    uint16_t *stage = reinterpret_cast<uint16_t *>(Bt + kBwd) + (threadIdx.x >> 6) * 512;
     __syncthreads();
     const uint4 *Bl = Bt + lane;
     const uint2 *B4 = reinterpret_cast<const uint2 *>(Bt + kBw4) + lane;
@@ -715,10 +749,14 @@ dn_bwd_mfma(int64_t n, const int32_t *__restrict__ n_dev, int64_t cap,
                     if (!((mask[layer] >> (8 * q + 4 + i)) & 1u)) d[2 * q + 1][i] = 0.f;
                 }
                 zb[q] = dpackb(d[2 * q], d[2 * q + 1]);
+                int u[8];
+                uint16_t v[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    Z[(layer * kWidth + dkh(q, g, j)) * 16 + c] =
-                        valid ? bfbits(j < 4 ? d[2 * q][j] : d[2 * q + 1][j - 4]) : (uint16_t)0;
+                for (int j = 0; j < 8; ++j) {
+                    u[j] = dkh(q, g, j) - 32 * q;
+                    v[j] = valid ? bfbits(j < 4 ? d[2 * q][j] : d[2 * q + 1][j - 4]) : (uint16_t)0;
+                }
+                dn_put_slice(stage, Z + (layer * kWidth + 32 * q) * 16, u, v, lane, c);
             }
             if (layer > 0) {
                 const int base = kBw1 + (layer - 1) * 32 * 64;
@@ -926,11 +964,9 @@ nvr_status dn_lds_opt_in() {
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(uint4) * kFwd)));
     NVR_HIP(hipFuncSetAttribute((const void *)dn_fwd_mfma<true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(uint4) * kFwd)));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kFwdStoreLds));
     NVR_HIP(hipFuncSetAttribute((const void *)dn_bwd_mfma,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(uint4) * kBwd)));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kBwdLds));
     done.fetch_or(bit);
     return NVR_OK;
 }
@@ -1004,7 +1040,7 @@ nvr_status mfma_forward(const GridParams &gp, int64_t n, const int32_t *n_dev, i
     NVR_TRY(mfma_prologue(gp, n, n_dev, cap, x, theta, table_half, params, w, true,
                           count ? &counter : nullptr, store, st));
     if (store)
-        dn_fwd_mfma<true><<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(
+        dn_fwd_mfma<true><<<dn_grid(cap), kDnBlock, kFwdStoreLds, st>>>(
             n, n_dev, cap, w.feat, w.bias, w.fwd, x, x_can, w.hbuf, w.mwords);
     else
         dn_fwd_mfma<false><<<dn_grid(cap), kDnBlock, sizeof(uint4) * kFwd, st>>>(
@@ -1049,7 +1085,7 @@ nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, 
     if (!features_ready)
         NVR_TRY(mfma_forward(gp, n, n_dev, cap, x, theta, table_half, params, nullptr, w, false,
                              true, st));
-    dn_bwd_mfma<<<dn_grid(cap, kDnBwdBlock), kDnBwdBlock, sizeof(uint4) * kBwd, st>>>(
+    dn_bwd_mfma<<<dn_grid(cap, kDnBwdBlock), kDnBwdBlock, kBwdLds, st>>>(
         n, n_dev, cap, w.bwd, w.mwords, dx_can, w.dfeat, w.zbuf);
     NVR_LAUNCHED();
     // W4 [3][128]: dZ4 rows at 512 (one tile) x H3 at 416
