@@ -221,6 +221,7 @@ warp_fwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
 // gradients likewise (every sample touches the same few joints, so global
 // atomics per sample would serialise on them).
 constexpr int kRun = 8;   // consecutive samples per thread in the backward
+constexpr int kNodeStride = 9;   // LDS words per node in the backward's gradient table
 // adds a joint slot's register sums into the bone-gradient table
 #define NVR_FLUSH_BONE(k)                                                                      \
     do {                                                                                       \
@@ -240,8 +241,10 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
     extern __shared__ float lds[];
     const int n_bacc = p.n_frames * p.n_joints * 12;
     float *bacc = lds;                                // [n_frames * n_joints * 12] if LDS_BONES
-    float *acc = bacc + (LDS_BONES ? n_bacc : 0);     // [n_frames * n_nodes * 8] if LDS_ACC
-    const int n_acc = p.n_frames * p.n_nodes * 8;
+    // [n_frames * n_nodes][kNodeStride] if LDS_ACC: a node's 8 sums padded to 9
+    // words, so that lanes adding to different nodes fall into different banks
+    float *acc = bacc + (LDS_BONES ? n_bacc : 0);
+    const int n_acc = p.n_frames * p.n_nodes * kNodeStride;
     if (LDS_ACC)
         for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0.f;
     if (LDS_BONES && d_bones != nullptr)
@@ -322,9 +325,9 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 const float v = sw * cs[c] * gb[c];
-                const size_t a = ((size_t)fr * p.n_nodes + id) * 8 + c;
-                if (LDS_ACC) atomicAdd(acc + a, v);
-                else unsafeAtomicAdd(d_dq + a, v);
+                const size_t key = (size_t)fr * p.n_nodes + id;
+                if (LDS_ACC) atomicAdd(acc + key * kNodeStride + c, v);
+                else unsafeAtomicAdd(d_dq + key * 8 + c, v);
                 gwk += cs[c] * q[c] * gb[c];
             }
             // weight w_k depends on y: dw/dy = w (-2 (y - g) / r^2)
@@ -392,8 +395,9 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
     if (LDS_ACC || LDS_BONES) __syncthreads();
     if (LDS_ACC) {
         for (int i = threadIdx.x; i < n_acc; i += blockDim.x) {
+            const int c = i % kNodeStride;
             const float v = acc[i];
-            if (v != 0.f) unsafeAtomicAdd(d_dq + i, v);
+            if (c < 8 && v != 0.f) unsafeAtomicAdd(d_dq + (size_t)(i / kNodeStride) * 8 + c, v);
         }
     }
     if (LDS_BONES && d_bones != nullptr) {
@@ -455,7 +459,7 @@ nvr_status launch_warp_bwd(const WarpParams &p, const nvr_warp_rig &rig, int64_t
                            const float *gz, int n_parts, int64_t part_stride, float *d_dq,
                            float *d_bones, float *dx_live, hipStream_t st) {
     if (cap <= 0) return NVR_OK;
-    const size_t acc_bytes = sizeof(float) * (size_t)p.n_frames * p.n_nodes * 8;
+    const size_t acc_bytes = sizeof(float) * (size_t)p.n_frames * p.n_nodes * kNodeStride;
     const size_t bone_bytes = sizeof(float) * (size_t)p.n_frames * p.n_joints * 12;
     const size_t base = 0;
     const bool lds_bones = bone_bytes <= 16 * 1024;
