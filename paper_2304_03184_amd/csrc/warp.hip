@@ -231,6 +231,15 @@ constexpr int kNodeStride = 9;   // LDS words per node in the backward's gradien
         }                                                                                      \
     } while (0)
 
+// adds a node slot's register sums into the node-gradient table
+#define NVR_FLUSH_NODE(k)                                                                      \
+    do {                                                                                       \
+        for (int c_ = 0; c_ < 8; ++c_) {                                                       \
+            if (LDS_ACC) atomicAdd(acc + (size_t)nkey[k] * kNodeStride + c_, nsum[k][c_]);     \
+            else unsafeAtomicAdd(d_dq + (size_t)nkey[k] * 8 + c_, nsum[k][c_]);               \
+        }                                                                                      \
+    } while (0)
+
 template <int KJ, int KN, bool LDS_ACC, bool LDS_BONES>
 __global__ void __launch_bounds__(kWarpBlock)
 warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int64_t n,
@@ -252,11 +261,18 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
     __syncthreads();
     const int64_t count = count_of(n, n_dev, cap);
     // Each thread takes runs of kRun consecutive samples, which nearly always
-    // share their nearest joints: the bone gradients of a joint slot are summed
-    // in registers while its joint stays the same and added to the table when
-    // it changes (and at the end), a small fraction of the per-sample adds.
-    int bkey[KJ];
-    float bsum[KJ][12];
+    // share their nearest joints and often their node list: the bone (node)
+    // gradients of a joint (node) slot are summed in registers while its joint
+    // (node) stays the same and added to the table when it changes (and at the
+    // end), a fraction of the per-sample adds.
+    int bkey[KJ], nkey[KN];
+    float bsum[KJ][12], nsum[KN][8];
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+        nkey[k] = -1;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) nsum[k][c] = 0.f;
+    }
 #pragma unroll
     for (int k = 0; k < KJ; ++k) {
         bkey[k] = -1;
@@ -322,12 +338,16 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
             const float sw = f.s[k] * f.w[k];
             const float *q = DQ + 8 * id;
             float gwk = 0.f;
+            const int key = fr * p.n_nodes + id;
+            if (nkey[k] != key) {
+                if (nkey[k] >= 0) NVR_FLUSH_NODE(k);
+                nkey[k] = key;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) nsum[k][c] = 0.f;
+            }
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                const float v = sw * cs[c] * gb[c];
-                const size_t key = (size_t)fr * p.n_nodes + id;
-                if (LDS_ACC) atomicAdd(acc + key * kNodeStride + c, v);
-                else unsafeAtomicAdd(d_dq + key * 8 + c, v);
+                nsum[k][c] += sw * cs[c] * gb[c];
                 gwk += cs[c] * q[c] * gb[c];
             }
             // weight w_k depends on y: dw/dy = w (-2 (y - g) / r^2)
@@ -391,7 +411,11 @@ warp_bwd_kernel(WarpParams p, nvr_warp_rig rig, const float *__restrict__ J, int
 #pragma unroll
     for (int k = 0; k < KJ; ++k)
         if (bkey[k] >= 0) NVR_FLUSH_BONE(k);
+#pragma unroll
+    for (int k = 0; k < KN; ++k)
+        if (nkey[k] >= 0) NVR_FLUSH_NODE(k);
 #undef NVR_FLUSH_BONE
+#undef NVR_FLUSH_NODE
     if (LDS_ACC || LDS_BONES) __syncthreads();
     if (LDS_ACC) {
         for (int i = threadIdx.x; i < n_acc; i += blockDim.x) {
