@@ -1081,7 +1081,7 @@ nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, 
                          const float *x, const float *theta, const void *table_half,
                          const float *params, const float *dx_can, float *dparams, float *dtable,
                          float *dx, float *dtheta, bool features_ready, bool counted, bool det,
-                         const DeformMfmaWs &w, hipStream_t st) {
+                         const DeformMfmaWs &w, hipStream_t st, const ScatterTail *tail) {
     if (!features_ready)
         NVR_TRY(mfma_forward(gp, n, n_dev, cap, x, theta, table_half, params, nullptr, w, false,
                              true, st));
@@ -1108,7 +1108,8 @@ nvr_status mfma_backward(const GridParams &gp, int64_t n, const int32_t *n_dev, 
                                    w.binned, st, parts ? w.jac : nullptr));
     else
         NVR_TRY(launch_scatter(gp, n, n_dev, cap, x, table_half, w.dfeat, dtable, parts, w.binned,
-                               st, counted && features_ready, 1024, 512, parts ? w.jac : nullptr));
+                               st, counted && features_ready, 1024, 512, parts ? w.jac : nullptr,
+                               tail));
     if (dx) {
         dn_dx_total<<<grid_for(cap * 3, 256, 16384), 256, 0, st>>>(n, n_dev, cap, w.dx_parts,
                                                                    dx_can, dx);
@@ -1224,7 +1225,7 @@ nvr_status run_bwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const i
                    int64_t cap, const float *x, const float *theta, const float *table,
                    const void *table_half, const float *params, const float *dx_can,
                    float *dparams, float *dtable, float *dx, float *dtheta, bool after_fwd,
-                   bool det, void *ws, hipStream_t st) {
+                   bool det, void *ws, hipStream_t st, const ScatterTail *tail = nullptr) {
     const GridParams gp = make_grid_params(g);
     if (matrix_cores) {
         DeformMfmaWs w;
@@ -1236,7 +1237,7 @@ nvr_status run_bwd(const nvr_grid_desc *g, bool matrix_cores, int64_t n, const i
             table_half = w.half;
         }
         return mfma_backward(gp, n, n_dev, cap, x, theta, table_half, params, dx_can, dparams,
-                             dtable, dx, dtheta, after_fwd, after_fwd && !det, det, w, st);
+                             dtable, dx, dtheta, after_fwd, after_fwd && !det, det, w, st, tail);
     }
     DeformWs w;
     carve(g, cap, det, static_cast<char *>(ws), &w);
@@ -1268,10 +1269,10 @@ nvr_status deform_bwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32
                           int64_t cap, const float *x, const float *theta, const float *table,
                           const void *table_half, const float *params, const float *dx_can,
                           float *dparams, float *dtable, float *dx, float *dtheta, bool det,
-                          void *ws, hipStream_t st) {
+                          void *ws, hipStream_t st, const ScatterTail *tail) {
     if (cap <= 0) return NVR_OK;
     return run_bwd(g, matrix_cores, 0, n_dev, cap, x, theta, table, table_half, params, dx_can,
-                   dparams, dtable, dx, dtheta, true, det, ws, st);
+                   dparams, dtable, dx, dtheta, true, det, ws, st, tail);
 }
 
 int64_t deform_param_count() { return kParams; }

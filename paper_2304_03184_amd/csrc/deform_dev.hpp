@@ -22,11 +22,14 @@ nvr_status deform_fwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32
                           bool det, void *ws, hipStream_t st);
 // After a training forward on the same workspace.  dparams, dtable, dx and
 // dtheta accumulate; dx and dtheta nullable.
+struct ScatterTail;
+// tail (nullable): second stream for the table gradient's accumulate (matrix
+// cores, non-deterministic scatter only)
 nvr_status deform_bwd_dev(const nvr_grid_desc *g, bool matrix_cores, const int32_t *n_dev,
                           int64_t cap, const float *x, const float *theta, const float *table,
                           const void *table_half, const float *params, const float *dx_can,
                           float *dparams, float *dtable, float *dx, float *dtheta, bool det,
-                          void *ws, hipStream_t st);
+                          void *ws, hipStream_t st, const ScatterTail *tail = nullptr);
 int64_t deform_param_count();
 // dst [cap][3] = sum of `parts` arrays src + p stride over the first *n_dev rows
 nvr_status launch_sum_parts(const int32_t *n_dev, int64_t cap, int parts, int64_t stride,

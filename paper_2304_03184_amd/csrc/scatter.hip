@@ -640,7 +640,8 @@ nvr_status launch_counter_reset(const GridParams &p, void *ws, hipStream_t st) {
 nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, int64_t cap,
                           const float *x, const void *table, const float *dfeat, float *dtable,
                           float *dx_parts, void *ws, hipStream_t st, bool counted,
-                          int emit_chunks, int emit_block, const uint32_t *jac) {
+                          int emit_chunks, int emit_block, const uint32_t *jac,
+                          const ScatterTail *tail) {
     if (cap <= 0) return NVR_OK;
     NVR_TRY(scatter_check(p));
     const int tb = tile_bits(p);
@@ -725,11 +726,17 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
     int dense_end = 0;   // levels are stored coarse to fine, the dense ones first
     while (dense_end < p.L && p.dense[dense_end]) ++dense_end;
     const int dense_tiles = (int)(((int64_t)p.off[dense_end] + (1 << tb) - 1) >> tb);
-    scatter_accum<<<ga, 64, acc_lds, st>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
+    hipStream_t sa = st;
+    if (tail != nullptr) {
+        NVR_HIP(hipEventRecord(tail->fork, st));
+        NVR_HIP(hipStreamWaitEvent(tail->stream, tail->fork, 0));
+        sa = tail->stream;
+    }
+    scatter_accum<<<ga, 64, acc_lds, sa>>>(tb, nt, p.off[p.L], w.start, w.item_start, w.n_items,
                                            w.rec, (float2 *)dtable, w.partial,
                                            item_records(cap, p.L), dense_tiles);
     NVR_LAUNCHED();
-    scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, st>>>(
+    scatter_reduce<<<dim3(((1u << tb) + 255) / 256, nt), 256, 0, sa>>>(
         tb, p.off[p.L], w.item_start, w.partial, (float2 *)dtable);
     NVR_LAUNCHED();
     return NVR_OK;

@@ -4,6 +4,16 @@
 
 namespace nvr {
 
+// Optional second stream for a scatter's accumulate and reduce launches: they
+// wait (fork event recorded on the caller's stream) for the launches before
+// them, and the caller joins the stream back before it reads the table
+// gradient; the work after the emit pass (which forms the position gradient)
+// then overlaps with them.
+struct ScatterTail {
+    hipStream_t stream;
+    hipEvent_t fork;
+};
+
 int scatter_tiles(const GridParams &p);
 size_t scatter_ws_bytes(const GridParams &p, int64_t cap);
 nvr_status scatter_check(const GridParams &p);
@@ -22,7 +32,7 @@ nvr_status launch_scatter(const GridParams &p, int64_t n, const int32_t *n_dev, 
                           const float *x, const void *table, const float *dfeat, float *dtable,
                           float *dx_parts, void *ws, hipStream_t st,
                           bool counted = false, int emit_chunks = 0, int emit_block = 0,
-                          const uint32_t *jac = nullptr);
+                          const uint32_t *jac = nullptr, const ScatterTail *tail = nullptr);
 // The deterministic variant: same records, order fixed by the inputs (tile
 // counts formed by its own pass; no launch-shape choices).
 size_t scatter_det_ws_bytes(const GridParams &p, int64_t cap);

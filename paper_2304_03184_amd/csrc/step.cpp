@@ -51,6 +51,10 @@ struct nvr_ctx {
     int device = 0;
     uint32_t flags = 0;
     hipStream_t capture = nullptr;
+    // second stream (default priority) on which a warped field's table-gradient
+    // accumulation overlaps its chain through the deformation network and warp
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join = nullptr;
     nvr::FieldWs ws[2];
     int comp_blocks = 0;           // compositing workgroups (autotuned; 0: default)
     float *ray_buf = nullptr;      // render: C, D per ray chunk
@@ -312,7 +316,7 @@ static nvr_status enqueue_fwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
 // Position gradient of the encoding (n_parts partial arrays in w.dx) back
 // through the deformation network, if any, and the warp.
 static nvr_status warp_chain_bwd(nvr_ctx *ctx, const nvr_field *f, FieldWs &w, int n_parts,
-                                 hipStream_t st) {
+                                 hipStream_t st, const ScatterTail *tail = nullptr) {
     const int64_t cap = w.cap;
     if (!f->deform)
         return run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dx, n_parts, 3 * cap,
@@ -327,14 +331,24 @@ static nvr_status warp_chain_bwd(nvr_ctx *ctx, const nvr_field *f, FieldWs &w, i
     NVR_TRY(deform_bwd_dev(&D->grid, w.precision == NVR_BF16, w.n_dev, cap, w.xc, D->theta,
                            D->table, D->table_half, D->params, dxd, D->params_grad,
                            D->table_grad, w.dxt, D->theta_grad, deterministic(ctx), w.deform_ws,
-                           st));
+                           st, tail));
     return run_warp_bwd(&f->warp, &f->rig, cap, w.n_dev, w.x, w.dxt, 1, 3 * cap, f->node_dq_grad,
                         f->bones_grad, st);
+}
+
+// A warped BF16 field's table-gradient accumulation (and its deformation
+// network's) runs on the context's second stream, overlapping the chain
+// through the network and the warp, which only needs the emit pass's position
+// gradient; the deterministic mode keeps one stream.
+static bool overlap(const nvr_ctx *ctx, const nvr_field *f) {
+    return f->has_warp && ctx->side != nullptr && !deterministic(ctx);
 }
 
 static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *const *fields,
                               const nvr_batch *b, const Net *nets, nvr_train_state *state,
                               hipStream_t st) {
+    const ScatterTail tails[2] = {{ctx->side, ctx->ev_fork[0]}, {ctx->side, ctx->ev_fork[1]}};
+    bool forked = false;
     for (int k = 0; k < s->n_fields; ++k) {
         const nvr_field *f = fields[k];
         FieldWs &w = ctx->ws[k];
@@ -353,8 +367,11 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                 NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                        f->table_grad, f->has_warp ? w.dx : nullptr, w.scatter_ws,
                                        st, /*counted=*/true, w.emit_chunks, w.emit_block,
-                                       f->has_warp ? w.jac : nullptr));
-            if (f->has_warp) NVR_TRY(warp_chain_bwd(ctx, f, w, kXcds, st));
+                                       f->has_warp ? w.jac : nullptr,
+                                       overlap(ctx, f) ? &tails[0] : nullptr));
+            if (f->has_warp)
+                NVR_TRY(warp_chain_bwd(ctx, f, w, kXcds, st, overlap(ctx, f) ? &tails[1] : nullptr));
+            forked |= overlap(ctx, f);
         } else {
             PlainView F{(float *)w.feat, 1, nets[k].n_in};
             PlainView dF{w.dfeat, 1, nets[k].n_in};
@@ -365,6 +382,10 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                                       f->table_grad, f->has_warp ? w.dx : nullptr, false, st));
             if (f->has_warp) NVR_TRY(warp_chain_bwd(ctx, f, w, 1, st));
         }
+    }
+    if (forked) {   // the second stream's work joins the caller's stream here
+        NVR_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+        NVR_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
     }
     if (!s->apply_update) return NVR_OK;
     NVR_TRY(launch_state_begin(state, st));
@@ -589,6 +610,17 @@ extern "C" nvr_status nvr_create(nvr_ctx **out, int32_t device, uint32_t flags) 
             return NVR_EHIP;
         }
     }
+    {
+        hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&c->ev_fork[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            nvr_destroy(c);
+            set_error("stream / event creation failed: %s", hipGetErrorString(e));
+            return NVR_EHIP;
+        }
+    }
     *out = c;
     return NVR_OK;
 }
@@ -606,6 +638,10 @@ extern "C" void nvr_destroy(nvr_ctx *ctx) {
     if (ctx->ray_buf) (void)hipFree(ctx->ray_buf);
     if (ctx->loss_part) (void)hipFree(ctx->loss_part);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    for (hipEvent_t e : ctx->ev_fork)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
 }
 
