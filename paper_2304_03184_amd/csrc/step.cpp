@@ -54,7 +54,7 @@ struct nvr_ctx {
     // second stream (default priority) on which a warped field's table-gradient
     // accumulation overlaps its chain through the deformation network and warp
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join = nullptr;
+    hipEvent_t ev_fork[3] = {nullptr, nullptr, nullptr}, ev_join = nullptr;
     nvr::FieldWs ws[2];
     int comp_blocks = 0;           // compositing workgroups (autotuned; 0: default)
     float *ray_buf = nullptr;      // render: C, D per ray chunk
@@ -349,16 +349,30 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
                               hipStream_t st) {
     const ScatterTail tails[2] = {{ctx->side, ctx->ev_fork[0]}, {ctx->side, ctx->ev_fork[1]}};
     bool forked = false;
-    for (int k = 0; k < s->n_fields; ++k) {
+    // beside a warped field, a field without a warp runs its whole backward on
+    // the second stream (it is independent of the warped field's), first
+    bool any_warp = false;
+    for (int k = 0; k < s->n_fields; ++k) any_warp |= overlap(ctx, fields[k]);
+    const bool side_plain = any_warp && s->n_fields > 1 && s->precision == NVR_BF16;
+    if (side_plain) {
+        NVR_HIP(hipEventRecord(ctx->ev_fork[2], st));
+        NVR_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork[2], 0));
+        forked = true;
+    }
+    int order[2] = {0, 1};
+    if (side_plain && fields[0]->has_warp) order[0] = 1, order[1] = 0;
+    for (int i = 0; i < s->n_fields; ++i) {
+        const int k = s->n_fields > 1 ? order[i] : i;
         const nvr_field *f = fields[k];
         FieldWs &w = ctx->ws[k];
         const int64_t cap = w.cap;
         const float *pos = enc_pos(f, w);
         const GridParams gp = make_grid_params(&f->grid);
         if (s->precision == NVR_BF16) {
+            const hipStream_t fs = side_plain && !f->has_warp ? ctx->side : st;
             NVR_TRY(mfma_bwd(nets[k], 0, w.n_dev, cap, (const uint16_t *)w.feat, true, b->d, w.ray_id,
                              f->params, true, w.dsigma, w.drgb, f->params_grad, w.dfeat, w.mlp_ws,
-                             st, w.mlp_bwd_blocks, w.sh));
+                             fs, w.mlp_bwd_blocks, w.sh));
             if (deterministic(ctx))
                 NVR_TRY(launch_scatter_det(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                            f->table_grad, f->has_warp ? w.dx : nullptr,
@@ -366,7 +380,7 @@ static nvr_status enqueue_bwd(nvr_ctx *ctx, const nvr_step_desc *s, nvr_field *c
             else
                 NVR_TRY(launch_scatter(gp, 0, w.n_dev, cap, pos, f->table_half, w.dfeat,
                                        f->table_grad, f->has_warp ? w.dx : nullptr, w.scatter_ws,
-                                       st, /*counted=*/true, w.emit_chunks, w.emit_block,
+                                       fs, /*counted=*/true, w.emit_chunks, w.emit_block,
                                        f->has_warp ? w.jac : nullptr,
                                        overlap(ctx, f) ? &tails[0] : nullptr));
             if (f->has_warp)
@@ -612,7 +626,7 @@ extern "C" nvr_status nvr_create(nvr_ctx **out, int32_t device, uint32_t flags) 
     }
     {
         hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-        for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        for (int i = 0; i < 3 && e == hipSuccess; ++i)
             e = hipEventCreateWithFlags(&c->ev_fork[i], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
         if (e != hipSuccess) {
